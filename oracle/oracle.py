@@ -1,0 +1,262 @@
+"""ctypes wrapper of the CPU oracle -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  The oracle is a plain single-threaded
+C++ implementation of the tracking method (see the header of
+``tpc_oracle.cpp`` for the steps it follows and which of them are pinned);
+it shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tpc_oracle.cpp")
+LIB = os.path.join(HERE, "libtpc_oracle.so")
+
+# Strict IEEE single precision: no contraction into FMA, no fast-math.
+CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+            "-fno-unsafe-math-optimizations", "-Wall"]
+
+STAGE_GRID, STAGE_LINKS, STAGE_TRACKLETS, STAGE_SELECT, STAGE_FIT, STAGE_MERGE = range(6)
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_float) for n in (
+        "win_dy_slope", "win_dy_const", "win_dz_slope", "win_dz_const", "link_cut",
+        "cy0", "cz0", "cs0", "ct0", "ck0", "cy1", "cz1", "cs1", "ct1", "ck1",
+        "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
+        ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
+        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge")]
+
+
+# The readings of every unstated constant (windows, cuts, priors, thresholds).
+DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_const=0.5,
+                link_cut=1.0, cy0=1.0, cz0=1.0, cs0=0.25, ct0=0.25, ck0=100.0,
+                cy1=1.0, cz1=1.0, cs1=1e-3, ct1=1e-3, ck1=1.0, sigma_y=0.1, sigma_z=0.1,
+                nwin=3.0, chi2_follow=15.0, max_miss=4, min_hits=10, smax=0.95, bz=0.5,
+                merge_edge=5.0, chi2_merge=50.0)
+
+
+def params(**over) -> Params:
+    d = dict(DEFAULTS)
+    d.update(over)
+    return Params(**d)
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["g++", *CXXFLAGS, "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [C.c_int32, P, P, P, P, C.c_int32, P, C.POINTER(Params)]
+        L.orc_destroy.argtypes = [P]
+        L.orc_set_brute.argtypes = [P, C.c_int32]
+        L.orc_status.argtypes = [P]
+        L.orc_run.argtypes = [P, C.c_int32]
+        L.orc_num_slot_members.restype = C.c_int64
+        L.orc_num_slot_members.argtypes = [P]
+        L.orc_get_rows.argtypes = [P, P, P]
+        L.orc_get_links.argtypes = [P, P, P, P, P]
+        L.orc_num_tracklets.argtypes = [P]
+        L.orc_num_tracklet_hits.restype = C.c_int64
+        L.orc_num_tracklet_hits.argtypes = [P]
+        L.orc_get_tracklets.argtypes = [P] * 7
+        L.orc_get_hitw.argtypes = [P, P]
+        L.orc_num_tracks.argtypes = [P, C.c_int32]
+        L.orc_num_track_hits.restype = C.c_int64
+        L.orc_num_track_hits.argtypes = [P, C.c_int32]
+        L.orc_get_tracks.argtypes = [P, C.c_int32] + [P] * 16
+        L.orc_propagate_f32.argtypes = [P, P, C.c_float, C.c_float, C.POINTER(Params)]
+        L.orc_propagate_f64.argtypes = [P, P, C.c_double, C.c_double, C.POINTER(Params)]
+        L.orc_update_f32.argtypes = [P, P, C.c_float, C.c_float, C.POINTER(Params), P]
+        L.orc_update_f64.argtypes = [P, P, C.c_double, C.c_double, C.POINTER(Params), P]
+        L.orc_asinc_f32.argtypes = [C.c_float, P, P]
+        L.orc_asinc_f64.argtypes = [C.c_double, P, P]
+        L.orc_row_x.restype = C.c_float
+        L.orc_row_x.argtypes = [C.c_int32]
+        L.orc_merge_chi2.restype = C.c_float
+        L.orc_merge_chi2.argtypes = [P, P, P, P]
+        L.orc_fit_hits_f64.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.orc_fit_hits_f32.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.orc_rotate_f64.argtypes = [P, P, P, P, C.c_int32, C.c_int32]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Run:
+    """Runs the oracle over a cluster list grouped into jobs and exposes stage outputs."""
+
+    def __init__(self, sector, row, y, z, job_off, prm: Params | None = None,
+                 last_stage: int = STAGE_MERGE, brute: bool = False):
+        L = lib()
+        self.prm = prm or params()
+        self.sector = np.ascontiguousarray(sector, np.uint8)
+        self.row = np.ascontiguousarray(row, np.int16)
+        self.y = np.ascontiguousarray(y, np.float32)
+        self.z = np.ascontiguousarray(z, np.float32)
+        self.job_off = np.ascontiguousarray(job_off, np.int32)
+        self.n = int(self.y.shape[0])
+        self.h = L.orc_create(self.n, _p(self.sector), _p(self.row), _p(self.y), _p(self.z),
+                              int(self.job_off.shape[0] - 1), _p(self.job_off),
+                              C.byref(self.prm))
+        L.orc_set_brute(self.h, int(brute))
+        L.orc_run(self.h, last_stage)
+        self.last_stage = last_stage
+
+    @classmethod
+    def from_set(cls, cs, prm=None, last_stage=STAGE_MERGE, brute=False):
+        return cls(cs.sector, cs.row, cs.y, cs.z, cs.job_off, prm, last_stage, brute)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_destroy(self.h)
+            self.h = None
+
+    @property
+    def status(self) -> int:
+        return lib().orc_status(self.h)
+
+    def rows(self):
+        """(slot_off[J*36*152+1], members) with members of each slot in ascending index."""
+        L = lib()
+        J = self.job_off.shape[0] - 1
+        off = np.zeros(J * 36 * 152 + 1, np.int64)
+        mem = np.zeros(L.orc_num_slot_members(self.h), np.int32)
+        L.orc_get_rows(self.h, _p(off), _p(mem))
+        return off, mem
+
+    def links(self):
+        a = [np.zeros(self.n, np.int32) for _ in range(4)]
+        lib().orc_get_links(self.h, *map(_p, a))
+        return dict(up_raw=a[0], down_raw=a[1], up=a[2], down=a[3])
+
+    def tracklets(self):
+        L = lib()
+        T = L.orc_num_tracklets(self.h)
+        H = L.orc_num_tracklet_hits(self.h)
+        start = np.zeros(T, np.int32)
+        off = np.zeros(T + 1, np.int32)
+        hits = np.zeros(H, np.int32)
+        P = np.zeros((T, 5), np.float32)
+        Cv = np.zeros((T, 15), np.float32)
+        x = np.zeros(T, np.float32)
+        L.orc_get_tracklets(self.h, _p(start), _p(off), _p(hits), _p(P), _p(Cv), _p(x))
+        w = np.zeros(self.n, np.uint64)
+        L.orc_get_hitw(self.h, _p(w))
+        return dict(start=start, off=off, hits=hits, P=P, C=Cv, x=x, hitw=w)
+
+    def tracks(self, merged: bool | None = None):
+        L = lib()
+        if merged is None:
+            merged = self.last_stage >= STAGE_MERGE
+        K = L.orc_num_tracks(self.h, int(merged))
+        H = L.orc_num_track_hits(self.h, int(merged))
+        out = dict(tracklet=np.zeros(K, np.int32), job=np.zeros(K, np.int32),
+                   sector=np.zeros(K, np.int32), sector2=np.zeros(K, np.int32),
+                   off=np.zeros(K + 1, np.int32), hits=np.zeros(H, np.int32),
+                   P=np.zeros((K, 5), np.float32), C=np.zeros((K, 15), np.float32),
+                   x=np.zeros(K, np.float32), chi2=np.zeros(K, np.float32),
+                   ndf=np.zeros(K, np.int32), Pd=np.zeros((K, 5), np.float64),
+                   Cd=np.zeros((K, 15), np.float64), xd=np.zeros(K, np.float64),
+                   chi2d=np.zeros(K, np.float64), ndfd=np.zeros(K, np.int32))
+        keys = ["tracklet", "job", "sector", "sector2", "off", "hits", "P", "C", "x", "chi2",
+                "ndf", "Pd", "Cd", "xd", "chi2d", "ndfd"]
+        L.orc_get_tracks(self.h, int(merged), *[_p(out[k]) for k in keys])
+        return out
+
+    def fit_hits(self, hits, stk, fp64=True):
+        L = lib()
+        hits = np.ascontiguousarray(hits, np.int32)
+        stk = np.ascontiguousarray(stk, np.float32)
+        dt = np.float64 if fp64 else np.float32
+        P = np.zeros(5, dt)
+        Cv = np.zeros(15, dt)
+        x = np.zeros(1, dt)
+        c2 = np.zeros(1, dt)
+        fn = L.orc_fit_hits_f64 if fp64 else L.orc_fit_hits_f32
+        ok = fn(self.h, len(hits), _p(hits), _p(stk), _p(P), _p(Cv), _p(x), _p(c2))
+        return bool(ok), P, Cv, float(x[0]), float(c2[0])
+
+
+# ----------------------------------------------------------------- unit hooks (pins)
+
+def _state(P, dt):
+    """5 values (hi) or 10 values (hi, lo) of the compensated state -> 10 values."""
+    P = np.asarray(P, dt).ravel()
+    return np.concatenate([P, np.zeros(5, dt)]) if P.size == 5 else P.copy()
+
+
+def propagate(P, Cv, x1, x2, prm=None, fp64=False):
+    """Returns (ok, state[10] = hi[5] + lo[5], C[15])."""
+    dt = np.float64 if fp64 else np.float32
+    P = _state(P, dt)
+    Cv = np.array(Cv, dt)
+    prm = prm or params()
+    fn = lib().orc_propagate_f64 if fp64 else lib().orc_propagate_f32
+    ok = fn(_p(P), _p(Cv), x1, x2, C.byref(prm))
+    return bool(ok), P, Cv
+
+
+def update(P, Cv, my, mz, prm=None, fp64=False):
+    dt = np.float64 if fp64 else np.float32
+    P = _state(P, dt)
+    Cv = np.array(Cv, dt)
+    c2 = np.zeros(1, dt)
+    prm = prm or params()
+    fn = lib().orc_update_f64 if fp64 else lib().orc_update_f32
+    ok = fn(_p(P), _p(Cv), my, mz, C.byref(prm), _p(c2))
+    return bool(ok), P, Cv, float(c2[0])
+
+
+def asinc(u, fp64=False):
+    dt = np.float64 if fp64 else np.float32
+    A = np.zeros(1, dt)
+    B = np.zeros(1, dt)
+    (lib().orc_asinc_f64 if fp64 else lib().orc_asinc_f32)(u, _p(A), _p(B))
+    return A[0], B[0]
+
+
+def row_x(r: int) -> float:
+    return lib().orc_row_x(r)
+
+
+def merge_chi2(PA, CA, PB, CB) -> float:
+    a = [np.ascontiguousarray(v, np.float32) for v in (PA, CA, PB, CB)]
+    return lib().orc_merge_chi2(*map(_p, a))
+
+
+def tri_to_full(Cv):
+    """Lower-triangle (15) -> symmetric 5x5."""
+    M = np.zeros((5, 5), dtype=np.asarray(Cv).dtype)
+    k = 0
+    for i in range(5):
+        for j in range(i + 1):
+            M[i, j] = M[j, i] = Cv[k]
+            k += 1
+    return M
+
+
+def full_to_tri(M):
+    return np.array([M[i, j] for i in range(5) for j in range(i + 1)], dtype=M.dtype)

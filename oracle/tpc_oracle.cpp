@@ -1,0 +1,921 @@
+// TPC track-reconstruction ORACLE -- test infrastructure only.
+//
+// A plain, slow, single-threaded CPU implementation of the tracking method:
+// cellular-automaton seeding (neighbour links on adjacent pad rows, mutual
+// cleaning, chains of >= 3 clusters) followed by Kalman-filter track following,
+// max-key hit arbitration, track selection, a Kalman refit and the merge of
+// track pieces across neighbouring sectors.  The paper (section 5: full TPC
+// tracking of every collision is required for track-model compression;
+// section 6: TPC tracking is the critical GPU step) states THAT this is
+// computed but not HOW; every algorithmic constant and step below is a reading
+// of the method written out explicitly, and the numbered "O" steps refer to
+// that reading (O1 frame/track model, O2 helix propagation, O3 grid (not
+// needed here: rows are searched in full or by binary search in z), O4
+// neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
+// O9 selection and fit, O10 merge).
+//
+// Only tests/, the smoke check and the CPU baseline leg of the benchmark may
+// load this library.  It shares no code, header, table or constant generator
+// with the HIP library.
+//
+// Two builds of every numerical step exist through one template:
+//   * float  -- the "FP32 mirror": the exact operation order that defines the
+//               bit-exact outputs (links, tracklet hits, track hit lists).
+//               Compile with -ffp-contract=off and without -ffast-math.
+//   * double -- the FP64 refit used as the reference for fitted parameters;
+//               its asin comes from libm.
+//
+// Pins (tests/): helix propagation against the closed-form circle and an RK4
+// integration of the Lorentz force; the propagation Jacobian against central
+// finite differences; the Kalman update against the information-form identity;
+// the FP32 asin(u)/u series against libm; neighbour links against a
+// brute-force triple search; chain/ownership invariants; zero-smear fits
+// recovering the truth.  The hit-picking heuristic of the tracklet following
+// (O7 window search) and the merge pairing (O10) are pinned only by invariants
+// and special cases: parity unpinned beyond those.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+constexpr int kRows = 152;
+constexpr int kSectors = 36;
+constexpr int kRowsPerSide = 18;
+
+// ---------------------------------------------------------------- parameters
+// Layout mirrored by oracle/oracle.py (ctypes).  Every float is used as is in
+// FP32; derived FP32 constants are formed in double and rounded once.
+struct Params {
+  float win_dy_slope, win_dy_const, win_dz_slope, win_dz_const;  // O4 up window
+  float link_cut;                                                // O4 second-difference cut
+  float cy0, cz0, cs0, ct0, ck0;                                 // O7 tracklet priors
+  float cy1, cz1, cs1, ct1, ck1;                                 // O9 fit priors
+  float sigma_y, sigma_z;                                        // O8 measurement errors
+  float nwin, chi2_follow;                                       // O7 following
+  int32_t max_miss, min_hits;
+  float smax;                                                    // |sin phi| limit
+  float bz;                                                      // field, tesla
+  float merge_edge, chi2_merge;                                  // O10
+};
+
+// Pad-row plane positions (O1, reading A2): x_r = 85 + r * 160/151 cm, rounded once.
+struct Geometry {
+  float x[kRows];
+  float cos20, sin20, tan10;
+  Geometry() {
+    for (int r = 0; r < kRows; ++r) x[r] = (float)(85.0 + (double)r * 160.0 / 151.0);
+    const double a = 20.0 * 3.14159265358979323846 / 180.0;
+    cos20 = (float)std::cos(a);
+    sin20 = (float)std::sin(a);
+    tan10 = (float)std::tan(a / 2.0);
+  }
+};
+const Geometry kGeo;
+
+// Signed curvature per unit q/pT: C = -kappa * B * (q/pT), kappa = 0.299792458e-2 GeV/(T cm).
+template <class T> T curvature_factor(const Params& p) {
+  return (T)(-0.299792458e-2 * (double)p.bz);
+}
+
+// ---------------------------------------------------------------- asin(u)/u
+// A(u) = asin(u)/u and B(u) = A'(u)/u.  FP32: Taylor coefficients of asin,
+// Horner in w = u^2 for |u| <= 1/2 (relative truncation error < 2^-25); above,
+// asin(u) = pi/2 - 2 asin(sqrt((1-|u|)/2)).  FP64: libm.
+const float kA[10] = {0x1p+0f,         0x1.555556p-3f, 0x1.333334p-4f, 0x1.6db6dcp-5f,
+                      0x1.f1c71cp-6f,  0x1.6e8ba2p-6f, 0x1.1c4ec4p-6f, 0x1.c9999ap-7f,
+                      0x1.7a8788p-7f,  0x1.3fde50p-7f};
+const float kB[12] = {0x1.555556p-2f, 0x1.333334p-2f, 0x1.124924p-2f, 0x1.f1c71cp-3f,
+                      0x1.ca2e8cp-3f, 0x1.aa7628p-3f, 0x1.906666p-3f, 0x1.7a8788p-3f,
+                      0x1.67da1ap-3f, 0x1.57ab0cp-3f, 0x1.497922p-3f, 0x1.3ce4aep-3f};
+
+float series_A(float w) {
+  float a = kA[9];
+  for (int i = 8; i >= 0; --i) a = kA[i] + w * a;
+  return a;
+}
+float series_B(float w) {
+  float b = kB[11];
+  for (int i = 10; i >= 0; --i) b = kB[i] + w * b;
+  return b;
+}
+
+void asinc(float u, float& A, float& B) {
+  const float au = std::fabs(u);
+  const float w = u * u;
+  if (au <= 0.5f) {
+    A = series_A(w);
+    B = series_B(w);
+  } else {
+    const float v = std::sqrt((1.0f - au) * 0.5f);
+    const float asn = 0x1.921fb6p+0f - 2.0f * (v * series_A(v * v));
+    A = asn / au;
+    const float g = 1.0f / std::sqrt((1.0f - u) * (1.0f + u));
+    B = (g - A) / w;
+  }
+}
+
+void asinc(double u, double& A, double& B) {
+  const double au = std::fabs(u);
+  const double w = u * u;
+  if (au < 0.05) {
+    // a_n = C(2n,n) / (4^n (2n+1)); B(u) = sum 2(n+1) a_{n+1} w^n
+    double an[9];
+    for (int n = 0; n < 9; ++n) {
+      double c = 1.0;
+      for (int i = 1; i <= n; ++i) c = c * (double)(n + i) / (double)(4 * i);
+      an[n] = c / (double)(2 * n + 1);
+    }
+    A = 0.0;
+    for (int n = 7; n >= 0; --n) A = an[n] + w * A;
+    B = 0.0;
+    for (int n = 7; n >= 0; --n) B = 2.0 * (double)(n + 1) * an[n + 1] + w * B;
+  } else {
+    A = std::asin(au) / au;
+    B = (1.0 / std::sqrt((1.0 - u) * (1.0 + u)) - A) / w;
+  }
+}
+
+// ---------------------------------------------------------------- track state
+// O1: state at a pad-row plane x: P = (y, z, s = sin phi, t = tan lambda, k = q/pT);
+// covariance stored as the lower triangle, index(i,j) = i(i+1)/2 + j, j <= i.
+inline int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+template <class T> bool all_finite(const T* P, const T* C) {
+  for (int i = 0; i < 5; ++i)
+    if (!(P[i] - P[i] == T(0))) return false;
+  for (int i = 0; i < 15; ++i)
+    if (!(C[i] - C[i] == T(0))) return false;
+  return true;
+}
+
+// The state vector is carried as an unevaluated sum hi + lo per component
+// (compensated accumulation): every increment is added with an exact two-sum and
+// the rounding error is kept in lo.  This keeps FP32 increments of 1e-3..1e-6
+// from being lost against O(1..100) state values.  hi is always fl(hi + lo).
+template <class T> inline void acc(T& hi, T& lo, T d) {
+  const T s = hi + d;
+  const T bb = s - hi;
+  const T e = (hi - (s - bb)) + (d - bb);
+  const T t = lo + e;
+  hi = s + t;
+  lo = t - (hi - s);
+}
+
+// O2: exact helix transport from plane x1 to plane x2 on the branch cos(phi) > 0,
+// with the analytic Jacobian J and C' = J C J^T.  Returns false on failure
+// (|s2| >= smax or |u| >= 1), leaving P and C untouched.
+template <class T>
+bool propagate(T* P, T* L, T* C, T x1, T x2, T cb, T smax) {
+  const T dx = x2 - x1;
+  if (dx == T(0)) return true;
+  const T curv = P[4] * cb;
+  const T s1 = P[2];
+  const T s2 = s1 + curv * dx;
+  if (!(std::fabs(s2) < smax)) return false;
+  const T c1 = std::sqrt((T(1) - s1) * (T(1) + s1));
+  const T c2 = std::sqrt((T(1) - s2) * (T(1) + s2));
+  const T cc = c1 + c2;
+  const T f = (s1 + s2) / cc;
+  const T dy = dx * f;
+  T ch = std::sqrt(dx * dx + dy * dy);
+  if (dx < T(0)) ch = -ch;
+  const T u = curv * ch * T(0.5);
+  if (!(std::fabs(u) < T(1))) return false;
+  T A, B;
+  asinc(u, A, B);
+  const T g = T(1) / std::sqrt((T(1) - u) * (T(1) + u));
+  const T dS = ch * A;
+  // Jacobian entries (all others are those of the identity)
+  const T q1 = s1 / c1;
+  const T q2 = s2 / c2;
+  const T fs = (T(2) + f * (q1 + q2)) / cc;
+  const T fc = dx * (T(1) + f * q2) / cc;
+  const T ja = dx * fs;                                  // dy / ds1
+  const T jb = dx * fc * cb;                             // dy / dk
+  const T chs = dy * ja / ch;
+  const T chk = dy * jb / ch;
+  const T dSs = g * chs;
+  const T dSk = g * chk + ch * ch * u * B * T(0.5) * cb;
+  const T t = P[3];
+  const T je = t * dSs;                                  // dz / ds1
+  const T jf = dS;                                       // dz / dt
+  const T jg = t * dSk;                                  // dz / dk
+  const T jh = cb * dx;                                  // ds2 / dk
+  // state
+  acc(P[0], L[0], dy);
+  acc(P[1], L[1], t * dS);
+  acc(P[2], L[2], curv * dx);
+  // covariance: M = J C, then C' = M J^T (lower triangle)
+  T c[5][5];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) c[i][j] = C[tri(i, j)];
+  T M[5][5];
+  for (int j = 0; j < 5; ++j) {
+    M[0][j] = c[0][j] + ja * c[2][j] + jb * c[4][j];
+    M[1][j] = c[1][j] + je * c[2][j] + jf * c[3][j] + jg * c[4][j];
+    M[2][j] = c[2][j] + jh * c[4][j];
+    M[3][j] = c[3][j];
+    M[4][j] = c[4][j];
+  }
+  for (int i = 0; i < 5; ++i) {
+    const T n0 = M[i][0] + ja * M[i][2] + jb * M[i][4];
+    const T n1 = M[i][1] + je * M[i][2] + jf * M[i][3] + jg * M[i][4];
+    const T n2 = M[i][2] + jh * M[i][4];
+    const T n3 = M[i][3];
+    const T n4 = M[i][4];
+    const T n[5] = {n0, n1, n2, n3, n4};
+    for (int j = 0; j <= i; ++j) C[tri(i, j)] = n[j];
+  }
+  return true;
+}
+
+// O8: the inverse of the 2x2 innovation covariance S = C[0:2,0:2] + diag(vy, vz).
+template <class T> struct SInv {
+  T i00, i10, i11;
+  bool ok;
+};
+template <class T> SInv<T> s_inverse(const T* C, T vy, T vz) {
+  SInv<T> r;
+  const T S00 = C[0] + vy;
+  const T S10 = C[1];
+  const T S11 = C[2] + vz;
+  const T det = S00 * S11 - S10 * S10;
+  r.ok = det > T(0);
+  const T idet = T(1) / det;
+  r.i00 = S11 * idet;
+  r.i10 = -(S10 * idet);
+  r.i11 = S00 * idet;
+  return r;
+}
+template <class T> T chi2_of(const SInv<T>& s, T r0, T r1) {
+  const T a0 = s.i00 * r0 + s.i10 * r1;
+  const T a1 = s.i10 * r0 + s.i11 * r1;
+  return r0 * a0 + r1 * a1;
+}
+
+// O8: Kalman update with the measurement (my, mz).  Returns false (state untouched)
+// if det <= 0, any value becomes non-finite, or |s| >= smax.
+template <class T>
+bool kf_update(T* P, T* L, T* C, T my, T mz, T vy, T vz, T smax, T* chi2_out) {
+  const SInv<T> si = s_inverse(C, vy, vz);
+  if (!si.ok) return false;
+  const T r0 = (my - P[0]) - L[0];
+  const T r1 = (mz - P[1]) - L[1];
+  const T chi2 = chi2_of(si, r0, r1);
+  T c0[5], c1[5];
+  for (int i = 0; i < 5; ++i) {
+    c0[i] = C[tri(i, 0)];
+    c1[i] = C[tri(i, 1)];
+  }
+  T K0[5], K1[5];
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = c0[i] * si.i00 + c1[i] * si.i10;
+    K1[i] = c0[i] * si.i10 + c1[i] * si.i11;
+  }
+  T Pn[5], Ln[5], Cn[15];
+  for (int i = 0; i < 5; ++i) {
+    Pn[i] = P[i];
+    Ln[i] = L[i];
+    acc(Pn[i], Ln[i], K0[i] * r0 + K1[i] * r1);
+  }
+  // Rows/columns of the measured components use the exact identity
+  // C'(i,m) = C(i,:m) S^-1 V = K(i,m) V (no cancellation); the rest is C - K H C.
+  for (int i = 0; i < 5; ++i) {
+    Cn[tri(i, 0)] = K0[i] * vy;
+    if (i >= 1) Cn[tri(i, 1)] = K1[i] * vz;
+    for (int j = 2; j <= i; ++j)
+      Cn[tri(i, j)] = C[tri(i, j)] - (K0[i] * c0[j] + K1[i] * c1[j]);
+  }
+  if (!all_finite(Pn, Cn)) return false;
+  if (!(std::fabs(Pn[2]) < smax)) return false;
+  std::memcpy(P, Pn, sizeof(Pn));
+  std::memcpy(L, Ln, sizeof(Ln));
+  std::memcpy(C, Cn, sizeof(Cn));
+  if (chi2_out) *chi2_out = chi2;
+  return true;
+}
+
+// ---------------------------------------------------------------- the oracle
+struct Tracklet {
+  int32_t start;              // original index of the first chain cluster
+  int32_t n;                  // hits
+  bool valid;                 // n >= min_hits
+  std::vector<int32_t> hits;  // original indices, rows ascending
+  float P[5], C[15], x;       // state at the last hit (after its update)
+};
+
+struct Track {
+  int32_t tracklet;           // tracklet id it was selected from (== track id)
+  int32_t job, sector;
+  std::vector<int32_t> hits;  // original indices, inner -> outer
+  float P[5], C[15], x, chi2; int32_t ndf;   // FP32 fit at the innermost hit
+  double Pd[5], Cd[15], xd, chi2d; int32_t ndfd;   // FP64 refit
+  // merge bookkeeping: a merged track keeps the inner piece's id; the outer piece is absorbed
+  int32_t merged_into = -1;
+  int32_t partner = -1;
+  int32_t sector2 = -1;       // sector of the absorbed outer piece, -1 if none
+};
+
+struct Oracle {
+  Params p;
+  int32_t n = 0, J = 0;
+  std::vector<uint8_t> sector;
+  std::vector<int16_t> row;
+  std::vector<float> y, z;
+  std::vector<int32_t> job_off, job_of;
+  std::vector<uint8_t> valid;
+  int32_t status = 0;  // bit 0: a cluster with an out-of-range field was excluded
+
+  // row lists: clusters of (job, sector, row), sorted by (z, index)
+  std::vector<int64_t> slot_off;
+  std::vector<int32_t> slot_idx;
+
+  std::vector<int32_t> up_raw, down_raw, up, down;
+  std::vector<int32_t> starts;
+  std::vector<Tracklet> tracklets;
+  std::vector<uint64_t> hitw;
+  std::vector<Track> tracks;      // selected, in tracklet-id order
+  bool brute = false;             // search whole rows instead of the z-sorted range
+
+  int64_t slot(int j, int s, int r) const { return ((int64_t)j * kSectors + s) * kRows + r; }
+
+  // -------- O3: group clusters by (job, sector, row) -- the search structure
+  void build_rows() {
+    const int64_t ns = (int64_t)J * kSectors * kRows;
+    slot_off.assign(ns + 1, 0);
+    std::vector<int64_t> key(n, -1);
+    for (int32_t i = 0; i < n; ++i) {
+      if (!valid[i]) continue;
+      key[i] = slot(job_of[i], sector[i], row[i]);
+      slot_off[key[i] + 1]++;
+    }
+    for (int64_t s = 0; s < ns; ++s) slot_off[s + 1] += slot_off[s];
+    slot_idx.assign(slot_off[ns], 0);
+    std::vector<int64_t> fill(slot_off.begin(), slot_off.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      if (key[i] >= 0) slot_idx[fill[key[i]]++] = i;
+    for (int64_t s = 0; s < ns; ++s)
+      std::sort(slot_idx.begin() + slot_off[s], slot_idx.begin() + slot_off[s + 1],
+                [&](int32_t a, int32_t b) { return z[a] < z[b] || (z[a] == z[b] && a < b); });
+  }
+
+  // index range [lo, hi) of slot s whose z lies in [zlo, zhi]
+  void z_range(int64_t s, float zlo, float zhi, int64_t& lo, int64_t& hi) const {
+    lo = slot_off[s];
+    hi = slot_off[s + 1];
+    if (brute) return;
+    const int32_t* b = slot_idx.data();
+    lo = std::lower_bound(b + lo, b + hi, zlo, [&](int32_t i, float v) { return z[i] < v; }) - b;
+    hi = std::upper_bound(b + lo, b + hi, zhi, [&](float v, int32_t i) { return v < z[i]; }) - b;
+  }
+
+  // -------- O4: neighbour links
+  void find_neighbours() {
+    up_raw.assign(n, -1);
+    down_raw.assign(n, -1);
+    const float cut2 = p.link_cut * p.link_cut;
+    const float zmargin = 0.01f;
+    for (int32_t h = 0; h < n; ++h) {
+      if (!valid[h]) continue;
+      const int r = row[h], s = sector[h], j = job_of[h];
+      const float yh = y[h], zh = z[h];
+      for (int d = 1; d <= 2; ++d) {
+        if (r - d < 0 || r + d >= kRows) break;
+        const float dxu = kGeo.x[r + d] - kGeo.x[r];
+        const float wy = p.win_dy_slope * dxu + p.win_dy_const;
+        const float wz = p.win_dz_slope * dxu + p.win_dz_const;
+        const float rho = kGeo.x[r + d] / kGeo.x[r];
+        const float yc = yh * rho;
+        float best = 0.f;
+        int32_t bu = -1, bd = -1;
+        int64_t ulo, uhi;
+        z_range(slot(j, s, r + d), zh - wz - zmargin, zh + wz + zmargin, ulo, uhi);
+        for (int64_t a = ulo; a < uhi; ++a) {
+          const int32_t u = slot_idx[a];
+          if (!(std::fabs(y[u] - yc) <= wy) || !(std::fabs(z[u] - zh) <= wz)) continue;
+          const float pz = (zh + zh) - z[u];
+          int64_t dlo, dhi;
+          z_range(slot(j, s, r - d), pz - p.link_cut - zmargin, pz + p.link_cut + zmargin, dlo, dhi);
+          for (int64_t b = dlo; b < dhi; ++b) {
+            const int32_t dd = slot_idx[b];
+            const float ry = (y[u] + y[dd]) - (yh + yh);
+            const float rz = (z[u] + z[dd]) - (zh + zh);
+            const float score = ry * ry + rz * rz;
+            if (!(score <= cut2)) continue;
+            if (bu < 0 || score < best || (score == best && (u < bu || (u == bu && dd < bd)))) {
+              best = score;
+              bu = u;
+              bd = dd;
+            }
+          }
+        }
+        if (bu >= 0) {
+          up_raw[h] = bu;
+          down_raw[h] = bd;
+          break;
+        }
+      }
+    }
+    // O5: keep mutual links only, evaluated from the raw arrays
+    up.assign(n, -1);
+    down.assign(n, -1);
+    for (int32_t h = 0; h < n; ++h) {
+      if (up_raw[h] >= 0 && down_raw[up_raw[h]] == h) up[h] = up_raw[h];
+      if (down_raw[h] >= 0 && up_raw[down_raw[h]] == h) down[h] = down_raw[h];
+    }
+  }
+
+  // -------- O6 + O7: starts, tracklet construction, hit weights
+  void construct_tracklets() {
+    starts.clear();
+    for (int32_t h = 0; h < n; ++h)
+      if (down[h] < 0 && up[h] >= 0 && up[up[h]] >= 0) starts.push_back(h);
+    tracklets.assign(starts.size(), Tracklet());
+    hitw.assign(n, 0);
+    const float cb = curvature_factor<float>(p);
+    const float vy = p.sigma_y * p.sigma_y, vz = p.sigma_z * p.sigma_z;
+    for (size_t id = 0; id < starts.size(); ++id) {
+      Tracklet& t = tracklets[id];
+      t.start = starts[id];
+      build_tracklet(t, cb, vy, vz);
+      t.n = (int32_t)t.hits.size();
+      t.valid = t.n >= p.min_hits;
+      if (t.valid) {
+        const uint64_t key = ((uint64_t)t.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)id);
+        for (int32_t h : t.hits) hitw[h] = std::max(hitw[h], key);
+      }
+    }
+  }
+
+  // The chain of a start h: h, up[h], up[up[h]], ...  A chain's innermost cluster has no
+  // lower neighbour, so it never gets an up link of its own; it is recovered as the
+  // start's raw down neighbour d when d has no up link (d is then prepended).
+  int32_t chain_first(int32_t h) const {
+    const int32_t d = down_raw[h];
+    return (d >= 0 && up_raw[d] < 0) ? d : h;
+  }
+  int32_t chain_next(int32_t c, int32_t h, int32_t first) const {
+    return (c == first && first != h) ? h : up[c];
+  }
+
+  void build_tracklet(Tracklet& t, float cb, float vy, float vz) {
+    const int32_t c0 = chain_first(t.start);
+    const int32_t c1 = chain_next(c0, t.start, c0), c2 = chain_next(c1, t.start, c0);
+    const int s = sector[c0], j = job_of[c0];
+    float P[5], L[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, C[15];
+    const float dx2 = kGeo.x[row[c2]] - kGeo.x[row[c0]];
+    const float dy2 = y[c2] - y[c0];
+    const float dz2 = z[c2] - z[c0];
+    const float den = std::sqrt(dx2 * dx2 + dy2 * dy2);
+    P[0] = y[c0];
+    P[1] = z[c0];
+    P[2] = dy2 / den;
+    P[3] = dz2 / den;
+    P[4] = 0.f;
+    for (int i = 0; i < 15; ++i) C[i] = 0.f;
+    C[tri(0, 0)] = p.cy0; C[tri(1, 1)] = p.cz0; C[tri(2, 2)] = p.cs0;
+    C[tri(3, 3)] = p.ct0; C[tri(4, 4)] = p.ck0;
+    float x = kGeo.x[row[c0]];
+    auto keep_state = [&]() {
+      std::memcpy(t.P, P, sizeof(P));
+      std::memcpy(t.C, C, sizeof(C));
+      t.x = x;
+    };
+    // the chain: every chain cluster is used unconditionally
+    for (int32_t h = c0; h >= 0; h = chain_next(h, t.start, c0)) {
+      const float xh = kGeo.x[row[h]];
+      if (!propagate(P, L, C, x, xh, cb, p.smax)) return;
+      x = xh;
+      if (!kf_update(P, L, C, y[h], z[h], vy, vz, p.smax, (float*)nullptr)) return;
+      t.hits.push_back(h);
+      keep_state();
+    }
+    // following on the rows above the chain
+    int misses = 0;
+    for (int r = row[t.hits.back()] + 1; r < kRows; ++r) {
+      const float xr = kGeo.x[r];
+      if (!propagate(P, L, C, x, xr, cb, p.smax)) return;
+      x = xr;
+      const SInv<float> si = s_inverse(C, vy, vz);
+      if (!si.ok) return;
+      const float wy = p.nwin * std::sqrt(C[tri(0, 0)] + vy);
+      const float wz = p.nwin * std::sqrt(C[tri(1, 1)] + vz);
+      int64_t lo, hi;
+      z_range(slot(j, s, r), P[1] - wz - 0.01f, P[1] + wz + 0.01f, lo, hi);
+      int32_t best = -1;
+      float bchi = 0.f;
+      for (int64_t a = lo; a < hi; ++a) {
+        const int32_t c = slot_idx[a];
+        const float r0 = (y[c] - P[0]) - L[0];
+        const float r1 = (z[c] - P[1]) - L[1];
+        if (!(std::fabs(r0) <= wy) || !(std::fabs(r1) <= wz)) continue;
+        const float chi2 = chi2_of(si, r0, r1);
+        if (best < 0 || chi2 < bchi || (chi2 == bchi && c < best)) {
+          best = c;
+          bchi = chi2;
+        }
+      }
+      if (best >= 0 && bchi <= p.chi2_follow) {
+        if (!kf_update(P, L, C, y[best], z[best], vy, vz, p.smax, (float*)nullptr)) return;
+        t.hits.push_back(best);
+        keep_state();
+        misses = 0;
+      } else if (++misses >= p.max_miss) {
+        return;
+      }
+    }
+  }
+
+  // -------- O9: selection
+  void select_tracks() {
+    tracks.clear();
+    for (size_t id = 0; id < tracklets.size(); ++id) {
+      const Tracklet& t = tracklets[id];
+      if (!t.valid) continue;
+      const uint64_t key = ((uint64_t)t.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)id);
+      Track tr;
+      for (int32_t h : t.hits)
+        if (hitw[h] == key) tr.hits.push_back(h);
+      if ((int32_t)tr.hits.size() < p.min_hits) continue;
+      tr.tracklet = (int32_t)id;
+      tr.job = job_of[t.start];
+      tr.sector = sector[t.start];
+      tracks.push_back(std::move(tr));
+    }
+  }
+
+  // -------- O9: Kalman refit from the outermost to the innermost hit
+  template <class T>
+  bool fit(const std::vector<int32_t>& hits, const float* sinit, int sec_outer,
+           const std::vector<int>& hit_sector, T* P, T* C, T& xout, T& chi2, int32_t& ndf) {
+    const T cb = curvature_factor<T>(p);
+    const T vy = (T)p.sigma_y * (T)p.sigma_y, vz = (T)p.sigma_z * (T)p.sigma_z;
+    const T smax = (T)p.smax;
+    const int nh = (int)hits.size();
+    const int32_t ho = hits[nh - 1];
+    P[0] = (T)y[ho];
+    P[1] = (T)z[ho];
+    P[2] = (T)sinit[0];
+    P[3] = (T)sinit[1];
+    P[4] = (T)sinit[2];
+    T L[5] = {T(0), T(0), T(0), T(0), T(0)};
+    for (int i = 0; i < 15; ++i) C[i] = T(0);
+    C[tri(0, 0)] = (T)p.cy1; C[tri(1, 1)] = (T)p.cz1; C[tri(2, 2)] = (T)p.cs1;
+    C[tri(3, 3)] = (T)p.ct1; C[tri(4, 4)] = (T)p.ck1;
+    T x = (T)kGeo.x[row[ho]];
+    chi2 = T(0);
+    int cur_sec = sec_outer;
+    for (int i = nh - 1; i >= 0; --i) {
+      const int32_t h = hits[i];
+      if (hit_sector[i] != cur_sec) {
+        // crossing into the neighbouring sector of the inner piece (O10)
+        if (!rotate(P, L, C, x, cur_sec, hit_sector[i])) return false;
+        cur_sec = hit_sector[i];
+      }
+      const T xh = (T)kGeo.x[row[h]];
+      if (!propagate(P, L, C, x, xh, cb, smax)) return false;
+      x = xh;
+      T c2;
+      if (!kf_update(P, L, C, (T)y[h], (T)z[h], vy, vz, smax, &c2)) return false;
+      chi2 = chi2 + c2;
+    }
+    xout = x;
+    ndf = 2 * nh - 5;
+    return true;
+  }
+
+  // O10: re-express a state in the frame of the adjacent sector `to` (same side; the
+  // sector angle changes by d = +-20 degrees).  The point keeps its global position:
+  // x' = x cos d + y sin d, y' = -x sin d + y cos d; the direction turns by -d:
+  // s' = s cos d - c sin d, c' = c cos d + s sin d; z, t, k are unchanged.  The new
+  // reference plane is x' = const, so a shift of y at fixed x moves the point off that
+  // plane; moving it back along the track gives dy'/dy = c/c' and dz'/dy = -t sin d / c'.
+  // Also ds'/ds = c'/c.  Fails unless c' > 0 and |s'| < smax.
+  template <class T> bool rotate(T* P, T* L, T* C, T& x, int from, int to) {
+    const int df = ((to % kRowsPerSide) - (from % kRowsPerSide) + kRowsPerSide) % kRowsPerSide;
+    if (df != 1 && df != kRowsPerSide - 1) return false;
+    const T ca = (T)kGeo.cos20;
+    const T sa = df == 1 ? (T)kGeo.sin20 : -(T)kGeo.sin20;
+    const T s = P[2];
+    const T c = std::sqrt((T(1) - s) * (T(1) + s));
+    const T xn = x * ca + P[0] * sa;
+    const T yn = P[0] * ca - x * sa;
+    const T sn = s * ca - c * sa;
+    const T cn = c * ca + s * sa;
+    if (!(cn > T(0)) || !(std::fabs(sn) < (T)p.smax)) return false;
+    const T ja = c / cn;                 // dy'/dy
+    const T jb = -(P[3] * sa / cn);      // dz'/dy
+    const T je = cn / c;                 // ds'/ds
+    T c5[5][5];
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) c5[i][j] = C[tri(i, j)];
+    T M[5][5];
+    for (int j = 0; j < 5; ++j) {
+      M[0][j] = ja * c5[0][j];
+      M[1][j] = jb * c5[0][j] + c5[1][j];
+      M[2][j] = je * c5[2][j];
+      M[3][j] = c5[3][j];
+      M[4][j] = c5[4][j];
+    }
+    for (int i = 0; i < 5; ++i) {
+      const T n[5] = {ja * M[i][0], jb * M[i][0] + M[i][1], je * M[i][2], M[i][3], M[i][4]};
+      for (int j = 0; j <= i; ++j) C[tri(i, j)] = n[j];
+    }
+    P[0] = yn;
+    P[2] = sn;
+    L[0] = T(0);
+    L[2] = T(0);
+    x = xn;
+    return all_finite(P, C);
+  }
+
+  void fit_all() {
+    for (Track& tr : tracks) fit_track(tr);
+  }
+
+  void fit_track(Track& tr) {
+    std::vector<int> hs(tr.hits.size());
+    for (size_t i = 0; i < tr.hits.size(); ++i) hs[i] = sector[tr.hits[i]];
+    int last = (int)(&tr - tracks.data());
+    while (tracks[last].partner >= 0) last = tracks[last].partner;
+    const Tracklet& st = tracklets[tracks[last].tracklet];
+    const float sinit[3] = {st.P[2], st.P[3], st.P[4]};
+    const int so = hs.back();
+    if (!fit<float>(tr.hits, sinit, so, hs, tr.P, tr.C, tr.x, tr.chi2, tr.ndf)) {
+      tr.ndf = -1;
+      for (float& v : tr.P) v = NAN;
+    }
+    if (!fit<double>(tr.hits, sinit, so, hs, tr.Pd, tr.Cd, tr.xd, tr.chi2d, tr.ndfd)) {
+      tr.ndfd = -1;
+      for (double& v : tr.Pd) v = NAN;
+    }
+  }
+
+  // -------- O10: merge track pieces that continue into an adjacent sector (same side).
+  // A (inner piece) ends within merge_edge of the sector edge it is heading for; B (outer
+  // piece) lies in the adjacent sector and starts within merge_edge of the same edge.
+  // A's tracklet end state is rotated into B's frame, propagated to B's innermost plane
+  // and compared with B's fitted state: chi2 = d^T (C_A + C_B)^-1 d.  Pairs with
+  // chi2 <= chi2_merge that are each other's best (ties: smaller id) are joined; joins
+  // chain through several sectors.  Merged hit list: inner piece first.  The merged
+  // track keeps the innermost piece's id and is refitted across the sector crossings.
+  void merge() {
+    const float cb = curvature_factor<float>(p);
+    const int K = (int)tracks.size();
+    std::vector<float> bestA(K, 0.f), bestB(K, 0.f);
+    std::vector<int32_t> argA(K, -1), argB(K, -1);
+    for (int a = 0; a < K; ++a) {
+      const Track& A = tracks[a];
+      if (A.ndf < 0) continue;
+      const Tracklet& ta = tracklets[A.tracklet];
+      const float edge = ta.x * kGeo.tan10 - std::fabs(ta.P[0]);
+      if (!(edge <= p.merge_edge)) continue;
+      const int dir = ta.P[0] > 0.f ? 1 : kRowsPerSide - 1;
+      const int sb = (A.sector / kRowsPerSide) * kRowsPerSide + (A.sector % kRowsPerSide + dir) % kRowsPerSide;
+      for (int b = 0; b < K; ++b) {
+        const Track& B = tracks[b];
+        if (B.ndf < 0 || B.job != A.job || B.sector != sb) continue;
+        const int32_t hb = B.hits.front();
+        const float eb = kGeo.x[row[hb]] * kGeo.tan10 - std::fabs(y[hb]);
+        if (!(eb <= p.merge_edge)) continue;
+        float P[5], L[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, C[15];
+        std::memcpy(P, ta.P, sizeof(P));
+        std::memcpy(C, ta.C, sizeof(C));
+        float x = ta.x;
+        if (!rotate(P, L, C, x, A.sector, sb)) continue;
+        if (!propagate(P, L, C, x, B.x, cb, p.smax)) continue;
+        const float c = merge_chi2(P, C, B.P, B.C);
+        if (!(c <= p.chi2_merge)) continue;
+        if (argA[a] < 0 || c < bestA[a] || (c == bestA[a] && b < argA[a])) { bestA[a] = c; argA[a] = b; }
+        if (argB[b] < 0 || c < bestB[b] || (c == bestB[b] && a < argB[b])) { bestB[b] = c; argB[b] = a; }
+      }
+    }
+    std::vector<int32_t> prev(K, -1);
+    for (int a = 0; a < K; ++a) {
+      const int b = argA[a];
+      if (b >= 0 && argB[b] == a) {
+        tracks[a].partner = b;
+        prev[b] = a;
+      }
+    }
+    for (int a = 0; a < K; ++a) {
+      if (prev[a] >= 0 || tracks[a].partner < 0) continue;   // chain heads only
+      Track& A = tracks[a];
+      int steps = 0;
+      for (int b = A.partner; b >= 0 && steps < kRowsPerSide; b = tracks[b].partner, ++steps) {
+        tracks[b].merged_into = a;
+        A.hits.insert(A.hits.end(), tracks[b].hits.begin(), tracks[b].hits.end());
+        A.sector2 = tracks[b].sector;
+      }
+      fit_track(A);
+    }
+  }
+
+  // chi2 = d^T (CA + CB)^-1 d over the 5 parameters, by Cholesky in fixed order
+  static float merge_chi2(const float* PA, const float* CA, const float* PB, const float* CB) {
+    float S[15], d[5];
+    for (int i = 0; i < 15; ++i) S[i] = CA[i] + CB[i];
+    for (int i = 0; i < 5; ++i) d[i] = PA[i] - PB[i];
+    float L[15];
+    for (int i = 0; i < 5; ++i) {
+      for (int j = 0; j <= i; ++j) {
+        float acc = S[tri(i, j)];
+        for (int k = 0; k < j; ++k) acc = acc - L[tri(i, k)] * L[tri(j, k)];
+        if (i == j) {
+          if (!(acc > 0.f)) return INFINITY;
+          L[tri(i, i)] = std::sqrt(acc);
+        } else {
+          L[tri(i, j)] = acc / L[tri(j, j)];
+        }
+      }
+    }
+    float w[5];
+    float c = 0.f;
+    for (int i = 0; i < 5; ++i) {
+      float acc = d[i];
+      for (int k = 0; k < i; ++k) acc = acc - L[tri(i, k)] * w[k];
+      w[i] = acc / L[tri(i, i)];
+      c = c + w[i] * w[i];
+    }
+    return c;
+  }
+};
+
+}  // namespace
+
+// ============================================================== C interface (ctypes)
+extern "C" {
+
+void* orc_create(int32_t n, const uint8_t* sector, const int16_t* row, const float* y,
+                 const float* z, int32_t n_jobs, const int32_t* job_off, const Params* p) {
+  Oracle* o = new Oracle();
+  o->p = *p;
+  o->n = n;
+  o->J = n_jobs;
+  o->sector.assign(sector, sector + n);
+  o->row.assign(row, row + n);
+  o->y.assign(y, y + n);
+  o->z.assign(z, z + n);
+  o->job_off.assign(job_off, job_off + n_jobs + 1);
+  o->job_of.assign(n, 0);
+  o->valid.assign(n, 1);
+  for (int j = 0; j < n_jobs; ++j)
+    for (int32_t i = job_off[j]; i < job_off[j + 1]; ++i) o->job_of[i] = j;
+  for (int32_t i = 0; i < n; ++i) {
+    const bool ok = sector[i] < kSectors && row[i] >= 0 && row[i] < kRows &&
+                    y[i] - y[i] == 0.f && z[i] - z[i] == 0.f;
+    if (!ok) {
+      o->valid[i] = 0;
+      o->status |= 1;
+    }
+  }
+  return o;
+}
+
+void orc_destroy(void* h) { delete (Oracle*)h; }
+void orc_set_brute(void* h, int32_t b) { ((Oracle*)h)->brute = b != 0; }
+int32_t orc_status(void* h) { return ((Oracle*)h)->status; }
+
+void orc_run(void* h, int32_t last_stage) {
+  Oracle* o = (Oracle*)h;
+  o->build_rows();
+  if (last_stage >= 1) o->find_neighbours();
+  if (last_stage >= 2) o->construct_tracklets();
+  if (last_stage >= 3) o->select_tracks();
+  if (last_stage >= 4) o->fit_all();
+  if (last_stage >= 5) o->merge();
+}
+
+// row lists: per slot (job, sector, row) the member indices in ascending index order
+int64_t orc_num_slot_members(void* h) { return (int64_t)((Oracle*)h)->slot_idx.size(); }
+void orc_get_rows(void* h, int64_t* slot_off, int32_t* members_sorted_by_index) {
+  Oracle* o = (Oracle*)h;
+  std::copy(o->slot_off.begin(), o->slot_off.end(), slot_off);
+  for (size_t s = 0; s + 1 < o->slot_off.size(); ++s) {
+    std::vector<int32_t> v(o->slot_idx.begin() + o->slot_off[s], o->slot_idx.begin() + o->slot_off[s + 1]);
+    std::sort(v.begin(), v.end());
+    std::copy(v.begin(), v.end(), members_sorted_by_index + o->slot_off[s]);
+  }
+}
+
+void orc_get_links(void* h, int32_t* up_raw, int32_t* down_raw, int32_t* up, int32_t* down) {
+  Oracle* o = (Oracle*)h;
+  std::copy(o->up_raw.begin(), o->up_raw.end(), up_raw);
+  std::copy(o->down_raw.begin(), o->down_raw.end(), down_raw);
+  std::copy(o->up.begin(), o->up.end(), up);
+  std::copy(o->down.begin(), o->down.end(), down);
+}
+
+int32_t orc_num_tracklets(void* h) { return (int32_t)((Oracle*)h)->tracklets.size(); }
+int64_t orc_num_tracklet_hits(void* h) {
+  int64_t s = 0;
+  for (auto& t : ((Oracle*)h)->tracklets) s += t.hits.size();
+  return s;
+}
+// start index, hit CSR (all tracklets, valid or not), state at the last hit
+void orc_get_tracklets(void* h, int32_t* start, int32_t* off, int32_t* hits, float* P, float* C,
+                       float* x) {
+  Oracle* o = (Oracle*)h;
+  int64_t k = 0;
+  off[0] = 0;
+  for (size_t i = 0; i < o->tracklets.size(); ++i) {
+    const Tracklet& t = o->tracklets[i];
+    start[i] = t.start;
+    for (int32_t v : t.hits) hits[k++] = v;
+    off[i + 1] = (int32_t)k;
+    std::memcpy(P + 5 * i, t.P, sizeof(t.P));
+    std::memcpy(C + 15 * i, t.C, sizeof(t.C));
+    x[i] = t.x;
+  }
+}
+void orc_get_hitw(void* h, uint64_t* w) {
+  Oracle* o = (Oracle*)h;
+  std::copy(o->hitw.begin(), o->hitw.end(), w);
+}
+
+// tracks after the last stage run; absorbed outer pieces are skipped when merged != 0
+int32_t orc_num_tracks(void* h, int32_t merged) {
+  int32_t c = 0;
+  for (auto& t : ((Oracle*)h)->tracks) c += (!merged || t.merged_into < 0);
+  return c;
+}
+int64_t orc_num_track_hits(void* h, int32_t merged) {
+  int64_t c = 0;
+  for (auto& t : ((Oracle*)h)->tracks)
+    if (!merged || t.merged_into < 0) c += t.hits.size();
+  return c;
+}
+void orc_get_tracks(void* h, int32_t merged, int32_t* tracklet, int32_t* job, int32_t* sector,
+                    int32_t* sector2, int32_t* off, int32_t* hits, float* P, float* C, float* x,
+                    float* chi2, int32_t* ndf, double* Pd, double* Cd, double* xd, double* chi2d,
+                    int32_t* ndfd) {
+  Oracle* o = (Oracle*)h;
+  int64_t k = 0, m = 0;
+  off[0] = 0;
+  for (auto& t : o->tracks) {
+    if (merged && t.merged_into >= 0) continue;
+    tracklet[m] = t.tracklet;
+    job[m] = t.job;
+    sector[m] = t.sector;
+    sector2[m] = t.sector2;
+    for (int32_t v : t.hits) hits[k++] = v;
+    off[m + 1] = (int32_t)k;
+    std::memcpy(P + 5 * m, t.P, sizeof(t.P));
+    std::memcpy(C + 15 * m, t.C, sizeof(t.C));
+    x[m] = t.x; chi2[m] = t.chi2; ndf[m] = t.ndf;
+    std::memcpy(Pd + 5 * m, t.Pd, sizeof(t.Pd));
+    std::memcpy(Cd + 15 * m, t.Cd, sizeof(t.Cd));
+    xd[m] = t.xd; chi2d[m] = t.chi2d; ndfd[m] = t.ndfd;
+    ++m;
+  }
+}
+
+// ---- unit hooks for the pins
+// P: 10 values (hi[5], lo[5]) of the compensated state
+int32_t orc_propagate_f32(float* P, float* C, float x1, float x2, const Params* p) {
+  return propagate<float>(P, P + 5, C, x1, x2, curvature_factor<float>(*p), p->smax);
+}
+int32_t orc_propagate_f64(double* P, double* C, double x1, double x2, const Params* p) {
+  return propagate<double>(P, P + 5, C, x1, x2, curvature_factor<double>(*p), (double)p->smax);
+}
+int32_t orc_update_f32(float* P, float* C, float my, float mz, const Params* p, float* chi2) {
+  return kf_update<float>(P, P + 5, C, my, mz, p->sigma_y * p->sigma_y, p->sigma_z * p->sigma_z, p->smax, chi2);
+}
+int32_t orc_update_f64(double* P, double* C, double my, double mz, const Params* p, double* chi2) {
+  const double sy = p->sigma_y, sz = p->sigma_z;
+  return kf_update<double>(P, P + 5, C, my, mz, sy * sy, sz * sz, (double)p->smax, chi2);
+}
+int32_t orc_rotate_f64(void* h, double* P, double* C, double* x, int32_t from, int32_t to) {
+  return ((Oracle*)h)->rotate<double>(P, P + 5, C, *x, from, to);
+}
+void orc_asinc_f32(float u, float* A, float* B) { asinc(u, *A, *B); }
+void orc_asinc_f64(double u, double* A, double* B) { asinc(u, *A, *B); }
+float orc_row_x(int32_t r) { return kGeo.x[r]; }
+float orc_merge_chi2(const float* PA, const float* CA, const float* PB, const float* CB) {
+  return Oracle::merge_chi2(PA, CA, PB, CB);
+}
+// FP64 refit of an arbitrary hit list (inner -> outer, one sector) from given (s, t, k)
+int32_t orc_fit_hits_f64(void* h, int32_t nh, const int32_t* hits, const float* stk, double* P,
+                         double* C, double* x, double* chi2) {
+  Oracle* o = (Oracle*)h;
+  std::vector<int32_t> v(hits, hits + nh);
+  std::vector<int> hs(nh);
+  for (int i = 0; i < nh; ++i) hs[i] = o->sector[hits[i]];
+  int32_t ndf;
+  return o->fit<double>(v, stk, hs.back(), hs, P, C, *x, *chi2, ndf);
+}
+int32_t orc_fit_hits_f32(void* h, int32_t nh, const int32_t* hits, const float* stk, float* P,
+                         float* C, float* x, float* chi2) {
+  Oracle* o = (Oracle*)h;
+  std::vector<int32_t> v(hits, hits + nh);
+  std::vector<int> hs(nh);
+  for (int i = 0; i < nh; ++i) hs[i] = o->sector[hits[i]];
+  int32_t ndf;
+  return o->fit<float>(v, stk, hs.back(), hs, P, C, *x, *chi2, ndf);
+}
+
+}  // extern "C"
