@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: TPC clusters tracked per second on one MI355X, batched vs plain.
+
+One step = the whole tracking path (grid build, neighbour links, tracklets,
+selection, fit and sector merge) over the workload's clusters, already resident
+in HBM.  The default workload is the batched form: 512 single-sector jobs of
+100..20000 primaries (log-uniform), ~89M clusters, tracked by one chain of
+persistent launches captured in a hipGraph; the same data is also run through
+the plain path (one launch sequence per sector-job) for comparison.
+
+Prints one JSON line (see the keys below).  Only --gpus 1 is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "TPC clusters tracked/sec at 1 MI355X (batched vs plain); p50/p99 chunk latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c1": "single TPC sector, 1 event: 200 primaries, no noise",
+    "c2": "full TPC, 1 central Pb-Pb-like event: 36 sectors, 8000 primaries, 5% noise, 10% inefficiency",
+    "c3": "time-frame slice: 50 collisions at 50 kHz, 500-8000 primaries each, drift-shifted z",
+    "c4": "batched form: 512 single-sector jobs, 100-20000 primaries each (log-uniform)",
+}
+SEEDS = {"c1": 11, "c2": 21, "c3": 31, "c4": 41}
+# Algorithmic bytes (unique bytes each kernel must move):
+#  neighbour kernel: per cluster y, z (8) + slot (4) + input index for tie-breaks (4)
+#                    + cell offsets (~2) + two links out (8) = 26 B
+#  tracklet kernel : per tracklet hit: next link (4) + y, z (8) + slot (4) + hit write (4)
+#                    + 64-bit weight read-modify-write (16) = 36 B; per tracklet: start (4)
+#                    + state write (21 x 4) = 88 B
+LINK_BYTES_PER_CLUSTER = 26
+TRK_BYTES_PER_HIT = 36
+TRK_BYTES_PER_TRACKLET = 88
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cs, cfg, budget_s):
+    """The oracle (single thread, as it stands) on a bounded sample of the same workload."""
+    import oracle.oracle as O
+    import tpcsynth as g
+    if cs.n_jobs > 1:
+        jobs = list(range(0, cs.n_jobs, 32))
+        sample = cs.subset_jobs(jobs)
+        desc = f"jobs {jobs[0]}..{jobs[-1]} step 32 ({len(jobs)} of {cs.n_jobs} sector-jobs, {sample.n} clusters)"
+    else:
+        sample = cs
+        desc = f"whole event ({cs.n} clusters)"
+    t0 = time.perf_counter()
+    r = O.Run.from_set(sample)
+    dt = time.perf_counter() - t0
+    ntr = len(r.tracks()["tracklet"])
+    if dt > budget_s * 3:
+        log(f"cpu baseline took {dt:.1f}s (budget {budget_s}s)")
+    return {"value": sample.n / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": desc + f"; {ntr} tracks; {dt:.1f} s single-threaded incl. FP64 refit"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--mode", default="persistent", choices=["batched", "persistent"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup+steps of the batched path only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import tpcsynth as g
+    seed = args.seed if args.seed is not None else SEEDS[args.config]
+    t0 = time.perf_counter()
+    cs = g.make_config(args.config, seed, workers=args.workers)  # before any GPU use
+    log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
+        f"in {time.perf_counter() - t0:.1f}s")
+
+    import torch
+
+    from paper_2402_01205_amd.evaluate import quality
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker, default_tuning
+    dev = "cuda:0"
+    ev = DeviceClusters.from_set(cs, dev)
+    torch.cuda.synchronize()
+
+    tuning = default_tuning(use_graph=0 if args.no_graph else 1)
+    tr = Tracker(0, mode=args.mode, tuning=tuning)
+
+    def timed(tracker, steps):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            tracker.run(ev)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    for i in range(args.warmup):
+        tr.run(ev)
+        log(f"warmup {i + 1}/{args.warmup}")
+    tr.sync()
+    ms = timed(tr, args.steps)
+    tr.sync()
+    log(f"batched ({args.mode}{'' if args.no_graph else ' + graph'}): {ms:.2f} ms/step")
+    if args.profile_only:
+        print(json.dumps({"ms_per_step": ms}), flush=True)
+        return
+    tracks = tr.tracks()
+
+    # per-kernel times with HIP events on the tracker's stream (same launch configuration)
+    tr.profile(True)
+    tr.profile_read(reset=True)
+    for _ in range(args.steps):
+        tr.run(ev)
+    prof = tr.profile_read(reset=True)
+    tr.profile(False)
+    T, H = tr.tracklet_counts()
+    n_valid = cs.n
+    kl_ms = prof["k_links"][0] / max(1, prof["k_links"][1])
+    kt_ms = prof["k_tracklets"][0] / max(1, prof["k_tracklets"][1])
+    link_bytes = LINK_BYTES_PER_CLUSTER * n_valid
+    trk_bytes = TRK_BYTES_PER_HIT * H + TRK_BYTES_PER_TRACKLET * T
+    kern = {
+        "k_links": dict(ms=kl_ms, bytes=link_bytes, gbs=link_bytes / kl_ms / 1e6),
+        "k_tracklets": dict(ms=kt_ms, bytes=trk_bytes, gbs=trk_bytes / kt_ms / 1e6),
+    }
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items()))
+    log("kernels: " + json.dumps(kern))
+
+    # plain path on the same data
+    plain_ms = None
+    if args.plain_steps > 0:
+        tp = Tracker(0, mode="plain")
+        tp.run(ev)
+        tp.sync()
+        plain_ms = timed(tp, args.plain_steps)
+        tp.sync()
+        pt = tp.tracks()
+        same = (pt["n"] == tracks["n"] and np.array_equal(pt["hits"], tracks["hits"]))
+        log(f"plain: {plain_ms:.2f} ms/step; identical to batched: {same}")
+        del tp
+
+    q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off)
+    log("quality: " + json.dumps(q))
+    value = cs.n / (ms / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "seed": seed,
+                   "n_clusters": cs.n, "n_jobs": cs.n_jobs,
+                   "mode": f"{args.mode}{'' if args.no_graph else '+hipGraph'}"},
+        "plain_value": (cs.n / (plain_ms / 1e3)) if plain_ms else None,
+        "plain_ms_per_step": plain_ms,
+        "batched_over_plain": (plain_ms / ms) if plain_ms else None,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_ms": kern[dom]["ms"], "algorithmic_bytes": kern[dom]["bytes"]},
+        "kernels": {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS}
+                    for k, v in kern.items()},
+        "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "tracks": int(tracks["n"]),
+        "tracklets": int(T),
+        "quality": q,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cs, args.config, args.cpu_budget)
+        out["cpu_baseline"]["cores"] = 1
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

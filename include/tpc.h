@@ -1,0 +1,206 @@
+/* tpc.h -- C ABI of the MI355X TPC track-reconstruction library (gfx950, HIP).
+ *
+ * The method: per TPC sector, cellular-automaton seeding (neighbour links between
+ * clusters on adjacent pad rows, mutual cleaning, chains of >= 3 clusters) followed
+ * by Kalman-filter track following, ownership arbitration, track selection, a
+ * Kalman refit and the merge of track pieces across neighbouring sectors.  The
+ * paper (arXiv 2402.01205) establishes that this step dominates the synchronous
+ * processing (section 5 and Table 1: TPC processing 99.37% of the time; Table 2:
+ * TPC tracking 61.41% of the asynchronous time), that it must track every
+ * collision because track-model compression stores cluster-to-track residuals
+ * (section 5), that its cost is linear in the number of TPC hits (section 6), and
+ * that it runs on GPUs (sections 6-7).  The paper does not spell the algorithm
+ * out; the library implements a fixed reading of it whose constants are the
+ * fields of tpc_params.
+ *
+ * Conventions
+ *  - Pointers are DEVICE pointers unless marked [host].  The caller owns every
+ *    buffer: inputs, outputs and the workspace (tpc_bind_workspace).  The library
+ *    allocates device memory only when no workspace was bound (then it grows its
+ *    own at tpc_grid_build).
+ *  - Stage calls enqueue work on the context's HIP stream and return without
+ *    synchronising; counts stay on the device.  Call tpc_sync() to wait and to
+ *    collect errors found by the kernels.
+ *  - Cluster indices in every output are 0-based indices into the caller's
+ *    cluster arrays.  Results do not depend on the input order except through the
+ *    index tie-breaks that define them.
+ *  - Units: cm, GeV/c, tesla, microseconds.  Track parameters (y, z, sin(phi),
+ *    tan(lambda), q/pT) are in the frame of the track's sector at plane x_ref.
+ *  - Return values: TPC_OK (0) or a negative TPC_E_* code; tpc_last_error()
+ *    describes the last failure of the context.
+ */
+#ifndef TPC_H
+#define TPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_OK 0
+#define TPC_E_ARG (-1)      /* invalid argument (null pointer, size, order of calls) */
+#define TPC_E_RANGE (-2)    /* a cluster had sector >= 36, row outside 0..151 or a non-finite
+                               y/z; such clusters are excluded from tracking */
+#define TPC_E_CAPACITY (-3) /* workspace or output capacity exceeded; results truncated */
+#define TPC_E_HIP (-4)      /* HIP runtime error; see tpc_last_error */
+
+#define TPC_N_SECTORS 36
+#define TPC_N_ROWS 152
+
+/* Every constant of the method.  tpc_params_default() fills the reading used by
+ * the library's tests; changing a field changes the computed result.        */
+typedef struct {
+  float win_dy_slope, win_dy_const;  /* up-neighbour window in y: slope*dx + const, cm */
+  float win_dz_slope, win_dz_const;  /* up-neighbour window in z, cm                   */
+  float link_cut;                    /* max second difference of a link triplet, cm    */
+  float cy0, cz0, cs0, ct0, ck0;     /* tracklet Kalman priors (diagonal)              */
+  float cy1, cz1, cs1, ct1, ck1;     /* refit Kalman priors (diagonal)                 */
+  float sigma_y, sigma_z;            /* cluster errors, cm                             */
+  float nwin;                        /* following window in sigmas                     */
+  float chi2_follow;                 /* max 2-D chi2 of a followed cluster             */
+  int32_t max_miss;                  /* consecutive empty rows that end the following  */
+  int32_t min_hits;                  /* hits of a valid tracklet / accepted track      */
+  float smax;                        /* limit of |sin(phi)|                            */
+  float bz;                          /* solenoid field along +z, tesla                 */
+  float merge_edge;                  /* distance to the sector edge of merge pieces, cm*/
+  float chi2_merge;                  /* max 5-D chi2 of a merged pair                  */
+} tpc_params;
+
+/* Tunable launch shapes.  Results are identical for every valid setting.     */
+typedef struct {
+  float cells_per_cluster;  /* grid cells per cluster of a row (search accelerator) */
+  int32_t block_links;      /* threads per workgroup of the neighbour kernel         */
+  int32_t block_tracklets;  /* threads per workgroup of the tracklet kernel          */
+  int32_t persistent_waves; /* resident waves per CU of persistent kernels (0 = off)  */
+  int32_t use_graph;        /* capture the batched stage chain into a hipGraph        */
+} tpc_tuning;
+
+/* Cluster list [n] in caller order.  sector: 0..35 (0..17 side A, z >= 0);
+ * row: pad row 0..151; y: sector-local y; z; time: arrival time (carried, unused
+ * by the tracking).                                                           */
+typedef struct {
+  int32_t n;
+  const uint8_t* sector;
+  const int16_t* row;
+  const float* y;
+  const float* z;
+  const float* time;
+} tpc_clusters;
+
+/* Independent tracking jobs: job j owns clusters [job_off[j], job_off[j+1]).
+ * Tracking is per (job, sector); pieces merge across adjacent sectors of jobs
+ * with the same event id (job_event NULL: every job is its own event).
+ * job_off_host is the same table in host memory (required).                   */
+typedef struct {
+  int32_t n_jobs;
+  const int32_t* job_off;       /* [n_jobs+1] device */
+  const int32_t* job_off_host;  /* [n_jobs+1] [host] */
+  const int32_t* job_event;     /* [n_jobs] device, or NULL */
+} tpc_jobs;
+
+/* Output tracks (after tpc_fit_merge).  Capacities are [host] values; counts
+ * are written on the device.  hits: CSR of cluster indices ordered along the
+ * track (inner piece rows ascending, then the outer piece).                  */
+typedef struct {
+  int32_t cap_tracks, cap_hits;   /* [host] */
+  int32_t* n_tracks;              /* [1] */
+  int32_t* hit_off;               /* [cap_tracks+1] */
+  int32_t* hits;                  /* [cap_hits] */
+  float* param;                   /* [cap_tracks][5] y, z, sin(phi), tan(lambda), q/pT */
+  float* cov;                     /* [cap_tracks][15] lower triangle, row-major        */
+  float* x_ref;                   /* [cap_tracks] plane of the parameters              */
+  float* chi2;                    /* [cap_tracks]                                      */
+  int32_t* ndf;                   /* [cap_tracks] 2n-5, or -1 if the fit failed       */
+  int32_t* sector;                /* [cap_tracks] sector of param (innermost piece)    */
+  int32_t* job;                   /* [cap_tracks]                                      */
+  int32_t* tracklet;              /* [cap_tracks] id of the innermost piece's tracklet */
+} tpc_tracks;
+
+typedef struct tpc_ctx tpc_ctx;
+
+/* Launch modes: how the stage entry points launch their kernels.             */
+#define TPC_MODE_PLAIN 0      /* one launch sequence per job (per sector-job)           */
+#define TPC_MODE_BATCHED 1    /* one launch per kernel over all jobs                    */
+#define TPC_MODE_PERSISTENT 2 /* batched, tracklet/fit stages as persistent work-queue  */
+
+int tpc_params_default(tpc_params* p);
+int tpc_tuning_default(tpc_tuning* t);
+
+/* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t; NULL =
+ * the null stream).  Copies *p (NULL = defaults).                              */
+int tpc_ctx_create(tpc_ctx** ctx, int device, void* hip_stream, const tpc_params* p);
+void tpc_ctx_destroy(tpc_ctx* ctx);
+int tpc_set_stream(tpc_ctx* ctx, void* hip_stream);
+int tpc_set_mode(tpc_ctx* ctx, int mode);
+int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);
+const char* tpc_last_error(const tpc_ctx* ctx);
+
+/* Device bytes of the workspace for n_clusters clusters in n_jobs jobs [host].
+ * Used by callers for admission control; exact for the current tuning.      */
+size_t tpc_workspace_size(const tpc_ctx* ctx, int64_t n_clusters, int32_t n_jobs);
+/* Bind caller-owned device memory as the workspace (>= tpc_workspace_size). */
+int tpc_bind_workspace(tpc_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* a1: validate the clusters and bin them into per-(job, sector, row) grids.
+ * The arrays in *c and *j must stay valid until tpc_fit_merge returns.       */
+int tpc_grid_build(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j);
+/* a2+a3: neighbour links and cleaning.  up/down ([n] device or NULL) receive the
+ * clean links as cluster indices (-1 = none).                                */
+int tpc_find_neighbours(tpc_ctx* ctx, int32_t* up, int32_t* down);
+/* a4: tracklet construction.  n_tracklets ([1] device or NULL) receives T.   */
+int tpc_construct_tracklets(tpc_ctx* ctx, int32_t* n_tracklets);
+/* a5: selection.  n_selected ([1] device or NULL) receives K.                */
+int tpc_select_tracks(tpc_ctx* ctx, int32_t* n_selected);
+/* a6: refit, sector merge and merged refit; writes *out.                    */
+int tpc_fit_merge(tpc_ctx* ctx, tpc_tracks* out);
+/* Run a1..a6 in order (graph-captured in TPC_MODE_BATCHED/PERSISTENT when the
+ * tuning asks for it).                                                        */
+int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* out);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around the
+ * launches of: the neighbour kernel (index 0), the tracklet kernel (1), the grid
+ * build (2), the selection (3) and fit + merge (4).  While enabled, tpc_run does
+ * not use a graph.  tpc_profile_read waits for the stream and returns the summed
+ * milliseconds and the number of timed launches per index since the last reset. */
+#define TPC_PROF_LINKS 0
+#define TPC_PROF_TRACKLETS 1
+#define TPC_PROF_GRID 2
+#define TPC_PROF_SELECT 3
+#define TPC_PROF_FIT_MERGE 4
+#define TPC_PROF_KERNELS 5
+int tpc_profile(tpc_ctx* ctx, int enable);
+int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
+
+/* Wait for the context's stream; returns TPC_E_RANGE / TPC_E_CAPACITY if the
+ * kernels reported one since the last tpc_grid_build, else TPC_OK.           */
+int tpc_sync(tpc_ctx* ctx);
+
+/* Test hooks (stage outputs, device pointers, sizes n or capacities):        */
+/* raw links before cleaning, as cluster indices                             */
+int tpc_get_links_raw(tpc_ctx* ctx, int32_t* up_raw, int32_t* down_raw);
+/* row membership: slot_off [n_jobs*36*152+1] and members sorted per slot by
+ * the grid order (cell order; within a cell any order)                       */
+int tpc_get_rows(tpc_ctx* ctx, int32_t* slot_off, int32_t* members);
+/* tracklets: [host] counts, then device arrays of capacity >= T / sum of hits:
+ * start[T], off[T+1], hits[sum], state[T][21] (y z s t k, C[15], x)          */
+int tpc_get_tracklet_counts(tpc_ctx* ctx, int32_t* n_tracklets, int64_t* n_hits);
+int tpc_get_tracklets(tpc_ctx* ctx, int32_t* start, int32_t* off, int32_t* hits, float* state,
+                      uint64_t* hit_weight);
+/* selected tracks before the fit: [host] counts then CSR (cluster indices)  */
+int tpc_get_selected_counts(tpc_ctx* ctx, int32_t* n_selected, int64_t* n_hits);
+int tpc_get_selected(tpc_ctx* ctx, int32_t* tracklet, int32_t* off, int32_t* hits);
+
+/* Unit hooks of the device track model (tests): n rows, device arrays.
+ * propagate: in [n][22] = (y, z, sin phi, tan lambda, q/pT, C[15], x1, x2),
+ *            out [n][26] = (ok, state hi[5], state lo[5], C[15]).
+ * update:    in [n][27] = (hi[5], lo[5], C[15], y_meas, z_meas),
+ *            out [n][27] = (ok, hi[5], lo[5], C[15], chi2).                  */
+int tpc_debug_propagate(tpc_ctx* ctx, const float* in, float* out, int32_t n);
+int tpc_debug_update(tpc_ctx* ctx, const float* in, float* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPC_H */

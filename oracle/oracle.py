@@ -66,7 +66,7 @@ def lib():
         L = C.CDLL(LIB)
         P = C.c_void_p
         L.orc_create.restype = P
-        L.orc_create.argtypes = [C.c_int32, P, P, P, P, C.c_int32, P, C.POINTER(Params)]
+        L.orc_create.argtypes = [C.c_int32, P, P, P, P, C.c_int32, P, P, C.POINTER(Params)]
         L.orc_destroy.argtypes = [P]
         L.orc_set_brute.argtypes = [P, C.c_int32]
         L.orc_status.argtypes = [P]
@@ -109,7 +109,7 @@ class Run:
     """Runs the oracle over a cluster list grouped into jobs and exposes stage outputs."""
 
     def __init__(self, sector, row, y, z, job_off, prm: Params | None = None,
-                 last_stage: int = STAGE_MERGE, brute: bool = False):
+                 last_stage: int = STAGE_MERGE, brute: bool = False, job_event=None):
         L = lib()
         self.prm = prm or params()
         self.sector = np.ascontiguousarray(sector, np.uint8)
@@ -118,16 +118,18 @@ class Run:
         self.z = np.ascontiguousarray(z, np.float32)
         self.job_off = np.ascontiguousarray(job_off, np.int32)
         self.n = int(self.y.shape[0])
+        self.job_event = None if job_event is None else np.ascontiguousarray(job_event, np.int32)
         self.h = L.orc_create(self.n, _p(self.sector), _p(self.row), _p(self.y), _p(self.z),
                               int(self.job_off.shape[0] - 1), _p(self.job_off),
+                              None if self.job_event is None else _p(self.job_event),
                               C.byref(self.prm))
         L.orc_set_brute(self.h, int(brute))
         L.orc_run(self.h, last_stage)
         self.last_stage = last_stage
 
     @classmethod
-    def from_set(cls, cs, prm=None, last_stage=STAGE_MERGE, brute=False):
-        return cls(cs.sector, cs.row, cs.y, cs.z, cs.job_off, prm, last_stage, brute)
+    def from_set(cls, cs, prm=None, last_stage=STAGE_MERGE, brute=False, job_event=None):
+        return cls(cs.sector, cs.row, cs.y, cs.z, cs.job_off, prm, last_stage, brute, job_event)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

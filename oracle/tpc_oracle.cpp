@@ -310,14 +310,15 @@ struct Tracklet {
 
 struct Track {
   int32_t tracklet;           // tracklet id it was selected from (== track id)
-  int32_t job, sector;
+  int32_t job, sector, event;
   std::vector<int32_t> hits;  // original indices, inner -> outer
   float P[5], C[15], x, chi2; int32_t ndf;   // FP32 fit at the innermost hit
   double Pd[5], Cd[15], xd, chi2d; int32_t ndfd;   // FP64 refit
   // merge bookkeeping: a merged track keeps the inner piece's id; the outer piece is absorbed
   int32_t merged_into = -1;
   int32_t partner = -1;
-  int32_t sector2 = -1;       // sector of the absorbed outer piece, -1 if none
+  int32_t sector2 = -1;       // sector of the last absorbed outer piece, -1 if none
+  std::vector<int32_t> pieces;  // chain head: its absorbed pieces, inner -> outer
 };
 
 struct Oracle {
@@ -326,7 +327,7 @@ struct Oracle {
   std::vector<uint8_t> sector;
   std::vector<int16_t> row;
   std::vector<float> y, z;
-  std::vector<int32_t> job_off, job_of;
+  std::vector<int32_t> job_off, job_of, job_event;
   std::vector<uint8_t> valid;
   int32_t status = 0;  // bit 0: a cluster with an out-of-range field was excluded
 
@@ -544,6 +545,7 @@ struct Oracle {
       tr.tracklet = (int32_t)id;
       tr.job = job_of[t.start];
       tr.sector = sector[t.start];
+      tr.event = job_event[tr.job];
       tracks.push_back(std::move(tr));
     }
   }
@@ -640,8 +642,7 @@ struct Oracle {
   void fit_track(Track& tr) {
     std::vector<int> hs(tr.hits.size());
     for (size_t i = 0; i < tr.hits.size(); ++i) hs[i] = sector[tr.hits[i]];
-    int last = (int)(&tr - tracks.data());
-    while (tracks[last].partner >= 0) last = tracks[last].partner;
+    const int last = tr.pieces.empty() ? (int)(&tr - tracks.data()) : tr.pieces.back();
     const Tracklet& st = tracklets[tracks[last].tracklet];
     const float sinit[3] = {st.P[2], st.P[3], st.P[4]};
     const int so = hs.back();
@@ -678,7 +679,7 @@ struct Oracle {
       const int sb = (A.sector / kRowsPerSide) * kRowsPerSide + (A.sector % kRowsPerSide + dir) % kRowsPerSide;
       for (int b = 0; b < K; ++b) {
         const Track& B = tracks[b];
-        if (B.ndf < 0 || B.job != A.job || B.sector != sb) continue;
+        if (B.ndf < 0 || B.event != A.event || B.sector != sb) continue;
         const int32_t hb = B.hits.front();
         const float eb = kGeo.x[row[hb]] * kGeo.tan10 - std::fabs(y[hb]);
         if (!(eb <= p.merge_edge)) continue;
@@ -705,9 +706,10 @@ struct Oracle {
     for (int a = 0; a < K; ++a) {
       if (prev[a] >= 0 || tracks[a].partner < 0) continue;   // chain heads only
       Track& A = tracks[a];
-      int steps = 0;
-      for (int b = A.partner; b >= 0 && steps < kRowsPerSide; b = tracks[b].partner, ++steps) {
+      // a chain walked from its head is a simple path (every piece has one inner partner)
+      for (int b = A.partner; b >= 0 && (int)A.pieces.size() < kRowsPerSide; b = tracks[b].partner) {
         tracks[b].merged_into = a;
+        A.pieces.push_back(b);
         A.hits.insert(A.hits.end(), tracks[b].hits.begin(), tracks[b].hits.end());
         A.sector2 = tracks[b].sector;
       }
@@ -751,7 +753,8 @@ struct Oracle {
 extern "C" {
 
 void* orc_create(int32_t n, const uint8_t* sector, const int16_t* row, const float* y,
-                 const float* z, int32_t n_jobs, const int32_t* job_off, const Params* p) {
+                 const float* z, int32_t n_jobs, const int32_t* job_off, const int32_t* job_event,
+                 const Params* p) {
   Oracle* o = new Oracle();
   o->p = *p;
   o->n = n;
@@ -762,6 +765,8 @@ void* orc_create(int32_t n, const uint8_t* sector, const int16_t* row, const flo
   o->z.assign(z, z + n);
   o->job_off.assign(job_off, job_off + n_jobs + 1);
   o->job_of.assign(n, 0);
+  o->job_event.resize(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) o->job_event[j] = job_event ? job_event[j] : j;
   o->valid.assign(n, 1);
   for (int j = 0; j < n_jobs; ++j)
     for (int32_t i = job_off[j]; i < job_off[j + 1]; ++i) o->job_of[i] = j;

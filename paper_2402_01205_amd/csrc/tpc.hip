@@ -1,0 +1,1852 @@
+// MI355X (gfx950) TPC track reconstruction: kernels and the C ABI host runtime.
+//
+// Stages (see include/tpc.h): grid build (counting sort into per-row cell grids),
+// neighbour links + cleaning + chain starts, tracklet construction (one lane per
+// tracklet, FP32 Kalman filter), selection (max-key ownership), refit and
+// sector merge.  No stage uses MFMA: nothing on this path is a dense contraction;
+// every kernel is bound by HBM traffic or by dependent-load latency.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpc.h"
+#include "tpc_kernels.h"
+#include "tpc_math.h"
+
+#pragma clang fp contract(off)
+
+using namespace tpc;
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t f2ord(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ int cell_of(float v, float lo, float inv, int n) {
+  float c = (v - lo) * inv;
+  c = fminf(fmaxf(c, 0.f), (float)(n - 1));
+  return (int)c;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if ((int)(threadIdx.x & 63) >= o) v += t;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of one value per thread (blockDim.x <= 1024, multiple of 64)
+__device__ __forceinline__ int block_excl_scan(int v, int* lds_waves, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int inc = wave_incl_scan(v);
+  if (lane == 63) lds_waves[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    int w = lane < nw ? lds_waves[lane] : 0;
+    const int wi = wave_incl_scan(w);
+    if (lane < nw) lds_waves[lane] = wi - w;
+    if (lane == nw - 1) lds_waves[32] = wi;
+  }
+  __syncthreads();
+  total = lds_waves[32];
+  const int r = inc - v + lds_waves[wave];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ fill / scan
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) p[k] = v;
+}
+__global__ void k_fill_range_i32(int32_t* p, Bound lo, Bound hi, int32_t v) {
+  const int32_t a = lo.get(), b = hi.get();
+  for (int64_t k = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+__global__ void k_fill_range_u64(uint64_t* p, Bound lo, Bound hi) {
+  const int32_t a = lo.get(), b = hi.get();
+  for (int64_t k = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = 0ull;
+}
+
+// Exclusive scan of in[lo..hi) into out[lo..hi], out[lo] = base (base = *base_p or 0).
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, Bound lo_b, Bound hi_b,
+                                                              int32_t* bsum) {
+  __shared__ int lds[40];
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int64_t start = (int64_t)lo + (int64_t)blockIdx.x * kScanTile;
+  int s = 0;
+  if (start < hi) {
+    const int64_t base = start + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q)
+      if (base + q < hi) s += in[base + q];
+  }
+  int total;
+  block_excl_scan(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+// base_from_out: the scan continues a previous one whose total sits in out[lo].
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* bsum, Bound lo_b, Bound hi_b,
+                                                      int32_t base_from_out, int32_t* out) {
+  __shared__ int lds[40];
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int nb = hi > lo ? (int)((hi - lo + kScanTile - 1) / kScanTile) : 0;
+  int carry = base_from_out ? out[lo] : 0;
+  __syncthreads();
+  for (int c = 0; c < nb; c += blockDim.x) {
+    const int i = c + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int total;
+    const int e = block_excl_scan(v, lds, total);
+    if (i < nb) bsum[i] = carry + e;
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[hi > lo ? hi : lo] = carry;
+}
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int32_t* out, Bound lo_b,
+                                                             Bound hi_b, const int32_t* bsum) {
+  __shared__ int lds[40];
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int64_t start = (int64_t)lo + (int64_t)blockIdx.x * kScanTile;
+  if (start >= hi) return;
+  const int64_t base = start + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = (base + q < hi) ? in[base + q] : 0;
+    s += v[q];
+  }
+  int total;
+  int e = block_excl_scan(s, lds, total) + bsum[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < hi) out[base + q] = e;
+    e += v[q];
+  }
+}
+
+// ------------------------------------------------------------------ a1: grid build
+struct In {
+  const uint8_t* sector;
+  const int16_t* row;
+  const float* y;
+  const float* z;
+  const int32_t* job_off;
+  int32_t n_jobs;
+};
+
+__device__ __forceinline__ int job_of(const int32_t* job_off, int n_jobs, int32_t i) {
+  int a = 0, b = n_jobs;  // job_off[a] <= i < job_off[b]
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (job_off[m] <= i) a = m; else b = m;
+  }
+  return a;
+}
+
+// Validate each input cluster, compute its slot, count clusters per slot and the
+// per-slot z range (order-preserving integer min/max).
+__global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32_t* slot_cnt,
+                             uint32_t* zmin, uint32_t* zmax, int32_t* counters) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hi) return;
+  const int s = in.sector[i];
+  const int r = in.row[i];
+  const float y = in.y[i], z = in.z[i];
+  const bool ok = s < kSectors && r >= 0 && r < kRows && finite_f(y) && finite_f(z);
+  if (!ok) {
+    ckey[i] = -1;
+    atomicOr(&counters[kCntStatus], kStatusRange);
+    return;
+  }
+  const int j = job_of(in.job_off, in.n_jobs, i);
+  const int32_t slot = (j * kSectors + s) * kRows + r;
+  ckey[i] = slot;
+  atomicAdd(&slot_cnt[slot], 1);
+  const uint32_t oz = f2ord(z);
+  atomicMin(&zmin[slot], oz);
+  atomicMax(&zmax[slot], oz);
+}
+
+// Cell geometry of every slot: roughly cells_per_cluster cells per cluster, square
+// cells in (y, z) over the row's acceptance in y and the slot's z range.
+__global__ void k_slot_geometry(const int32_t* slot_cnt, const uint32_t* zmin, const uint32_t* zmax,
+                                SlotGrid* sg, int32_t* ncell, int32_t s0, int32_t s1, Consts k,
+                                float cpc) {
+  const int32_t s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s1) return;
+  const int n = slot_cnt[s];
+  SlotGrid g;
+  g.pad = 0;
+  if (n == 0) {
+    g.ylo = g.zlo = g.inv_by = g.inv_bz = 0.f;
+    g.ny = g.nz = g.ncell = 0;
+  } else {
+    const float x = k.x[s % kRows];
+    const float yh = x * k.tan10 + 1.f;
+    const float ywid = 2.f * yh;
+    const float z0 = ord2f(zmin[s]), z1 = ord2f(zmax[s]);
+    const float zspan = fmaxf(z1 - z0, 1e-3f) * 1.000001f + 1e-3f;
+    const float target = fmaxf(1.f, (float)n * cpc);
+    const float b = fmaxf(sqrtf(ywid * zspan / target), 0.2f);
+    int ny = (int)(ywid / b);
+    ny = max(1, min(ny, min(1024, max(1, (int)target))));
+    int nz = max(1, min((int)(target / (float)ny), 1 << 22));
+    g.ylo = -yh;
+    g.zlo = z0;
+    g.inv_by = (float)ny / ywid;
+    g.inv_bz = (float)nz / zspan;
+    g.ny = ny;
+    g.nz = nz;
+    g.ncell = ny * nz;
+  }
+  sg[s] = g;
+  ncell[s] = g.ncell;
+}
+
+__global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const SlotGrid* sg,
+                             const int32_t* cell_base, int32_t* ccell, int32_t* cell_cnt) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hi) return;
+  const int32_t slot = ckey[i];
+  if (slot < 0) return;
+  const SlotGrid g = sg[slot];
+  const int cy = cell_of(in.y[i], g.ylo, g.inv_by, g.ny);
+  const int cz = cell_of(in.z[i], g.zlo, g.inv_bz, g.nz);
+  const int32_t gc = cell_base[slot] + cz * g.ny + cy;
+  ccell[i] = gc;
+  atomicAdd(&cell_cnt[gc], 1);
+}
+
+__global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
+                          const int32_t* cell_off, int32_t* cell_fill, float* gy, float* gz,
+                          int32_t* gidx, int32_t* gslot) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hi) return;
+  const int32_t slot = ckey[i];
+  if (slot < 0) return;
+  const int32_t gc = ccell[i];
+  const int32_t pos = cell_off[gc] + atomicAdd(&cell_fill[gc], 1);
+  gy[pos] = in.y[i];
+  gz[pos] = in.z[i];
+  gidx[pos] = i;
+  gslot[pos] = slot;
+}
+
+// ------------------------------------------------------------------ a2: neighbours
+struct GridView {
+  const float* gy;
+  const float* gz;
+  const int32_t* gidx;
+  const int32_t* gslot;
+  const SlotGrid* sg;
+  const int32_t* cell_base;
+  const int32_t* cell_off;
+};
+
+// For each cluster h (grid order): over delta = 1, then 2, the pair (d on row r-delta,
+// u on row r+delta) with the smallest second difference inside the windows; ties go to
+// the smaller input index of u, then of d.  Links are stored in grid order.
+__global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_b, int32_t* up_raw,
+                                               int32_t* dn_raw, Consts k) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t slot = G.gslot[h];
+  const int r = slot % kRows;
+  const float yh = G.gy[h], zh = G.gz[h];
+  const float y2 = yh + yh, z2 = zh + zh;
+  const float m = 0.01f;
+  int32_t bu = -1, bd = -1, bu_o = 0, bd_o = 0;
+  float best = 0.f;
+  for (int d = 1; d <= 2; ++d) {
+    if (r - d < 0 || r + d >= kRows) break;
+    const float dxu = k.x[r + d] - k.x[r];
+    const float wy = k.win_dy_slope * dxu + k.win_dy_const;
+    const float wz = k.win_dz_slope * dxu + k.win_dz_const;
+    const float rho = div_rn(k.x[r + d], k.x[r]);
+    const float yc = yh * rho;
+    const int32_t su = slot + d, sd = slot - d;
+    const SlotGrid gu = G.sg[su];
+    const SlotGrid gd = G.sg[sd];
+    if (gu.ncell == 0 || gd.ncell == 0) continue;
+    const int32_t ubase = G.cell_base[su], dbase = G.cell_base[sd];
+    const int uy0 = cell_of(yc - wy - m, gu.ylo, gu.inv_by, gu.ny);
+    const int uy1 = cell_of(yc + wy + m, gu.ylo, gu.inv_by, gu.ny);
+    const int uz0 = cell_of(zh - wz - m, gu.zlo, gu.inv_bz, gu.nz);
+    const int uz1 = cell_of(zh + wz + m, gu.zlo, gu.inv_bz, gu.nz);
+    for (int cz = uz0; cz <= uz1; ++cz) {
+      const int32_t c0 = ubase + cz * gu.ny;
+      const int32_t a0 = G.cell_off[c0 + uy0], a1 = G.cell_off[c0 + uy1 + 1];
+      for (int32_t u = a0; u < a1; ++u) {
+        const float yu = G.gy[u], zu = G.gz[u];
+        if (!(fabsf(yu - yc) <= wy) || !(fabsf(zu - zh) <= wz)) continue;
+        const float py = y2 - yu, pz = z2 - zu;
+        const int32_t uo = G.gidx[u];
+        const int dy0 = cell_of(py - k.link_cut - m, gd.ylo, gd.inv_by, gd.ny);
+        const int dy1 = cell_of(py + k.link_cut + m, gd.ylo, gd.inv_by, gd.ny);
+        const int dz0 = cell_of(pz - k.link_cut - m, gd.zlo, gd.inv_bz, gd.nz);
+        const int dz1 = cell_of(pz + k.link_cut + m, gd.zlo, gd.inv_bz, gd.nz);
+        for (int ez = dz0; ez <= dz1; ++ez) {
+          const int32_t e0 = dbase + ez * gd.ny;
+          const int32_t b0 = G.cell_off[e0 + dy0], b1 = G.cell_off[e0 + dy1 + 1];
+          for (int32_t dd = b0; dd < b1; ++dd) {
+            const float ry = (yu + G.gy[dd]) - y2;
+            const float rz = (zu + G.gz[dd]) - z2;
+            const float sc = ry * ry + rz * rz;
+            if (!(sc <= k.cut2)) continue;
+            const int32_t dor = G.gidx[dd];
+            if (bu < 0 || sc < best || (sc == best && (uo < bu_o || (uo == bu_o && dor < bd_o)))) {
+              best = sc;
+              bu = u;
+              bd = dd;
+              bu_o = uo;
+              bd_o = dor;
+            }
+          }
+        }
+      }
+    }
+    if (bu >= 0) break;
+  }
+  up_raw[h] = bu;
+  dn_raw[h] = bd;
+}
+
+// Mutual cleaning, evaluated on the raw links only.
+__global__ void k_clean(const int32_t* up_raw, const int32_t* dn_raw, int32_t* up, int32_t* dn,
+                        Bound lo_b, Bound hi_b) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t u = up_raw[h], d = dn_raw[h];
+  up[h] = (u >= 0 && dn_raw[u] == h) ? u : -1;
+  dn[h] = (d >= 0 && up_raw[d] == h) ? d : -1;
+}
+
+// Chain starts flagged at their input index: no clean down link, a clean up link whose
+// own clean up link exists.
+__global__ void k_start_flags(const int32_t* up, const int32_t* dn, const int32_t* gidx, int32_t* flag,
+                              Bound lo_b, Bound hi_b) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t u = up[h];
+  if (dn[h] < 0 && u >= 0 && up[u] >= 0) flag[gidx[h]] = 1;
+}
+
+__global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, int32_t* out_off,
+                              int32_t j0, int32_t j1, int32_t cap) {
+  const int32_t j = j0 + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > j1) return;
+  out_off[j] = scanned[min(job_off[j], cap)];
+}
+
+__global__ void k_write_starts(const int32_t* up, const int32_t* dn, const int32_t* gidx,
+                               const int32_t* fid, int32_t* start, int32_t capT, Bound lo_b,
+                               Bound hi_b, int32_t* counters) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t u = up[h];
+  if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
+  const int32_t t = fid[gidx[h]];
+  if (t < capT) start[t] = h;
+  else atomicOr(&counters[kCntStatus], kStatusCapacity);
+}
+
+// ------------------------------------------------------------------ a4: tracklets
+struct TrackletView {
+  const int32_t* start;
+  const int32_t* up_raw;
+  const int32_t* dn_raw;
+  const int32_t* up;
+  int32_t* hits;      // [kRows][capT]
+  int32_t* nhits;     // [capT]
+  float* state;       // [21][capT]
+  uint64_t* hitw;     // [N] grid order
+  int32_t capT;
+};
+
+__device__ __forceinline__ void init_cov(State& S, const float* prior) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) S.C[i] = 0.f;
+  S.C[tri(0, 0)] = prior[0];
+  S.C[tri(1, 1)] = prior[1];
+  S.C[tri(2, 2)] = prior[2];
+  S.C[tri(3, 3)] = prior[3];
+  S.C[tri(4, 4)] = prior[4];
+}
+
+// One lane per tracklet: Kalman filter along the chain (every chain cluster used),
+// then following on the rows above (minimum chi2 in a 3-sigma window).
+__device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t, const Consts& k) {
+  const int32_t h = V.start[t];
+  const int32_t dr = V.dn_raw[h];
+  const int32_t first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : h;
+  auto next = [&](int32_t c) -> int32_t { return (c == first && first != h) ? h : V.up[c]; };
+  const int32_t c1 = next(first), c2 = next(c1);
+  const int32_t slot0 = G.gslot[first];
+  const int r0 = slot0 % kRows;
+  const int32_t slot_base = slot0 - r0;
+  const int rc2 = G.gslot[c2] % kRows;
+  State S;
+  const float y0 = G.gy[first], z0 = G.gz[first];
+  const float dx2 = k.x[rc2] - k.x[r0];
+  const float dy2 = G.gy[c2] - y0;
+  const float dz2 = G.gz[c2] - z0;
+  const float den = sqrt_rn(dx2 * dx2 + dy2 * dy2);
+  S.P[0] = y0;
+  S.P[1] = z0;
+  S.P[2] = div_rn(dy2, den);
+  S.P[3] = div_rn(dz2, den);
+  S.P[4] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
+  init_cov(S, k.prior0);
+  float x = k.x[r0];
+  float keepP[5], keepC[15], keepx = x;
+  int n = 0;
+  int last_row = r0;
+  bool alive = true;
+  for (int32_t c = first; c >= 0; c = next(c)) {
+    const int rc = G.gslot[c] % kRows;
+    const float xh = k.x[rc];
+    if (!propagate(S, x, xh, k)) { alive = false; break; }
+    x = xh;
+    if (!kf_update(S, G.gy[c], G.gz[c], k, nullptr)) { alive = false; break; }
+    V.hits[(int64_t)n * V.capT + t] = c;
+    ++n;
+    last_row = rc;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
+    keepx = x;
+  }
+  if (alive) {
+    int misses = 0;
+    for (int r = last_row + 1; r < kRows; ++r) {
+      const float xr = k.x[r];
+      if (!propagate(S, x, xr, k)) break;
+      x = xr;
+      const SInv si = s_inverse(S.C, k.vy, k.vz);
+      if (!si.ok) break;
+      const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
+      const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
+      const int32_t slot = slot_base + r;
+      const SlotGrid g = G.sg[slot];
+      int32_t best = -1, best_o = 0;
+      float bchi = 0.f;
+      if (g.ncell > 0) {
+        const int32_t cb0 = G.cell_base[slot];
+        const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+        const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+        const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+        const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+        for (int cz = z0c; cz <= z1c; ++cz) {
+          const int32_t e0 = cb0 + cz * g.ny;
+          const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
+          for (int32_t c = a0; c < a1; ++c) {
+            const float rr0 = (G.gy[c] - S.P[0]) - S.L[0];
+            const float rr1 = (G.gz[c] - S.P[1]) - S.L[1];
+            if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+            const float chi2 = chi2_of(si, rr0, rr1);
+            const int32_t co = G.gidx[c];
+            if (best < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
+              best = c;
+              best_o = co;
+              bchi = chi2;
+            }
+          }
+        }
+      }
+      if (best >= 0 && bchi <= k.chi2_follow) {
+        if (!kf_update(S, G.gy[best], G.gz[best], k, nullptr)) break;
+        V.hits[(int64_t)n * V.capT + t] = best;
+        ++n;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
+        keepx = x;
+        misses = 0;
+      } else if (++misses >= k.max_miss) {
+        break;
+      }
+    }
+  }
+  V.nhits[t] = n;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = keepP[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = keepC[i];
+  V.state[(int64_t)20 * V.capT + t] = keepx;
+  if (n >= k.min_hits) {
+    const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+    for (int q = 0; q < n; ++q) atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]],
+                                          (unsigned long long)key);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tracklets(GridView G, TrackletView V, Bound lo_b, Bound hi_b,
+                                                   Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), V.capT);
+  const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hi) return;
+  build_tracklet(G, V, t, k);
+}
+
+// Persistent variant: waves take tracklets from a device ticket counter.
+__global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, TrackletView V, Bound lo_b,
+                                                              Bound hi_b, Consts k, int32_t* ticket) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), V.capT);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(ticket, 64);
+    base = __shfl(base, 0, 64);
+    const int32_t t = lo + base + lane;
+    if (lo + base >= hi) break;
+    if (t < hi) build_tracklet(G, V, t, k);
+  }
+}
+
+// ------------------------------------------------------------------ a5: selection
+__global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* own, int32_t* accf,
+                               Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), V.capT);
+  const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hi) return;
+  const int n = V.nhits[t];
+  int cnt = 0;
+  if (n >= k.min_hits) {
+    const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+    for (int q = 0; q < n; ++q) cnt += V.hitw[V.hits[(int64_t)q * V.capT + t]] == key;
+  }
+  const bool a = n >= k.min_hits && cnt >= k.min_hits;
+  own[t] = a ? cnt : 0;
+  accf[t] = a ? 1 : 0;
+}
+
+__global__ void k_select_write(TrackletView V, Bound lo_b, Bound hi_b, const int32_t* accf,
+                               const int32_t* kid, const int32_t* hoff, int32_t* sel_from,
+                               int32_t* sel_off, int32_t* sel_hits, int32_t capK, int32_t capH,
+                               int32_t* counters) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), V.capT);
+  const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hi || !accf[t]) return;
+  const int32_t kk = kid[t];
+  const int32_t o = hoff[t];
+  const int n = V.nhits[t];
+  if (kk >= capK) {
+    atomicOr(&counters[kCntStatus], kStatusCapacity);
+    return;
+  }
+  sel_from[kk] = t;
+  sel_off[kk] = o;
+  const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+  int w = 0;
+  for (int q = 0; q < n; ++q) {
+    const int32_t c = V.hits[(int64_t)q * V.capT + t];
+    if (V.hitw[c] == key) {
+      if (o + w < capH) sel_hits[o + w] = c;
+      ++w;
+    }
+  }
+  if (o + w > capH) atomicOr(&counters[kCntStatus], kStatusCapacity);
+}
+
+__global__ void k_select_finish(const int32_t* kid, const int32_t* hoff, Bound thi_b, int32_t capT,
+                                int32_t* sel_off, int32_t capK, int32_t* counters) {
+  const int32_t thi = min(thi_b.get(), capT);
+  const int32_t K = kid[thi];
+  const int32_t H = hoff[thi];
+  counters[kCntSelected] = K;
+  counters[kCntSelHits] = H;
+  if (K <= capK) sel_off[K] = H;
+}
+
+// ------------------------------------------------------------------ a6: fit and merge
+struct FitView {
+  const int32_t* sel_from;
+  const int32_t* sel_off;
+  const int32_t* sel_hits;
+  const int32_t* chain_next;  // merged outer piece of a track, -1 if none (NULL: no merge)
+  const int32_t* chain_prev;  // merged inner piece, -1 if none; chains are walked from heads only
+  float* P;                   // [5][capK]
+  float* C;                   // [15][capK]
+  float* x;
+  float* chi2;
+  int32_t* ndf;
+  int32_t capK;
+};
+
+// Fit of a hit list given as up to 18 consecutive pieces (inner -> outer); crossing a
+// piece boundary rotates the state into the inner piece's sector frame.
+__device__ void fit_track(const GridView& G, const TrackletView& V, const FitView& F, int32_t kk,
+                          const Consts& k) {
+  // collect the piece chain (a head and at most kHalf absorbed pieces)
+  int32_t pieces[kHalf + 1];
+  int np = 0;
+  const bool walk = F.chain_next && F.chain_prev[kk] < 0;
+  for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1) pieces[np++] = p;
+  const int32_t last_piece = pieces[np - 1];
+  const int32_t tl = F.sel_from[last_piece];
+  State S;
+  const int32_t ho = F.sel_hits[F.sel_off[last_piece + 1] - 1];
+  S.P[0] = G.gy[ho];
+  S.P[1] = G.gz[ho];
+  S.P[2] = V.state[(int64_t)2 * V.capT + tl];
+  S.P[3] = V.state[(int64_t)3 * V.capT + tl];
+  S.P[4] = V.state[(int64_t)4 * V.capT + tl];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
+  init_cov(S, k.prior1);
+  float x = k.x[G.gslot[ho] % kRows];
+  float chi2 = 0.f;
+  int nh = 0;
+  bool ok = true;
+  int cur_sec = (G.gslot[ho] / kRows) % kSectors;
+  for (int pi = np - 1; pi >= 0 && ok; --pi) {
+    const int32_t p = pieces[pi];
+    const int32_t a = F.sel_off[p], b = F.sel_off[p + 1];
+    for (int32_t q = b - 1; q >= a; --q) {
+      const int32_t h = F.sel_hits[q];
+      const int32_t sl = G.gslot[h];
+      const int sec = (sl / kRows) % kSectors;
+      if (sec != cur_sec) {
+        if (!rotate(S, x, cur_sec, sec, k)) { ok = false; break; }
+        cur_sec = sec;
+      }
+      const float xh = k.x[sl % kRows];
+      if (!propagate(S, x, xh, k)) { ok = false; break; }
+      x = xh;
+      float c2;
+      if (!kf_update(S, G.gy[h], G.gz[h], k, &c2)) { ok = false; break; }
+      chi2 = chi2 + c2;
+      ++nh;
+    }
+  }
+  const int capK = F.capK;
+  if (ok) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) F.P[(int64_t)i * capK + kk] = S.P[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) F.C[(int64_t)i * capK + kk] = S.C[i];
+    F.x[kk] = x;
+    F.chi2[kk] = chi2;
+    F.ndf[kk] = 2 * nh - 5;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) F.P[(int64_t)i * capK + kk] = __builtin_nanf("");
+#pragma unroll
+    for (int i = 0; i < 15; ++i) F.C[(int64_t)i * capK + kk] = 0.f;
+    F.x[kk] = 0.f;
+    F.chi2[kk] = 0.f;
+    F.ndf[kk] = -1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fit(GridView G, TrackletView V, FitView F, Bound lo_b,
+                                             Bound hi_b, Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  fit_track(G, V, F, kk, k);
+}
+
+// Refit of the merged chain heads only.
+__global__ __launch_bounds__(256) void k_fit_heads(GridView G, TrackletView V, FitView F,
+                                                   const int32_t* head_list, const int32_t* n_heads,
+                                                   Consts k) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_heads) return;
+  fit_track(G, V, F, head_list[i], k);
+}
+
+// --- merge: candidate search.  Tracks are bucketed by (event, sector).
+struct MergeView {
+  const int32_t* trk_event;   // [capK] event of each selected track
+  int32_t* bucket_cnt;        // [n_events*36]
+  int32_t* bucket_off;        // [n_events*36+1]
+  int32_t* bucket_fill;       // [n_events*36]
+  int32_t* bucket_trk;        // [capK]
+  uint64_t* bestA;            // [capK] packed (chi2 bits, id) best partner of A
+  uint64_t* bestB;            // [capK]
+  int32_t* chain_next;        // [capK]
+  int32_t* chain_prev;        // [capK]
+  int32_t* head_list;         // [capK]
+  int32_t* n_heads;           // [1]
+  int32_t n_events;
+};
+
+__global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const int32_t* gidx,
+                              const int32_t* gslot, const int32_t* job_event, int32_t* trk_event,
+                              int32_t* bucket_cnt, Bound lo_b, Bound hi_b, int32_t capK,
+                              int32_t n_events, int32_t* counters) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  const int32_t h = start[sel_from[kk]];
+  const int32_t sl = gslot[h];
+  const int job = sl / (kSectors * kRows);
+  const int sec = (sl / kRows) % kSectors;
+  int ev = job_event ? job_event[job] : job;
+  if (ev < 0 || ev >= n_events) {  // events must be numbered 0..n_jobs-1
+    atomicOr(&counters[kCntStatus], kStatusRange);
+    ev = job;
+  }
+  trk_event[kk] = ev;
+  atomicAdd(&bucket_cnt[ev * kSectors + sec], 1);
+}
+
+__global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const int32_t* gslot,
+                               MergeView M, Bound lo_b, Bound hi_b, int32_t capK) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  const int32_t sl = gslot[start[sel_from[kk]]];
+  const int sec = (sl / kRows) % kSectors;
+  const int b = M.trk_event[kk] * kSectors + sec;
+  M.bucket_trk[M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1)] = kk;
+}
+
+// packed (chi2, id): chi2 >= 0 so its bits order like the value; smaller wins.
+__device__ __forceinline__ uint64_t pack_best(float c, int32_t id) {
+  return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)id;
+}
+
+__global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletView V, FitView F,
+                                                          MergeView M, Bound lo_b, Bound hi_b,
+                                                          Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t a = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= hi) return;
+  if (F.ndf[a] < 0) return;
+  const int32_t ta = F.sel_from[a];
+  const float ya = V.state[(int64_t)0 * V.capT + ta];
+  const float xa = V.state[(int64_t)20 * V.capT + ta];
+  const float edge = xa * k.tan10 - fabsf(ya);
+  if (!(edge <= k.merge_edge)) return;
+  const int32_t sla = G.gslot[V.start[ta]];
+  const int seca = (sla / kRows) % kSectors;
+  const int dir = ya > 0.f ? 1 : kHalf - 1;
+  const int sb = (seca / kHalf) * kHalf + (seca % kHalf + dir) % kHalf;
+  const int bucket = M.trk_event[a] * kSectors + sb;
+  const int32_t b0 = M.bucket_off[bucket], b1 = M.bucket_off[bucket + 1];
+  for (int32_t q = b0; q < b1; ++q) {
+    const int32_t b = M.bucket_trk[q];
+    if (F.ndf[b] < 0) continue;
+    const int32_t hb = F.sel_hits[F.sel_off[b]];
+    const float eb = k.x[G.gslot[hb] % kRows] * k.tan10 - fabsf(G.gy[hb]);
+    if (!(eb <= k.merge_edge)) continue;
+    State S;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      S.P[i] = V.state[(int64_t)i * V.capT + ta];
+      S.L[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 15; ++i) S.C[i] = V.state[(int64_t)(5 + i) * V.capT + ta];
+    float x = xa;
+    if (!rotate(S, x, seca, sb, k)) continue;
+    if (!propagate(S, x, F.x[b], k)) continue;
+    float PB[5], CB[15];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) PB[i] = F.P[(int64_t)i * F.capK + b];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) CB[i] = F.C[(int64_t)i * F.capK + b];
+    const float c = merge_chi2(S.P, S.C, PB, CB);
+    if (!(c <= k.chi2_merge)) continue;
+    atomicMin((unsigned long long*)&M.bestA[a], (unsigned long long)pack_best(c, b));
+    atomicMin((unsigned long long*)&M.bestB[b], (unsigned long long)pack_best(c, a));
+  }
+}
+
+// Mutual best pairs -> chain links.
+__global__ void k_merge_links(MergeView M, Bound lo_b, Bound hi_b, int32_t capK) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), capK);
+  const int32_t a = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= hi) return;
+  const uint64_t ba = M.bestA[a];
+  if (ba == ~0ull) return;
+  const int32_t b = (int32_t)(uint32_t)ba;
+  const uint64_t bb = M.bestB[b];
+  if ((int32_t)(uint32_t)bb != a) return;
+  M.chain_next[a] = b;
+  M.chain_prev[b] = a;
+}
+
+// Chain heads (no inner partner, an outer partner) are listed for the refit; every
+// track gets its output flag: absorbed pieces are dropped.
+__global__ void k_merge_heads(MergeView M, Bound lo_b, Bound hi_b, int32_t capK, int32_t* keep) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), capK);
+  const int32_t a = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= hi) return;
+  // a piece is absorbed if a head reaches it within kHalf steps (pure cycles stay apart)
+  bool absorbed = false;
+  if (M.chain_prev[a] >= 0) {
+    int32_t p = a;
+    int steps = 0;
+    while (M.chain_prev[p] >= 0 && steps < kHalf) {
+      p = M.chain_prev[p];
+      ++steps;
+    }
+    absorbed = M.chain_prev[p] < 0;
+  }
+  keep[a] = absorbed ? 0 : 1;
+  if (M.chain_prev[a] < 0 && M.chain_next[a] >= 0) {
+    const int32_t i = atomicAdd(M.n_heads, 1);
+    M.head_list[i] = a;
+  }
+}
+
+// ------------------------------------------------------------------ output
+struct OutView {
+  int32_t cap_tracks, cap_hits;
+  int32_t* n_tracks;
+  int32_t* hit_off;
+  int32_t* hits;
+  float* param;
+  float* cov;
+  float* x_ref;
+  float* chi2;
+  int32_t* ndf;
+  int32_t* sector;
+  int32_t* job;
+  int32_t* tracklet;
+};
+
+__global__ void k_out_count(FitView F, const int32_t* keep, int32_t* outn, Bound lo_b, Bound hi_b) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  int n = 0;
+  if (keep[kk]) {
+    const bool walk = F.chain_next && F.chain_prev[kk] < 0;
+    int np = 0;
+    for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1, ++np)
+      n += F.sel_off[p + 1] - F.sel_off[p];
+  }
+  outn[kk] = n;
+}
+
+__global__ void k_out_write(GridView G, TrackletView V, FitView F, OutView O, const int32_t* keep,
+                            const int32_t* oid, const int32_t* ooff, Bound lo_b, Bound hi_b,
+                            int32_t* counters) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi || !keep[kk]) return;
+  const int32_t o = oid[kk];
+  const int32_t h0 = ooff[kk];
+  if (o >= O.cap_tracks) {
+    atomicOr(&counters[kCntStatus], kStatusCapacity);
+    return;
+  }
+  O.hit_off[o] = h0;
+  int w = 0;
+  const bool walk = F.chain_next && F.chain_prev[kk] < 0;
+  int np = 0;
+  for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1, ++np) {
+    for (int32_t q = F.sel_off[p]; q < F.sel_off[p + 1]; ++q) {
+      if (h0 + w < O.cap_hits) O.hits[h0 + w] = G.gidx[F.sel_hits[q]];
+      ++w;
+    }
+  }
+  if (h0 + w > O.cap_hits) atomicOr(&counters[kCntStatus], kStatusCapacity);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) O.param[(int64_t)o * 5 + i] = F.P[(int64_t)i * F.capK + kk];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) O.cov[(int64_t)o * 15 + i] = F.C[(int64_t)i * F.capK + kk];
+  O.x_ref[o] = F.x[kk];
+  O.chi2[o] = F.chi2[kk];
+  O.ndf[o] = F.ndf[kk];
+  const int32_t t = F.sel_from[kk];
+  const int32_t sl = G.gslot[V.start[t]];
+  O.sector[o] = (sl / kRows) % kSectors;
+  O.job[o] = sl / (kSectors * kRows);
+  O.tracklet[o] = t;
+}
+
+__global__ void k_out_finish(const int32_t* oid, const int32_t* ooff, Bound hi_b, int32_t capK,
+                             OutView O, int32_t* counters) {
+  const int32_t hi = min(hi_b.get(), capK);
+  const int32_t K = oid[hi], H = ooff[hi];
+  counters[kCntOut] = K;
+  counters[kCntOutHits] = H;
+  if (O.n_tracks) *O.n_tracks = K;
+  if (K <= O.cap_tracks) O.hit_off[K] = H;
+}
+
+// ------------------------------------------------------------------ test hooks
+__global__ void k_links_to_input(const int32_t* a, const int32_t* b, const int32_t* gidx, int32_t* oa,
+                                 int32_t* ob, Bound hi_b) {
+  const int32_t hi = hi_b.get();
+  const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t i = gidx[h];
+  if (oa) oa[i] = a[h] >= 0 ? gidx[a[h]] : -1;
+  if (ob) ob[i] = b[h] >= 0 ? gidx[b[h]] : -1;
+}
+
+__global__ void k_copy_tracklets(TrackletView V, const int32_t* gidx, const int32_t* toff, int32_t T,
+                                 int32_t* start, int32_t* hits, float* state) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  start[t] = gidx[V.start[t]];
+  const int n = V.nhits[t];
+  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gidx[V.hits[(int64_t)q * V.capT + t]];
+  for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)i * V.capT + t];
+}
+
+__global__ void k_hitw_to_input(const uint64_t* w, const int32_t* gidx, uint64_t* out, Bound hi_b) {
+  const int32_t hi = hi_b.get();
+  const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  out[gidx[h]] = w[h];
+}
+
+__global__ void k_copy_selected(const int32_t* sel_from, const int32_t* sel_off, const int32_t* sel_hits,
+                                const int32_t* gidx, int32_t K, int32_t* tr, int32_t* off, int32_t* hits) {
+  const int32_t kk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk > K) return;
+  off[kk] = sel_off[kk];
+  if (kk == K) return;
+  tr[kk] = sel_from[kk];
+  for (int32_t q = sel_off[kk]; q < sel_off[kk + 1]; ++q) hits[q] = gidx[sel_hits[q]];
+}
+
+__global__ void k_debug_propagate(const float* in, float* out, int32_t n, Consts k) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* a = in + (int64_t)i * 22;
+  State S;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    S.P[q] = a[q];
+    S.L[q] = 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) S.C[q] = a[5 + q];
+  const bool ok = propagate(S, a[20], a[21], k);
+  float* o = out + (int64_t)i * 26;
+  o[0] = ok ? 1.f : 0.f;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    o[1 + q] = S.P[q];
+    o[6 + q] = S.L[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) o[11 + q] = S.C[q];
+}
+
+__global__ void k_debug_update(const float* in, float* out, int32_t n, Consts k) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* a = in + (int64_t)i * 27;
+  State S;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    S.P[q] = a[q];
+    S.L[q] = a[5 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) S.C[q] = a[10 + q];
+  float chi2 = 0.f;
+  const bool ok = kf_update(S, a[25], a[26], k, &chi2);
+  float* o = out + (int64_t)i * 27;
+  o[0] = ok ? 1.f : 0.f;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    o[1 + q] = S.P[q];
+    o[6 + q] = S.L[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) o[11 + q] = S.C[q];
+  o[26] = chi2;
+}
+
+__global__ void k_members(const int32_t* gidx, int32_t* out, Bound hi_b) {
+  const int32_t hi = hi_b.get();
+  const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < hi) out[h] = gidx[h];
+}
+
+}  // namespace
+
+// ==================================================================== host runtime
+namespace {
+
+struct Layout {
+  // capacities
+  int64_t N = 0;
+  int32_t J = 0, S = 0;
+  int64_t capCells = 0;
+  int32_t capT = 0, capK = 0, capH = 0, capE = 0;
+  int64_t bsumN = 0;
+  size_t bytes = 0;
+  // arrays
+  int32_t *ckey, *ccell, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_cnt, *cell_off, *cell_fill;
+  uint32_t *zmin, *zmax;
+  SlotGrid* sg;
+  float *gy, *gz;
+  int32_t *gidx, *gslot, *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start;
+  int32_t *trk_hits, *trk_n;
+  float* trk_state;
+  uint64_t* hitw;
+  int32_t *own, *accf, *kid, *hoff, *sel_off, *sel_hits, *sel_from;
+  float *fitP, *fitC, *fitx, *fitchi2;
+  int32_t* fitndf;
+  int32_t *T_off, *K_off, *counters, *bsum;
+  // merge
+  int32_t *trk_event, *bucket_cnt, *bucket_off, *bucket_fill, *bucket_trk, *chain_next, *chain_prev,
+      *head_list, *keep, *outn, *oid, *ooff;
+  uint64_t *bestA, *bestB;
+};
+
+template <class T> void carve(char*& p, T*& out, int64_t count, size_t& total, bool do_set) {
+  const size_t b = ((size_t)std::max<int64_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+  if (do_set) out = (T*)p;
+  p += b;
+  total += b;
+}
+
+void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
+  L.N = N;
+  L.J = J;
+  L.S = J * kSlotsPerJob;
+  L.capCells = (int64_t)std::ceil((double)N * (double)cpc) + L.S + 2;
+  L.capT = (int32_t)std::min<int64_t>(N / 8 + 1024, N + 1024);
+  L.capK = L.capT;
+  L.capH = (int32_t)(N + 1);
+  L.capE = J * kSectors;
+  const int64_t big = std::max<int64_t>({N + 1, L.capCells + 1, (int64_t)L.S + 1, (int64_t)L.capT + 1});
+  L.bsumN = big / kScanTile + 4;
+  char* p = base;
+  size_t t = 0;
+  carve(p, L.ckey, N, t, set);
+  carve(p, L.ccell, N, t, set);
+  carve(p, L.slot_cnt, L.S + 1, t, set);
+  carve(p, L.slot_off, L.S + 1, t, set);
+  carve(p, L.zmin, L.S, t, set);
+  carve(p, L.zmax, L.S, t, set);
+  carve(p, L.sg, L.S, t, set);
+  carve(p, L.ncell, L.S + 1, t, set);
+  carve(p, L.cell_base, L.S + 1, t, set);
+  carve(p, L.cell_cnt, L.capCells + 1, t, set);
+  carve(p, L.cell_off, L.capCells + 1, t, set);
+  carve(p, L.cell_fill, L.capCells + 1, t, set);
+  carve(p, L.gy, N, t, set);
+  carve(p, L.gz, N, t, set);
+  carve(p, L.gidx, N, t, set);
+  carve(p, L.gslot, N, t, set);
+  carve(p, L.up_raw, N, t, set);
+  carve(p, L.dn_raw, N, t, set);
+  carve(p, L.up, N, t, set);
+  carve(p, L.dn, N, t, set);
+  carve(p, L.flag, N + 1, t, set);
+  carve(p, L.fid, N + 1, t, set);
+  carve(p, L.start, L.capT, t, set);
+  carve(p, L.trk_hits, (int64_t)kRows * L.capT, t, set);
+  carve(p, L.trk_n, L.capT, t, set);
+  carve(p, L.trk_state, (int64_t)21 * L.capT, t, set);
+  carve(p, L.hitw, N, t, set);
+  carve(p, L.own, L.capT + 1, t, set);
+  carve(p, L.accf, L.capT + 1, t, set);
+  carve(p, L.kid, L.capT + 1, t, set);
+  carve(p, L.hoff, L.capT + 1, t, set);
+  carve(p, L.sel_off, L.capK + 1, t, set);
+  carve(p, L.sel_hits, L.capH, t, set);
+  carve(p, L.sel_from, L.capK, t, set);
+  carve(p, L.fitP, (int64_t)5 * L.capK, t, set);
+  carve(p, L.fitC, (int64_t)15 * L.capK, t, set);
+  carve(p, L.fitx, L.capK, t, set);
+  carve(p, L.fitchi2, L.capK, t, set);
+  carve(p, L.fitndf, L.capK, t, set);
+  carve(p, L.T_off, J + 1, t, set);
+  carve(p, L.K_off, J + 1, t, set);
+  carve(p, L.counters, kNumCounters, t, set);
+  carve(p, L.bsum, L.bsumN, t, set);
+  carve(p, L.trk_event, L.capK, t, set);
+  carve(p, L.bucket_cnt, L.capE + 1, t, set);
+  carve(p, L.bucket_off, L.capE + 1, t, set);
+  carve(p, L.bucket_fill, L.capE + 1, t, set);
+  carve(p, L.bucket_trk, L.capK, t, set);
+  carve(p, L.chain_next, L.capK, t, set);
+  carve(p, L.chain_prev, L.capK, t, set);
+  carve(p, L.head_list, L.capK, t, set);
+  carve(p, L.keep, L.capK + 1, t, set);
+  carve(p, L.outn, L.capK + 1, t, set);
+  carve(p, L.oid, L.capK + 1, t, set);
+  carve(p, L.ooff, L.capK + 1, t, set);
+  carve(p, L.bestA, L.capK, t, set);
+  carve(p, L.bestB, L.capK, t, set);
+  L.bytes = t + 256;
+}
+
+int blocks_for(int64_t n, int threads) {
+  const int64_t b = (n + threads - 1) / threads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 30));
+}
+
+}  // namespace
+
+struct tpc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tpc_params p;
+  tpc_tuning tune;
+  Consts k;
+  int mode = TPC_MODE_BATCHED;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  Layout L;
+  bool laid_out = false;
+  // bound inputs
+  tpc_clusters in{};
+  tpc_jobs jobs{};
+  std::vector<int32_t> job_off_h;
+  int stage = 0;  // last completed stage
+  std::string err;
+  int32_t* pinned = nullptr;  // host-pinned counters for tpc_sync
+  // graph cache (batched modes): the chain is captured once per set of buffers
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<uintptr_t> gkey;
+  bool capturing = false;
+  // per-kernel timing with HIP events on the context's stream
+  bool prof = false;
+  struct Mark {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[TPC_PROF_KERNELS] = {};
+  int32_t prof_n[TPC_PROF_KERNELS] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(tpc_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+// Bracket the launches between prof_begin and prof_end with events on the stream.
+int prof_begin(tpc_ctx* c, int id) {
+  if (!c->prof || c->capturing) return -1;
+  tpc_ctx::Mark m{id, take_event(c), take_event(c)};
+  (void)hipEventRecord(m.a, c->stream);
+  c->marks.push_back(m);
+  return (int)c->marks.size() - 1;
+}
+void prof_end(tpc_ctx* c, int h) {
+  if (h < 0) return;
+  (void)hipEventRecord(c->marks[h].b, c->stream);
+}
+
+int fail(tpc_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
+      return TPC_E_HIP;                                                                     \
+    }                                                                                       \
+  } while (0)
+
+void make_consts(const tpc_params& p, Consts& k) {
+  for (int r = 0; r < kRows; ++r) k.x[r] = (float)(85.0 + (double)r * 160.0 / 151.0);
+  k.cb = (float)(-0.299792458e-2 * (double)p.bz);
+  const double a = 20.0 * 3.14159265358979323846 / 180.0;
+  k.cos20 = (float)std::cos(a);
+  k.sin20 = (float)std::sin(a);
+  k.tan10 = (float)std::tan(a / 2.0);
+  k.vy = p.sigma_y * p.sigma_y;
+  k.vz = p.sigma_z * p.sigma_z;
+  k.cut2 = p.link_cut * p.link_cut;
+  k.smax = p.smax;
+  k.win_dy_slope = p.win_dy_slope;
+  k.win_dy_const = p.win_dy_const;
+  k.win_dz_slope = p.win_dz_slope;
+  k.win_dz_const = p.win_dz_const;
+  k.link_cut = p.link_cut;
+  k.nwin = p.nwin;
+  k.chi2_follow = p.chi2_follow;
+  k.max_miss = p.max_miss;
+  k.min_hits = p.min_hits;
+  k.prior0[0] = p.cy0; k.prior0[1] = p.cz0; k.prior0[2] = p.cs0; k.prior0[3] = p.ct0; k.prior0[4] = p.ck0;
+  k.prior1[0] = p.cy1; k.prior1[1] = p.cz1; k.prior1[2] = p.cs1; k.prior1[3] = p.ct1; k.prior1[4] = p.ck1;
+  k.merge_edge = p.merge_edge;
+  k.chi2_merge = p.chi2_merge;
+}
+
+Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
+Bound db(const int32_t* p) { return Bound{p, 0, INT32_MAX}; }
+Bound dbc(const int32_t* p, int32_t cap) { return Bound{p, 0, cap}; }
+
+void fill_i32(tpc_ctx* c, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  const int b = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(b, 65536)), dim3(256), 0, c->stream, p, n, v);
+}
+
+// exclusive scan over [lo, hi) (bound <= host upper bound of hi-lo)
+// base_from_out: continue from the total a previous scan left in out[lo]
+void scan(tpc_ctx* c, const int32_t* in, int32_t* out, Bound lo, Bound hi, int64_t bound,
+          bool base_from_out) {
+  Layout& L = c->L;
+  const int nb = (int)std::max<int64_t>(1, (bound + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, c->stream, in, lo, hi, L.bsum);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c->stream, L.bsum, lo, hi,
+                     (int32_t)base_from_out, out);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, lo, hi, L.bsum);
+}
+
+In make_in(tpc_ctx* c) {
+  In in;
+  in.sector = c->in.sector;
+  in.row = c->in.row;
+  in.y = c->in.y;
+  in.z = c->in.z;
+  in.job_off = c->jobs.job_off;
+  in.n_jobs = c->jobs.n_jobs;
+  return in;
+}
+GridView make_grid(tpc_ctx* c) {
+  Layout& L = c->L;
+  return GridView{L.gy, L.gz, L.gidx, L.gslot, L.sg, L.cell_base, L.cell_off};
+}
+TrackletView make_tv(tpc_ctx* c) {
+  Layout& L = c->L;
+  return TrackletView{L.start, L.up_raw, L.dn_raw, L.up, L.trk_hits, L.trk_n, L.trk_state, L.hitw, L.capT};
+}
+FitView make_fv(tpc_ctx* c, bool with_chain) {
+  Layout& L = c->L;
+  return FitView{L.sel_from, L.sel_off, L.sel_hits, with_chain ? L.chain_next : nullptr,
+                 with_chain ? L.chain_prev : nullptr, L.fitP, L.fitC, L.fitx, L.fitchi2, L.fitndf, L.capK};
+}
+
+// ---- stage launch sequences over the job range [j0, j1)
+void launch_grid(tpc_ctx* c, int j0, int j1) {
+  Layout& L = c->L;
+  const int32_t* jo = c->jobs.job_off;
+  const int64_t nbound = c->job_off_h[j1] - c->job_off_h[j0];
+  const int32_t s0 = j0 * kSlotsPerJob, s1 = j1 * kSlotsPerJob;
+  In in = make_in(c);
+  // clear per-slot counters
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.slot_cnt,
+                     hb(s0), hb(s1), 0);
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream,
+                     (int32_t*)L.zmin, hb(s0), hb(s1), -1);
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream,
+                     (int32_t*)L.zmax, hb(s0), hb(s1), 0);
+  hipLaunchKernelGGL(k_grid_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in,
+                     db(jo + j0), db(jo + j1), L.ckey, L.slot_cnt, L.zmin, L.zmax, L.counters);
+  // slot offsets in grid order (base: clusters of earlier jobs)
+  scan(c, L.slot_cnt, L.slot_off, hb(s0), hb(s1), s1 - s0, j0 != 0);
+  hipLaunchKernelGGL(k_slot_geometry, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.slot_cnt,
+                     L.zmin, L.zmax, L.sg, L.ncell, s0, s1, c->k, c->tune.cells_per_cluster);
+  scan(c, L.ncell, L.cell_base, hb(s0), hb(s1), s1 - s0, j0 != 0);
+  const int64_t cbound = (int64_t)std::ceil((double)nbound * c->tune.cells_per_cluster) + (s1 - s0) + 1;
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_cnt,
+                     db(L.cell_base + s0), db(L.cell_base + s1), 0);
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_fill,
+                     db(L.cell_base + s0), db(L.cell_base + s1), 0);
+  hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
+                     db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.cell_cnt);
+  scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
+                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gy, L.gz, L.gidx, L.gslot);
+}
+
+void launch_links(tpc_ctx* c, int j0, int j1) {
+  Layout& L = c->L;
+  const int64_t nbound = c->job_off_h[j1] - c->job_off_h[j0];
+  const int32_t s0 = j0 * kSlotsPerJob, s1 = j1 * kSlotsPerJob;
+  const Bound lo = db(L.slot_off + s0), hi = db(L.slot_off + s1);
+  const int bl = c->tune.block_links > 0 ? c->tune.block_links : 256;
+  const int pm = prof_begin(c, TPC_PROF_LINKS);
+  hipLaunchKernelGGL(k_links, dim3(blocks_for(nbound, bl)), dim3(bl), 0, c->stream, make_grid(c), lo, hi,
+                     L.up_raw, L.dn_raw, c->k);
+  prof_end(c, pm);
+  hipLaunchKernelGGL(k_clean, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up_raw, L.dn_raw,
+                     L.up, L.dn, lo, hi);
+  // starts: flags in input order -> ranked ids
+  const int32_t* jo = c->jobs.job_off;
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.flag,
+                     db(jo + j0), db(jo + j1), 0);
+  hipLaunchKernelGGL(k_start_flags, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
+                     L.gidx, L.flag, lo, hi);
+  scan(c, L.flag, L.fid, db(jo + j0), db(jo + j1), nbound, j0 != 0);
+  hipLaunchKernelGGL(k_job_offsets, dim3(blocks_for(j1 - j0, 256)), dim3(256), 0, c->stream, L.fid, jo,
+                     L.T_off, j0, j1, (int32_t)L.N);
+  hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
+                     L.gidx, L.fid, L.start, L.capT, lo, hi, L.counters);
+  // tracklet hit weights of this range start at zero
+  hipLaunchKernelGGL(k_fill_range_u64, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, lo,
+                     hi);
+}
+
+int64_t tbound(tpc_ctx* c, int j0, int j1) {
+  const int64_t n = c->job_off_h[j1] - c->job_off_h[j0];
+  return std::min<int64_t>(n / 3 + 1, c->L.capT);
+}
+
+void launch_tracklets(tpc_ctx* c, int j0, int j1) {
+  Layout& L = c->L;
+  const Bound lo = dbc(L.T_off + j0, L.capT), hi = dbc(L.T_off + j1, L.capT);
+  const int bt = c->tune.block_tracklets > 0 ? c->tune.block_tracklets : 256;
+  const int pm = prof_begin(c, TPC_PROF_TRACKLETS);
+  if (c->mode == TPC_MODE_PERSISTENT && c->tune.persistent_waves > 0) {
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    const int waves = ncu * c->tune.persistent_waves;
+    const int blocks = std::max(1, waves * 64 / bt);
+    fill_i32(c, L.counters + kCntQueue, 1, 0);
+    hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
+                       make_tv(c), lo, hi, c->k, L.counters + kCntQueue);
+  } else {
+    hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tbound(c, j0, j1), bt)), dim3(bt), 0, c->stream,
+                       make_grid(c), make_tv(c), lo, hi, c->k);
+  }
+  prof_end(c, pm);
+}
+
+void launch_select(tpc_ctx* c, int j0, int j1) {
+  Layout& L = c->L;
+  const Bound lo = dbc(L.T_off + j0, L.capT), hi = dbc(L.T_off + j1, L.capT);
+  const int64_t tb = tbound(c, j0, j1);
+  hipLaunchKernelGGL(k_select_count, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
+                     L.own, L.accf, c->k);
+  // the scans run over [T_off[j0], min(T_off[j1], capT)); clamp via a copy of the bound
+  scan(c, L.accf, L.kid, lo, hi, tb, j0 != 0);
+  scan(c, L.own, L.hoff, lo, hi, tb, j0 != 0);
+  hipLaunchKernelGGL(k_select_write, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
+                     L.accf, L.kid, L.hoff, L.sel_from, L.sel_off, L.sel_hits, L.capK, L.capH, L.counters);
+  hipLaunchKernelGGL(k_select_finish, dim3(1), dim3(1), 0, c->stream, L.kid, L.hoff, hi, L.capT, L.sel_off,
+                     L.capK, L.counters);
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+int tpc_params_default(tpc_params* p) {
+  if (!p) return TPC_E_ARG;
+  p->win_dy_slope = 1.0f;
+  p->win_dy_const = 0.5f;
+  p->win_dz_slope = 2.0f;
+  p->win_dz_const = 0.5f;
+  p->link_cut = 1.0f;
+  p->cy0 = 1.0f; p->cz0 = 1.0f; p->cs0 = 0.25f; p->ct0 = 0.25f; p->ck0 = 100.0f;
+  p->cy1 = 1.0f; p->cz1 = 1.0f; p->cs1 = 1e-3f; p->ct1 = 1e-3f; p->ck1 = 1.0f;
+  p->sigma_y = 0.1f;
+  p->sigma_z = 0.1f;
+  p->nwin = 3.0f;
+  p->chi2_follow = 15.0f;
+  p->max_miss = 4;
+  p->min_hits = 10;
+  p->smax = 0.95f;
+  p->bz = 0.5f;
+  p->merge_edge = 5.0f;
+  p->chi2_merge = 50.0f;
+  return TPC_OK;
+}
+
+int tpc_tuning_default(tpc_tuning* t) {
+  if (!t) return TPC_E_ARG;
+  t->cells_per_cluster = 0.5f;
+  t->block_links = 256;
+  t->block_tracklets = 128;
+  t->persistent_waves = 8;
+  t->use_graph = 1;
+  return TPC_OK;
+}
+
+int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p) {
+  if (!out) return TPC_E_ARG;
+  tpc_ctx* c = new tpc_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (p) c->p = *p; else tpc_params_default(&c->p);
+  tpc_tuning_default(&c->tune);
+  make_consts(c->p, c->k);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return TPC_E_HIP;
+  }
+  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return TPC_E_HIP;
+  }
+  *out = c;
+  return TPC_OK;
+}
+
+void tpc_ctx_destroy(tpc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (auto& m : c->marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+int tpc_set_stream(tpc_ctx* c, void* s) {
+  if (!c) return TPC_E_ARG;
+  c->stream = (hipStream_t)s;
+  return TPC_OK;
+}
+
+int tpc_set_mode(tpc_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 2) return TPC_E_ARG;
+  c->mode = mode;
+  return TPC_OK;
+}
+
+int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
+  if (!c || !t || !(t->cells_per_cluster > 0.f) || t->cells_per_cluster > 8.f) return TPC_E_ARG;
+  if (t->block_links % 64 || t->block_links <= 0 || t->block_links > 1024) return TPC_E_ARG;
+  if (t->block_tracklets % 64 || t->block_tracklets <= 0 || t->block_tracklets > 256) return TPC_E_ARG;
+  c->tune = *t;
+  c->laid_out = false;
+  return TPC_OK;
+}
+
+const char* tpc_last_error(const tpc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t tpc_workspace_size(const tpc_ctx* c, int64_t n, int32_t J) {
+  if (!c || n < 0 || J <= 0) return 0;
+  Layout L;
+  layout(L, std::max<int64_t>(n, 1), J, c->tune.cells_per_cluster, nullptr, false);
+  return L.bytes;
+}
+
+int tpc_bind_workspace(tpc_ctx* c, void* p, size_t bytes) {
+  if (!c || !p) return TPC_E_ARG;
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  c->ws = p;
+  c->ws_bytes = bytes;
+  c->own_ws = false;
+  c->laid_out = false;
+  return TPC_OK;
+}
+
+int tpc_grid_build(tpc_ctx* c, const tpc_clusters* cl, const tpc_jobs* jb) {
+  if (!c || !cl || !jb) return TPC_E_ARG;
+  if (cl->n < 0 || jb->n_jobs <= 0 || !jb->job_off || !jb->job_off_host) return fail(c, TPC_E_ARG, "bad sizes");
+  if (cl->n > 0 && (!cl->sector || !cl->row || !cl->y || !cl->z)) return fail(c, TPC_E_ARG, "null cluster array");
+  if (jb->job_off_host[0] != 0 || jb->job_off_host[jb->n_jobs] != cl->n)
+    return fail(c, TPC_E_ARG, "job_off must start at 0 and end at n");
+  for (int j = 0; j < jb->n_jobs; ++j)
+    if (jb->job_off_host[j + 1] < jb->job_off_host[j]) return fail(c, TPC_E_ARG, "job_off not ascending");
+  if ((int64_t)jb->n_jobs * kSlotsPerJob > (int64_t)INT32_MAX / 2) return fail(c, TPC_E_ARG, "too many jobs");
+  if (!c->capturing) HIPCHK(c, hipSetDevice(c->device));
+  c->in = *cl;
+  c->jobs = *jb;
+  c->job_off_h.assign(jb->job_off_host, jb->job_off_host + jb->n_jobs + 1);
+  const int64_t N = std::max<int32_t>(cl->n, 1);
+  Layout L;
+  layout(L, N, jb->n_jobs, c->tune.cells_per_cluster, nullptr, false);
+  if (!c->ws || c->ws_bytes < L.bytes) {
+    if (c->ws && !c->own_ws) return fail(c, TPC_E_CAPACITY, "bound workspace too small");
+    if (c->ws) (void)hipFree(c->ws);
+    c->ws = nullptr;
+    HIPCHK(c, hipMalloc(&c->ws, L.bytes));
+    c->ws_bytes = L.bytes;
+    c->own_ws = true;
+  }
+  char* base = (char*)(((uintptr_t)c->ws + 255) & ~(uintptr_t)255);
+  layout(c->L, N, jb->n_jobs, c->tune.cells_per_cluster, base, true);
+  c->laid_out = true;
+  fill_i32(c, c->L.counters, kNumCounters, 0);
+  fill_i32(c, c->L.T_off, 1, 0);
+  fill_i32(c, c->L.K_off, 1, 0);
+  const int pm = prof_begin(c, TPC_PROF_GRID);
+  if (c->mode == TPC_MODE_PLAIN) {
+    for (int j = 0; j < jb->n_jobs; ++j) launch_grid(c, j, j + 1);
+  } else {
+    launch_grid(c, 0, jb->n_jobs);
+  }
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  c->stage = 1;
+  return TPC_OK;
+}
+
+int tpc_find_neighbours(tpc_ctx* c, int32_t* up, int32_t* down) {
+  if (!c || c->stage < 1) return fail(c, TPC_E_ARG, "grid not built");
+  const int J = c->jobs.n_jobs;
+  if (c->mode == TPC_MODE_PLAIN) {
+    for (int j = 0; j < J; ++j) launch_links(c, j, j + 1);
+  } else {
+    launch_links(c, 0, J);
+  }
+  if (up || down)
+    hipLaunchKernelGGL(k_links_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.up,
+                       c->L.dn, c->L.gidx, up, down, db(c->L.slot_off + c->L.S));
+  HIPCHK(c, hipGetLastError());
+  c->stage = 2;
+  return TPC_OK;
+}
+
+int tpc_construct_tracklets(tpc_ctx* c, int32_t* n_tracklets) {
+  if (!c || c->stage < 2) return fail(c, TPC_E_ARG, "links not found");
+  const int J = c->jobs.n_jobs;
+  if (c->mode == TPC_MODE_PLAIN) {
+    for (int j = 0; j < J; ++j) launch_tracklets(c, j, j + 1);
+  } else {
+    launch_tracklets(c, 0, J);
+  }
+  if (n_tracklets)
+    HIPCHK(c, hipMemcpyAsync(n_tracklets, c->L.T_off + J, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipGetLastError());
+  c->stage = 3;
+  return TPC_OK;
+}
+
+int tpc_select_tracks(tpc_ctx* c, int32_t* n_selected) {
+  if (!c || c->stage < 3) return fail(c, TPC_E_ARG, "tracklets not built");
+  const int J = c->jobs.n_jobs;
+  const int pm = prof_begin(c, TPC_PROF_SELECT);
+  if (c->mode == TPC_MODE_PLAIN) {
+    for (int j = 0; j < J; ++j) {
+      launch_select(c, j, j + 1);
+      // K_off[j+1] = number of tracks after job j
+      hipLaunchKernelGGL(k_job_offsets, dim3(1), dim3(64), 0, c->stream, c->L.kid, c->L.T_off, c->L.K_off,
+                         j, j + 1, c->L.capT);
+    }
+  } else {
+    launch_select(c, 0, J);
+    hipLaunchKernelGGL(k_job_offsets, dim3(blocks_for(J, 256)), dim3(256), 0, c->stream, c->L.kid,
+                       c->L.T_off, c->L.K_off, 0, J, c->L.capT);
+  }
+  prof_end(c, pm);
+  if (n_selected)
+    HIPCHK(c, hipMemcpyAsync(n_selected, c->L.counters + kCntSelected, sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipGetLastError());
+  c->stage = 4;
+  return TPC_OK;
+}
+
+int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
+  if (!c || c->stage < 4) return fail(c, TPC_E_ARG, "tracks not selected");
+  if (!out || !out->hit_off || !out->hits || !out->param || !out->cov || !out->x_ref || !out->chi2 ||
+      !out->ndf || !out->sector || !out->job || !out->tracklet || out->cap_tracks < 0 || out->cap_hits < 0)
+    return fail(c, TPC_E_ARG, "bad output struct");
+  Layout& L = c->L;
+  const int J = c->jobs.n_jobs;
+  const int64_t kb = std::min<int64_t>(c->L.N / 3 + 1, L.capK);
+  const int pm = prof_begin(c, TPC_PROF_FIT_MERGE);
+  // per-track fit (no merge yet): the track range is [K_off[j0], K_off[j1])
+  auto fit_range = [&](int j0, int j1, int64_t bound) {
+    hipLaunchKernelGGL(k_fit, dim3(blocks_for(bound, 128)), dim3(128), 0, c->stream, make_grid(c), make_tv(c),
+                       make_fv(c, false), dbc(L.K_off + j0, L.capK), dbc(L.K_off + j1, L.capK), c->k);
+  };
+  if (c->mode == TPC_MODE_PLAIN) {
+    for (int j = 0; j < J; ++j) fit_range(j, j + 1, std::min<int64_t>((c->job_off_h[j + 1] - c->job_off_h[j]) / 3 + 1, L.capK));
+  } else {
+    fit_range(0, J, kb);
+  }
+  // ---- merge across adjacent sectors of one event
+  const Bound klo = hb(0), khi = dbc(L.counters + kCntSelected, L.capK);
+  const int nev = J;
+  fill_i32(c, L.bucket_cnt, (int64_t)nev * kSectors + 1, 0);
+  fill_i32(c, L.bucket_fill, (int64_t)nev * kSectors + 1, 0);
+  fill_i32(c, L.chain_next, L.capK, -1);
+  fill_i32(c, L.chain_prev, L.capK, -1);
+  fill_i32(c, (int32_t*)L.bestA, 2 * (int64_t)L.capK, -1);
+  fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
+  fill_i32(c, L.counters + kCntMergeCand, 1, 0);
+  hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
+                     L.gidx, L.gslot, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi, L.capK, nev,
+                     L.counters);
+  scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb(nev * kSectors), (int64_t)nev * kSectors, false);
+  MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bestA, L.bestB,
+              L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev};
+  hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
+                     L.gslot, M, klo, khi, L.capK);
+  hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
+                     make_tv(c), make_fv(c, false), M, klo, khi, c->k);
+  hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);
+  hipLaunchKernelGGL(k_merge_heads, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK,
+                     L.keep);
+  hipLaunchKernelGGL(k_fit_heads, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
+                     make_tv(c), make_fv(c, true), L.head_list, L.counters + kCntMergeCand, c->k);
+  // ---- output compaction in track-id order
+  hipLaunchKernelGGL(k_out_count, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_fv(c, true),
+                     L.keep, L.outn, klo, khi);
+  scan(c, L.keep, L.oid, klo, khi, kb, false);
+  scan(c, L.outn, L.ooff, klo, khi, kb, false);
+  OutView O{out->cap_tracks, out->cap_hits, out->n_tracks, out->hit_off, out->hits, out->param, out->cov,
+            out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet};
+  hipLaunchKernelGGL(k_out_write, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
+                     make_fv(c, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters);
+  hipLaunchKernelGGL(k_out_finish, dim3(1), dim3(1), 0, c->stream, L.oid, L.ooff, khi, L.capK, O, L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  c->stage = 5;
+  return TPC_OK;
+}
+
+static int run_chain(tpc_ctx* c, const tpc_clusters* cl, const tpc_jobs* jb, tpc_tracks* out) {
+  int rc = tpc_grid_build(c, cl, jb);
+  if (rc) return rc;
+  if ((rc = tpc_find_neighbours(c, nullptr, nullptr))) return rc;
+  if ((rc = tpc_construct_tracklets(c, nullptr))) return rc;
+  if ((rc = tpc_select_tracks(c, nullptr))) return rc;
+  return tpc_fit_merge(c, out);
+}
+
+int tpc_run(tpc_ctx* c, const tpc_clusters* cl, const tpc_jobs* jb, tpc_tracks* out) {
+  if (!c || !cl || !jb || !out) return TPC_E_ARG;
+  const bool graph = c->tune.use_graph && c->mode != TPC_MODE_PLAIN && !c->prof;
+  if (!graph) return run_chain(c, cl, jb, out);
+  // The captured chain depends on every pointer and size it was built with.
+  std::vector<uintptr_t> key = {(uintptr_t)c->stream, (uintptr_t)cl->n, (uintptr_t)cl->sector,
+                                (uintptr_t)cl->row, (uintptr_t)cl->y, (uintptr_t)cl->z,
+                                (uintptr_t)jb->n_jobs, (uintptr_t)jb->job_off, (uintptr_t)jb->job_event,
+                                (uintptr_t)c->ws, (uintptr_t)c->ws_bytes, (uintptr_t)c->mode,
+                                (uintptr_t)out->cap_tracks, (uintptr_t)out->cap_hits,
+                                (uintptr_t)out->n_tracks, (uintptr_t)out->hit_off, (uintptr_t)out->hits,
+                                (uintptr_t)out->param, (uintptr_t)out->cov, (uintptr_t)out->x_ref,
+                                (uintptr_t)out->chi2, (uintptr_t)out->ndf, (uintptr_t)out->sector,
+                                (uintptr_t)out->job, (uintptr_t)out->tracklet};
+  for (int j = 0; j <= jb->n_jobs; ++j) key.push_back((uintptr_t)(uint32_t)jb->job_off_host[j]);
+  if (!c->gexec || key != c->gkey) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    if (c->graph) {
+      (void)hipGraphDestroy(c->graph);
+      c->graph = nullptr;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    // workspace sizing happens outside the capture (it may allocate)
+    if (c->own_ws || !c->ws) {
+      Layout L;
+      layout(L, std::max<int32_t>(cl->n, 1), jb->n_jobs, c->tune.cells_per_cluster, nullptr, false);
+      if (!c->ws || c->ws_bytes < L.bytes) return run_chain(c, cl, jb, out);
+    }
+    if (c->stream == nullptr) return run_chain(c, cl, jb, out);  // the null stream cannot be captured
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    const int rc = run_chain(c, cl, jb, out);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(c, TPC_E_HIP, "graph capture failed");
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->gkey = key;
+  } else {
+    // host-side state of the stages (bound inputs) as the capture left it
+    c->in = *cl;
+    c->jobs = *jb;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  c->stage = 5;
+  return TPC_OK;
+}
+
+int tpc_profile(tpc_ctx* c, int enable) {
+  if (!c) return TPC_E_ARG;
+  c->prof = enable != 0;
+  return TPC_OK;
+}
+
+int tpc_profile_read(tpc_ctx* c, double* ms, int32_t* launches, int32_t n, int32_t reset) {
+  if (!c || n < 0) return TPC_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& m : c->marks) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) {
+      c->prof_ms[m.id] += t;
+      c->prof_n[m.id] += 1;
+    }
+    c->event_pool.push_back(m.a);
+    c->event_pool.push_back(m.b);
+  }
+  c->marks.clear();
+  for (int i = 0; i < n && i < TPC_PROF_KERNELS; ++i) {
+    if (ms) ms[i] = c->prof_ms[i];
+    if (launches) launches[i] = c->prof_n[i];
+  }
+  if (reset)
+    for (int i = 0; i < TPC_PROF_KERNELS; ++i) {
+      c->prof_ms[i] = 0.0;
+      c->prof_n[i] = 0;
+    }
+  return TPC_OK;
+}
+
+int tpc_sync(tpc_ctx* c) {
+  if (!c) return TPC_E_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!c->laid_out) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TPC_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->pinned, c->L.counters, kNumCounters * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int32_t st = c->pinned[kCntStatus];
+  if (st & kStatusCapacity) return fail(c, TPC_E_CAPACITY, "capacity exceeded");
+  if (st & kStatusRange) return fail(c, TPC_E_RANGE, "cluster with sector/row out of range or non-finite y/z");
+  return TPC_OK;
+}
+
+int tpc_get_links_raw(tpc_ctx* c, int32_t* up_raw, int32_t* down_raw) {
+  if (!c || c->stage < 2) return TPC_E_ARG;
+  hipLaunchKernelGGL(k_links_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.up_raw,
+                     c->L.dn_raw, c->L.gidx, up_raw, down_raw, db(c->L.slot_off + c->L.S));
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_get_rows(tpc_ctx* c, int32_t* slot_off, int32_t* members) {
+  if (!c || c->stage < 1) return TPC_E_ARG;
+  HIPCHK(c, hipMemcpyAsync(slot_off, c->L.slot_off, ((size_t)c->L.S + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_members, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.gidx, members,
+                     db(c->L.slot_off + c->L.S));
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_get_tracklet_counts(tpc_ctx* c, int32_t* T, int64_t* H) {
+  if (!c || c->stage < 3 || !T || !H) return TPC_E_ARG;
+  int32_t t = 0;
+  HIPCHK(c, hipMemcpyAsync(&t, c->L.T_off + c->jobs.n_jobs, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  t = std::min(t, c->L.capT);
+  std::vector<int32_t> n(t);
+  if (t) HIPCHK(c, hipMemcpy(n.data(), c->L.trk_n, (size_t)t * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int64_t s = 0;
+  for (int32_t v : n) s += v;
+  *T = t;
+  *H = s;
+  return TPC_OK;
+}
+
+int tpc_get_tracklets(tpc_ctx* c, int32_t* start, int32_t* off, int32_t* hits, float* state, uint64_t* w) {
+  if (!c || c->stage < 3) return TPC_E_ARG;
+  int32_t T;
+  int64_t H;
+  int rc = tpc_get_tracklet_counts(c, &T, &H);
+  if (rc) return rc;
+  std::vector<int32_t> n(T), o(T + 1, 0);
+  if (T) HIPCHK(c, hipMemcpy(n.data(), c->L.trk_n, (size_t)T * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int i = 0; i < T; ++i) o[i + 1] = o[i] + n[i];
+  HIPCHK(c, hipMemcpy(off, o.data(), (size_t)(T + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (T)
+    hipLaunchKernelGGL(k_copy_tracklets, dim3(blocks_for(T, 256)), dim3(256), 0, c->stream, make_tv(c),
+                       c->L.gidx, off, T, start, hits, state);
+  if (w)
+    hipLaunchKernelGGL(k_hitw_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.hitw,
+                       c->L.gidx, w, db(c->L.slot_off + c->L.S));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPC_OK;
+}
+
+int tpc_get_selected_counts(tpc_ctx* c, int32_t* K, int64_t* H) {
+  if (!c || c->stage < 4 || !K || !H) return TPC_E_ARG;
+  int32_t v[kNumCounters];
+  HIPCHK(c, hipMemcpyAsync(v, c->L.counters, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *K = std::min(v[kCntSelected], c->L.capK);
+  *H = v[kCntSelHits];
+  return TPC_OK;
+}
+
+int tpc_get_selected(tpc_ctx* c, int32_t* tr, int32_t* off, int32_t* hits) {
+  if (!c || c->stage < 4) return TPC_E_ARG;
+  int32_t K;
+  int64_t H;
+  int rc = tpc_get_selected_counts(c, &K, &H);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_copy_selected, dim3(blocks_for(K + 1, 256)), dim3(256), 0, c->stream, c->L.sel_from,
+                     c->L.sel_off, c->L.sel_hits, c->L.gidx, K, tr, off, hits);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPC_OK;
+}
+
+int tpc_debug_propagate(tpc_ctx* c, const float* in, float* out, int32_t n) {
+  if (!c || !in || !out || n < 0) return TPC_E_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (n) hipLaunchKernelGGL(k_debug_propagate, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream, in, out, n, c->k);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_debug_update(tpc_ctx* c, const float* in, float* out, int32_t n) {
+  if (!c || !in || !out || n < 0) return TPC_E_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (n) hipLaunchKernelGGL(k_debug_update, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream, in, out, n, c->k);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Kernels of the TPC tracking path (gfx950).  All index spaces are int32.
+//
+// Data layout in HBM (all structure-of-arrays, one workspace):
+//   input order   : the caller's cluster arrays; ckey/ccell per input cluster.
+//   slots         : one per (job, sector, row) = (j*36 + s)*152 + r; slot_off is the
+//                   start of each slot in grid order, sgrid its cell geometry.
+//   grid order    : clusters sorted by (slot, cell); gy, gz, gidx (input index),
+//                   gslot; every later stage works in this space.
+//   tracklets     : ids ranked by the input index of their start cluster; hits are
+//                   stored hit-major (k*capT + t) so that lanes of a wave write
+//                   neighbouring words; state is [21][capT].
+//   tracks        : CSR (sel_off, sel_hits) in tracklet-id order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tpc_math.h"
+
+namespace tpc {
+
+// A range bound known either on the host (ptr == nullptr) or in device memory.
+// The value is clamped to `max` (capacities of the arrays it indexes).
+struct Bound {
+  const int32_t* ptr;
+  int32_t off;
+  int32_t max;
+  __device__ __forceinline__ int32_t get() const {
+    const int32_t v = (ptr ? *ptr : 0) + off;
+    return v < max ? v : max;
+  }
+};
+
+struct SlotGrid {
+  float ylo, zlo, inv_by, inv_bz;
+  int32_t ny, nz, ncell, pad;
+};
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// status bits
+constexpr int32_t kStatusRange = 1;
+constexpr int32_t kStatusCapacity = 2;
+
+// counters
+enum Counter { kCntStatus = 0, kCntTracklets = 1, kCntSelected = 2, kCntSelHits = 3,
+               kCntOut = 4, kCntOutHits = 5, kCntMergeCand = 6, kCntQueue = 7, kCntQueue2 = 8,
+               kNumCounters = 16 };
+
+}  // namespace tpc

@@ -14,43 +14,50 @@ MIN_FINDABLE = 30
 PURITY = 0.9
 
 
-def quality(label, job_off, sector, trk_off, trk_hits, trk_job=None, part_off=None):
+def quality(label, job_off, sector, trk_off, trk_hits, part_off=None):
     label = np.asarray(label)
+    job_off = np.asarray(job_off, np.int64)
     n_jobs = len(job_off) - 1
     job_of = np.repeat(np.arange(n_jobs), np.diff(job_off))
-    # global particle id = part_off[job] + label
-    if part_off is None:
-        part_off = np.zeros(n_jobs + 1, np.int64)
-        for j in range(n_jobs):
-            lab = label[job_off[j]:job_off[j + 1]]
-            part_off[j + 1] = part_off[j] + (int(lab.max()) + 1 if lab.size and lab.max() >= 0 else 0)
+    if part_off is None:  # particles per job = max label + 1
+        mx = np.full(n_jobs, -1, np.int64)
+        if label.size:
+            np.maximum.at(mx, job_of, label.astype(np.int64))
+        part_off = np.concatenate([[0], np.cumsum(mx + 1)])
+    part_off = np.asarray(part_off, np.int64)
     gl = np.where(label >= 0, part_off[job_of] + label, -1)
     n_part = int(part_off[-1])
-    # findable: >= MIN_FINDABLE clusters of the particle in one sector
     sig = gl >= 0
-    key = gl[sig].astype(np.int64) * 36 + np.asarray(sector)[sig]
+    key = gl[sig] * 36 + np.asarray(sector)[sig]
     uk, cnt = np.unique(key, return_counts=True)
     findable = np.zeros(n_part, bool)
-    findable[(uk[cnt >= MIN_FINDABLE] // 36)] = True
+    findable[uk[cnt >= MIN_FINDABLE] // 36] = True
+    trk_off = np.asarray(trk_off, np.int64)
     K = len(trk_off) - 1
+    if K == 0:
+        return dict(n_tracks=0, n_findable=int(findable.sum()), efficiency=0.0, fake_rate=0.0,
+                    clone_rate=0.0, hits_in_tracks=0)
     nh = np.diff(trk_off)
+    tid = np.repeat(np.arange(K), nh)
+    lab = gl[np.asarray(trk_hits)]
+    m = lab >= 0
+    # majority label per track: count (track, label) pairs
+    pair = tid[m].astype(np.int64) * (n_part + 1) + lab[m]
+    up, pc = np.unique(pair, return_counts=True)
+    pt = up // (n_part + 1)
+    pl = up % (n_part + 1)
+    order = np.lexsort((-pc, pt))          # per track, largest count first
+    first = np.ones(len(order), bool)
+    first[1:] = pt[order][1:] != pt[order][:-1]
+    best_t = pt[order][first]
+    best_l = pl[order][first]
+    best_c = pc[order][first]
+    good = best_c >= PURITY * nh[best_t]
     found = np.zeros(n_part, np.int64)
-    fakes = 0
-    for t in range(K):
-        hl = gl[trk_hits[trk_off[t]:trk_off[t + 1]]]
-        good = hl[hl >= 0]
-        if good.size == 0:
-            fakes += 1
-            continue
-        vals, c = np.unique(good, return_counts=True)
-        m = c.argmax()
-        if c[m] < PURITY * nh[t]:
-            fakes += 1
-            continue
-        found[vals[m]] += 1
+    np.add.at(found, best_l[good], 1)
+    n_good = int(good.sum())
     nf = int(findable.sum())
     eff = float((found[findable] > 0).sum()) / nf if nf else float("nan")
     clones = int(np.maximum(found - 1, 0).sum())
-    return dict(n_tracks=K, n_findable=nf, efficiency=eff, fake_rate=fakes / K if K else 0.0,
-                clone_rate=clones / K if K else 0.0, hits_in_tracks=int(trk_off[-1]),
-                found_any=int((found > 0).sum()))
+    return dict(n_tracks=K, n_findable=nf, efficiency=eff, fake_rate=(K - n_good) / K,
+                clone_rate=clones / K, hits_in_tracks=int(trk_off[-1]))

@@ -1,0 +1,41 @@
+"""The C ABI library loads and exports every declared entry point (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import oracle.oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "tpc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2402_01205_amd import tpc
+    lib = ctypes.CDLL(tpc.LIB_PATH)
+    names = declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(tpc.EXPORTED) == names
+
+
+def test_default_params_equal_the_oracle_reading():
+    from paper_2402_01205_amd import tpc
+    p = tpc.default_params()
+    for name, v in O.DEFAULTS.items():
+        got = getattr(p, name)
+        assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2402_01205_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"import\s+oracle|from\s+oracle|libtpc_oracle|\borc_[a-z]", txt), f

@@ -1,0 +1,167 @@
+"""HIP path against the CPU oracle, stage by stage, through the C ABI (needs a gfx950 GPU).
+
+Bit-exact: row membership, raw and clean links, tracklet starts/hits/states/hit weights,
+selected tracks, final track hit lists, and the FP32 fitted parameters (the oracle's FP32
+path uses the same operation order).  FP32 fit vs the FP64 oracle refit: 1e-4 relative on
+q/pT (floor 0.1 GeV^-1) and 1e-3 cm on y, z.
+"""
+import numpy as np
+import pytest
+
+import tpcsynth as g
+from tests.gpu_helpers import compare_all, gpu_run, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_01205_amd import tpc
+    tpc.lib()  # fails loudly if the HIP library is missing
+
+
+def test_device_math_bit_exact():
+    """Propagation and Kalman update of the device model against the oracle's FP32 path."""
+    import oracle.oracle as O
+    from paper_2402_01205_amd.tpc import Tracker
+    rng = np.random.default_rng(7)
+    n = 4000
+    P = np.stack([rng.uniform(-40, 40, n), rng.uniform(-300, 300, n), rng.uniform(-0.9, 0.9, n),
+                  rng.uniform(-1.1, 1.1, n), rng.uniform(-10, 10, n)], 1).astype(np.float32)
+    A = rng.normal(size=(n, 5, 5))
+    Cf = np.einsum("nij,nkj->nik", A, A) * 0.05 + np.eye(5) * 0.01
+    Ct = np.stack([O.full_to_tri(c) for c in Cf]).astype(np.float32)
+    r1 = rng.integers(0, 152, n)
+    r2 = np.clip(r1 + rng.integers(-30, 30, n), 0, 151)
+    x1 = np.array([O.row_x(int(r)) for r in r1], np.float32)
+    x2 = np.array([O.row_x(int(r)) for r in r2], np.float32)
+    tr = Tracker(0)
+    out = tr.debug_propagate(np.concatenate([P, Ct, x1[:, None], x2[:, None]], 1))
+    n_ok = 0
+    for i in range(n):
+        ok, Pn, Cn = O.propagate(P[i], Ct[i], float(x1[i]), float(x2[i]))
+        assert bool(out[i, 0]) == ok, i
+        if ok:
+            n_ok += 1
+            assert np.array_equal(out[i, 1:11].view(np.uint32), Pn.view(np.uint32)), i
+            assert np.array_equal(out[i, 11:].view(np.uint32), Cn.view(np.uint32)), i
+    assert n_ok > n // 2
+    L = (rng.normal(size=(n, 5)) * 1e-7).astype(np.float32)
+    m = (P[:, :2] + rng.normal(size=(n, 2)) * 0.3).astype(np.float32)
+    out = tr.debug_update(np.concatenate([P, L, Ct, m], 1))
+    for i in range(n):
+        ok, Pn, Cn, c2 = O.update(np.concatenate([P[i], L[i]]), Ct[i], float(m[i, 0]), float(m[i, 1]))
+        assert bool(out[i, 0]) == ok
+        if ok:
+            assert np.array_equal(out[i, 1:11].view(np.uint32), Pn.view(np.uint32)), i
+            assert np.array_equal(out[i, 11:26].view(np.uint32), Cn.view(np.uint32)), i
+            assert np.float32(out[i, 26]) == np.float32(c2)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_single_sector_event(seed):
+    cs = g.make_config("c1", seed)
+    say("c1 seed", seed, "n", cs.n)
+    s = compare_all(gpu_run(cs), oracle_run(cs))
+    assert s["n_tracks"] > 50
+
+
+@pytest.mark.parametrize("seed,scale", [(21, 0.25), (22, 1.0)])
+def test_full_tpc_event(seed, scale):
+    cs = g.make_config("c2", seed, scale=scale)
+    say("c2 seed", seed, "scale", scale, "n", cs.n)
+    s = compare_all(gpu_run(cs), oracle_run(cs))
+    assert s["merged"] > 100
+
+
+def test_timeframe_slice():
+    cs = g.make_config("c3", 31, scale=0.06)
+    say("c3 slice n", cs.n)
+    compare_all(gpu_run(cs), oracle_run(cs))
+
+
+def test_batched_uneven_jobs():
+    sizes = g.c4_job_sizes(41)
+    jobs = sorted(set(list(range(0, 512, 64)) + [int(np.argmax(sizes)), int(np.argmin(sizes))]))
+    cs = g.make_config("c4", 41, jobs=jobs)
+    say("c4 jobs", jobs, "n", cs.n)
+    compare_all(gpu_run(cs), oracle_run(cs))
+
+
+def test_sector_jobs_of_one_event_merge_across_jobs():
+    """An event split into per-sector jobs with a shared event id tracks and merges exactly
+    like the oracle given the same grouping."""
+    cs = g.make_config("c2", 23, scale=0.2)
+    order = np.argsort(cs.sector, kind="stable")
+    cuts = np.searchsorted(cs.sector[order], np.arange(37)).astype(np.int32)
+    split = g.ClusterSet(cs.sector[order], cs.row[order], cs.y[order], cs.z[order], cs.time[order],
+                         cs.label[order], cuts, cs.part_pt, cs.part_eta, cs.part_phi, cs.part_q,
+                         np.array([0, len(cs.part_pt)]), {})
+    ev = np.zeros(36, np.int32)
+    s = compare_all(gpu_run(split, job_event=ev), oracle_run(split, job_event=ev))
+    assert s["merged"] > 50
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+def test_launch_modes_identical(mode):
+    sizes = g.c4_job_sizes(41)
+    cs = g.make_config("c4", 41, jobs=[3, 100, 200, int(np.argmax(sizes))])
+    a = gpu_run(cs, mode="batched")
+    b = gpu_run(cs, mode=mode)
+    for k in ("up", "down"):
+        assert np.array_equal(a[k], b[k])
+    for k in ("off", "hits", "tracklet", "ndf"):
+        assert np.array_equal(a["tracks"][k], b["tracks"][k])
+    assert np.array_equal(a["tracks"]["param"].view(np.uint32), b["tracks"]["param"].view(np.uint32))
+
+
+@pytest.mark.parametrize("cpc", [0.125, 1.0, 3.0])
+def test_grid_cell_size_invariance(cpc):
+    from paper_2402_01205_amd.tpc import default_tuning
+    cs = g.make_config("c2", 21, scale=0.2)
+    a = gpu_run(cs)
+    b = gpu_run(cs, tuning=default_tuning(cells_per_cluster=cpc))
+    assert np.array_equal(a["raw"]["up_raw"], b["raw"]["up_raw"])
+    for k in ("off", "hits", "tracklet"):
+        assert np.array_equal(a["tracks"][k], b["tracks"][k])
+
+
+def test_repeatable():
+    cs = g.make_config("c2", 22, scale=0.2)
+    a = gpu_run(cs)
+    b = gpu_run(cs)
+    assert np.array_equal(a["trk"]["hitw"], b["trk"]["hitw"])
+    assert np.array_equal(a["tracks"]["hits"], b["tracks"]["hits"])
+
+
+def test_invalid_clusters_reported_and_excluded():
+    from paper_2402_01205_amd.tpc import TPC_E_RANGE
+    cs = g.make_config("c1", 11)
+    cs.row = cs.row.copy(); cs.sector = cs.sector.copy(); cs.y = cs.y.copy()
+    cs.row[5] = 200
+    cs.sector[6] = 40
+    cs.y[7] = np.nan
+    gres = gpu_run(cs)
+    assert gres["status"] == TPC_E_RANGE
+    compare_all(gres, oracle_run(cs))
+
+
+def test_empty_and_tiny_inputs():
+    cs = g.make_config("c1", 11)
+    empty = cs.job(0)
+    idx = np.arange(0)
+    tiny = g.ClusterSet(cs.sector[:2], cs.row[:2], cs.y[:2], cs.z[:2], cs.time[:2], cs.label[:2],
+                        np.array([0, 2], np.int32), cs.part_pt, cs.part_eta, cs.part_phi, cs.part_q,
+                        np.array([0, len(cs.part_pt)]), {})
+    r = gpu_run(tiny)
+    assert r["tracks"]["n"] == 0
+    nothing = g.ClusterSet(cs.sector[idx], cs.row[idx], cs.y[idx], cs.z[idx], cs.time[idx],
+                           cs.label[idx], np.array([0, 0], np.int32), cs.part_pt, cs.part_eta,
+                           cs.part_phi, cs.part_q, np.array([0, len(cs.part_pt)]), {})
+    r = gpu_run(nothing, stages=False)
+    assert r["tracks"]["n"] == 0
+    # an empty job between two real ones
+    both = g.concat([cs, nothing, cs])
+    compare_all(gpu_run(both), oracle_run(both))
