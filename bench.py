@@ -68,6 +68,24 @@ def cpu_baseline(cs, cfg, budget_s):
             "sample": desc + f"; {ntr} tracks; {dt:.1f} s single-threaded incl. FP64 refit"}
 
 
+def copy_probe(tr, torch, mib, reps):
+    """Achieved GB/s of the library's streaming copy kernel (read + write bytes)."""
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    tr.copy_probe(a, b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        tr.copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2.0 * a.numel() * 4 / ms / 1e6
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,10 +101,20 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the batched path only (for rocprofv3)")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="run only the streaming-copy probe (counter calibration)")
+    ap.add_argument("--probe-mib", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+
+    if args.probe_only:
+        import torch
+        from paper_2402_01205_amd.tpc import Tracker
+        gbs = copy_probe(Tracker(0), torch, args.probe_mib, args.steps)
+        print(json.dumps({"copy_probe_GBs": gbs, "bytes_per_launch": 2 * args.probe_mib << 20}), flush=True)
+        return
 
     import tpcsynth as g
     seed = args.seed if args.seed is not None else SEEDS[args.config]
@@ -163,6 +191,8 @@ def main():
         log(f"plain: {plain_ms:.2f} ms/step; identical to batched: {same}")
         del tp
 
+    probe = copy_probe(tr, torch, 1024, 5)
+    log(f"copy probe: {probe:.0f} GB/s")
     q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off)
     log("quality: " + json.dumps(q))
     value = cs.n / (ms / 1e3)
@@ -190,6 +220,7 @@ def main():
                      "kernel_ms": kern[dom]["ms"], "algorithmic_bytes": kern[dom]["bytes"]},
         "kernels": {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS}
                     for k, v in kern.items()},
+        "copy_probe_GBs": probe,
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "tracks": int(tracks["n"]),
         "tracklets": int(T),

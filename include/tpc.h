@@ -192,6 +192,11 @@ int tpc_get_tracklets(tpc_ctx* ctx, int32_t* start, int32_t* off, int32_t* hits,
 int tpc_get_selected_counts(tpc_ctx* ctx, int32_t* n_selected, int64_t* n_hits);
 int tpc_get_selected(tpc_ctx* ctx, int32_t* tracklet, int32_t* off, int32_t* hits);
 
+/* Streaming copy of `bytes` (multiple of 16) from src to dst on the context's
+ * stream: the achievable-bandwidth probe of the roofline and the reference for
+ * calibrating hardware traffic counters.                                      */
+int tpc_copy_probe(tpc_ctx* ctx, const void* src, void* dst, size_t bytes);
+
 /* Unit hooks of the device track model (tests): n rows, device arrays.
  * propagate: in [n][22] = (y, z, sin phi, tan lambda, q/pT, C[15], x1, x2),
  *            out [n][26] = (ok, state hi[5], state lo[5], C[15]).

@@ -1001,6 +1001,14 @@ __global__ void k_debug_update(const float* in, float* out, int32_t n, Consts k)
   o[26] = chi2;
 }
 
+// Plain streaming copy (16-byte vectors, grid-stride): measures achievable HBM bandwidth
+// and calibrates the hardware traffic counters.
+__global__ __launch_bounds__(256) void k_copy_probe(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                    int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_members(const int32_t* gidx, int32_t* out, Bound hi_b) {
   const int32_t hi = hi_b.get();
   const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1830,6 +1838,19 @@ int tpc_get_selected(tpc_ctx* c, int32_t* tr, int32_t* off, int32_t* hits) {
                      c->L.sel_off, c->L.sel_hits, c->L.gidx, K, tr, off, hits);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPC_OK;
+}
+
+int tpc_copy_probe(tpc_ctx* c, const void* src, void* dst, size_t bytes) {
+  if (!c || !src || !dst || bytes % 16) return TPC_E_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  const int64_t n = (int64_t)(bytes / 16);
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, (int64_t)ncu * 16);
+  if (n) hipLaunchKernelGGL(k_copy_probe, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream,
+                            (const float4*)src, (float4*)dst, n);
+  HIPCHK(c, hipGetLastError());
   return TPC_OK;
 }
 

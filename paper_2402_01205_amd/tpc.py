@@ -96,6 +96,7 @@ def lib():
         L.tpc_debug_propagate.argtypes = [V, V, V, C.c_int32]
         L.tpc_debug_update.argtypes = [V, V, V, C.c_int32]
         L.tpc_profile.argtypes = [V, I]
+        L.tpc_copy_probe.argtypes = [V, V, V, C.c_size_t]
         L.tpc_profile_read.argtypes = [V, V, V, C.c_int32, C.c_int32]
         _lib = L
     return _lib
@@ -107,7 +108,7 @@ EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_c
             "tpc_construct_tracklets", "tpc_select_tracks", "tpc_fit_merge", "tpc_run", "tpc_sync",
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
-            "tpc_profile", "tpc_profile_read"]
+            "tpc_profile", "tpc_profile_read", "tpc_copy_probe"]
 PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge"]
 
 
@@ -267,6 +268,11 @@ class Tracker:
 
     run = tpc_run
     sync = tpc_sync
+
+    def copy_probe(self, src, dst):
+        """Streaming copy src -> dst (torch tensors of equal byte size, multiple of 16)."""
+        nbytes = src.numel() * src.element_size()
+        self._check(lib().tpc_copy_probe(self.ctx, _ptr(src), _ptr(dst), nbytes), "tpc_copy_probe")
 
     def profile(self, enable: bool = True):
         self._check(lib().tpc_profile(self.ctx, int(enable)), "tpc_profile")

@@ -165,3 +165,29 @@ def test_empty_and_tiny_inputs():
     # an empty job between two real ones
     both = g.concat([cs, nothing, cs])
     compare_all(gpu_run(both), oracle_run(both))
+
+
+def test_graph_replays_match_eager():
+    """The captured stage chain, replayed several times with eager work and synchronisations
+    in between, reproduces the eager result every time."""
+    import torch
+
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker, default_tuning
+    sizes = g.c4_job_sizes(41)
+    cs = g.make_config("c4", 41, jobs=[7, 77, int(np.argmax(sizes))])
+    ev = DeviceClusters.from_set(cs, "cuda:0")
+    eager = Tracker(0, mode="batched", tuning=default_tuning(use_graph=0))
+    eager.run(ev)
+    ref = eager.tracks()
+    for mode in ("batched", "persistent"):
+        gr = Tracker(0, mode=mode, tuning=default_tuning(use_graph=1))
+        for rep in range(4):
+            gr.run(ev)
+            got = gr.tracks()
+            assert got["n"] == ref["n"], (mode, rep)
+            assert np.array_equal(got["hits"], ref["hits"]), (mode, rep)
+            assert np.array_equal(got["param"].view(np.uint32), ref["param"].view(np.uint32)), (mode, rep)
+            x = torch.randn(1 << 20, device="cuda:0")
+            (x * 2).sum().item()   # eager work between replays
+            torch.cuda.synchronize()
+        assert gr.ctx.value
