@@ -86,6 +86,32 @@ def copy_probe(tr, torch, mib, reps):
     return 2.0 * a.numel() * 4 / ms / 1e6
 
 
+def serve_run(args, tuning, log):
+    """Continuous-batching serving of time-frame chunks (Poisson arrivals)."""
+    import tpcsynth as g
+    from paper_2402_01205_amd.serve import Pool, Server, make_stream
+    t0 = time.perf_counter()
+    cols = g.gen_collision_pool(51, args.serve_pool, workers=0)
+    pool = Pool.from_collisions(cols)
+    del cols
+    chunks = make_stream(args.serve_pool, args.serve_chunks, rate_hz=args.serve_rate, seed=52)
+    log(f"serving pool of {args.serve_pool} collisions built in {time.perf_counter() - t0:.1f}s")
+    srv = Server(pool, 0, n_slots=3, tuning=default_tuning_from(tuning))
+    res = srv.run(chunks, realtime=True, log=log)
+    res.pop("tracks")
+    res.pop("latencies")
+    res["saturated"] = res["clusters_per_s"] < 0.95 * res["offered_clusters_per_s"]
+    res["rate_hz"] = args.serve_rate
+    res["pool_collisions"] = args.serve_pool
+    log("serving: " + json.dumps(res))
+    return res
+
+
+def default_tuning_from(t):
+    from paper_2402_01205_amd.tpc import default_tuning
+    return default_tuning(**{k: getattr(t, k) for k, _ in t._fields_})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +130,12 @@ def main():
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the streaming-copy probe (counter calibration)")
     ap.add_argument("--probe-mib", type=int, default=2048)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-chunks", type=int, default=100,
+                    help="chunks of the serving run (0 = skip); the workload states 2000")
+    ap.add_argument("--serve-pool", type=int, default=64,
+                    help="collisions in the serving pool; the workload states 512")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -131,7 +163,18 @@ def main():
     ev = DeviceClusters.from_set(cs, dev)
     torch.cuda.synchronize()
 
-    tuning = default_tuning(use_graph=0 if args.no_graph else 1)
+    tune_report = None
+    if args.no_autotune:
+        tuning = default_tuning(use_graph=0 if args.no_graph else 1)
+    else:
+        from paper_2402_01205_amd.autotune import tune
+        sample = cs.subset_jobs(range(0, cs.n_jobs, 8)) if cs.n_jobs >= 64 else cs
+        t1 = time.perf_counter()
+        tuning, tune_report = tune(DeviceClusters.from_set(sample, dev), 0, reps=2)
+        tuning.use_graph = 0 if args.no_graph else 1
+        log(f"autotune on {sample.n} clusters: {tune_report['best']} "
+            f"({len(tune_report['trials'])} candidates, all bit-identical) in {time.perf_counter() - t1:.1f}s")
+    args.mode = "persistent" if tuning.persistent_waves > 0 else "batched"
     tr = Tracker(0, mode=args.mode, tuning=tuning)
 
     def timed(tracker, steps):
@@ -195,6 +238,12 @@ def main():
     log(f"copy probe: {probe:.0f} GB/s")
     q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off)
     log("quality: " + json.dumps(q))
+    serving = None
+    if args.serve_chunks > 0:
+        del tr, ev                 # the serving run sizes its admission by free HBM
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        serving = serve_run(args, tuning, log)
     value = cs.n / (ms / 1e3)
     out = {
         "metric": METRIC,
@@ -221,6 +270,10 @@ def main():
         "kernels": {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS}
                     for k, v in kern.items()},
         "copy_probe_GBs": probe,
+        "p50_chunk_latency_ms": serving["p50_ms"] if serving else None,
+        "p99_chunk_latency_ms": serving["p99_ms"] if serving else None,
+        "serving": serving,
+        "tuning": tune_report["best"] if tune_report else None,
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "tracks": int(tracks["n"]),
         "tracklets": int(T),

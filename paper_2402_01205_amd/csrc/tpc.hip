@@ -67,6 +67,17 @@ __device__ __forceinline__ int block_excl_scan(int v, int* lds_waves, int& total
   return r;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs by block index; remapping
+// block b to logical tile (b % 8) * ceil(nb / 8) + b / 8 gives each XCD (and its L2)
+// a contiguous range of tiles.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t per = (nb + kXcds - 1) / kXcds;
+  const int64_t x = b % kXcds, i = b / kXcds;
+  const int64_t full = nb % kXcds == 0 ? kXcds : nb % kXcds;  // XCDs that get `per` tiles
+  return x < full ? x * per + i : full * per + (x - full) * (per - 1) + i;
+}
+
 // ------------------------------------------------------------------ fill / scan
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -188,6 +199,72 @@ __global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32
   atomicMax(&zmax[slot], oz);
 }
 
+// Same as k_grid_count, with the per-slot counters and z ranges of the block's job
+// privatised in LDS (a block covers kCountTile consecutive input clusters, almost
+// always of one job) and flushed with one global atomic per touched slot.  Clusters
+// of another job (at a job boundary) update global memory directly.
+constexpr int kCountThreads = 1024;
+constexpr int kCountTile = kCountThreads * 4;
+__global__ __launch_bounds__(kCountThreads) void k_grid_count_lds(In in, Bound lo_b, Bound hi_b, int32_t* ckey,
+                                                                   int32_t* slot_cnt, uint32_t* zmin,
+                                                                   uint32_t* zmax, int32_t* counters) {
+  extern __shared__ uint32_t lds[];
+  uint32_t* s_cnt = lds;
+  uint32_t* s_zmin = lds + kSlotsPerJob;
+  uint32_t* s_zmax = lds + 2 * kSlotsPerJob;
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int64_t base = (int64_t)lo + (int64_t)blockIdx.x * kCountTile;
+  if (base >= hi) return;
+  const int32_t end = (int32_t)std::min<int64_t>(base + kCountTile, hi);
+  const int job0 = job_of(in.job_off, in.n_jobs, (int32_t)base);
+  const bool one_job = in.job_off[job0 + 1] >= end;
+  for (int s = threadIdx.x; s < kSlotsPerJob; s += kCountThreads) {
+    s_cnt[s] = 0u;
+    s_zmin[s] = 0xFFFFFFFFu;
+    s_zmax[s] = 0u;
+  }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < kCountTile / kCountThreads; ++q) {
+    const int32_t i = (int32_t)base + q * kCountThreads + threadIdx.x;
+    if (i >= end) break;
+    const int s = in.sector[i];
+    const int r = in.row[i];
+    const float y = in.y[i], z = in.z[i];
+    if (!(s < kSectors && r >= 0 && r < kRows && finite_f(y) && finite_f(z))) {
+      ckey[i] = -1;
+      bad = true;
+      continue;
+    }
+    const int j = one_job ? job0 : job_of(in.job_off, in.n_jobs, i);
+    const int local = s * kRows + r;
+    const int32_t slot = j * kSlotsPerJob + local;
+    ckey[i] = slot;
+    const uint32_t oz = f2ord(z);
+    if (j == job0) {
+      atomicAdd(&s_cnt[local], 1u);
+      atomicMin(&s_zmin[local], oz);
+      atomicMax(&s_zmax[local], oz);
+    } else {
+      atomicAdd(&slot_cnt[slot], 1);
+      atomicMin(&zmin[slot], oz);
+      atomicMax(&zmax[slot], oz);
+    }
+  }
+  if (bad) atomicOr(&counters[kCntStatus], kStatusRange);
+  __syncthreads();
+  for (int s = threadIdx.x; s < kSlotsPerJob; s += kCountThreads) {
+    const uint32_t c = s_cnt[s];
+    if (c) {
+      const int32_t slot = job0 * kSlotsPerJob + s;
+      atomicAdd(&slot_cnt[slot], (int32_t)c);
+      atomicMin(&zmin[slot], s_zmin[s]);
+      atomicMax(&zmax[slot], s_zmax[s]);
+    }
+  }
+}
+
 // Cell geometry of every slot: roughly cells_per_cluster cells per cluster, square
 // cells in (y, z) over the row's acceptance in y and the slot's z range.
 __global__ void k_slot_geometry(const int32_t* slot_cnt, const uint32_t* zmin, const uint32_t* zmax,
@@ -240,8 +317,7 @@ __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey,
 }
 
 __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
-                          const int32_t* cell_off, int32_t* cell_fill, float* gy, float* gz,
-                          int32_t* gidx, int32_t* gslot) {
+                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
@@ -249,18 +325,12 @@ __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, co
   if (slot < 0) return;
   const int32_t gc = ccell[i];
   const int32_t pos = cell_off[gc] + atomicAdd(&cell_fill[gc], 1);
-  gy[pos] = in.y[i];
-  gz[pos] = in.z[i];
-  gidx[pos] = i;
-  gslot[pos] = slot;
+  sth(gh + pos, in.y[i], in.z[i], slot, i);
 }
 
 // ------------------------------------------------------------------ a2: neighbours
 struct GridView {
-  const float* gy;
-  const float* gz;
-  const int32_t* gidx;
-  const int32_t* gslot;
+  const GHit* gh;
   const SlotGrid* sg;
   const int32_t* cell_base;
   const int32_t* cell_off;
@@ -272,11 +342,12 @@ struct GridView {
 __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_b, int32_t* up_raw,
                                                int32_t* dn_raw, Consts k) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t h = lo + (int32_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  const int32_t slot = G.gslot[h];
+  const GHit Hh = ldh(G.gh + h);
+  const int32_t slot = Hh.slot;
   const int r = slot % kRows;
-  const float yh = G.gy[h], zh = G.gz[h];
+  const float yh = Hh.y, zh = Hh.z;
   const float y2 = yh + yh, z2 = zh + zh;
   const float m = 0.01f;
   int32_t bu = -1, bd = -1, bu_o = 0, bd_o = 0;
@@ -297,27 +368,39 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
     const int uy1 = cell_of(yc + wy + m, gu.ylo, gu.inv_by, gu.ny);
     const int uz0 = cell_of(zh - wz - m, gu.zlo, gu.inv_bz, gu.nz);
     const int uz1 = cell_of(zh + wz + m, gu.zlo, gu.inv_bz, gu.nz);
-    for (int cz = uz0; cz <= uz1; ++cz) {
+    const int uzc = cell_of(zh, gu.zlo, gu.inv_bz, gu.nz);
+    // Search radius of the down box: link_cut, shrunk to sqrt(best score) once a pair
+    // is known.  A down cluster outside [p - r - m, p + r + m] has |ry| or |rz| > r, so
+    // its score exceeds the best one and it cannot win (ties need an equal score).
+    float rad = k.link_cut;
+    const int maxd = max(uzc - uz0, uz1 - uzc);
+    for (int q = 0; q <= 2 * maxd; ++q) {
+      // cell rows in z from the window centre outwards (offsets 0, +1, -1, +2, -2, ...):
+      // good pairs come early and shrink the boxes of the later candidates
+      const int cz = uzc + ((q & 1) ? ((q + 1) >> 1) : -(q >> 1));
+      if (cz < uz0 || cz > uz1) continue;
       const int32_t c0 = ubase + cz * gu.ny;
       const int32_t a0 = G.cell_off[c0 + uy0], a1 = G.cell_off[c0 + uy1 + 1];
       for (int32_t u = a0; u < a1; ++u) {
-        const float yu = G.gy[u], zu = G.gz[u];
+        const GHit U = ldh(G.gh + u);
+        const float yu = U.y, zu = U.z;
         if (!(fabsf(yu - yc) <= wy) || !(fabsf(zu - zh) <= wz)) continue;
         const float py = y2 - yu, pz = z2 - zu;
-        const int32_t uo = G.gidx[u];
-        const int dy0 = cell_of(py - k.link_cut - m, gd.ylo, gd.inv_by, gd.ny);
-        const int dy1 = cell_of(py + k.link_cut + m, gd.ylo, gd.inv_by, gd.ny);
-        const int dz0 = cell_of(pz - k.link_cut - m, gd.zlo, gd.inv_bz, gd.nz);
-        const int dz1 = cell_of(pz + k.link_cut + m, gd.zlo, gd.inv_bz, gd.nz);
+        const int32_t uo = U.idx;
+        const int dy0 = cell_of(py - rad - m, gd.ylo, gd.inv_by, gd.ny);
+        const int dy1 = cell_of(py + rad + m, gd.ylo, gd.inv_by, gd.ny);
+        const int dz0 = cell_of(pz - rad - m, gd.zlo, gd.inv_bz, gd.nz);
+        const int dz1 = cell_of(pz + rad + m, gd.zlo, gd.inv_bz, gd.nz);
         for (int ez = dz0; ez <= dz1; ++ez) {
           const int32_t e0 = dbase + ez * gd.ny;
           const int32_t b0 = G.cell_off[e0 + dy0], b1 = G.cell_off[e0 + dy1 + 1];
           for (int32_t dd = b0; dd < b1; ++dd) {
-            const float ry = (yu + G.gy[dd]) - y2;
-            const float rz = (zu + G.gz[dd]) - z2;
+            const GHit D = ldh(G.gh + dd);
+            const float ry = (yu + D.y) - y2;
+            const float rz = (zu + D.z) - z2;
             const float sc = ry * ry + rz * rz;
             if (!(sc <= k.cut2)) continue;
-            const int32_t dor = G.gidx[dd];
+            const int32_t dor = D.idx;
             if (bu < 0 || sc < best || (sc == best && (uo < bu_o || (uo == bu_o && dor < bd_o)))) {
               best = sc;
               bu = u;
@@ -327,6 +410,7 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
             }
           }
         }
+        if (bu >= 0) rad = fminf(k.link_cut, sqrt_rn(best) * 1.0001f);
       }
     }
     if (bu >= 0) break;
@@ -348,13 +432,13 @@ __global__ void k_clean(const int32_t* up_raw, const int32_t* dn_raw, int32_t* u
 
 // Chain starts flagged at their input index: no clean down link, a clean up link whose
 // own clean up link exists.
-__global__ void k_start_flags(const int32_t* up, const int32_t* dn, const int32_t* gidx, int32_t* flag,
+__global__ void k_start_flags(const int32_t* up, const int32_t* dn, const GHit* gh, int32_t* flag,
                               Bound lo_b, Bound hi_b) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
   const int32_t u = up[h];
-  if (dn[h] < 0 && u >= 0 && up[u] >= 0) flag[gidx[h]] = 1;
+  if (dn[h] < 0 && u >= 0 && up[u] >= 0) flag[gh[h].idx] = 1;
 }
 
 __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, int32_t* out_off,
@@ -364,17 +448,30 @@ __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, in
   out_off[j] = scanned[min(job_off[j], cap)];
 }
 
-__global__ void k_write_starts(const int32_t* up, const int32_t* dn, const int32_t* gidx,
-                               const int32_t* fid, int32_t* start, int32_t capT, Bound lo_b,
-                               Bound hi_b, int32_t* counters) {
+// Start flags in grid order (for the grid-ordered work list of the tracklet kernel).
+__global__ void k_start_flags_grid(const int32_t* up, const int32_t* dn, int32_t* flagg, Bound lo_b,
+                                   Bound hi_b) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const int32_t u = up[h];
+  flagg[h] = (dn[h] < 0 && u >= 0 && up[u] >= 0) ? 1 : 0;
+}
+
+// start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order
+__global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit* gh,
+                               const int32_t* fid, const int32_t* posg, int32_t* start, int32_t* order,
+                               int32_t capT, Bound lo_b, Bound hi_b, int32_t* counters) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
   const int32_t u = up[h];
   if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
-  const int32_t t = fid[gidx[h]];
+  const int32_t t = fid[gh[h].idx];
+  const int32_t p = posg[h];
   if (t < capT) start[t] = h;
-  else atomicOr(&counters[kCntStatus], kStatusCapacity);
+  if (p < capT) order[p] = t < capT ? t : -1;
+  if (t >= capT || p >= capT) atomicOr(&counters[kCntStatus], kStatusCapacity);
 }
 
 // ------------------------------------------------------------------ a4: tracklets
@@ -408,15 +505,17 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
   const int32_t first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : h;
   auto next = [&](int32_t c) -> int32_t { return (c == first && first != h) ? h : V.up[c]; };
   const int32_t c1 = next(first), c2 = next(c1);
-  const int32_t slot0 = G.gslot[first];
+  const GHit F0 = ldh(G.gh + first);
+  const GHit F2 = ldh(G.gh + c2);
+  const int32_t slot0 = F0.slot;
   const int r0 = slot0 % kRows;
   const int32_t slot_base = slot0 - r0;
-  const int rc2 = G.gslot[c2] % kRows;
+  const int rc2 = F2.slot % kRows;
   State S;
-  const float y0 = G.gy[first], z0 = G.gz[first];
+  const float y0 = F0.y, z0 = F0.z;
   const float dx2 = k.x[rc2] - k.x[r0];
-  const float dy2 = G.gy[c2] - y0;
-  const float dz2 = G.gz[c2] - z0;
+  const float dy2 = F2.y - y0;
+  const float dz2 = F2.z - z0;
   const float den = sqrt_rn(dx2 * dx2 + dy2 * dy2);
   S.P[0] = y0;
   S.P[1] = z0;
@@ -432,11 +531,12 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
   int last_row = r0;
   bool alive = true;
   for (int32_t c = first; c >= 0; c = next(c)) {
-    const int rc = G.gslot[c] % kRows;
+    const GHit Hc = ldh(G.gh + c);
+    const int rc = Hc.slot % kRows;
     const float xh = k.x[rc];
     if (!propagate(S, x, xh, k)) { alive = false; break; }
     x = xh;
-    if (!kf_update(S, G.gy[c], G.gz[c], k, nullptr)) { alive = false; break; }
+    if (!kf_update(S, Hc.y, Hc.z, k, nullptr)) { alive = false; break; }
     V.hits[(int64_t)n * V.capT + t] = c;
     ++n;
     last_row = rc;
@@ -459,7 +559,7 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
       const int32_t slot = slot_base + r;
       const SlotGrid g = G.sg[slot];
       int32_t best = -1, best_o = 0;
-      float bchi = 0.f;
+      float bchi = 0.f, by = 0.f, bz = 0.f;
       if (g.ncell > 0) {
         const int32_t cb0 = G.cell_base[slot];
         const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
@@ -470,21 +570,24 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
           const int32_t e0 = cb0 + cz * g.ny;
           const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
           for (int32_t c = a0; c < a1; ++c) {
-            const float rr0 = (G.gy[c] - S.P[0]) - S.L[0];
-            const float rr1 = (G.gz[c] - S.P[1]) - S.L[1];
+            const GHit Cc = ldh(G.gh + c);
+            const float rr0 = (Cc.y - S.P[0]) - S.L[0];
+            const float rr1 = (Cc.z - S.P[1]) - S.L[1];
             if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
             const float chi2 = chi2_of(si, rr0, rr1);
-            const int32_t co = G.gidx[c];
+            const int32_t co = Cc.idx;
             if (best < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
               best = c;
               best_o = co;
               bchi = chi2;
+              by = Cc.y;
+              bz = Cc.z;
             }
           }
         }
       }
       if (best >= 0 && bchi <= k.chi2_follow) {
-        if (!kf_update(S, G.gy[best], G.gz[best], k, nullptr)) break;
+        if (!kf_update(S, by, bz, k, nullptr)) break;
         V.hits[(int64_t)n * V.capT + t] = best;
         ++n;
 #pragma unroll
@@ -511,28 +614,45 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
   }
 }
 
-__global__ __launch_bounds__(256) void k_tracklets(GridView G, TrackletView V, Bound lo_b, Bound hi_b,
-                                                   Consts k) {
+// Lanes take tracklets in the grid order of their start clusters (order[]), so the
+// lanes of a wave follow neighbouring tracks through the same cells.
+__global__ __launch_bounds__(256) void k_tracklets(GridView G, TrackletView V, const int32_t* order,
+                                                   Bound lo_b, Bound hi_b, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), V.capT);
-  const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= hi) return;
-  build_tracklet(G, V, t, k);
+  const int32_t p = lo + (int32_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (p >= hi) return;
+  const int32_t t = order[p];
+  if (t >= 0 && t < V.capT) build_tracklet(G, V, t, k);
 }
 
-// Persistent variant: waves take tracklets from a device ticket counter.
-__global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, TrackletView V, Bound lo_b,
+// Persistent variant: the grid-ordered work list is cut into one contiguous range per
+// XCD; waves take 64 tracklets at a time from their XCD's ticket counter, then steal
+// from the other ranges.  Every wave exits once all ranges are exhausted.
+__global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, TrackletView V,
+                                                              const int32_t* order, Bound lo_b,
                                                               Bound hi_b, Consts k, int32_t* ticket) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), V.capT);
+  const int32_t n = hi > lo ? hi - lo : 0;
+  const int32_t per = (n + kXcds - 1) / kXcds;
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    int32_t base = 0;
-    if (lane == 0) base = atomicAdd(ticket, 64);
-    base = __shfl(base, 0, 64);
-    const int32_t t = lo + base + lane;
-    if (lo + base >= hi) break;
-    if (t < hi) build_tracklet(G, V, t, k);
+  const int x0 = blockIdx.x % kXcds;
+  for (int q = 0; q < kXcds; ++q) {
+    const int x = (x0 + q) % kXcds;
+    const int32_t a = lo + x * per;
+    const int32_t b = min(hi, a + per);
+    for (;;) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(&ticket[x], 64);
+      base = __shfl(base, 0, 64);
+      if (a + base >= b) break;
+      const int32_t p = a + base + lane;
+      if (p < b) {
+        const int32_t t = order[p];
+        if (t >= 0 && t < V.capT) build_tracklet(G, V, t, k);
+      }
+    }
   }
 }
 
@@ -621,25 +741,26 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
   const int32_t tl = F.sel_from[last_piece];
   State S;
   const int32_t ho = F.sel_hits[F.sel_off[last_piece + 1] - 1];
-  S.P[0] = G.gy[ho];
-  S.P[1] = G.gz[ho];
+  const GHit Ho = ldh(G.gh + ho);
+  S.P[0] = Ho.y;
+  S.P[1] = Ho.z;
   S.P[2] = V.state[(int64_t)2 * V.capT + tl];
   S.P[3] = V.state[(int64_t)3 * V.capT + tl];
   S.P[4] = V.state[(int64_t)4 * V.capT + tl];
 #pragma unroll
   for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
   init_cov(S, k.prior1);
-  float x = k.x[G.gslot[ho] % kRows];
+  float x = k.x[Ho.slot % kRows];
   float chi2 = 0.f;
   int nh = 0;
   bool ok = true;
-  int cur_sec = (G.gslot[ho] / kRows) % kSectors;
+  int cur_sec = (Ho.slot / kRows) % kSectors;
   for (int pi = np - 1; pi >= 0 && ok; --pi) {
     const int32_t p = pieces[pi];
     const int32_t a = F.sel_off[p], b = F.sel_off[p + 1];
     for (int32_t q = b - 1; q >= a; --q) {
-      const int32_t h = F.sel_hits[q];
-      const int32_t sl = G.gslot[h];
+      const GHit Hq = ldh(G.gh + F.sel_hits[q]);
+      const int32_t sl = Hq.slot;
       const int sec = (sl / kRows) % kSectors;
       if (sec != cur_sec) {
         if (!rotate(S, x, cur_sec, sec, k)) { ok = false; break; }
@@ -649,7 +770,7 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
       if (!propagate(S, x, xh, k)) { ok = false; break; }
       x = xh;
       float c2;
-      if (!kf_update(S, G.gy[h], G.gz[h], k, &c2)) { ok = false; break; }
+      if (!kf_update(S, Hq.y, Hq.z, k, &c2)) { ok = false; break; }
       chi2 = chi2 + c2;
       ++nh;
     }
@@ -708,8 +829,8 @@ struct MergeView {
   int32_t n_events;
 };
 
-__global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const int32_t* gidx,
-                              const int32_t* gslot, const int32_t* job_event, int32_t* trk_event,
+__global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const GHit* gh,
+                              const int32_t* job_event, int32_t* trk_event,
                               int32_t* bucket_cnt, Bound lo_b, Bound hi_b, int32_t capK,
                               int32_t n_events, int32_t* counters) {
   const int32_t lo = lo_b.get();
@@ -717,7 +838,7 @@ __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, con
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
   const int32_t h = start[sel_from[kk]];
-  const int32_t sl = gslot[h];
+  const int32_t sl = gh[h].slot;
   const int job = sl / (kSectors * kRows);
   const int sec = (sl / kRows) % kSectors;
   int ev = job_event ? job_event[job] : job;
@@ -729,13 +850,13 @@ __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, con
   atomicAdd(&bucket_cnt[ev * kSectors + sec], 1);
 }
 
-__global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const int32_t* gslot,
+__global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const GHit* gh,
                                MergeView M, Bound lo_b, Bound hi_b, int32_t capK) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
-  const int32_t sl = gslot[start[sel_from[kk]]];
+  const int32_t sl = gh[start[sel_from[kk]]].slot;
   const int sec = (sl / kRows) % kSectors;
   const int b = M.trk_event[kk] * kSectors + sec;
   M.bucket_trk[M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1)] = kk;
@@ -759,7 +880,7 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   const float xa = V.state[(int64_t)20 * V.capT + ta];
   const float edge = xa * k.tan10 - fabsf(ya);
   if (!(edge <= k.merge_edge)) return;
-  const int32_t sla = G.gslot[V.start[ta]];
+  const int32_t sla = G.gh[V.start[ta]].slot;
   const int seca = (sla / kRows) % kSectors;
   const int dir = ya > 0.f ? 1 : kHalf - 1;
   const int sb = (seca / kHalf) * kHalf + (seca % kHalf + dir) % kHalf;
@@ -768,8 +889,8 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   for (int32_t q = b0; q < b1; ++q) {
     const int32_t b = M.bucket_trk[q];
     if (F.ndf[b] < 0) continue;
-    const int32_t hb = F.sel_hits[F.sel_off[b]];
-    const float eb = k.x[G.gslot[hb] % kRows] * k.tan10 - fabsf(G.gy[hb]);
+    const GHit Hb = ldh(G.gh + F.sel_hits[F.sel_off[b]]);
+    const float eb = k.x[Hb.slot % kRows] * k.tan10 - fabsf(Hb.y);
     if (!(eb <= k.merge_edge)) continue;
     State S;
 #pragma unroll
@@ -884,7 +1005,7 @@ __global__ void k_out_write(GridView G, TrackletView V, FitView F, OutView O, co
   int np = 0;
   for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1, ++np) {
     for (int32_t q = F.sel_off[p]; q < F.sel_off[p + 1]; ++q) {
-      if (h0 + w < O.cap_hits) O.hits[h0 + w] = G.gidx[F.sel_hits[q]];
+      if (h0 + w < O.cap_hits) O.hits[h0 + w] = G.gh[F.sel_hits[q]].idx;
       ++w;
     }
   }
@@ -897,7 +1018,7 @@ __global__ void k_out_write(GridView G, TrackletView V, FitView F, OutView O, co
   O.chi2[o] = F.chi2[kk];
   O.ndf[o] = F.ndf[kk];
   const int32_t t = F.sel_from[kk];
-  const int32_t sl = G.gslot[V.start[t]];
+  const int32_t sl = G.gh[V.start[t]].slot;
   O.sector[o] = (sl / kRows) % kSectors;
   O.job[o] = sl / (kSectors * kRows);
   O.tracklet[o] = t;
@@ -914,41 +1035,41 @@ __global__ void k_out_finish(const int32_t* oid, const int32_t* ooff, Bound hi_b
 }
 
 // ------------------------------------------------------------------ test hooks
-__global__ void k_links_to_input(const int32_t* a, const int32_t* b, const int32_t* gidx, int32_t* oa,
+__global__ void k_links_to_input(const int32_t* a, const int32_t* b, const GHit* gh, int32_t* oa,
                                  int32_t* ob, Bound hi_b) {
   const int32_t hi = hi_b.get();
   const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  const int32_t i = gidx[h];
-  if (oa) oa[i] = a[h] >= 0 ? gidx[a[h]] : -1;
-  if (ob) ob[i] = b[h] >= 0 ? gidx[b[h]] : -1;
+  const int32_t i = gh[h].idx;
+  if (oa) oa[i] = a[h] >= 0 ? gh[a[h]].idx : -1;
+  if (ob) ob[i] = b[h] >= 0 ? gh[b[h]].idx : -1;
 }
 
-__global__ void k_copy_tracklets(TrackletView V, const int32_t* gidx, const int32_t* toff, int32_t T,
+__global__ void k_copy_tracklets(TrackletView V, const GHit* gh, const int32_t* toff, int32_t T,
                                  int32_t* start, int32_t* hits, float* state) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  start[t] = gidx[V.start[t]];
+  start[t] = gh[V.start[t]].idx;
   const int n = V.nhits[t];
-  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gidx[V.hits[(int64_t)q * V.capT + t]];
+  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gh[V.hits[(int64_t)q * V.capT + t]].idx;
   for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)i * V.capT + t];
 }
 
-__global__ void k_hitw_to_input(const uint64_t* w, const int32_t* gidx, uint64_t* out, Bound hi_b) {
+__global__ void k_hitw_to_input(const uint64_t* w, const GHit* gh, uint64_t* out, Bound hi_b) {
   const int32_t hi = hi_b.get();
   const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  out[gidx[h]] = w[h];
+  out[gh[h].idx] = w[h];
 }
 
 __global__ void k_copy_selected(const int32_t* sel_from, const int32_t* sel_off, const int32_t* sel_hits,
-                                const int32_t* gidx, int32_t K, int32_t* tr, int32_t* off, int32_t* hits) {
+                                const GHit* gh, int32_t K, int32_t* tr, int32_t* off, int32_t* hits) {
   const int32_t kk = blockIdx.x * blockDim.x + threadIdx.x;
   if (kk > K) return;
   off[kk] = sel_off[kk];
   if (kk == K) return;
   tr[kk] = sel_from[kk];
-  for (int32_t q = sel_off[kk]; q < sel_off[kk + 1]; ++q) hits[q] = gidx[sel_hits[q]];
+  for (int32_t q = sel_off[kk]; q < sel_off[kk + 1]; ++q) hits[q] = gh[sel_hits[q]].idx;
 }
 
 __global__ void k_debug_propagate(const float* in, float* out, int32_t n, Consts k) {
@@ -1009,10 +1130,10 @@ __global__ __launch_bounds__(256) void k_copy_probe(const float4* __restrict__ s
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-__global__ void k_members(const int32_t* gidx, int32_t* out, Bound hi_b) {
+__global__ void k_members(const GHit* gh, int32_t* out, Bound hi_b) {
   const int32_t hi = hi_b.get();
   const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < hi) out[h] = gidx[h];
+  if (h < hi) out[h] = gh[h].idx;
 }
 
 }  // namespace
@@ -1032,8 +1153,8 @@ struct Layout {
   int32_t *ckey, *ccell, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_cnt, *cell_off, *cell_fill;
   uint32_t *zmin, *zmax;
   SlotGrid* sg;
-  float *gy, *gz;
-  int32_t *gidx, *gslot, *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start;
+  GHit* gh;
+  int32_t *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start, *flagg, *posg, *order;
   int32_t *trk_hits, *trk_n;
   float* trk_state;
   uint64_t* hitw;
@@ -1079,10 +1200,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.cell_cnt, L.capCells + 1, t, set);
   carve(p, L.cell_off, L.capCells + 1, t, set);
   carve(p, L.cell_fill, L.capCells + 1, t, set);
-  carve(p, L.gy, N, t, set);
-  carve(p, L.gz, N, t, set);
-  carve(p, L.gidx, N, t, set);
-  carve(p, L.gslot, N, t, set);
+  carve(p, L.gh, N, t, set);
   carve(p, L.up_raw, N, t, set);
   carve(p, L.dn_raw, N, t, set);
   carve(p, L.up, N, t, set);
@@ -1090,6 +1208,9 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.flag, N + 1, t, set);
   carve(p, L.fid, N + 1, t, set);
   carve(p, L.start, L.capT, t, set);
+  carve(p, L.flagg, N + 1, t, set);
+  carve(p, L.posg, N + 1, t, set);
+  carve(p, L.order, L.capT, t, set);
   carve(p, L.trk_hits, (int64_t)kRows * L.capT, t, set);
   carve(p, L.trk_n, L.capT, t, set);
   carve(p, L.trk_state, (int64_t)21 * L.capT, t, set);
@@ -1153,6 +1274,7 @@ struct tpc_ctx {
   int stage = 0;  // last completed stage
   std::string err;
   int32_t* pinned = nullptr;  // host-pinned counters for tpc_sync
+  bool lds_count_ok = false;  // the device grants the LDS of k_grid_count_lds
   // graph cache (batched modes): the chain is captured once per set of buffers
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1269,7 +1391,7 @@ In make_in(tpc_ctx* c) {
 }
 GridView make_grid(tpc_ctx* c) {
   Layout& L = c->L;
-  return GridView{L.gy, L.gz, L.gidx, L.gslot, L.sg, L.cell_base, L.cell_off};
+  return GridView{L.gh, L.sg, L.cell_base, L.cell_off};
 }
 TrackletView make_tv(tpc_ctx* c) {
   Layout& L = c->L;
@@ -1295,8 +1417,14 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
                      (int32_t*)L.zmin, hb(s0), hb(s1), -1);
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream,
                      (int32_t*)L.zmax, hb(s0), hb(s1), 0);
-  hipLaunchKernelGGL(k_grid_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in,
-                     db(jo + j0), db(jo + j1), L.ckey, L.slot_cnt, L.zmin, L.zmax, L.counters);
+  if (c->lds_count_ok) {
+    hipLaunchKernelGGL(k_grid_count_lds, dim3(blocks_for(nbound, kCountTile)), dim3(kCountThreads),
+                       3 * kSlotsPerJob * sizeof(uint32_t), c->stream, in, db(jo + j0), db(jo + j1), L.ckey,
+                       L.slot_cnt, L.zmin, L.zmax, L.counters);
+  } else {
+    hipLaunchKernelGGL(k_grid_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in,
+                       db(jo + j0), db(jo + j1), L.ckey, L.slot_cnt, L.zmin, L.zmax, L.counters);
+  }
   // slot offsets in grid order (base: clusters of earlier jobs)
   scan(c, L.slot_cnt, L.slot_off, hb(s0), hb(s1), s1 - s0, j0 != 0);
   hipLaunchKernelGGL(k_slot_geometry, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.slot_cnt,
@@ -1311,7 +1439,7 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
                      db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.cell_cnt);
   scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gy, L.gz, L.gidx, L.gslot);
+                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh);
 }
 
 void launch_links(tpc_ctx* c, int j0, int j1) {
@@ -1331,12 +1459,15 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.flag,
                      db(jo + j0), db(jo + j1), 0);
   hipLaunchKernelGGL(k_start_flags, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gidx, L.flag, lo, hi);
+                     L.gh, L.flag, lo, hi);
   scan(c, L.flag, L.fid, db(jo + j0), db(jo + j1), nbound, j0 != 0);
   hipLaunchKernelGGL(k_job_offsets, dim3(blocks_for(j1 - j0, 256)), dim3(256), 0, c->stream, L.fid, jo,
                      L.T_off, j0, j1, (int32_t)L.N);
+  hipLaunchKernelGGL(k_start_flags_grid, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
+                     L.flagg, lo, hi);
+  scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gidx, L.fid, L.start, L.capT, lo, hi, L.counters);
+                     L.gh, L.fid, L.posg, L.start, L.order, L.capT, lo, hi, L.counters);
   // tracklet hit weights of this range start at zero
   hipLaunchKernelGGL(k_fill_range_u64, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, lo,
                      hi);
@@ -1351,18 +1482,21 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
   Layout& L = c->L;
   const Bound lo = dbc(L.T_off + j0, L.capT), hi = dbc(L.T_off + j1, L.capT);
   const int bt = c->tune.block_tracklets > 0 ? c->tune.block_tracklets : 256;
+  const int64_t tb = tbound(c, j0, j1);
+  // tracklets that overflow the work list are never built: their lengths read as 0
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.trk_n, lo, hi, 0);
   const int pm = prof_begin(c, TPC_PROF_TRACKLETS);
   if (c->mode == TPC_MODE_PERSISTENT && c->tune.persistent_waves > 0) {
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
     const int waves = ncu * c->tune.persistent_waves;
-    const int blocks = std::max(1, waves * 64 / bt);
-    fill_i32(c, L.counters + kCntQueue, 1, 0);
+    const int blocks = std::max(kXcds, (waves * 64 / bt) / kXcds * kXcds);
+    fill_i32(c, L.counters + kCntQueue, kXcds, 0);
     hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
-                       make_tv(c), lo, hi, c->k, L.counters + kCntQueue);
+                       make_tv(c), L.order, lo, hi, c->k, L.counters + kCntQueue);
   } else {
-    hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tbound(c, j0, j1), bt)), dim3(bt), 0, c->stream,
-                       make_grid(c), make_tv(c), lo, hi, c->k);
+    hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tb, bt)), dim3(bt), 0, c->stream,
+                       make_grid(c), make_tv(c), L.order, lo, hi, c->k);
   }
   prof_end(c, pm);
 }
@@ -1414,7 +1548,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->cells_per_cluster = 0.5f;
   t->block_links = 256;
   t->block_tracklets = 128;
-  t->persistent_waves = 8;
+  t->persistent_waves = 32;
   t->use_graph = 1;
   return TPC_OK;
 }
@@ -1434,6 +1568,16 @@ int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p)
   if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return TPC_E_HIP;
+  }
+  {
+    int lds_max = 0;
+    const int need = 3 * kSlotsPerJob * (int)sizeof(uint32_t);
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        lds_max >= need) {
+      c->lds_count_ok = hipFuncSetAttribute((const void*)k_grid_count_lds,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, need) == hipSuccess;
+    }
+    (void)hipGetLastError();
   }
   *out = c;
   return TPC_OK;
@@ -1546,7 +1690,7 @@ int tpc_find_neighbours(tpc_ctx* c, int32_t* up, int32_t* down) {
   }
   if (up || down)
     hipLaunchKernelGGL(k_links_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.up,
-                       c->L.dn, c->L.gidx, up, down, db(c->L.slot_off + c->L.S));
+                       c->L.dn, c->L.gh, up, down, db(c->L.slot_off + c->L.S));
   HIPCHK(c, hipGetLastError());
   c->stage = 2;
   return TPC_OK;
@@ -1622,13 +1766,13 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
   fill_i32(c, L.counters + kCntMergeCand, 1, 0);
   hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.gidx, L.gslot, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi, L.capK, nev,
+                     L.gh, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi, L.capK, nev,
                      L.counters);
   scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb(nev * kSectors), (int64_t)nev * kSectors, false);
   MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bestA, L.bestB,
               L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev};
   hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.gslot, M, klo, khi, L.capK);
+                     L.gh, M, klo, khi, L.capK);
   hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
                      make_tv(c), make_fv(c, false), M, klo, khi, c->k);
   hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);
@@ -1767,7 +1911,7 @@ int tpc_sync(tpc_ctx* c) {
 int tpc_get_links_raw(tpc_ctx* c, int32_t* up_raw, int32_t* down_raw) {
   if (!c || c->stage < 2) return TPC_E_ARG;
   hipLaunchKernelGGL(k_links_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.up_raw,
-                     c->L.dn_raw, c->L.gidx, up_raw, down_raw, db(c->L.slot_off + c->L.S));
+                     c->L.dn_raw, c->L.gh, up_raw, down_raw, db(c->L.slot_off + c->L.S));
   HIPCHK(c, hipGetLastError());
   return TPC_OK;
 }
@@ -1776,7 +1920,7 @@ int tpc_get_rows(tpc_ctx* c, int32_t* slot_off, int32_t* members) {
   if (!c || c->stage < 1) return TPC_E_ARG;
   HIPCHK(c, hipMemcpyAsync(slot_off, c->L.slot_off, ((size_t)c->L.S + 1) * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL(k_members, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.gidx, members,
+  hipLaunchKernelGGL(k_members, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.gh, members,
                      db(c->L.slot_off + c->L.S));
   HIPCHK(c, hipGetLastError());
   return TPC_OK;
@@ -1809,10 +1953,10 @@ int tpc_get_tracklets(tpc_ctx* c, int32_t* start, int32_t* off, int32_t* hits, f
   HIPCHK(c, hipMemcpy(off, o.data(), (size_t)(T + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   if (T)
     hipLaunchKernelGGL(k_copy_tracklets, dim3(blocks_for(T, 256)), dim3(256), 0, c->stream, make_tv(c),
-                       c->L.gidx, off, T, start, hits, state);
+                       c->L.gh, off, T, start, hits, state);
   if (w)
     hipLaunchKernelGGL(k_hitw_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.hitw,
-                       c->L.gidx, w, db(c->L.slot_off + c->L.S));
+                       c->L.gh, w, db(c->L.slot_off + c->L.S));
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TPC_OK;
@@ -1835,7 +1979,7 @@ int tpc_get_selected(tpc_ctx* c, int32_t* tr, int32_t* off, int32_t* hits) {
   int rc = tpc_get_selected_counts(c, &K, &H);
   if (rc) return rc;
   hipLaunchKernelGGL(k_copy_selected, dim3(blocks_for(K + 1, 256)), dim3(256), 0, c->stream, c->L.sel_from,
-                     c->L.sel_off, c->L.sel_hits, c->L.gidx, K, tr, off, hits);
+                     c->L.sel_off, c->L.sel_hits, c->L.gh, K, tr, off, hits);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TPC_OK;

@@ -30,6 +30,25 @@ struct Bound {
   }
 };
 
+// One cluster in grid order: position, slot and input index in one 16-byte record,
+// read with a single 16-byte load.
+struct __attribute__((aligned(16))) GHit {
+  float y, z;
+  int32_t slot, idx;
+};
+__device__ __forceinline__ GHit ldh(const GHit* p) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  GHit h;
+  h.y = v.x;
+  h.z = v.y;
+  h.slot = __float_as_int(v.z);
+  h.idx = __float_as_int(v.w);
+  return h;
+}
+__device__ __forceinline__ void sth(GHit* p, float y, float z, int32_t slot, int32_t idx) {
+  *reinterpret_cast<float4*>(p) = make_float4(y, z, __int_as_float(slot), __int_as_float(idx));
+}
+
 struct SlotGrid {
   float ylo, zlo, inv_by, inv_bz;
   int32_t ny, nz, ncell, pad;
@@ -45,7 +64,7 @@ constexpr int32_t kStatusCapacity = 2;
 
 // counters
 enum Counter { kCntStatus = 0, kCntTracklets = 1, kCntSelected = 2, kCntSelHits = 3,
-               kCntOut = 4, kCntOutHits = 5, kCntMergeCand = 6, kCntQueue = 7, kCntQueue2 = 8,
+               kCntOut = 4, kCntOutHits = 5, kCntMergeCand = 6, kCntQueue = 8,  // 8 per-XCD tickets
                kNumCounters = 16 };
 
 }  // namespace tpc

@@ -1,0 +1,286 @@
+"""Serving loop: continuous batching of time-frame chunks on one GPU.
+
+Chunks (a time window holding 10..200 collisions) arrive as a Poisson stream.
+The scheduler admits every arrived chunk it can, as slots and device memory
+free up: all admitted waiting chunks are packed as independent jobs (one job
+and event per chunk) into one batched library launch on a free slot; slots are
+separate HIP streams, so a batch that arrives while others are on the GPU
+overlaps with them.  Admission is sized by free HBM: a batch is launched only if
+its workspace (tpc_workspace_size), its cluster buffers and its outputs fit in
+the budget left by the batches in flight.  Cluster and track state stay on the
+device; each chunk's results are copied to pinned host memory when its batch
+completes, which ends the chunk's latency (measured from its arrival time).
+
+A chunk's tracks depend only on its own clusters (jobs are independent), so a
+chunk gives the same result alone and in any mix.
+
+Chunk assembly from a device-resident collision pool (input synthesis, not part
+of the method): each collision's clusters are stored sorted by |z| descending,
+so the clusters that arrive inside the chunk's window are a prefix of each
+collision; the prefix lengths are computed on the host.  Measured z is shifted
+by the drift of the collision time, and uniform noise clusters (5%) are drawn on
+the device.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .tpc import DeviceClusters, Tracker, default_tuning
+
+V_DRIFT = 2.58
+DRIFT_LENGTH = 250.0
+TAN10 = math.tan(math.radians(10.0))
+
+
+@dataclass
+class Pool:
+    """Collisions at t = 0, each stored sorted by |z| descending, resident on the device."""
+    sector: object
+    row: object
+    y: object
+    z: object
+    off: np.ndarray            # [P+1] host
+    absz_sorted: list          # per collision, host -|z| ascending (float32)
+
+    @classmethod
+    def from_collisions(cls, cols, device="cuda:0"):
+        import torch
+        secs, rows, ys, zs, offs, az = [], [], [], [], [0], []
+        for c in cols:
+            o = np.argsort(-np.abs(c["z"]), kind="stable")
+            secs.append(np.asarray(c["sec"])[o]); rows.append(np.asarray(c["row"])[o])
+            ys.append(np.asarray(c["y"])[o]); zs.append(np.asarray(c["z"])[o])
+            offs.append(offs[-1] + len(o))
+            az.append(-np.abs(zs[-1]).astype(np.float32))   # ascending
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(np.concatenate(a), dt)).to(device)
+        return cls(t(secs, np.uint8), t(rows, np.int16), t(ys, np.float32), t(zs, np.float32),
+                   np.asarray(offs, np.int64), az)
+
+
+@dataclass
+class ChunkSpec:
+    cid: int
+    arrival: float              # seconds from the start of the stream
+    colls: np.ndarray           # pool indices
+    t_coll: np.ndarray          # collision times within the chunk (us)
+    window: float               # us
+    noise_seed: int
+    n_signal: int = 0
+    keep: np.ndarray = None     # clusters kept per collision
+
+
+def make_stream(n_pool, n_chunks, rate_hz=20.0, coll_range=(10, 200), mean_spacing_us=20.0, seed=52):
+    rng = np.random.default_rng(seed)
+    arr = np.cumsum(rng.exponential(1.0 / rate_hz, n_chunks))
+    out = []
+    for i in range(n_chunks):
+        m = int(rng.integers(coll_range[0], coll_range[1] + 1))
+        colls = rng.integers(0, n_pool, m)
+        tk = np.cumsum(rng.exponential(mean_spacing_us, m))
+        out.append(ChunkSpec(i, float(arr[i]), colls, tk, m * mean_spacing_us, int(rng.integers(1 << 31))))
+    return out
+
+
+def plan_chunk(pool: Pool, ch: ChunkSpec):
+    """Clusters of collision k arrive at t_k + (250-|z|)/v_d and are kept if before the
+    window end, i.e. |z| > 250 - v_d (window - t_k): a prefix of the |z|-sorted collision."""
+    thr = DRIFT_LENGTH - V_DRIFT * (ch.window - ch.t_coll)
+    keep = np.empty(len(ch.colls), np.int64)
+    for i, c in enumerate(ch.colls):
+        keep[i] = int(np.searchsorted(pool.absz_sorted[c], -thr[i], side="left"))  # |z| > thr
+    ch.keep = keep
+    ch.n_signal = int(keep.sum())
+    return ch
+
+
+def n_noise(ch: ChunkSpec, frac=0.05) -> int:
+    return int(round(frac * ch.n_signal))
+
+
+def assemble(pool: Pool, chunks, stream, device="cuda:0"):
+    """Device-side assembly of a batch (one job per chunk) without host synchronisation:
+    one gather of the kept prefixes of every collision, the drift shift of each
+    collision's time, then each chunk's noise."""
+    import torch
+    starts, lens, shifts, job_off = [], [], [], [0]
+    for ch in chunks:
+        starts.append(pool.off[ch.colls])
+        lens.append(ch.keep)
+        shifts.append(V_DRIFT * ch.t_coll)
+    starts = np.concatenate(starts).astype(np.int64)
+    lens = np.concatenate(lens).astype(np.int64)
+    shifts = np.concatenate(shifts).astype(np.float32)
+    total = int(lens.sum())
+    out_off = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    with torch.cuda.stream(stream):
+        dt = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=t, non_blocking=False)
+        rep = dt(lens, torch.int64)
+        idx = torch.arange(total, device=device, dtype=torch.int64) + torch.repeat_interleave(
+            dt(starts - out_off, torch.int64), rep, output_size=total)
+        sh = torch.repeat_interleave(dt(shifts, torch.float32), rep, output_size=total)
+        sec = pool.sector[idx]
+        zsig = torch.where(sec < 18, pool.z[idx] - sh, pool.z[idx] + sh)
+        parts = {"sector": [], "row": [], "y": [], "z": []}
+        pos = 0
+        for ch in chunks:
+            k = ch.n_signal
+            parts["sector"].append(sec[pos:pos + k]); parts["row"].append(pool.row[idx[pos:pos + k]])
+            parts["y"].append(pool.y[idx[pos:pos + k]]); parts["z"].append(zsig[pos:pos + k])
+            pos += k
+            nn = n_noise(ch)
+            if nn:
+                g = torch.Generator(device=device)
+                g.manual_seed(ch.noise_seed)
+                nsec = torch.randint(0, 36, (nn,), generator=g, device=device)
+                nrow = torch.randint(0, 152, (nn,), generator=g, device=device)
+                x = 85.0 + nrow.to(torch.float32) * (160.0 / 151.0)
+                ny = (torch.rand(nn, generator=g, device=device) * 2 - 1) * x * TAN10
+                t = torch.rand(nn, generator=g, device=device) * ch.window
+                nz = torch.where(nsec < 18, 1.0, -1.0) * (DRIFT_LENGTH - V_DRIFT * t)
+                parts["sector"].append(nsec.to(torch.uint8)); parts["row"].append(nrow.to(torch.int16))
+                parts["y"].append(ny.to(torch.float32)); parts["z"].append(nz.to(torch.float32))
+            job_off.append(job_off[-1] + k + nn)
+        cat = lambda k, t: (torch.cat(parts[k]) if parts[k] else torch.zeros(0, dtype=t, device=device))
+        sector, row = cat("sector", torch.uint8), cat("row", torch.int16)
+        y, z = cat("y", torch.float32), cat("z", torch.float32)
+        jo = np.asarray(job_off, np.int32)
+        ev = DeviceClusters(sector, row, y, z, torch.zeros_like(y), dt(jo, torch.int32), jo,
+                            torch.arange(len(chunks), dtype=torch.int32, device=device))
+    return ev
+
+
+@dataclass
+class Slot:
+    stream: object
+    tracker: Tracker
+    busy: bool = False
+    batch: list = field(default_factory=list)
+    done_event: object = None
+    bytes: int = 0
+    ev: object = None
+    host: dict = None
+
+
+def _bytes_of(tracker: Tracker, n, j):
+    # workspace + inputs (15 B/cluster) + outputs (about 100 B per possible track + 4 B per hit)
+    capT = min(n // 8 + 1024, n + 1024)
+    return tracker.workspace_size(n, j) + 15 * n + 100 * capT + 4 * n
+
+
+class Server:
+    def __init__(self, pool: Pool, device=0, n_slots=3, hbm_budget=None, tuning=None, max_batch=64,
+                 max_batch_clusters=150_000_000):
+        import torch
+        self.torch = torch
+        self.pool = pool
+        self.device = device
+        torch.cuda.synchronize(device)
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info(device)
+        self.budget = int(hbm_budget if hbm_budget is not None else 0.7 * free)
+        self.max_batch_clusters = max_batch_clusters
+        tuning = tuning or default_tuning(use_graph=0)
+        tuning.use_graph = 0
+        self.slots = []
+        for _ in range(n_slots):
+            s = torch.cuda.Stream(device)
+            self.slots.append(Slot(s, Tracker(device, mode="persistent" if tuning.persistent_waves else "batched",
+                                              tuning=tuning, stream=s)))
+        self.max_batch = max_batch
+        self.in_flight_bytes = 0
+
+    def _launch(self, slot: Slot, batch):
+        torch = self.torch
+        ev = assemble(self.pool, batch, slot.stream, f"cuda:{self.device}")
+        with torch.cuda.stream(slot.stream):
+            slot.tracker.run(ev)
+            o = slot.tracker.out
+            # per-chunk results to pinned host memory
+            host = {k: torch.empty(o[k].shape, dtype=o[k].dtype, pin_memory=True)
+                    for k in ("n_tracks", "hit_off", "job")}
+            for k in host:
+                host[k].copy_(o[k], non_blocking=True)
+            done = torch.cuda.Event()
+            done.record(slot.stream)
+        slot.busy, slot.batch, slot.done_event, slot.ev, slot.host = True, batch, done, ev, host
+
+    def run(self, chunks, realtime=True, log=None, deadline_s=900.0):
+        """Serve the chunk stream; returns per-chunk latencies and totals."""
+        for ch in chunks:
+            plan_chunk(self.pool, ch)
+        pending = []
+        order = sorted(chunks, key=lambda c: c.arrival)
+        nxt = 0
+        lat = {}
+        tracks = {}
+        t0 = time.perf_counter()
+        busy_time = 0.0
+        n_batches = 0
+        max_conc = 0
+        t_start = time.perf_counter()
+        while len(lat) < len(chunks):
+            if time.perf_counter() - t_start > deadline_s:
+                raise RuntimeError(f"serving did not finish within {deadline_s} s")
+            now = time.perf_counter() - t0
+            if not realtime and nxt < len(order) and not pending and all(not s.busy for s in self.slots):
+                now = order[nxt].arrival  # skip idle gaps when not pacing in real time
+                t0 = time.perf_counter() - now
+            while nxt < len(order) and order[nxt].arrival <= now:
+                pending.append(order[nxt])
+                nxt += 1
+            # completions
+            for s in self.slots:
+                if s.busy and s.done_event.query():
+                    tdone = time.perf_counter() - t0
+                    K = int(s.host["n_tracks"][0])
+                    jobs = s.host["job"][:K].numpy()
+                    cnt = np.bincount(jobs, minlength=len(s.batch))
+                    for i, ch in enumerate(s.batch):
+                        lat[ch.cid] = tdone - ch.arrival
+                        tracks[ch.cid] = int(cnt[i])
+                    if log:
+                        log(f"t={tdone:7.3f}s done {len(s.batch)} chunks, {K} tracks; served {len(lat)}")
+                    self.in_flight_bytes -= s.bytes
+                    s.busy, s.batch, s.ev, s.host = False, [], None, None
+            # admissions: pack waiting chunks into one launch per free slot
+            for s in self.slots:
+                if s.busy or not pending:
+                    continue
+                batch, n = [], 0
+                for ch in list(pending):
+                    if len(batch) >= self.max_batch:
+                        break
+                    add = ch.n_signal + n_noise(ch)
+                    if batch and n + add > self.max_batch_clusters:
+                        break
+                    need = _bytes_of(s.tracker, n + add, len(batch) + 1)
+                    if self.in_flight_bytes + need > self.budget and batch:
+                        break
+                    if self.in_flight_bytes + need > self.budget and self.in_flight_bytes > 0:
+                        break
+                    batch.append(ch)
+                    n += add
+                if not batch:
+                    continue
+                for ch in batch:
+                    pending.remove(ch)
+                s.bytes = _bytes_of(s.tracker, n, len(batch))
+                self.in_flight_bytes += s.bytes
+                self._launch(s, batch)
+                n_batches += 1
+                max_conc = max(max_conc, sum(x.busy for x in self.slots))
+                if log:
+                    log(f"t={now:7.3f}s launch {len(batch)} chunks, {n} clusters, pending {len(pending)}")
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        lats = np.array([lat[c.cid] for c in chunks])
+        n_cl = sum(c.n_signal + n_noise(c) for c in chunks)
+        offered = n_cl / max(order[-1].arrival, 1e-9)
+        return dict(n_chunks=len(chunks), clusters=n_cl, wall_s=wall, clusters_per_s=n_cl / wall,
+                    offered_clusters_per_s=offered, p50_ms=float(np.percentile(lats, 50) * 1e3),
+                    p99_ms=float(np.percentile(lats, 99) * 1e3), mean_ms=float(lats.mean() * 1e3),
+                    batches=n_batches, max_concurrent=max_conc, tracks=tracks, latencies=lats)

@@ -191,3 +191,44 @@ def test_graph_replays_match_eager():
             (x * 2).sum().item()   # eager work between replays
             torch.cuda.synchronize()
         assert gr.ctx.value
+
+
+def test_autotune_candidates_are_bit_identical():
+    from paper_2402_01205_amd.autotune import tune
+    from paper_2402_01205_amd.tpc import DeviceClusters
+    cs = g.make_config("c2", 21, scale=0.1)
+    best, rep = tune(DeviceClusters.from_set(cs, "cuda:0"), 0, reps=1)
+    assert rep["verified"] and len(rep["trials"]) >= 8
+
+
+def test_serving_chunk_alone_equals_chunk_in_mix():
+    """A chunk's tracks are the same when it is tracked alone and when it shares a batch."""
+    import torch
+
+    from paper_2402_01205_amd.serve import Pool, Server, assemble, make_stream, plan_chunk
+    from paper_2402_01205_amd.tpc import Tracker
+    cols = g.gen_collision_pool(61, 8, mult_range=(100, 400))
+    pool = Pool.from_collisions(cols)
+    chunks = [plan_chunk(pool, c) for c in make_stream(8, 5, coll_range=(2, 6), seed=62)]
+    s = torch.cuda.current_stream()
+
+    def tracks_of(batch, which):
+        ev = assemble(pool, batch, s)
+        tr = Tracker(0, mode="batched")
+        tr.run(ev)
+        t = tr.tracks()
+        jo = ev.job_off_host
+        sel = np.nonzero(t["job"] == which)[0]
+        hits = [t["hits"][t["off"][i]:t["off"][i + 1]] - jo[which] for i in sel]
+        return hits, t["param"][sel]
+
+    for i in (0, 2, 4):
+        alone_h, alone_p = tracks_of([chunks[i]], 0)
+        mix_h, mix_p = tracks_of(chunks, i)
+        assert len(alone_h) == len(mix_h) > 0
+        assert all(np.array_equal(a, b) for a, b in zip(alone_h, mix_h))
+        assert np.array_equal(alone_p.view(np.uint32), mix_p.view(np.uint32))
+    # and the scheduler serves every chunk
+    srv = Server(pool, 0, n_slots=2)
+    res = srv.run(make_stream(8, 12, rate_hz=200.0, coll_range=(2, 6), seed=63), realtime=False)
+    assert res["n_chunks"] == 12 and res["p99_ms"] >= res["p50_ms"] > 0
