@@ -486,6 +486,7 @@ struct Oracle {
       std::memcpy(t.C, C, sizeof(C));
       t.x = x;
     };
+    keep_state();  // the recorded state is the initial one until a cluster is accepted
     // the chain: every chain cluster is used unconditionally
     for (int32_t h = c0; h >= 0; h = chain_next(h, t.start, c0)) {
       const float xh = kGeo.x[row[h]];

@@ -274,7 +274,7 @@ __global__ void k_slot_geometry(const int32_t* slot_cnt, const uint32_t* zmin, c
   if (s >= s1) return;
   const int n = slot_cnt[s];
   SlotGrid g;
-  g.pad = 0;
+  g.cbase = 0;
   if (n == 0) {
     g.ylo = g.zlo = g.inv_by = g.inv_bz = 0.f;
     g.ny = g.nz = g.ncell = 0;
@@ -299,6 +299,12 @@ __global__ void k_slot_geometry(const int32_t* slot_cnt, const uint32_t* zmin, c
   }
   sg[s] = g;
   ncell[s] = g.ncell;
+}
+
+// the slot's first global cell index, once the cell counts are scanned
+__global__ void k_slot_cellbase(SlotGrid* sg, const int32_t* cell_base, int32_t s0, int32_t s1) {
+  const int32_t s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < s1) sg[s].cbase = cell_base[s];
 }
 
 __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const SlotGrid* sg,
@@ -363,7 +369,7 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
     const SlotGrid gu = G.sg[su];
     const SlotGrid gd = G.sg[sd];
     if (gu.ncell == 0 || gd.ncell == 0) continue;
-    const int32_t ubase = G.cell_base[su], dbase = G.cell_base[sd];
+    const int32_t ubase = gu.cbase, dbase = gd.cbase;
     const int uy0 = cell_of(yc - wy - m, gu.ylo, gu.inv_by, gu.ny);
     const int uy1 = cell_of(yc + wy + m, gu.ylo, gu.inv_by, gu.ny);
     const int uz0 = cell_of(zh - wz - m, gu.zlo, gu.inv_bz, gu.nz);
@@ -526,7 +532,11 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
   for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
   init_cov(S, k.prior0);
   float x = k.x[r0];
-  float keepP[5], keepC[15], keepx = x;
+  float keepP[5], keepC[15], keepx = x;  // initial state until a cluster is accepted
+#pragma unroll
+  for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
   int n = 0;
   int last_row = r0;
   bool alive = true;
@@ -561,7 +571,7 @@ __device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t
       int32_t best = -1, best_o = 0;
       float bchi = 0.f, by = 0.f, bz = 0.f;
       if (g.ncell > 0) {
-        const int32_t cb0 = G.cell_base[slot];
+        const int32_t cb0 = g.cbase;
         const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
         const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
         const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
@@ -626,37 +636,213 @@ __global__ __launch_bounds__(256) void k_tracklets(GridView G, TrackletView V, c
   if (t >= 0 && t < V.capT) build_tracklet(G, V, t, k);
 }
 
-// Persistent variant: the grid-ordered work list is cut into one contiguous range per
-// XCD; waves take 64 tracklets at a time from their XCD's ticket counter, then steal
-// from the other ranges.  Every wave exits once all ranges are exhausted.
+// Persistent variant with lane refill.  The grid-ordered work list is cut into one
+// contiguous range per XCD; each lane runs its tracklet as a step machine (one step =
+// one chain cluster or one following row, the same operations in the same order as
+// build_tracklet), and a lane whose tracklet has ended takes the next one: lanes that
+// need work are counted with a ballot and served by one atomicAdd per wave on the
+// ticket of the current range, then of the other ranges (stealing).  The wave exits
+// when every range is exhausted and no lane holds a tracklet.
 __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, TrackletView V,
                                                               const int32_t* order, Bound lo_b,
                                                               Bound hi_b, Consts k, int32_t* ticket) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), V.capT);
-  const int32_t n = hi > lo ? hi - lo : 0;
-  const int32_t per = (n + kXcds - 1) / kXcds;
+  const int32_t nwork = hi > lo ? hi - lo : 0;
+  const int32_t per = (nwork + kXcds - 1) / kXcds;
   const int lane = threadIdx.x & 63;
   const int x0 = blockIdx.x % kXcds;
-  for (int q = 0; q < kXcds; ++q) {
-    const int x = (x0 + q) % kXcds;
-    const int32_t a = lo + x * per;
-    const int32_t b = min(hi, a + per);
-    for (;;) {
+  int qi = 0;  // ranges tried so far (wave-uniform)
+  // lane state
+  bool active = false;
+  int phase = 0;  // 1 chain, 2 follow
+  int32_t t = 0, h = 0, first = 0, cur = -1, slot_base = 0;
+  int n = 0, last_row = 0, r = 0, misses = 0;
+  float x = 0.f, keepx = 0.f;
+  State S;
+  float keepP[5], keepC[15];
+  for (;;) {
+    // ---- refill lanes without a tracklet
+    while (qi < kXcds) {
+      const uint64_t need = __ballot(!active);
+      if (need == 0) break;
+      const int cnt = __popcll(need);
+      const int xr = (x0 + qi) % kXcds;
+      const int32_t a = lo + xr * per;
+      const int32_t b = min(hi, a + per);
       int32_t base = 0;
-      if (lane == 0) base = atomicAdd(&ticket[x], 64);
+      if (lane == 0) base = atomicAdd(&ticket[xr], cnt);
       base = __shfl(base, 0, 64);
-      if (a + base >= b) break;
-      const int32_t p = a + base + lane;
-      if (p < b) {
-        const int32_t t = order[p];
-        if (t >= 0 && t < V.capT) build_tracklet(G, V, t, k);
+      const int rank = __popcll(need & ((1ull << lane) - 1ull));
+      if (!active) {
+        const int32_t p = a + base + rank;
+        if (p < b) {
+          const int32_t tt = order[p];
+          if (tt >= 0 && tt < V.capT) {
+            // ---- start a tracklet (same initialisation as build_tracklet)
+            t = tt;
+            h = V.start[t];
+            const int32_t dr = V.dn_raw[h];
+            first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : h;
+            const int32_t c1 = (first != h) ? h : V.up[first];
+            const int32_t c2 = (c1 == first && first != h) ? h : V.up[c1];
+            const GHit F0 = ldh(G.gh + first);
+            const GHit F2 = ldh(G.gh + c2);
+            const int r0 = F0.slot % kRows;
+            slot_base = F0.slot - r0;
+            const float dx2 = k.x[F2.slot % kRows] - k.x[r0];
+            const float dy2 = F2.y - F0.y;
+            const float dz2 = F2.z - F0.z;
+            const float den = sqrt_rn(dx2 * dx2 + dy2 * dy2);
+            S.P[0] = F0.y;
+            S.P[1] = F0.z;
+            S.P[2] = div_rn(dy2, den);
+            S.P[3] = div_rn(dz2, den);
+            S.P[4] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
+            init_cov(S, k.prior0);
+            x = k.x[r0];
+            keepx = x;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
+            n = 0;
+            last_row = r0;
+            cur = first;
+            phase = 1;
+            active = true;
+          }
+        }
       }
+      // this range is exhausted for lanes beyond its end: move on
+      if (base + cnt >= b - a) ++qi;
+    }
+    if (!__any(active)) break;
+    if (!active) continue;
+    // ---- one step of this lane's tracklet
+    bool end = false;
+    if (phase == 1) {
+      const GHit Hc = ldh(G.gh + cur);
+      const int rc = Hc.slot % kRows;
+      const float xh = k.x[rc];
+      if (!propagate(S, x, xh, k)) {
+        end = true;
+      } else {
+        x = xh;
+        if (!kf_update(S, Hc.y, Hc.z, k, nullptr)) {
+          end = true;
+        } else {
+          V.hits[(int64_t)n * V.capT + t] = cur;
+          ++n;
+          last_row = rc;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+          for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
+          keepx = x;
+          cur = (cur == first && first != h) ? h : V.up[cur];
+          if (cur < 0) {
+            phase = 2;
+            r = last_row + 1;
+            misses = 0;
+            if (r >= kRows) end = true;
+          }
+        }
+      }
+    } else {
+      const float xr = k.x[r];
+      if (!propagate(S, x, xr, k)) {
+        end = true;
+      } else {
+        x = xr;
+        const SInv si = s_inverse(S.C, k.vy, k.vz);
+        if (!si.ok) {
+          end = true;
+        } else {
+          const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
+          const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
+          const int32_t slot = slot_base + r;
+          const SlotGrid g = G.sg[slot];
+          int32_t best = -1, best_o = 0;
+          float bchi = 0.f, by = 0.f, bz = 0.f;
+          if (g.ncell > 0) {
+            const int32_t cb0 = g.cbase;
+            const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+            const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+            const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+            const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+            for (int cz = z0c; cz <= z1c; ++cz) {
+              const int32_t e0 = cb0 + cz * g.ny;
+              const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
+              for (int32_t c = a0; c < a1; ++c) {
+                const GHit Cc = ldh(G.gh + c);
+                const float rr0 = (Cc.y - S.P[0]) - S.L[0];
+                const float rr1 = (Cc.z - S.P[1]) - S.L[1];
+                if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+                const float chi2 = chi2_of(si, rr0, rr1);
+                const int32_t co = Cc.idx;
+                if (best < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
+                  best = c;
+                  best_o = co;
+                  bchi = chi2;
+                  by = Cc.y;
+                  bz = Cc.z;
+                }
+              }
+            }
+          }
+          if (best >= 0 && bchi <= k.chi2_follow) {
+            if (!kf_update(S, by, bz, k, nullptr)) {
+              end = true;
+            } else {
+              V.hits[(int64_t)n * V.capT + t] = best;
+              ++n;
+#pragma unroll
+              for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+#pragma unroll
+              for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
+              keepx = x;
+              misses = 0;
+            }
+          } else if (++misses >= k.max_miss) {
+            end = true;
+          }
+          if (!end && ++r >= kRows) end = true;
+        }
+      }
+    }
+    if (end) {
+      V.nhits[t] = n;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = keepP[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = keepC[i];
+      V.state[(int64_t)20 * V.capT + t] = keepx;
+      if (n >= k.min_hits) {
+        const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+        for (int q = 0; q < n; ++q)
+          atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]], (unsigned long long)key);
+      }
+      active = false;
     }
   }
 }
 
 // ------------------------------------------------------------------ a5: selection
+// Owned-hit counts from one coalesced pass over the clusters: a cluster's weight is the
+// key of the tracklet that owns it, whose low 32 bits are 2^32-1 - id.
+__global__ void k_own_count(const uint64_t* hitw, int32_t* own, Bound lo_b, Bound hi_b, int32_t capT) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const uint64_t w = hitw[h];
+  if (w == 0ull) return;
+  const uint32_t t = 0xFFFFFFFFu - (uint32_t)w;
+  if (t < (uint32_t)capT) atomicAdd(&own[t], 1);
+}
+
 __global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* own, int32_t* accf,
                                Consts k) {
   const int32_t lo = lo_b.get();
@@ -664,11 +850,7 @@ __global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* 
   const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= hi) return;
   const int n = V.nhits[t];
-  int cnt = 0;
-  if (n >= k.min_hits) {
-    const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
-    for (int q = 0; q < n; ++q) cnt += V.hitw[V.hits[(int64_t)q * V.capT + t]] == key;
-  }
+  const int cnt = own[t];
   const bool a = n >= k.min_hits && cnt >= k.min_hits;
   own[t] = a ? cnt : 0;
   accf[t] = a ? 1 : 0;
@@ -1430,6 +1612,8 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
   hipLaunchKernelGGL(k_slot_geometry, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.slot_cnt,
                      L.zmin, L.zmax, L.sg, L.ncell, s0, s1, c->k, c->tune.cells_per_cluster);
   scan(c, L.ncell, L.cell_base, hb(s0), hb(s1), s1 - s0, j0 != 0);
+  hipLaunchKernelGGL(k_slot_cellbase, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.sg, L.cell_base,
+                     s0, s1);
   const int64_t cbound = (int64_t)std::ceil((double)nbound * c->tune.cells_per_cluster) + (s1 - s0) + 1;
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_cnt,
                      db(L.cell_base + s0), db(L.cell_base + s1), 0);
@@ -1505,6 +1689,11 @@ void launch_select(tpc_ctx* c, int j0, int j1) {
   Layout& L = c->L;
   const Bound lo = dbc(L.T_off + j0, L.capT), hi = dbc(L.T_off + j1, L.capT);
   const int64_t tb = tbound(c, j0, j1);
+  const int64_t nbound = c->job_off_h[j1] - c->job_off_h[j0];
+  const int32_t s0 = j0 * kSlotsPerJob, s1 = j1 * kSlotsPerJob;
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.own, lo, hi, 0);
+  hipLaunchKernelGGL(k_own_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, L.own,
+                     db(L.slot_off + s0), db(L.slot_off + s1), L.capT);
   hipLaunchKernelGGL(k_select_count, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
                      L.own, L.accf, c->k);
   // the scans run over [T_off[j0], min(T_off[j1], capT)); clamp via a copy of the bound

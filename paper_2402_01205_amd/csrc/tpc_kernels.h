@@ -51,7 +51,7 @@ __device__ __forceinline__ void sth(GHit* p, float y, float z, int32_t slot, int
 
 struct SlotGrid {
   float ylo, zlo, inv_by, inv_bz;
-  int32_t ny, nz, ncell, pad;
+  int32_t ny, nz, ncell, cbase;  // cbase: global index of the slot's first cell
 };
 
 constexpr int kScanThreads = 256;
