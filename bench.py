@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=64,
                     help="collisions in the serving pool; the workload states 512")
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--also", default="c2,c3",
+                    help="other workloads timed in the same launch configuration (comma list, '' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -154,6 +156,11 @@ def main():
     cs = g.make_config(args.config, seed, workers=args.workers)  # before any GPU use
     log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
         f"in {time.perf_counter() - t0:.1f}s")
+    others = {}
+    if not args.profile_only:
+        for name in [x for x in args.also.split(",") if x and x != args.config]:
+            others[name] = g.make_config(name, SEEDS[name], workers=args.workers)
+            log(f"generated {name}: {others[name].n} clusters")
 
     import torch
 
@@ -236,8 +243,29 @@ def main():
 
     probe = copy_probe(tr, torch, 1024, 5)
     log(f"copy probe: {probe:.0f} GB/s")
-    q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off)
+    q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off, cs.part_pt)
     log("quality: " + json.dumps(q))
+    also = {}
+    for name, ocs in others.items():
+        oev = DeviceClusters.from_set(ocs, dev)
+        otr = Tracker(0, mode=args.mode, tuning=tuning)
+        otr.run(oev)
+        otr.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            otr.run(oev)
+        e1.record()
+        torch.cuda.synchronize()
+        oms = e0.elapsed_time(e1) / args.steps
+        ot = otr.tracks()
+        oq = quality(ocs.label, ocs.job_off, ocs.sector, ot["off"], ot["hits"], ocs.part_off, ocs.part_pt)
+        also[name] = {"workload": WORKLOADS[name], "n_clusters": ocs.n, "ms_per_step": oms,
+                      "clusters_per_s": ocs.n / (oms / 1e3), "tracks": int(ot["n"]), "quality": oq}
+        log(f"{name}: {oms:.3f} ms/step, {ocs.n / (oms / 1e3):.3e} clusters/s, quality {oq}")
+        del otr, oev
     serving = None
     if args.serve_chunks > 0:
         del tr, ev                 # the serving run sizes its admission by free HBM
@@ -273,6 +301,7 @@ def main():
         "p50_chunk_latency_ms": serving["p50_ms"] if serving else None,
         "p99_chunk_latency_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
+        "other_workloads": also,
         "tuning": tune_report["best"] if tune_report else None,
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "tracks": int(tracks["n"]),

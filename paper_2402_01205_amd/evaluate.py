@@ -14,7 +14,10 @@ MIN_FINDABLE = 30
 PURITY = 0.9
 
 
-def quality(label, job_off, sector, trk_off, trk_hits, part_off=None):
+PT_BINS = (0.1, 0.2, 0.5, 1.0, 10.0001)
+
+
+def quality(label, job_off, sector, trk_off, trk_hits, part_off=None, part_pt=None):
     label = np.asarray(label)
     job_off = np.asarray(job_off, np.int64)
     n_jobs = len(job_off) - 1
@@ -59,5 +62,13 @@ def quality(label, job_off, sector, trk_off, trk_hits, part_off=None):
     nf = int(findable.sum())
     eff = float((found[findable] > 0).sum()) / nf if nf else float("nan")
     clones = int(np.maximum(found - 1, 0).sum())
-    return dict(n_tracks=K, n_findable=nf, efficiency=eff, fake_rate=(K - n_good) / K,
-                clone_rate=clones / K, hits_in_tracks=int(trk_off[-1]))
+    out = dict(n_tracks=K, n_findable=nf, efficiency=eff, fake_rate=(K - n_good) / K,
+               clone_rate=clones / K, hits_in_tracks=int(trk_off[-1]))
+    if part_pt is not None:
+        pt = np.asarray(part_pt)
+        eff_pt = {}
+        for lo, hi in zip(PT_BINS[:-1], PT_BINS[1:]):
+            m = findable & (pt >= lo) & (pt < hi)
+            eff_pt[f"{lo:g}-{min(hi, 10):g}"] = float((found[m] > 0).mean()) if m.any() else None
+        out["efficiency_vs_pt"] = eff_pt
+    return out
