@@ -66,6 +66,7 @@ typedef struct {
   float bz;                          /* solenoid field along +z, tesla                 */
   float merge_edge;                  /* distance to the sector edge of merge pieces, cm*/
   float chi2_merge;                  /* max 5-D chi2 of a merged pair                  */
+  float merge_dz;                    /* max |z| gap between the pieces' ends, cm        */
 } tpc_params;
 
 /* Tunable launch shapes.  Results are identical for every valid setting.     */
@@ -75,6 +76,8 @@ typedef struct {
   int32_t block_tracklets;  /* threads per workgroup of the tracklet kernel          */
   int32_t persistent_waves; /* resident waves per CU of persistent kernels (0 = off)  */
   int32_t use_graph;        /* capture the batched stage chain into a hipGraph        */
+  int32_t tracklet_order;   /* work order of the tracklet kernel: 0 = tracklet id,    */
+                            /* 1 = grid position of the start cluster                */
 } tpc_tuning;
 
 /* Cluster list [n] in caller order.  sector: 0..35 (0..17 side A, z >= 0);

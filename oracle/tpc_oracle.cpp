@@ -60,6 +60,7 @@ struct Params {
   float smax;                                                    // |sin phi| limit
   float bz;                                                      // field, tesla
   float merge_edge, chi2_merge;                                  // O10
+  float merge_dz;                                                // O10 z gate
 };
 
 // Pad-row plane positions (O1, reading A2): x_r = 85 + r * 160/151 cm, rounded once.
@@ -684,6 +685,7 @@ struct Oracle {
         const int32_t hb = B.hits.front();
         const float eb = kGeo.x[row[hb]] * kGeo.tan10 - std::fabs(y[hb]);
         if (!(eb <= p.merge_edge)) continue;
+        if (!(std::fabs(ta.P[1] - z[hb]) <= p.merge_dz)) continue;
         float P[5], L[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, C[15];
         std::memcpy(P, ta.P, sizeof(P));
         std::memcpy(C, ta.C, sizeof(C));

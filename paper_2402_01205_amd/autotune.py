@@ -19,6 +19,7 @@ import numpy as np
 from .tpc import DeviceClusters, Tracker, default_tuning
 
 SPACE = [
+    ("tracklet_order", [0, 1]),
     ("cells_per_cluster", [0.25, 0.5, 1.0, 2.0]),
     ("block_links", [64, 128, 256]),
     ("persistent_waves", [0, 16, 32]),

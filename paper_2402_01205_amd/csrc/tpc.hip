@@ -474,10 +474,12 @@ __global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit*
   const int32_t u = up[h];
   if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
   const int32_t t = fid[gh[h].idx];
-  const int32_t p = posg[h];
   if (t < capT) start[t] = h;
-  if (p < capT) order[p] = t < capT ? t : -1;
-  if (t >= capT || p >= capT) atomicOr(&counters[kCntStatus], kStatusCapacity);
+  else atomicOr(&counters[kCntStatus], kStatusCapacity);
+  if (order) {
+    const int32_t p = posg[h];
+    if (p < capT) order[p] = t < capT ? t : -1;
+  }
 }
 
 // ------------------------------------------------------------------ a4: tracklets
@@ -632,7 +634,7 @@ __global__ __launch_bounds__(256) void k_tracklets(GridView G, TrackletView V, c
   const int32_t hi = min(hi_b.get(), V.capT);
   const int32_t p = lo + (int32_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= hi) return;
-  const int32_t t = order[p];
+  const int32_t t = order ? order[p] : p;
   if (t >= 0 && t < V.capT) build_tracklet(G, V, t, k);
 }
 
@@ -677,7 +679,7 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
       if (!active) {
         const int32_t p = a + base + rank;
         if (p < b) {
-          const int32_t tt = order[p];
+          const int32_t tt = order ? order[p] : p;
           if (tt >= 0 && tt < V.capT) {
             // ---- start a tracklet (same initialisation as build_tracklet)
             t = tt;
@@ -996,6 +998,9 @@ __global__ __launch_bounds__(256) void k_fit_heads(GridView G, TrackletView V, F
 }
 
 // --- merge: candidate search.  Tracks are bucketed by (event, sector).
+// Merge buckets: (event, sector, z bin of the track's innermost cluster); bins are
+// merge_dz wide, clamped at the ends, so the candidates of A within merge_dz of its end
+// z lie in 2-3 consecutive bins of one bucket.
 struct MergeView {
   const int32_t* trk_event;   // [capK] event of each selected track
   int32_t* bucket_cnt;        // [n_events*36]
@@ -1009,12 +1014,20 @@ struct MergeView {
   int32_t* head_list;         // [capK]
   int32_t* n_heads;           // [1]
   int32_t n_events;
+  int32_t nz;                 // z bins per (event, sector)
+  float dz;
 };
 
-__global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const GHit* gh,
-                              const int32_t* job_event, int32_t* trk_event,
-                              int32_t* bucket_cnt, Bound lo_b, Bound hi_b, int32_t capK,
-                              int32_t n_events, int32_t* counters) {
+__device__ __forceinline__ int merge_zbin(float z, float dz, int nz) {
+  float b = floorf(z / dz) + (float)(nz / 2);
+  b = fminf(fmaxf(b, 0.f), (float)(nz - 1));
+  return (int)b;
+}
+
+__global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
+                              const int32_t* sel_hits, const GHit* gh, const int32_t* job_event,
+                              int32_t* trk_event, int32_t* bucket_cnt, Bound lo_b, Bound hi_b, int32_t capK,
+                              int32_t n_events, int32_t nz, float dz, int32_t* counters) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1029,18 +1042,21 @@ __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, con
     ev = job;
   }
   trk_event[kk] = ev;
-  atomicAdd(&bucket_cnt[ev * kSectors + sec], 1);
+  const float zb = gh[sel_hits[sel_off[kk]]].z;
+  atomicAdd(&bucket_cnt[(ev * kSectors + sec) * nz + merge_zbin(zb, dz, nz)], 1);
 }
 
-__global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const GHit* gh,
-                               MergeView M, Bound lo_b, Bound hi_b, int32_t capK) {
+__global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
+                               const int32_t* sel_hits, const GHit* gh, MergeView M, Bound lo_b,
+                               Bound hi_b, int32_t capK) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
   const int32_t sl = gh[start[sel_from[kk]]].slot;
   const int sec = (sl / kRows) % kSectors;
-  const int b = M.trk_event[kk] * kSectors + sec;
+  const float zb = gh[sel_hits[sel_off[kk]]].z;
+  const int b = (M.trk_event[kk] * kSectors + sec) * M.nz + merge_zbin(zb, M.dz, M.nz);
   M.bucket_trk[M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1)] = kk;
 }
 
@@ -1059,6 +1075,7 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   if (F.ndf[a] < 0) return;
   const int32_t ta = F.sel_from[a];
   const float ya = V.state[(int64_t)0 * V.capT + ta];
+  const float za = V.state[(int64_t)1 * V.capT + ta];
   const float xa = V.state[(int64_t)20 * V.capT + ta];
   const float edge = xa * k.tan10 - fabsf(ya);
   if (!(edge <= k.merge_edge)) return;
@@ -1066,14 +1083,16 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   const int seca = (sla / kRows) % kSectors;
   const int dir = ya > 0.f ? 1 : kHalf - 1;
   const int sb = (seca / kHalf) * kHalf + (seca % kHalf + dir) % kHalf;
-  const int bucket = M.trk_event[a] * kSectors + sb;
-  const int32_t b0 = M.bucket_off[bucket], b1 = M.bucket_off[bucket + 1];
+  const int bucket = (M.trk_event[a] * kSectors + sb) * M.nz;
+  const int32_t b0 = M.bucket_off[bucket + merge_zbin(za - k.merge_dz, M.dz, M.nz)];
+  const int32_t b1 = M.bucket_off[bucket + merge_zbin(za + k.merge_dz, M.dz, M.nz) + 1];
   for (int32_t q = b0; q < b1; ++q) {
     const int32_t b = M.bucket_trk[q];
     if (F.ndf[b] < 0) continue;
     const GHit Hb = ldh(G.gh + F.sel_hits[F.sel_off[b]]);
     const float eb = k.x[Hb.slot % kRows] * k.tan10 - fabsf(Hb.y);
     if (!(eb <= k.merge_edge)) continue;
+    if (!(fabsf(za - Hb.z) <= k.merge_dz)) continue;
     State S;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -1328,7 +1347,7 @@ struct Layout {
   int64_t N = 0;
   int32_t J = 0, S = 0;
   int64_t capCells = 0;
-  int32_t capT = 0, capK = 0, capH = 0, capE = 0;
+  int32_t capT = 0, capK = 0, capH = 0, capE = 0, nzb = 1;
   int64_t bsumN = 0;
   size_t bytes = 0;
   // arrays
@@ -1365,8 +1384,10 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   L.capT = (int32_t)std::min<int64_t>(N / 8 + 1024, N + 1024);
   L.capK = L.capT;
   L.capH = (int32_t)(N + 1);
-  L.capE = J * kSectors;
-  const int64_t big = std::max<int64_t>({N + 1, L.capCells + 1, (int64_t)L.S + 1, (int64_t)L.capT + 1});
+  L.nzb = std::max(1, std::min(2048, 4194304 / std::max(1, J * kSectors)));
+  L.capE = J * kSectors * L.nzb;
+  const int64_t big = std::max<int64_t>(
+      {N + 1, L.capCells + 1, (int64_t)L.S + 1, (int64_t)L.capT + 1, (int64_t)L.capE + 1});
   L.bsumN = big / kScanTile + 4;
   char* p = base;
   size_t t = 0;
@@ -1537,6 +1558,7 @@ void make_consts(const tpc_params& p, Consts& k) {
   k.prior1[0] = p.cy1; k.prior1[1] = p.cz1; k.prior1[2] = p.cs1; k.prior1[3] = p.ct1; k.prior1[4] = p.ck1;
   k.merge_edge = p.merge_edge;
   k.chi2_merge = p.chi2_merge;
+  k.merge_dz = p.merge_dz;
 }
 
 Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
@@ -1647,11 +1669,15 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
   scan(c, L.flag, L.fid, db(jo + j0), db(jo + j1), nbound, j0 != 0);
   hipLaunchKernelGGL(k_job_offsets, dim3(blocks_for(j1 - j0, 256)), dim3(256), 0, c->stream, L.fid, jo,
                      L.T_off, j0, j1, (int32_t)L.N);
-  hipLaunchKernelGGL(k_start_flags_grid, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.flagg, lo, hi);
-  scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
+  const bool grid_order = c->tune.tracklet_order == 1;
+  if (grid_order) {
+    hipLaunchKernelGGL(k_start_flags_grid, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
+                       L.flagg, lo, hi);
+    scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
+  }
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gh, L.fid, L.posg, L.start, L.order, L.capT, lo, hi, L.counters);
+                     L.gh, L.fid, grid_order ? L.posg : nullptr, L.start, grid_order ? L.order : nullptr,
+                     L.capT, lo, hi, L.counters);
   // tracklet hit weights of this range start at zero
   hipLaunchKernelGGL(k_fill_range_u64, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, lo,
                      hi);
@@ -1677,10 +1703,11 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
     const int blocks = std::max(kXcds, (waves * 64 / bt) / kXcds * kXcds);
     fill_i32(c, L.counters + kCntQueue, kXcds, 0);
     hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
-                       make_tv(c), L.order, lo, hi, c->k, L.counters + kCntQueue);
+                       make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
+                       L.counters + kCntQueue);
   } else {
     hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tb, bt)), dim3(bt), 0, c->stream,
-                       make_grid(c), make_tv(c), L.order, lo, hi, c->k);
+                       make_grid(c), make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k);
   }
   prof_end(c, pm);
 }
@@ -1729,6 +1756,7 @@ int tpc_params_default(tpc_params* p) {
   p->bz = 0.5f;
   p->merge_edge = 5.0f;
   p->chi2_merge = 50.0f;
+  p->merge_dz = 20.0f;
   return TPC_OK;
 }
 
@@ -1739,6 +1767,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->block_tracklets = 128;
   t->persistent_waves = 32;
   t->use_graph = 1;
+  t->tracklet_order = 0;
   return TPC_OK;
 }
 
@@ -1803,6 +1832,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (!c || !t || !(t->cells_per_cluster > 0.f) || t->cells_per_cluster > 8.f) return TPC_E_ARG;
   if (t->block_links % 64 || t->block_links <= 0 || t->block_links > 1024) return TPC_E_ARG;
   if (t->block_tracklets % 64 || t->block_tracklets <= 0 || t->block_tracklets > 256) return TPC_E_ARG;
+  if (t->tracklet_order != 0 && t->tracklet_order != 1) return TPC_E_ARG;
   c->tune = *t;
   c->laid_out = false;
   return TPC_OK;
@@ -1947,21 +1977,22 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   // ---- merge across adjacent sectors of one event
   const Bound klo = hb(0), khi = dbc(L.counters + kCntSelected, L.capK);
   const int nev = J;
-  fill_i32(c, L.bucket_cnt, (int64_t)nev * kSectors + 1, 0);
-  fill_i32(c, L.bucket_fill, (int64_t)nev * kSectors + 1, 0);
+  const int64_t nbk = (int64_t)nev * kSectors * L.nzb;
+  fill_i32(c, L.bucket_cnt, nbk + 1, 0);
+  fill_i32(c, L.bucket_fill, nbk + 1, 0);
   fill_i32(c, L.chain_next, L.capK, -1);
   fill_i32(c, L.chain_prev, L.capK, -1);
   fill_i32(c, (int32_t*)L.bestA, 2 * (int64_t)L.capK, -1);
   fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
   fill_i32(c, L.counters + kCntMergeCand, 1, 0);
   hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.gh, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi, L.capK, nev,
-                     L.counters);
-  scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb(nev * kSectors), (int64_t)nev * kSectors, false);
+                     L.sel_off, L.sel_hits, L.gh, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi,
+                     L.capK, nev, L.nzb, c->p.merge_dz, L.counters);
+  scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb((int32_t)nbk), nbk, false);
   MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bestA, L.bestB,
-              L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev};
+              L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev, L.nzb, c->p.merge_dz};
   hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.gh, M, klo, khi, L.capK);
+                     L.sel_off, L.sel_hits, L.gh, M, klo, khi, L.capK);
   hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
                      make_tv(c), make_fv(c, false), M, klo, khi, c->k);
   hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);

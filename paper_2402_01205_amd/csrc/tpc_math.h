@@ -31,7 +31,7 @@ struct Consts {
   float nwin, chi2_follow;
   int32_t max_miss, min_hits;
   float prior0[5], prior1[5];
-  float merge_edge, chi2_merge;
+  float merge_edge, chi2_merge, merge_dz;
 };
 
 // lower-triangle index of a symmetric 5x5 (i >= j)

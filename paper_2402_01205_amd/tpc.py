@@ -32,13 +32,13 @@ class tpc_params(C.Structure):
         "cy0", "cz0", "cs0", "ct0", "ck0", "cy1", "cz1", "cs1", "ct1", "ck1",
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
-        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge")]
+        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz")]
 
 
 class tpc_tuning(C.Structure):
     _fields_ = [("cells_per_cluster", C.c_float), ("block_links", C.c_int32),
                 ("block_tracklets", C.c_int32), ("persistent_waves", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("tracklet_order", C.c_int32)]
 
 
 class tpc_clusters(C.Structure):
