@@ -78,6 +78,8 @@ typedef struct {
   int32_t use_graph;        /* capture the batched stage chain into a hipGraph        */
   int32_t tracklet_order;   /* work order of the tracklet kernel: 0 = tracklet id,    */
                             /* 1 = grid position of the start cluster                */
+  int32_t persistent_refill;/* persistent tracklet kernel: 1 = a lane whose tracklet  */
+                            /* ended takes the next one, 0 = a wave takes 64 at once */
 } tpc_tuning;
 
 /* Cluster list [n] in caller order.  sector: 0..35 (0..17 side A, z >= 0);
@@ -132,7 +134,9 @@ int tpc_params_default(tpc_params* p);
 int tpc_tuning_default(tpc_tuning* t);
 
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t; NULL =
- * the null stream).  Copies *p (NULL = defaults).                              */
+ * the null stream).  Copies *p (NULL = defaults).  TPC_E_ARG if a field of *p is
+ * not finite or outside its domain (sigma_y, sigma_z, nwin > 0; 0 < smax < 1;
+ * min_hits >= 3; max_miss >= 1; merge_dz >= 0).                                */
 int tpc_ctx_create(tpc_ctx** ctx, int device, void* hip_stream, const tpc_params* p);
 void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_set_stream(tpc_ctx* ctx, void* hip_stream);

@@ -685,6 +685,9 @@ struct Oracle {
         const int32_t hb = B.hits.front();
         const float eb = kGeo.x[row[hb]] * kGeo.tan10 - std::fabs(y[hb]);
         if (!(eb <= p.merge_edge)) continue;
+        // B starts at the edge it shares with A's sector: its -y edge when A leaves
+        // through its +y edge, and the other way round
+        if (dir == 1 ? !(y[hb] < 0.f) : !(y[hb] >= 0.f)) continue;
         if (!(std::fabs(ta.P[1] - z[hb]) <= p.merge_dz)) continue;
         float P[5], L[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, C[15];
         std::memcpy(P, ta.P, sizeof(P));

@@ -2,8 +2,8 @@
 
 Tunes, by coordinate descent on a sample of the workload, the grid cell density
 (cells per cluster), the workgroup sizes of the neighbour and tracklet kernels
-and the number of resident waves of the persistent tracklet kernel (0 = plain
-grid launch).  Every candidate's tracks are compared with the reference
+the number of resident waves of the persistent tracklet kernel (0 = plain grid
+launch) and how it hands out work (lane refill or 64 tracklets per wave).  Every candidate's tracks are compared with the reference
 configuration's: tuning may change speed only, never the result.  Choices are
 cached per (device name, size class) in a JSON file.
 """
@@ -23,6 +23,7 @@ SPACE = [
     ("cells_per_cluster", [0.25, 0.5, 1.0, 2.0]),
     ("block_links", [64, 128, 256]),
     ("persistent_waves", [0, 16, 32]),
+    ("persistent_refill", [0, 1]),
     ("block_tracklets", [64, 128, 256]),
 ]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tpc_mi355x_autotune.json")

@@ -506,124 +506,161 @@ __device__ __forceinline__ void init_cov(State& S, const float* prior) {
 }
 
 // One lane per tracklet: Kalman filter along the chain (every chain cluster used),
-// then following on the rows above (minimum chi2 in a 3-sigma window).
-__device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t, const Consts& k) {
-  const int32_t h = V.start[t];
-  const int32_t dr = V.dn_raw[h];
-  const int32_t first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : h;
-  auto next = [&](int32_t c) -> int32_t { return (c == first && first != h) ? h : V.up[c]; };
-  const int32_t c1 = next(first), c2 = next(c1);
-  const GHit F0 = ldh(G.gh + first);
-  const GHit F2 = ldh(G.gh + c2);
-  const int32_t slot0 = F0.slot;
-  const int r0 = slot0 % kRows;
-  const int32_t slot_base = slot0 - r0;
-  const int rc2 = F2.slot % kRows;
+// then following on the rows above (minimum chi2 in a 3-sigma window).  The tracklet
+// runs as a step machine: a step propagates to the next plane (the next chain
+// cluster's row, or the next row when following), picks the cluster (the chain link,
+// or the window search) and updates.  Propagation and update are one code path for
+// both phases, so the lanes of a wave in different phases do not diverge there.
+struct TrkLane {
   State S;
-  const float y0 = F0.y, z0 = F0.z;
-  const float dx2 = k.x[rc2] - k.x[r0];
-  const float dy2 = F2.y - y0;
-  const float dz2 = F2.z - z0;
+  float keepP[5], keepC[15], keepx, x;
+  int32_t t, h, first, cur, slot_base;
+  int n, last_row, r, misses, phase;  // phase 1: chain, 2: following
+};
+
+__device__ __forceinline__ void trk_begin(const GridView& G, const TrackletView& V, TrkLane& T, int32_t t,
+                                          const Consts& k) {
+  T.t = t;
+  T.h = V.start[t];
+  const int32_t dr = V.dn_raw[T.h];
+  T.first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : T.h;
+  const int32_t c1 = (T.first != T.h) ? T.h : V.up[T.first];
+  const int32_t c2 = (c1 == T.first && T.first != T.h) ? T.h : V.up[c1];
+  const GHit F0 = ldh(G.gh + T.first);
+  const GHit F2 = ldh(G.gh + c2);
+  const int r0 = F0.slot % kRows;
+  T.slot_base = F0.slot - r0;
+  const float dx2 = k.x[F2.slot % kRows] - k.x[r0];
+  const float dy2 = F2.y - F0.y;
+  const float dz2 = F2.z - F0.z;
   const float den = sqrt_rn(dx2 * dx2 + dy2 * dy2);
-  S.P[0] = y0;
-  S.P[1] = z0;
-  S.P[2] = div_rn(dy2, den);
-  S.P[3] = div_rn(dz2, den);
-  S.P[4] = 0.f;
+  T.S.P[0] = F0.y;
+  T.S.P[1] = F0.z;
+  T.S.P[2] = div_rn(dy2, den);
+  T.S.P[3] = div_rn(dz2, den);
+  T.S.P[4] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
-  init_cov(S, k.prior0);
-  float x = k.x[r0];
-  float keepP[5], keepC[15], keepx = x;  // initial state until a cluster is accepted
+  for (int i = 0; i < 5; ++i) T.S.L[i] = 0.f;
+  init_cov(T.S, k.prior0);
+  T.x = k.x[r0];
+  T.keepx = T.x;  // the recorded state is the initial one until a cluster is accepted
 #pragma unroll
-  for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
+  for (int i = 0; i < 5; ++i) T.keepP[i] = T.S.P[i];
 #pragma unroll
-  for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-  int n = 0;
-  int last_row = r0;
-  bool alive = true;
-  for (int32_t c = first; c >= 0; c = next(c)) {
-    const GHit Hc = ldh(G.gh + c);
-    const int rc = Hc.slot % kRows;
-    const float xh = k.x[rc];
-    if (!propagate(S, x, xh, k)) { alive = false; break; }
-    x = xh;
-    if (!kf_update(S, Hc.y, Hc.z, k, nullptr)) { alive = false; break; }
-    V.hits[(int64_t)n * V.capT + t] = c;
-    ++n;
-    last_row = rc;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-    keepx = x;
+  for (int i = 0; i < 15; ++i) T.keepC[i] = T.S.C[i];
+  T.n = 0;
+  T.last_row = r0;
+  T.cur = T.first;
+  T.phase = 1;
+  T.r = 0;
+  T.misses = 0;
+}
+
+// One step; returns true when the tracklet has ended.
+__device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& V, TrkLane& T,
+                                         const Consts& k) {
+  const bool chain = T.phase == 1;
+  int row;
+  float cy = 0.f, cz = 0.f;
+  int32_t cand = -1;
+  if (chain) {
+    const GHit Hc = ldh(G.gh + T.cur);
+    row = Hc.slot % kRows;
+    cy = Hc.y;
+    cz = Hc.z;
+    cand = T.cur;
+  } else {
+    row = T.r;
   }
-  if (alive) {
-    int misses = 0;
-    for (int r = last_row + 1; r < kRows; ++r) {
-      const float xr = k.x[r];
-      if (!propagate(S, x, xr, k)) break;
-      x = xr;
-      const SInv si = s_inverse(S.C, k.vy, k.vz);
-      if (!si.ok) break;
-      const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
-      const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
-      const int32_t slot = slot_base + r;
-      const SlotGrid g = G.sg[slot];
-      int32_t best = -1, best_o = 0;
-      float bchi = 0.f, by = 0.f, bz = 0.f;
-      if (g.ncell > 0) {
-        const int32_t cb0 = g.cbase;
-        const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
-        const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
-        const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
-        const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
-        for (int cz = z0c; cz <= z1c; ++cz) {
-          const int32_t e0 = cb0 + cz * g.ny;
-          const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
-          for (int32_t c = a0; c < a1; ++c) {
-            const GHit Cc = ldh(G.gh + c);
-            const float rr0 = (Cc.y - S.P[0]) - S.L[0];
-            const float rr1 = (Cc.z - S.P[1]) - S.L[1];
-            if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
-            const float chi2 = chi2_of(si, rr0, rr1);
-            const int32_t co = Cc.idx;
-            if (best < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
-              best = c;
-              best_o = co;
-              bchi = chi2;
-              by = Cc.y;
-              bz = Cc.z;
-            }
+  const float xt = k.x[row];
+  if (!propagate(T.S, T.x, xt, k)) return true;
+  T.x = xt;
+  bool take = chain;
+  if (!chain) {
+    const SInv si = s_inverse(T.S.C, k.vy, k.vz);
+    if (!si.ok) return true;
+    const float wy = k.nwin * sqrt_rn(T.S.C[0] + k.vy);
+    const float wz = k.nwin * sqrt_rn(T.S.C[2] + k.vz);
+    const int32_t slot = T.slot_base + row;
+    const SlotGrid g = G.sg[slot];
+    int32_t best_o = 0;
+    float bchi = 0.f;
+    if (g.ncell > 0) {
+      const int32_t cb0 = g.cbase;
+      const int y0c = cell_of(T.S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+      const int y1c = cell_of(T.S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+      const int z0c = cell_of(T.S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+      const int z1c = cell_of(T.S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+      for (int zc = z0c; zc <= z1c; ++zc) {
+        const int32_t e0 = cb0 + zc * g.ny;
+        const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
+        for (int32_t c = a0; c < a1; ++c) {
+          const GHit Cc = ldh(G.gh + c);
+          const float rr0 = (Cc.y - T.S.P[0]) - T.S.L[0];
+          const float rr1 = (Cc.z - T.S.P[1]) - T.S.L[1];
+          if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+          const float chi2 = chi2_of(si, rr0, rr1);
+          const int32_t co = Cc.idx;
+          if (cand < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
+            cand = c;
+            best_o = co;
+            bchi = chi2;
+            cy = Cc.y;
+            cz = Cc.z;
           }
         }
       }
-      if (best >= 0 && bchi <= k.chi2_follow) {
-        if (!kf_update(S, by, bz, k, nullptr)) break;
-        V.hits[(int64_t)n * V.capT + t] = best;
-        ++n;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
-#pragma unroll
-        for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-        keepx = x;
-        misses = 0;
-      } else if (++misses >= k.max_miss) {
-        break;
-      }
     }
+    take = cand >= 0 && bchi <= k.chi2_follow;
   }
-  V.nhits[t] = n;
+  if (take) {
+    if (!kf_update(T.S, cy, cz, k, nullptr)) return true;
+    V.hits[(int64_t)T.n * V.capT + T.t] = cand;
+    ++T.n;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = keepP[i];
+    for (int i = 0; i < 5; ++i) T.keepP[i] = T.S.P[i];
 #pragma unroll
-  for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = keepC[i];
-  V.state[(int64_t)20 * V.capT + t] = keepx;
-  if (n >= k.min_hits) {
-    const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
-    for (int q = 0; q < n; ++q) atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]],
-                                          (unsigned long long)key);
+    for (int i = 0; i < 15; ++i) T.keepC[i] = T.S.C[i];
+    T.keepx = T.x;
+    if (chain) {
+      T.last_row = row;
+      T.cur = (T.cur == T.first && T.first != T.h) ? T.h : V.up[T.cur];
+      if (T.cur < 0) {
+        T.phase = 2;
+        T.r = T.last_row + 1;
+        T.misses = 0;
+        return T.r >= kRows;
+      }
+      return false;
+    }
+    T.misses = 0;
+  } else if (++T.misses >= k.max_miss) {
+    return true;
   }
+  return ++T.r >= kRows;
+}
+
+__device__ __forceinline__ void trk_finish(const TrackletView& V, const TrkLane& T, const Consts& k) {
+  const int32_t t = T.t;
+  V.nhits[t] = T.n;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = T.keepP[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = T.keepC[i];
+  V.state[(int64_t)20 * V.capT + t] = T.keepx;
+  if (T.n >= k.min_hits) {
+    const uint64_t key = ((uint64_t)T.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+    for (int q = 0; q < T.n; ++q)
+      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]], (unsigned long long)key);
+  }
+}
+
+__device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t, const Consts& k) {
+  TrkLane T;
+  trk_begin(G, V, T, t, k);
+  while (!trk_step(G, V, T, k)) {
+  }
+  trk_finish(V, T, k);
 }
 
 // Lanes take tracklets in the grid order of their start clusters (order[]), so the
@@ -654,17 +691,11 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
   const int32_t per = (nwork + kXcds - 1) / kXcds;
   const int lane = threadIdx.x & 63;
   const int x0 = blockIdx.x % kXcds;
-  int qi = 0;  // ranges tried so far (wave-uniform)
-  // lane state
+  int qi = 0;  // ranges exhausted so far (wave-uniform)
   bool active = false;
-  int phase = 0;  // 1 chain, 2 follow
-  int32_t t = 0, h = 0, first = 0, cur = -1, slot_base = 0;
-  int n = 0, last_row = 0, r = 0, misses = 0;
-  float x = 0.f, keepx = 0.f;
-  State S;
-  float keepP[5], keepC[15];
+  TrkLane T;
   for (;;) {
-    // ---- refill lanes without a tracklet
+    // refill the lanes without a tracklet: one atomicAdd per wave and range
     while (qi < kXcds) {
       const uint64_t need = __ballot(!active);
       if (need == 0) break;
@@ -681,153 +712,46 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
         if (p < b) {
           const int32_t tt = order ? order[p] : p;
           if (tt >= 0 && tt < V.capT) {
-            // ---- start a tracklet (same initialisation as build_tracklet)
-            t = tt;
-            h = V.start[t];
-            const int32_t dr = V.dn_raw[h];
-            first = (dr >= 0 && V.up_raw[dr] < 0) ? dr : h;
-            const int32_t c1 = (first != h) ? h : V.up[first];
-            const int32_t c2 = (c1 == first && first != h) ? h : V.up[c1];
-            const GHit F0 = ldh(G.gh + first);
-            const GHit F2 = ldh(G.gh + c2);
-            const int r0 = F0.slot % kRows;
-            slot_base = F0.slot - r0;
-            const float dx2 = k.x[F2.slot % kRows] - k.x[r0];
-            const float dy2 = F2.y - F0.y;
-            const float dz2 = F2.z - F0.z;
-            const float den = sqrt_rn(dx2 * dx2 + dy2 * dy2);
-            S.P[0] = F0.y;
-            S.P[1] = F0.z;
-            S.P[2] = div_rn(dy2, den);
-            S.P[3] = div_rn(dz2, den);
-            S.P[4] = 0.f;
-#pragma unroll
-            for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
-            init_cov(S, k.prior0);
-            x = k.x[r0];
-            keepx = x;
-#pragma unroll
-            for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
-#pragma unroll
-            for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-            n = 0;
-            last_row = r0;
-            cur = first;
-            phase = 1;
+            trk_begin(G, V, T, tt, k);
             active = true;
           }
         }
       }
-      // this range is exhausted for lanes beyond its end: move on
       if (base + cnt >= b - a) ++qi;
     }
     if (!__any(active)) break;
-    if (!active) continue;
-    // ---- one step of this lane's tracklet
-    bool end = false;
-    if (phase == 1) {
-      const GHit Hc = ldh(G.gh + cur);
-      const int rc = Hc.slot % kRows;
-      const float xh = k.x[rc];
-      if (!propagate(S, x, xh, k)) {
-        end = true;
-      } else {
-        x = xh;
-        if (!kf_update(S, Hc.y, Hc.z, k, nullptr)) {
-          end = true;
-        } else {
-          V.hits[(int64_t)n * V.capT + t] = cur;
-          ++n;
-          last_row = rc;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
-#pragma unroll
-          for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-          keepx = x;
-          cur = (cur == first && first != h) ? h : V.up[cur];
-          if (cur < 0) {
-            phase = 2;
-            r = last_row + 1;
-            misses = 0;
-            if (r >= kRows) end = true;
-          }
-        }
-      }
-    } else {
-      const float xr = k.x[r];
-      if (!propagate(S, x, xr, k)) {
-        end = true;
-      } else {
-        x = xr;
-        const SInv si = s_inverse(S.C, k.vy, k.vz);
-        if (!si.ok) {
-          end = true;
-        } else {
-          const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
-          const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
-          const int32_t slot = slot_base + r;
-          const SlotGrid g = G.sg[slot];
-          int32_t best = -1, best_o = 0;
-          float bchi = 0.f, by = 0.f, bz = 0.f;
-          if (g.ncell > 0) {
-            const int32_t cb0 = g.cbase;
-            const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
-            const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
-            const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
-            const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
-            for (int cz = z0c; cz <= z1c; ++cz) {
-              const int32_t e0 = cb0 + cz * g.ny;
-              const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
-              for (int32_t c = a0; c < a1; ++c) {
-                const GHit Cc = ldh(G.gh + c);
-                const float rr0 = (Cc.y - S.P[0]) - S.L[0];
-                const float rr1 = (Cc.z - S.P[1]) - S.L[1];
-                if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
-                const float chi2 = chi2_of(si, rr0, rr1);
-                const int32_t co = Cc.idx;
-                if (best < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
-                  best = c;
-                  best_o = co;
-                  bchi = chi2;
-                  by = Cc.y;
-                  bz = Cc.z;
-                }
-              }
-            }
-          }
-          if (best >= 0 && bchi <= k.chi2_follow) {
-            if (!kf_update(S, by, bz, k, nullptr)) {
-              end = true;
-            } else {
-              V.hits[(int64_t)n * V.capT + t] = best;
-              ++n;
-#pragma unroll
-              for (int i = 0; i < 5; ++i) keepP[i] = S.P[i];
-#pragma unroll
-              for (int i = 0; i < 15; ++i) keepC[i] = S.C[i];
-              keepx = x;
-              misses = 0;
-            }
-          } else if (++misses >= k.max_miss) {
-            end = true;
-          }
-          if (!end && ++r >= kRows) end = true;
-        }
-      }
-    }
-    if (end) {
-      V.nhits[t] = n;
-#pragma unroll
-      for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = keepP[i];
-#pragma unroll
-      for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = keepC[i];
-      V.state[(int64_t)20 * V.capT + t] = keepx;
-      if (n >= k.min_hits) {
-        const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
-        for (int q = 0; q < n; ++q)
-          atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]], (unsigned long long)key);
-      }
+    if (active && trk_step(G, V, T, k)) {
+      trk_finish(V, T, k);
       active = false;
+    }
+  }
+}
+
+// Persistent variant without refill: a wave takes 64 consecutive tracklets of its
+// XCD's range per ticket (one per lane), runs them to the end, then takes the next
+// 64; exhausted ranges are followed by the other XCDs' ranges.
+__global__ __launch_bounds__(256) void k_tracklets_chunked(GridView G, TrackletView V, const int32_t* order,
+                                                           Bound lo_b, Bound hi_b, Consts k, int32_t* ticket) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), V.capT);
+  const int32_t nwork = hi > lo ? hi - lo : 0;
+  const int32_t per = (nwork + kXcds - 1) / kXcds;
+  const int lane = threadIdx.x & 63;
+  const int x0 = blockIdx.x % kXcds;
+  for (int qi = 0; qi < kXcds; ++qi) {
+    const int xr = (x0 + qi) % kXcds;
+    const int32_t a = lo + xr * per;
+    const int32_t b = min(hi, a + per);
+    for (;;) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(&ticket[xr], 64);
+      base = __shfl(base, 0, 64);
+      if (a + base >= b) break;
+      const int32_t p = a + base + lane;
+      if (p < b) {
+        const int32_t tt = order ? order[p] : p;
+        if (tt >= 0 && tt < V.capT) build_tracklet(G, V, tt, k);
+      }
     }
   }
 }
@@ -1007,6 +931,7 @@ struct MergeView {
   int32_t* bucket_off;        // [n_events*36+1]
   int32_t* bucket_fill;       // [n_events*36]
   int32_t* bucket_trk;        // [capK]
+  float* bucket_z;            // [capK] z of the innermost cluster of each bucketed track
   uint64_t* bestA;            // [capK] packed (chi2 bits, id) best partner of A
   uint64_t* bestB;            // [capK]
   int32_t* chain_next;        // [capK]
@@ -1024,10 +949,22 @@ __device__ __forceinline__ int merge_zbin(float z, float dz, int nz) {
   return (int)b;
 }
 
+// Event of every selected track; tracks that can be an outer piece (fitted, innermost
+// cluster within merge_edge of a sector edge) are counted into the bucket of their
+// (event, sector, edge side, z bin).  Side 0: the -y edge (y < 0), side 1: the +y edge.
+__device__ __forceinline__ int merge_bkey(int ev, int sec, int side, float z, float dz, int nz) {
+  return ((ev * kSectors + sec) * 2 + side) * nz + merge_zbin(z, dz, nz);
+}
+__device__ __forceinline__ bool outer_piece(const GHit& Hb, const int32_t* ndf, int32_t kk, const Consts& k) {
+  const float eb = k.x[Hb.slot % kRows] * k.tan10 - fabsf(Hb.y);
+  return ndf[kk] >= 0 && eb <= k.merge_edge;
+}
+
 __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
                               const int32_t* sel_hits, const GHit* gh, const int32_t* job_event,
-                              int32_t* trk_event, int32_t* bucket_cnt, Bound lo_b, Bound hi_b, int32_t capK,
-                              int32_t n_events, int32_t nz, float dz, int32_t* counters) {
+                              const int32_t* ndf, int32_t* trk_event, int32_t* bucket_cnt, Bound lo_b,
+                              Bound hi_b, int32_t capK, int32_t n_events, int32_t nz, Consts k,
+                              int32_t* counters) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1042,22 +979,26 @@ __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, con
     ev = job;
   }
   trk_event[kk] = ev;
-  const float zb = gh[sel_hits[sel_off[kk]]].z;
-  atomicAdd(&bucket_cnt[(ev * kSectors + sec) * nz + merge_zbin(zb, dz, nz)], 1);
+  const GHit Hb = ldh(gh + sel_hits[sel_off[kk]]);
+  if (outer_piece(Hb, ndf, kk, k))
+    atomicAdd(&bucket_cnt[merge_bkey(ev, sec, Hb.y < 0.f ? 0 : 1, Hb.z, k.merge_dz, nz)], 1);
 }
 
 __global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
-                               const int32_t* sel_hits, const GHit* gh, MergeView M, Bound lo_b,
-                               Bound hi_b, int32_t capK) {
+                               const int32_t* sel_hits, const GHit* gh, const int32_t* ndf, MergeView M,
+                               Bound lo_b, Bound hi_b, int32_t capK, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
   const int32_t sl = gh[start[sel_from[kk]]].slot;
   const int sec = (sl / kRows) % kSectors;
-  const float zb = gh[sel_hits[sel_off[kk]]].z;
-  const int b = (M.trk_event[kk] * kSectors + sec) * M.nz + merge_zbin(zb, M.dz, M.nz);
-  M.bucket_trk[M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1)] = kk;
+  const GHit Hb = ldh(gh + sel_hits[sel_off[kk]]);
+  if (!outer_piece(Hb, ndf, kk, k)) return;
+  const int b = merge_bkey(M.trk_event[kk], sec, Hb.y < 0.f ? 0 : 1, Hb.z, k.merge_dz, M.nz);
+  const int32_t q = M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1);
+  M.bucket_trk[q] = kk;
+  M.bucket_z[q] = Hb.z;
 }
 
 // packed (chi2, id): chi2 >= 0 so its bits order like the value; smaller wins.
@@ -1083,16 +1024,17 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   const int seca = (sla / kRows) % kSectors;
   const int dir = ya > 0.f ? 1 : kHalf - 1;
   const int sb = (seca / kHalf) * kHalf + (seca % kHalf + dir) % kHalf;
-  const int bucket = (M.trk_event[a] * kSectors + sb) * M.nz;
-  const int32_t b0 = M.bucket_off[bucket + merge_zbin(za - k.merge_dz, M.dz, M.nz)];
-  const int32_t b1 = M.bucket_off[bucket + merge_zbin(za + k.merge_dz, M.dz, M.nz) + 1];
+  // outer pieces start at the edge shared with A's sector: their -y edge if A leaves
+  // through its +y edge (side 0), else their +y edge (side 1)
+  // (the bin range is padded by 1 cm so that rounding of za -/+ merge_dz never drops a
+  // track the exact gate below accepts)
+  const int side = dir == 1 ? 0 : 1;
+  const float zlo = za - k.merge_dz - 1.f, zhi = za + k.merge_dz + 1.f;
+  const int32_t b0 = M.bucket_off[merge_bkey(M.trk_event[a], sb, side, zlo, k.merge_dz, M.nz)];
+  const int32_t b1 = M.bucket_off[merge_bkey(M.trk_event[a], sb, side, zhi, k.merge_dz, M.nz) + 1];
   for (int32_t q = b0; q < b1; ++q) {
+    if (!(fabsf(za - M.bucket_z[q]) <= k.merge_dz)) continue;
     const int32_t b = M.bucket_trk[q];
-    if (F.ndf[b] < 0) continue;
-    const GHit Hb = ldh(G.gh + F.sel_hits[F.sel_off[b]]);
-    const float eb = k.x[Hb.slot % kRows] * k.tan10 - fabsf(Hb.y);
-    if (!(eb <= k.merge_edge)) continue;
-    if (!(fabsf(za - Hb.z) <= k.merge_dz)) continue;
     State S;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -1364,6 +1306,7 @@ struct Layout {
   int32_t* fitndf;
   int32_t *T_off, *K_off, *counters, *bsum;
   // merge
+  float* bucket_z;
   int32_t *trk_event, *bucket_cnt, *bucket_off, *bucket_fill, *bucket_trk, *chain_next, *chain_prev,
       *head_list, *keep, *outn, *oid, *ooff;
   uint64_t *bestA, *bestB;
@@ -1385,7 +1328,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   L.capK = L.capT;
   L.capH = (int32_t)(N + 1);
   L.nzb = std::max(1, std::min(2048, 4194304 / std::max(1, J * kSectors)));
-  L.capE = J * kSectors * L.nzb;
+  L.capE = J * kSectors * 2 * L.nzb;
   const int64_t big = std::max<int64_t>(
       {N + 1, L.capCells + 1, (int64_t)L.S + 1, (int64_t)L.capT + 1, (int64_t)L.capE + 1});
   L.bsumN = big / kScanTile + 4;
@@ -1439,6 +1382,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.bucket_off, L.capE + 1, t, set);
   carve(p, L.bucket_fill, L.capE + 1, t, set);
   carve(p, L.bucket_trk, L.capK, t, set);
+  carve(p, L.bucket_z, L.capK, t, set);
   carve(p, L.chain_next, L.capK, t, set);
   carve(p, L.chain_prev, L.capK, t, set);
   carve(p, L.head_list, L.capK, t, set);
@@ -1702,9 +1646,14 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
     const int waves = ncu * c->tune.persistent_waves;
     const int blocks = std::max(kXcds, (waves * 64 / bt) / kXcds * kXcds);
     fill_i32(c, L.counters + kCntQueue, kXcds, 0);
-    hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
-                       make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
-                       L.counters + kCntQueue);
+    if (c->tune.persistent_refill)
+      hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
+                         make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
+                         L.counters + kCntQueue);
+    else
+      hipLaunchKernelGGL(k_tracklets_chunked, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
+                         make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
+                         L.counters + kCntQueue);
   } else {
     hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tb, bt)), dim3(bt), 0, c->stream,
                        make_grid(c), make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k);
@@ -1768,11 +1717,23 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->persistent_waves = 32;
   t->use_graph = 1;
   t->tracklet_order = 0;
+  t->persistent_refill = 1;
   return TPC_OK;
+}
+
+static bool params_ok(const tpc_params& p) {
+  const float f[] = {p.win_dy_slope, p.win_dy_const, p.win_dz_slope, p.win_dz_const, p.link_cut, p.cy0,
+                     p.cz0, p.cs0, p.ct0, p.ck0, p.cy1, p.cz1, p.cs1, p.ct1, p.ck1, p.sigma_y, p.sigma_z,
+                     p.nwin, p.chi2_follow, p.smax, p.bz, p.merge_edge, p.chi2_merge, p.merge_dz};
+  for (float v : f)
+    if (!std::isfinite(v)) return false;
+  return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
+         p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f;
 }
 
 int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p) {
   if (!out) return TPC_E_ARG;
+  if (p && !params_ok(*p)) return TPC_E_ARG;
   tpc_ctx* c = new tpc_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -1833,6 +1794,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (t->block_links % 64 || t->block_links <= 0 || t->block_links > 1024) return TPC_E_ARG;
   if (t->block_tracklets % 64 || t->block_tracklets <= 0 || t->block_tracklets > 256) return TPC_E_ARG;
   if (t->tracklet_order != 0 && t->tracklet_order != 1) return TPC_E_ARG;
+  if (t->persistent_refill != 0 && t->persistent_refill != 1) return TPC_E_ARG;
   c->tune = *t;
   c->laid_out = false;
   return TPC_OK;
@@ -1977,7 +1939,7 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   // ---- merge across adjacent sectors of one event
   const Bound klo = hb(0), khi = dbc(L.counters + kCntSelected, L.capK);
   const int nev = J;
-  const int64_t nbk = (int64_t)nev * kSectors * L.nzb;
+  const int64_t nbk = (int64_t)nev * kSectors * 2 * L.nzb;
   fill_i32(c, L.bucket_cnt, nbk + 1, 0);
   fill_i32(c, L.bucket_fill, nbk + 1, 0);
   fill_i32(c, L.chain_next, L.capK, -1);
@@ -1986,13 +1948,14 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
   fill_i32(c, L.counters + kCntMergeCand, 1, 0);
   hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.sel_off, L.sel_hits, L.gh, c->jobs.job_event, L.trk_event, L.bucket_cnt, klo, khi,
-                     L.capK, nev, L.nzb, c->p.merge_dz, L.counters);
+                     L.sel_off, L.sel_hits, L.gh, c->jobs.job_event, L.fitndf, L.trk_event, L.bucket_cnt, klo,
+                     khi, L.capK, nev, L.nzb, c->k, L.counters);
   scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb((int32_t)nbk), nbk, false);
-  MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bestA, L.bestB,
-              L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev, L.nzb, c->p.merge_dz};
+  MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bucket_z, L.bestA,
+              L.bestB, L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev, L.nzb,
+              c->p.merge_dz};
   hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.sel_off, L.sel_hits, L.gh, M, klo, khi, L.capK);
+                     L.sel_off, L.sel_hits, L.gh, L.fitndf, M, klo, khi, L.capK, c->k);
   hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
                      make_tv(c), make_fv(c, false), M, klo, khi, c->k);
   hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);
@@ -2040,6 +2003,12 @@ int tpc_run(tpc_ctx* c, const tpc_clusters* cl, const tpc_jobs* jb, tpc_tracks* 
                                 (uintptr_t)out->chi2, (uintptr_t)out->ndf, (uintptr_t)out->sector,
                                 (uintptr_t)out->job, (uintptr_t)out->tracklet};
   for (int j = 0; j <= jb->n_jobs; ++j) key.push_back((uintptr_t)(uint32_t)jb->job_off_host[j]);
+  // ... and on the launch shapes
+  {
+    uint32_t w[sizeof(tpc_tuning) / 4];
+    std::memcpy(w, &c->tune, sizeof(w));
+    for (uint32_t v : w) key.push_back(v);
+  }
   if (!c->gexec || key != c->gkey) {
     if (c->gexec) {
       (void)hipGraphExecDestroy(c->gexec);

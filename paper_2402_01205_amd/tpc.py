@@ -38,7 +38,8 @@ class tpc_params(C.Structure):
 class tpc_tuning(C.Structure):
     _fields_ = [("cells_per_cluster", C.c_float), ("block_links", C.c_int32),
                 ("block_tracklets", C.c_int32), ("persistent_waves", C.c_int32),
-                ("use_graph", C.c_int32), ("tracklet_order", C.c_int32)]
+                ("use_graph", C.c_int32), ("tracklet_order", C.c_int32),
+                ("persistent_refill", C.c_int32)]
 
 
 class tpc_clusters(C.Structure):

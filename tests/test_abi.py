@@ -39,3 +39,19 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"import\s+oracle|from\s+oracle|libtpc_oracle|\borc_[a-z]", txt), f
+
+
+def test_context_rejects_parameters_outside_their_domain():
+    """Parameter validation runs on the host before any device call."""
+    from paper_2402_01205_amd import tpc
+    lib = tpc.lib()
+    bad = [("sigma_y", 0.0), ("sigma_z", -1.0), ("nwin", 0.0), ("smax", 1.0), ("smax", 0.0),
+           ("min_hits", 2), ("max_miss", 0), ("merge_dz", -0.5), ("link_cut", float("nan")),
+           ("bz", float("inf")), ("chi2_merge", float("-inf"))]
+    for name, v in bad:
+        p = tpc.default_params()
+        setattr(p, name, v)
+        ctx = ctypes.c_void_p()
+        assert lib.tpc_ctx_create(ctypes.byref(ctx), 0, None, ctypes.byref(p)) == tpc.TPC_E_ARG, name
+        assert not ctx.value
+    assert lib.tpc_ctx_create(None, 0, None, None) == tpc.TPC_E_ARG

@@ -104,12 +104,14 @@ def test_sector_jobs_of_one_event_merge_across_jobs():
     assert s["merged"] > 50
 
 
-@pytest.mark.parametrize("mode", ["plain", "persistent"])
-def test_launch_modes_identical(mode):
+@pytest.mark.parametrize("mode,refill,order", [("plain", 1, 0), ("persistent", 1, 0), ("persistent", 0, 0),
+                                               ("persistent", 1, 1), ("persistent", 0, 1), ("batched", 1, 1)])
+def test_launch_modes_identical(mode, refill, order):
+    from paper_2402_01205_amd.tpc import default_tuning
     sizes = g.c4_job_sizes(41)
     cs = g.make_config("c4", 41, jobs=[3, 100, 200, int(np.argmax(sizes))])
     a = gpu_run(cs, mode="batched")
-    b = gpu_run(cs, mode=mode)
+    b = gpu_run(cs, mode=mode, tuning=default_tuning(persistent_refill=refill, tracklet_order=order))
     for k in ("up", "down"):
         assert np.array_equal(a[k], b[k])
     for k in ("off", "hits", "tracklet", "ndf"):
