@@ -1032,19 +1032,23 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   const float zlo = za - k.merge_dz - 1.f, zhi = za + k.merge_dz + 1.f;
   const int32_t b0 = M.bucket_off[merge_bkey(M.trk_event[a], sb, side, zlo, k.merge_dz, M.nz)];
   const int32_t b1 = M.bucket_off[merge_bkey(M.trk_event[a], sb, side, zhi, k.merge_dz, M.nz) + 1];
+  if (b0 >= b1) return;
+  // A's end state in B's frame: the same for every candidate
+  State R;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    R.P[i] = V.state[(int64_t)i * V.capT + ta];
+    R.L[i] = 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < 15; ++i) R.C[i] = V.state[(int64_t)(5 + i) * V.capT + ta];
+  float xr = xa;
+  if (!rotate(R, xr, seca, sb, k)) return;
   for (int32_t q = b0; q < b1; ++q) {
     if (!(fabsf(za - M.bucket_z[q]) <= k.merge_dz)) continue;
     const int32_t b = M.bucket_trk[q];
-    State S;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      S.P[i] = V.state[(int64_t)i * V.capT + ta];
-      S.L[i] = 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 15; ++i) S.C[i] = V.state[(int64_t)(5 + i) * V.capT + ta];
-    float x = xa;
-    if (!rotate(S, x, seca, sb, k)) continue;
+    State S = R;
+    float x = xr;
     if (!propagate(S, x, F.x[b], k)) continue;
     float PB[5], CB[15];
 #pragma unroll
@@ -1711,13 +1715,13 @@ int tpc_params_default(tpc_params* p) {
 
 int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_E_ARG;
-  t->cells_per_cluster = 0.5f;
+  t->cells_per_cluster = 2.0f;
   t->block_links = 256;
   t->block_tracklets = 128;
-  t->persistent_waves = 32;
+  t->persistent_waves = 16;
   t->use_graph = 1;
-  t->tracklet_order = 0;
-  t->persistent_refill = 1;
+  t->tracklet_order = 1;
+  t->persistent_refill = 0;
   return TPC_OK;
 }
 
