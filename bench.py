@@ -47,6 +47,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_2402_01205_amd/csrc/tpc.hip", "paper_2402_01205_amd/csrc/tpc_math.h",
+                  "paper_2402_01205_amd/csrc/tpc_kernels.h")
+
+
+def source_digest() -> str:
+    """sha256 over the kernel sources: a traffic record holds only for the code it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summaries under profiles/
+    (a line `<!-- traffic-record {json} -->`), or None when there is none for the current
+    kernel sources."""
+    import glob
+    import re
+    digest = source_digest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for m in re.finditer(r"<!-- traffic-record (\{.*?\}) -->", open(f).read()):
+            rec = json.loads(m.group(1))
+            if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("sources") == digest:
+                rec["file"] = os.path.relpath(f, ROOT)
+                return rec
+    return None
+
+
 def cpu_baseline(cs, cfg, budget_s):
     """The oracle (single thread, as it stands) on a bounded sample of the same workload."""
     import oracle.oracle as O
@@ -203,7 +233,8 @@ def main():
     tr.sync()
     log(f"batched ({args.mode}{'' if args.no_graph else ' + graph'}): {ms:.2f} ms/step")
     if args.profile_only:
-        print(json.dumps({"ms_per_step": ms}), flush=True)
+        print(json.dumps({"ms_per_step": ms, "sources": source_digest(),
+                          "tuning": {k: getattr(tuning, k) for k, _ in tuning._fields_}}), flush=True)
         return
     tracks = tr.tracks()
 
@@ -225,6 +256,10 @@ def main():
         "k_tracklets": dict(ms=kt_ms, bytes=trk_bytes, gbs=trk_bytes / kt_ms / 1e6),
     }
     dom = max(kern, key=lambda k: kern[k]["ms"])
+    trec = traffic_record(dom, args.config)
+    traffic = None
+    if trec and trec.get("read_bytes") is not None and trec.get("write_bytes") is not None:
+        traffic = trec["read_bytes"] + trec["write_bytes"]
     log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items()))
     log("kernels: " + json.dumps(kern))
 
@@ -293,8 +328,9 @@ def main():
         "plain_ms_per_step": plain_ms,
         "batched_over_plain": (plain_ms / ms) if plain_ms else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel_ms": kern[dom]["ms"], "algorithmic_bytes": kern[dom]["bytes"]},
+                     "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel_ms": kern[dom]["ms"], "algorithmic_bytes": kern[dom]["bytes"],
+                     "traffic_source": trec["file"] if trec else None},
         "kernels": {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS}
                     for k, v in kern.items()},
         "copy_probe_GBs": probe,

@@ -323,7 +323,7 @@ __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey,
 }
 
 __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
-                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh) {
+                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh, float2* gyz) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
@@ -331,7 +331,9 @@ __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, co
   if (slot < 0) return;
   const int32_t gc = ccell[i];
   const int32_t pos = cell_off[gc] + atomicAdd(&cell_fill[gc], 1);
-  sth(gh + pos, in.y[i], in.z[i], slot, i);
+  const float y = in.y[i], z = in.z[i];
+  sth(gh + pos, y, z, slot, i);
+  gyz[pos] = make_float2(y, z);
 }
 
 // ------------------------------------------------------------------ a2: neighbours
@@ -340,20 +342,15 @@ struct GridView {
   const SlotGrid* sg;
   const int32_t* cell_base;
   const int32_t* cell_off;
+  const float2* yz;  // positions alone, grid order (8 bytes per cluster)
 };
 
 // For each cluster h (grid order): over delta = 1, then 2, the pair (d on row r-delta,
 // u on row r+delta) with the smallest second difference inside the windows; ties go to
-// the smaller input index of u, then of d.  Links are stored in grid order.
-__global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_b, int32_t* up_raw,
-                                               int32_t* dn_raw, Consts k) {
-  const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t h = lo + (int32_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (h >= hi) return;
-  const GHit Hh = ldh(G.gh + h);
-  const int32_t slot = Hh.slot;
+// the smaller input index of u, then of d.
+__device__ __forceinline__ void link_search(const GridView& G, int32_t slot, float yh, float zh,
+                                            const Consts& k, int32_t& bu_out, int32_t& bd_out) {
   const int r = slot % kRows;
-  const float yh = Hh.y, zh = Hh.z;
   const float y2 = yh + yh, z2 = zh + zh;
   const float m = 0.01f;
   int32_t bu = -1, bd = -1, bu_o = 0, bd_o = 0;
@@ -416,11 +413,26 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
             }
           }
         }
-        if (bu >= 0) rad = fminf(k.link_cut, sqrt_rn(best) * 1.0001f);
+        // (the radius only prunes, so the hardware square root, within a few ulp, does;
+        // the 1e-4 margin keeps it above sqrt(best))
+        if (bu >= 0) rad = fminf(k.link_cut, __builtin_amdgcn_sqrtf(best) * 1.0001f);
       }
     }
     if (bu >= 0) break;
   }
+  bu_out = bu;
+  bd_out = bd;
+}
+
+// One lane per cluster.  Links are stored in grid order.
+__global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_b, int32_t* up_raw,
+                                               int32_t* dn_raw, Consts k) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t h = lo + (int32_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (h >= hi) return;
+  const GHit Hh = ldh(G.gh + h);
+  int32_t bu, bd;
+  link_search(G, Hh.slot, Hh.y, Hh.z, k, bu, bd);
   up_raw[h] = bu;
   dn_raw[h] = bd;
 }
@@ -488,7 +500,7 @@ struct TrackletView {
   const int32_t* up_raw;
   const int32_t* dn_raw;
   const int32_t* up;
-  int32_t* hits;      // [kRows][capT]
+  int32_t* hits;      // [capT][kRows]: the hits of a tracklet are contiguous
   int32_t* nhits;     // [capT]
   float* state;       // [21][capT]
   uint64_t* hitw;     // [N] grid order
@@ -511,12 +523,28 @@ __device__ __forceinline__ void init_cov(State& S, const float* prior) {
 // cluster's row, or the next row when following), picks the cluster (the chain link,
 // or the window search) and updates.  Propagation and update are one code path for
 // both phases, so the lanes of a wave in different phases do not diverge there.
+// The state recorded at the last accepted cluster (5 parameters, 15 covariance terms,
+// x) is kept in LDS, 21 consecutive words per lane of a [blockDim][21] array of dynamic
+// LDS (21 is odd, so the lanes of a wave hit distinct banks), which frees 21 registers
+// per lane.
+constexpr int kKeepWords = 21;
+typedef __attribute__((address_space(3))) float lds_f32;
+
 struct TrkLane {
   State S;
-  float keepP[5], keepC[15], keepx, x;
+  float x;
+  lds_f32* keep;  // this lane's 21 words of the [blockDim][21] LDS array
   int32_t t, h, first, cur, slot_base;
   int n, last_row, r, misses, phase;  // phase 1: chain, 2: following
 };
+
+__device__ __forceinline__ void keep_state(TrkLane& T) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) T.keep[i] = T.S.P[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) T.keep[5 + i] = T.S.C[i];
+  T.keep[20] = T.x;
+}
 
 __device__ __forceinline__ void trk_begin(const GridView& G, const TrackletView& V, TrkLane& T, int32_t t,
                                           const Consts& k) {
@@ -543,11 +571,7 @@ __device__ __forceinline__ void trk_begin(const GridView& G, const TrackletView&
   for (int i = 0; i < 5; ++i) T.S.L[i] = 0.f;
   init_cov(T.S, k.prior0);
   T.x = k.x[r0];
-  T.keepx = T.x;  // the recorded state is the initial one until a cluster is accepted
-#pragma unroll
-  for (int i = 0; i < 5; ++i) T.keepP[i] = T.S.P[i];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) T.keepC[i] = T.S.C[i];
+  keep_state(T);  // the recorded state is the initial one until a cluster is accepted
   T.n = 0;
   T.last_row = r0;
   T.cur = T.first;
@@ -583,7 +607,6 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
     const float wz = k.nwin * sqrt_rn(T.S.C[2] + k.vz);
     const int32_t slot = T.slot_base + row;
     const SlotGrid g = G.sg[slot];
-    int32_t best_o = 0;
     float bchi = 0.f;
     if (g.ncell > 0) {
       const int32_t cb0 = g.cbase;
@@ -595,18 +618,17 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
         const int32_t e0 = cb0 + zc * g.ny;
         const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
         for (int32_t c = a0; c < a1; ++c) {
-          const GHit Cc = ldh(G.gh + c);
-          const float rr0 = (Cc.y - T.S.P[0]) - T.S.L[0];
-          const float rr1 = (Cc.z - T.S.P[1]) - T.S.L[1];
+          const float2 Cc = G.yz[c];
+          const float rr0 = (Cc.x - T.S.P[0]) - T.S.L[0];
+          const float rr1 = (Cc.y - T.S.P[1]) - T.S.L[1];
           if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
           const float chi2 = chi2_of(si, rr0, rr1);
-          const int32_t co = Cc.idx;
-          if (cand < 0 || chi2 < bchi || (chi2 == bchi && co < best_o)) {
+          // equal chi2: the smaller input index wins (read only for such ties)
+          if (cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx)) {
             cand = c;
-            best_o = co;
             bchi = chi2;
-            cy = Cc.y;
-            cz = Cc.z;
+            cy = Cc.x;
+            cz = Cc.y;
           }
         }
       }
@@ -615,13 +637,9 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
   }
   if (take) {
     if (!kf_update(T.S, cy, cz, k, nullptr)) return true;
-    V.hits[(int64_t)T.n * V.capT + T.t] = cand;
+    V.hits[(int64_t)T.t * kRows + T.n] = cand;
     ++T.n;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) T.keepP[i] = T.S.P[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) T.keepC[i] = T.S.C[i];
-    T.keepx = T.x;
+    keep_state(T);
     if (chain) {
       T.last_row = row;
       T.cur = (T.cur == T.first && T.first != T.h) ? T.h : V.up[T.cur];
@@ -644,19 +662,21 @@ __device__ __forceinline__ void trk_finish(const TrackletView& V, const TrkLane&
   const int32_t t = T.t;
   V.nhits[t] = T.n;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) V.state[(int64_t)i * V.capT + t] = T.keepP[i];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) V.state[(int64_t)(5 + i) * V.capT + t] = T.keepC[i];
-  V.state[(int64_t)20 * V.capT + t] = T.keepx;
+  for (int i = 0; i < 21; ++i) V.state[(int64_t)i * V.capT + t] = T.keep[i];
   if (T.n >= k.min_hits) {
     const uint64_t key = ((uint64_t)T.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
     for (int q = 0; q < T.n; ++q)
-      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)q * V.capT + t]], (unsigned long long)key);
+      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)t * kRows + q]], (unsigned long long)key);
   }
 }
 
-__device__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t, const Consts& k) {
+extern __shared__ float trk_keep[];
+__device__ __forceinline__ lds_f32* keep_column() { return (lds_f32*)&trk_keep[threadIdx.x * kKeepWords]; }
+
+__device__ __forceinline__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t,
+                                               const Consts& k) {
   TrkLane T;
+  T.keep = keep_column();
   trk_begin(G, V, T, t, k);
   while (!trk_step(G, V, T, k)) {
   }
@@ -694,6 +714,7 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
   int qi = 0;  // ranges exhausted so far (wave-uniform)
   bool active = false;
   TrkLane T;
+  T.keep = keep_column();
   for (;;) {
     // refill the lanes without a tracklet: one atomicAdd per wave and range
     while (qi < kXcds) {
@@ -730,7 +751,8 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
 // Persistent variant without refill: a wave takes 64 consecutive tracklets of its
 // XCD's range per ticket (one per lane), runs them to the end, then takes the next
 // 64; exhausted ranges are followed by the other XCDs' ranges.
-__global__ __launch_bounds__(256) void k_tracklets_chunked(GridView G, TrackletView V, const int32_t* order,
+__global__ __launch_bounds__(256) void k_tracklets_chunked(
+    GridView G, TrackletView V, const int32_t* order,
                                                            Bound lo_b, Bound hi_b, Consts k, int32_t* ticket) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), V.capT);
@@ -738,21 +760,21 @@ __global__ __launch_bounds__(256) void k_tracklets_chunked(GridView G, TrackletV
   const int32_t per = (nwork + kXcds - 1) / kXcds;
   const int lane = threadIdx.x & 63;
   const int x0 = blockIdx.x % kXcds;
-  for (int qi = 0; qi < kXcds; ++qi) {
+  int qi = 0;
+  while (qi < kXcds) {
     const int xr = (x0 + qi) % kXcds;
     const int32_t a = lo + xr * per;
     const int32_t b = min(hi, a + per);
-    for (;;) {
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(&ticket[xr], 64);
-      base = __shfl(base, 0, 64);
-      if (a + base >= b) break;
-      const int32_t p = a + base + lane;
-      if (p < b) {
-        const int32_t tt = order ? order[p] : p;
-        if (tt >= 0 && tt < V.capT) build_tracklet(G, V, tt, k);
-      }
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&ticket[xr], 64);
+    base = __shfl(base, 0, 64);
+    if (a + base >= b) {
+      ++qi;
+      continue;
     }
+    const int32_t p = a + base + lane;
+    const int32_t tt = p < b ? (order ? order[p] : p) : -1;
+    if (tt >= 0 && tt < V.capT) build_tracklet(G, V, tt, k);
   }
 }
 
@@ -802,7 +824,7 @@ __global__ void k_select_write(TrackletView V, Bound lo_b, Bound hi_b, const int
   const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
   int w = 0;
   for (int q = 0; q < n; ++q) {
-    const int32_t c = V.hits[(int64_t)q * V.capT + t];
+    const int32_t c = V.hits[(int64_t)t * kRows + q];
     if (V.hitw[c] == key) {
       if (o + w < capH) sel_hits[o + w] = c;
       ++w;
@@ -1198,7 +1220,7 @@ __global__ void k_copy_tracklets(TrackletView V, const GHit* gh, const int32_t* 
   if (t >= T) return;
   start[t] = gh[V.start[t]].idx;
   const int n = V.nhits[t];
-  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gh[V.hits[(int64_t)q * V.capT + t]].idx;
+  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gh[V.hits[(int64_t)t * kRows + q]].idx;
   for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)i * V.capT + t];
 }
 
@@ -1301,6 +1323,7 @@ struct Layout {
   uint32_t *zmin, *zmax;
   SlotGrid* sg;
   GHit* gh;
+  float2* gyz;
   int32_t *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start, *flagg, *posg, *order;
   int32_t *trk_hits, *trk_n;
   float* trk_state;
@@ -1351,6 +1374,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.cell_off, L.capCells + 1, t, set);
   carve(p, L.cell_fill, L.capCells + 1, t, set);
   carve(p, L.gh, N, t, set);
+  carve(p, L.gyz, N, t, set);
   carve(p, L.up_raw, N, t, set);
   carve(p, L.dn_raw, N, t, set);
   carve(p, L.up, N, t, set);
@@ -1543,7 +1567,7 @@ In make_in(tpc_ctx* c) {
 }
 GridView make_grid(tpc_ctx* c) {
   Layout& L = c->L;
-  return GridView{L.gh, L.sg, L.cell_base, L.cell_off};
+  return GridView{L.gh, L.sg, L.cell_base, L.cell_off, L.gyz};
 }
 TrackletView make_tv(tpc_ctx* c) {
   Layout& L = c->L;
@@ -1593,7 +1617,7 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
                      db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.cell_cnt);
   scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh);
+                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh, L.gyz);
 }
 
 void launch_links(tpc_ctx* c, int j0, int j1) {
@@ -1643,6 +1667,7 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
   const int64_t tb = tbound(c, j0, j1);
   // tracklets that overflow the work list are never built: their lengths read as 0
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.trk_n, lo, hi, 0);
+  const size_t keep_bytes = (size_t)kKeepWords * bt * sizeof(float);
   const int pm = prof_begin(c, TPC_PROF_TRACKLETS);
   if (c->mode == TPC_MODE_PERSISTENT && c->tune.persistent_waves > 0) {
     int ncu = 256;
@@ -1651,15 +1676,15 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
     const int blocks = std::max(kXcds, (waves * 64 / bt) / kXcds * kXcds);
     fill_i32(c, L.counters + kCntQueue, kXcds, 0);
     if (c->tune.persistent_refill)
-      hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
+      hipLaunchKernelGGL(k_tracklets_persistent, dim3(blocks), dim3(bt), keep_bytes, c->stream, make_grid(c),
                          make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
                          L.counters + kCntQueue);
     else
-      hipLaunchKernelGGL(k_tracklets_chunked, dim3(blocks), dim3(bt), 0, c->stream, make_grid(c),
+      hipLaunchKernelGGL(k_tracklets_chunked, dim3(blocks), dim3(bt), keep_bytes, c->stream, make_grid(c),
                          make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k,
                          L.counters + kCntQueue);
   } else {
-    hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tb, bt)), dim3(bt), 0, c->stream,
+    hipLaunchKernelGGL(k_tracklets, dim3(blocks_for(tb, bt)), dim3(bt), keep_bytes, c->stream,
                        make_grid(c), make_tv(c), c->tune.tracklet_order ? L.order : nullptr, lo, hi, c->k);
   }
   prof_end(c, pm);
@@ -1717,7 +1742,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_E_ARG;
   t->cells_per_cluster = 2.0f;
   t->block_links = 256;
-  t->block_tracklets = 128;
+  t->block_tracklets = 64;
   t->persistent_waves = 16;
   t->use_graph = 1;
   t->tracklet_order = 1;

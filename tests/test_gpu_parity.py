@@ -104,14 +104,19 @@ def test_sector_jobs_of_one_event_merge_across_jobs():
     assert s["merged"] > 50
 
 
-@pytest.mark.parametrize("mode,refill,order", [("plain", 1, 0), ("persistent", 1, 0), ("persistent", 0, 0),
-                                               ("persistent", 1, 1), ("persistent", 0, 1), ("batched", 1, 1)])
-def test_launch_modes_identical(mode, refill, order):
+@pytest.mark.parametrize("mode,tune", [
+    ("plain", {}), ("batched", dict(tracklet_order=0)),
+    ("persistent", dict(persistent_refill=1, tracklet_order=0)),
+    ("persistent", dict(persistent_refill=0, tracklet_order=0)),
+    ("persistent", dict(persistent_refill=1, tracklet_order=1)),
+    ("persistent", dict(persistent_refill=0, tracklet_order=0, persistent_waves=32))])
+def test_launch_modes_identical(mode, tune):
+    """Every launch mode and tuning choice gives the default batched form's result."""
     from paper_2402_01205_amd.tpc import default_tuning
     sizes = g.c4_job_sizes(41)
     cs = g.make_config("c4", 41, jobs=[3, 100, 200, int(np.argmax(sizes))])
     a = gpu_run(cs, mode="batched")
-    b = gpu_run(cs, mode=mode, tuning=default_tuning(persistent_refill=refill, tracklet_order=order))
+    b = gpu_run(cs, mode=mode, tuning=default_tuning(**tune))
     for k in ("up", "down"):
         assert np.array_equal(a[k], b[k])
     for k in ("off", "hits", "tracklet", "ndf"):
@@ -119,7 +124,7 @@ def test_launch_modes_identical(mode, refill, order):
     assert np.array_equal(a["tracks"]["param"].view(np.uint32), b["tracks"]["param"].view(np.uint32))
 
 
-@pytest.mark.parametrize("cpc", [0.125, 1.0, 3.0])
+@pytest.mark.parametrize("cpc", [0.125, 1.0, 3.0, 8.0])
 def test_grid_cell_size_invariance(cpc):
     from paper_2402_01205_amd.tpc import default_tuning
     cs = g.make_config("c2", 21, scale=0.2)
