@@ -500,9 +500,9 @@ struct TrackletView {
   const int32_t* up_raw;
   const int32_t* dn_raw;
   const int32_t* up;
-  int32_t* hits;      // [capT][kRows]: the hits of a tracklet are contiguous
+  int32_t* hits;      // [capT][kHitStride]: the hits of a tracklet are contiguous
   int32_t* nhits;     // [capT]
-  float* state;       // [21][capT]
+  float* state;       // [capT][kStateStride]: P[5], C[15], x
   uint64_t* hitw;     // [N] grid order
   int32_t capT;
 };
@@ -523,20 +523,39 @@ __device__ __forceinline__ void init_cov(State& S, const float* prior) {
 // cluster's row, or the next row when following), picks the cluster (the chain link,
 // or the window search) and updates.  Propagation and update are one code path for
 // both phases, so the lanes of a wave in different phases do not diverge there.
-// The state recorded at the last accepted cluster (5 parameters, 15 covariance terms,
-// x) is kept in LDS, 21 consecutive words per lane of a [blockDim][21] array of dynamic
-// LDS (21 is odd, so the lanes of a wave hit distinct banks), which frees 21 registers
-// per lane.
+// Each lane has 37 words of dynamic LDS (37 is odd, so the lanes of a wave hit distinct
+// banks): the state recorded at the last accepted cluster (5 parameters, 15 covariance
+// terms, x), which frees 21 registers, and a ring of the last 16 accepted hits, written
+// to HBM as one full 64-byte line per 16 hits instead of one partial line per hit.
 constexpr int kKeepWords = 21;
+constexpr int kRingWords = 16;
+constexpr int kLaneWords = kKeepWords + kRingWords;
 typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
 
 struct TrkLane {
   State S;
   float x;
-  lds_f32* keep;  // this lane's 21 words of the [blockDim][21] LDS array
+  lds_f32* keep;  // this lane's recorded state (21 words of LDS)
+  lds_i32* ring;  // and its last kRingWords hits
   int32_t t, h, first, cur, slot_base;
   int n, last_row, r, misses, phase;  // phase 1: chain, 2: following
 };
+
+// Writes the first `cnt` ring words (the hits cnt..1 back from the n-th) to the
+// tracklet's hit list: whole 16-byte stores when a full ring is flushed.
+__device__ __forceinline__ void flush_ring(const TrackletView& V, const TrkLane& T, int cnt) {
+  if (cnt == 0) return;
+  const int base = (T.n - 1) & ~(kRingWords - 1);  // hit index of ring word 0
+  int32_t* dst = V.hits + (int64_t)T.t * kHitStride + base;
+  if (cnt == kRingWords) {
+#pragma unroll
+    for (int i = 0; i < kRingWords; i += 4)
+      *reinterpret_cast<int4*>(dst + i) = make_int4(T.ring[i], T.ring[i + 1], T.ring[i + 2], T.ring[i + 3]);
+  } else {
+    for (int i = 0; i < cnt; ++i) dst[i] = T.ring[i];
+  }
+}
 
 __device__ __forceinline__ void keep_state(TrkLane& T) {
 #pragma unroll
@@ -637,8 +656,9 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
   }
   if (take) {
     if (!kf_update(T.S, cy, cz, k, nullptr)) return true;
-    V.hits[(int64_t)T.t * kRows + T.n] = cand;
+    T.ring[T.n & (kRingWords - 1)] = cand;
     ++T.n;
+    if ((T.n & (kRingWords - 1)) == 0) flush_ring(V, T, kRingWords);
     keep_state(T);
     if (chain) {
       T.last_row = row;
@@ -661,22 +681,29 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
 __device__ __forceinline__ void trk_finish(const TrackletView& V, const TrkLane& T, const Consts& k) {
   const int32_t t = T.t;
   V.nhits[t] = T.n;
+  float* st = V.state + (int64_t)t * kStateStride;
 #pragma unroll
-  for (int i = 0; i < 21; ++i) V.state[(int64_t)i * V.capT + t] = T.keep[i];
+  for (int i = 0; i < 20; i += 4)
+    *reinterpret_cast<float4*>(st + i) = make_float4(T.keep[i], T.keep[i + 1], T.keep[i + 2], T.keep[i + 3]);
+  st[20] = T.keep[20];
+  flush_ring(V, T, T.n & (kRingWords - 1));
   if (T.n >= k.min_hits) {
     const uint64_t key = ((uint64_t)T.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
     for (int q = 0; q < T.n; ++q)
-      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)t * kRows + q]], (unsigned long long)key);
+      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)t * kHitStride + q]], (unsigned long long)key);
   }
 }
 
 extern __shared__ float trk_keep[];
-__device__ __forceinline__ lds_f32* keep_column() { return (lds_f32*)&trk_keep[threadIdx.x * kKeepWords]; }
+__device__ __forceinline__ void lane_lds(TrkLane& T) {
+  T.keep = (lds_f32*)&trk_keep[threadIdx.x * kLaneWords];
+  T.ring = (lds_i32*)&trk_keep[threadIdx.x * kLaneWords + kKeepWords];
+}
 
 __device__ __forceinline__ void build_tracklet(const GridView& G, const TrackletView& V, int32_t t,
                                                const Consts& k) {
   TrkLane T;
-  T.keep = keep_column();
+  lane_lds(T);
   trk_begin(G, V, T, t, k);
   while (!trk_step(G, V, T, k)) {
   }
@@ -714,7 +741,7 @@ __global__ __launch_bounds__(256) void k_tracklets_persistent(GridView G, Trackl
   int qi = 0;  // ranges exhausted so far (wave-uniform)
   bool active = false;
   TrkLane T;
-  T.keep = keep_column();
+  lane_lds(T);
   for (;;) {
     // refill the lanes without a tracklet: one atomicAdd per wave and range
     while (qi < kXcds) {
@@ -824,7 +851,7 @@ __global__ void k_select_write(TrackletView V, Bound lo_b, Bound hi_b, const int
   const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
   int w = 0;
   for (int q = 0; q < n; ++q) {
-    const int32_t c = V.hits[(int64_t)t * kRows + q];
+    const int32_t c = V.hits[(int64_t)t * kHitStride + q];
     if (V.hitw[c] == key) {
       if (o + w < capH) sel_hits[o + w] = c;
       ++w;
@@ -874,9 +901,9 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
   const GHit Ho = ldh(G.gh + ho);
   S.P[0] = Ho.y;
   S.P[1] = Ho.z;
-  S.P[2] = V.state[(int64_t)2 * V.capT + tl];
-  S.P[3] = V.state[(int64_t)3 * V.capT + tl];
-  S.P[4] = V.state[(int64_t)4 * V.capT + tl];
+  S.P[2] = V.state[(int64_t)tl * kStateStride + 2];
+  S.P[3] = V.state[(int64_t)tl * kStateStride + 3];
+  S.P[4] = V.state[(int64_t)tl * kStateStride + 4];
 #pragma unroll
   for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
   init_cov(S, k.prior1);
@@ -1037,9 +1064,9 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   if (a >= hi) return;
   if (F.ndf[a] < 0) return;
   const int32_t ta = F.sel_from[a];
-  const float ya = V.state[(int64_t)0 * V.capT + ta];
-  const float za = V.state[(int64_t)1 * V.capT + ta];
-  const float xa = V.state[(int64_t)20 * V.capT + ta];
+  const float ya = V.state[(int64_t)ta * kStateStride + 0];
+  const float za = V.state[(int64_t)ta * kStateStride + 1];
+  const float xa = V.state[(int64_t)ta * kStateStride + 20];
   const float edge = xa * k.tan10 - fabsf(ya);
   if (!(edge <= k.merge_edge)) return;
   const int32_t sla = G.gh[V.start[ta]].slot;
@@ -1059,11 +1086,11 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   State R;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    R.P[i] = V.state[(int64_t)i * V.capT + ta];
+    R.P[i] = V.state[(int64_t)ta * kStateStride + i];
     R.L[i] = 0.f;
   }
 #pragma unroll
-  for (int i = 0; i < 15; ++i) R.C[i] = V.state[(int64_t)(5 + i) * V.capT + ta];
+  for (int i = 0; i < 15; ++i) R.C[i] = V.state[(int64_t)ta * kStateStride + 5 + i];
   float xr = xa;
   if (!rotate(R, xr, seca, sb, k)) return;
   for (int32_t q = b0; q < b1; ++q) {
@@ -1220,8 +1247,8 @@ __global__ void k_copy_tracklets(TrackletView V, const GHit* gh, const int32_t* 
   if (t >= T) return;
   start[t] = gh[V.start[t]].idx;
   const int n = V.nhits[t];
-  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gh[V.hits[(int64_t)t * kRows + q]].idx;
-  for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)i * V.capT + t];
+  for (int q = 0; q < n; ++q) hits[toff[t] + q] = gh[V.hits[(int64_t)t * kHitStride + q]].idx;
+  for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)t * kStateStride + i];
 }
 
 __global__ void k_hitw_to_input(const uint64_t* w, const GHit* gh, uint64_t* out, Bound hi_b) {
@@ -1385,9 +1412,9 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.flagg, N + 1, t, set);
   carve(p, L.posg, N + 1, t, set);
   carve(p, L.order, L.capT, t, set);
-  carve(p, L.trk_hits, (int64_t)kRows * L.capT, t, set);
+  carve(p, L.trk_hits, (int64_t)kHitStride * L.capT, t, set);
   carve(p, L.trk_n, L.capT, t, set);
-  carve(p, L.trk_state, (int64_t)21 * L.capT, t, set);
+  carve(p, L.trk_state, (int64_t)kStateStride * L.capT, t, set);
   carve(p, L.hitw, N, t, set);
   carve(p, L.own, L.capT + 1, t, set);
   carve(p, L.accf, L.capT + 1, t, set);
@@ -1667,7 +1694,7 @@ void launch_tracklets(tpc_ctx* c, int j0, int j1) {
   const int64_t tb = tbound(c, j0, j1);
   // tracklets that overflow the work list are never built: their lengths read as 0
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.trk_n, lo, hi, 0);
-  const size_t keep_bytes = (size_t)kKeepWords * bt * sizeof(float);
+  const size_t keep_bytes = (size_t)kLaneWords * bt * sizeof(float);
   const int pm = prof_begin(c, TPC_PROF_TRACKLETS);
   if (c->mode == TPC_MODE_PERSISTENT && c->tune.persistent_waves > 0) {
     int ncu = 256;

@@ -49,6 +49,11 @@ __device__ __forceinline__ void sth(GHit* p, float y, float z, int32_t slot, int
   *reinterpret_cast<float4*>(p) = make_float4(y, z, __int_as_float(slot), __int_as_float(idx));
 }
 
+// Tracklet records: hit list rows of kHitStride ints (64-byte aligned, at least kRows),
+// state rows of kStateStride floats (P[5], C[15], x; 32-byte aligned).
+constexpr int kHitStride = 160;
+constexpr int kStateStride = 24;
+
 struct SlotGrid {
   float ylo, zlo, inv_by, inv_bz;
   int32_t ny, nz, ncell, cbase;  // cbase: global index of the slot's first cell
