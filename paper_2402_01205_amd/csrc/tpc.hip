@@ -90,12 +90,6 @@ __global__ void k_fill_range_i32(int32_t* p, Bound lo, Bound hi, int32_t v) {
        k += (int64_t)gridDim.x * blockDim.x)
     p[k] = v;
 }
-__global__ void k_fill_range_u64(uint64_t* p, Bound lo, Bound hi) {
-  const int32_t a = lo.get(), b = hi.get();
-  for (int64_t k = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b;
-       k += (int64_t)gridDim.x * blockDim.x)
-    p[k] = 0ull;
-}
 
 // Exclusive scan of in[lo..hi) into out[lo..hi], out[lo] = base (base = *base_p or 0).
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, Bound lo_b, Bound hi_b,
@@ -478,16 +472,19 @@ __global__ void k_start_flags_grid(const int32_t* up, const int32_t* dn, int32_t
 
 // start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order
 __global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit* gh,
-                               const int32_t* fid, const int32_t* posg, int32_t* start, int32_t* order,
-                               int32_t capT, Bound lo_b, Bound hi_b, int32_t* counters) {
+                               const int32_t* fid, const int32_t* posg, const int32_t* T_off, int32_t* start,
+                               int32_t* order, int32_t capT, Bound lo_b, Bound hi_b, int32_t* counters) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
   const int32_t u = up[h];
   if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
-  const int32_t t = fid[gh[h].idx];
+  const GHit H = ldh(gh + h);
+  const int32_t t = fid[H.idx];
   if (t < capT) start[t] = h;
   else atomicOr(&counters[kCntStatus], kStatusCapacity);
+  // the 32-bit hit-weight key holds a job-local tracklet id of 24 bits
+  if (t - T_off[H.slot / kSlotsPerJob] > kLocalIdMax) atomicOr(&counters[kCntStatus], kStatusCapacity);
   if (order) {
     const int32_t p = posg[h];
     if (p < capT) order[p] = t < capT ? t : -1;
@@ -503,9 +500,23 @@ struct TrackletView {
   int32_t* hits;      // [capT][kHitStride]: the hits of a tracklet are contiguous
   int32_t* nhits;     // [capT]
   float* state;       // [capT][kStateStride]: P[5], C[15], x
-  uint64_t* hitw;     // [N] grid order
+  uint32_t* hitw;     // [N] grid order: max key over the tracklets that took the cluster
+  const int32_t* T_off;  // [J+1] first tracklet id of each job
   int32_t capT;
 };
+
+// Hit-weight key of a tracklet: (n_hits << 24) | (2^24-1 - job-local id).  Within one
+// job (the only tracklets that can share a cluster) it orders like the 64-bit key
+// (n_hits << 32) | (2^32-1 - id), since local ids and global ids differ by the job's
+// first id.  0 when the local id does not fit in 24 bits (reported at the starts).
+__device__ __forceinline__ uint32_t trk_key(const TrackletView& V, int32_t slot_base, int32_t t, int n) {
+  const int32_t local = t - V.T_off[slot_base / kSlotsPerJob];
+  if (local < 0 || local > kLocalIdMax) return 0u;
+  return ((uint32_t)n << 24) | (uint32_t)(kLocalIdMax - local);
+}
+__device__ __forceinline__ int32_t key_tracklet(uint32_t key, const int32_t* T_off, int32_t slot) {
+  return T_off[slot / kSlotsPerJob] + (kLocalIdMax - (int32_t)(key & (uint32_t)kLocalIdMax));
+}
 
 __device__ __forceinline__ void init_cov(State& S, const float* prior) {
 #pragma unroll
@@ -687,10 +698,10 @@ __device__ __forceinline__ void trk_finish(const TrackletView& V, const TrkLane&
     *reinterpret_cast<float4*>(st + i) = make_float4(T.keep[i], T.keep[i + 1], T.keep[i + 2], T.keep[i + 3]);
   st[20] = T.keep[20];
   flush_ring(V, T, T.n & (kRingWords - 1));
-  if (T.n >= k.min_hits) {
-    const uint64_t key = ((uint64_t)T.n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
-    for (int q = 0; q < T.n; ++q)
-      atomicMax((unsigned long long*)&V.hitw[V.hits[(int64_t)t * kHitStride + q]], (unsigned long long)key);
+  const uint32_t key = trk_key(V, T.slot_base, t, T.n);
+  st[21] = __uint_as_float(key);
+  if (T.n >= k.min_hits && key != 0u) {
+    for (int q = 0; q < T.n; ++q) atomicMax(&V.hitw[V.hits[(int64_t)t * kHitStride + q]], key);
   }
 }
 
@@ -808,14 +819,15 @@ __global__ __launch_bounds__(256) void k_tracklets_chunked(
 // ------------------------------------------------------------------ a5: selection
 // Owned-hit counts from one coalesced pass over the clusters: a cluster's weight is the
 // key of the tracklet that owns it, whose low 32 bits are 2^32-1 - id.
-__global__ void k_own_count(const uint64_t* hitw, int32_t* own, Bound lo_b, Bound hi_b, int32_t capT) {
+__global__ void k_own_count(const uint32_t* hitw, const GHit* gh, const int32_t* T_off, int32_t* own,
+                            Bound lo_b, Bound hi_b, int32_t capT) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  const uint64_t w = hitw[h];
-  if (w == 0ull) return;
-  const uint32_t t = 0xFFFFFFFFu - (uint32_t)w;
-  if (t < (uint32_t)capT) atomicAdd(&own[t], 1);
+  const uint32_t w = hitw[h];
+  if (w == 0u) return;
+  const int32_t t = key_tracklet(w, T_off, gh[h].slot);
+  if ((uint32_t)t < (uint32_t)capT) atomicAdd(&own[t], 1);
 }
 
 __global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* own, int32_t* accf,
@@ -848,7 +860,7 @@ __global__ void k_select_write(TrackletView V, Bound lo_b, Bound hi_b, const int
   }
   sel_from[kk] = t;
   sel_off[kk] = o;
-  const uint64_t key = ((uint64_t)n << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+  const uint32_t key = __float_as_uint(V.state[(int64_t)t * kStateStride + 21]);
   int w = 0;
   for (int q = 0; q < n; ++q) {
     const int32_t c = V.hits[(int64_t)t * kHitStride + q];
@@ -1251,11 +1263,20 @@ __global__ void k_copy_tracklets(TrackletView V, const GHit* gh, const int32_t* 
   for (int i = 0; i < 21; ++i) state[(int64_t)t * 21 + i] = V.state[(int64_t)t * kStateStride + i];
 }
 
-__global__ void k_hitw_to_input(const uint64_t* w, const GHit* gh, uint64_t* out, Bound hi_b) {
+// The weights in input order, as 64-bit keys (n_hits << 32) | (2^32-1 - global id).
+__global__ void k_hitw_to_input(const uint32_t* w, const GHit* gh, const int32_t* T_off, uint64_t* out,
+                                Bound hi_b) {
   const int32_t hi = hi_b.get();
   const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  out[gh[h].idx] = w[h];
+  const GHit H = ldh(gh + h);
+  const uint32_t k = w[h];
+  uint64_t v = 0ull;
+  if (k != 0u) {
+    const int32_t t = key_tracklet(k, T_off, H.slot);
+    v = ((uint64_t)(k >> 24) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+  }
+  out[H.idx] = v;
 }
 
 __global__ void k_copy_selected(const int32_t* sel_from, const int32_t* sel_off, const int32_t* sel_hits,
@@ -1354,7 +1375,7 @@ struct Layout {
   int32_t *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start, *flagg, *posg, *order;
   int32_t *trk_hits, *trk_n;
   float* trk_state;
-  uint64_t* hitw;
+  uint32_t* hitw;
   int32_t *own, *accf, *kid, *hoff, *sel_off, *sel_hits, *sel_from;
   float *fitP, *fitC, *fitx, *fitchi2;
   int32_t* fitndf;
@@ -1598,7 +1619,8 @@ GridView make_grid(tpc_ctx* c) {
 }
 TrackletView make_tv(tpc_ctx* c) {
   Layout& L = c->L;
-  return TrackletView{L.start, L.up_raw, L.dn_raw, L.up, L.trk_hits, L.trk_n, L.trk_state, L.hitw, L.capT};
+  return TrackletView{L.start, L.up_raw, L.dn_raw, L.up, L.trk_hits, L.trk_n, L.trk_state, L.hitw, L.T_off,
+                      L.capT};
 }
 FitView make_fv(tpc_ctx* c, bool with_chain) {
   Layout& L = c->L;
@@ -1675,11 +1697,11 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
     scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
   }
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gh, L.fid, grid_order ? L.posg : nullptr, L.start, grid_order ? L.order : nullptr,
-                     L.capT, lo, hi, L.counters);
+                     L.gh, L.fid, grid_order ? L.posg : nullptr, L.T_off, L.start,
+                     grid_order ? L.order : nullptr, L.capT, lo, hi, L.counters);
   // tracklet hit weights of this range start at zero
-  hipLaunchKernelGGL(k_fill_range_u64, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, lo,
-                     hi);
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream,
+                     (int32_t*)L.hitw, lo, hi, 0);
 }
 
 int64_t tbound(tpc_ctx* c, int j0, int j1) {
@@ -1724,8 +1746,8 @@ void launch_select(tpc_ctx* c, int j0, int j1) {
   const int64_t nbound = c->job_off_h[j1] - c->job_off_h[j0];
   const int32_t s0 = j0 * kSlotsPerJob, s1 = j1 * kSlotsPerJob;
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.own, lo, hi, 0);
-  hipLaunchKernelGGL(k_own_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, L.own,
-                     db(L.slot_off + s0), db(L.slot_off + s1), L.capT);
+  hipLaunchKernelGGL(k_own_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, L.gh,
+                     L.T_off, L.own, db(L.slot_off + s0), db(L.slot_off + s1), L.capT);
   hipLaunchKernelGGL(k_select_count, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
                      L.own, L.accf, c->k);
   // the scans run over [T_off[j0], min(T_off[j1], capT)); clamp via a copy of the bound
@@ -2201,7 +2223,7 @@ int tpc_get_tracklets(tpc_ctx* c, int32_t* start, int32_t* off, int32_t* hits, f
                        c->L.gh, off, T, start, hits, state);
   if (w)
     hipLaunchKernelGGL(k_hitw_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.hitw,
-                       c->L.gh, w, db(c->L.slot_off + c->L.S));
+                       c->L.gh, c->L.T_off, w, db(c->L.slot_off + c->L.S));
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TPC_OK;

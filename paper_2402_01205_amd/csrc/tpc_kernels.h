@@ -52,6 +52,8 @@ __device__ __forceinline__ void sth(GHit* p, float y, float z, int32_t slot, int
 // Tracklet records: hit list rows of kHitStride ints (64-byte aligned, at least kRows),
 // state rows of kStateStride floats (P[5], C[15], x; 32-byte aligned).
 constexpr int kHitStride = 160;
+// Largest job-local tracklet id that the 32-bit hit-weight key can hold.
+constexpr int32_t kLocalIdMax = (1 << 24) - 1;
 constexpr int kStateStride = 24;
 
 struct SlotGrid {
