@@ -342,12 +342,13 @@ struct GridView {
 // For each cluster h (grid order): over delta = 1, then 2, the pair (d on row r-delta,
 // u on row r+delta) with the smallest second difference inside the windows; ties go to
 // the smaller input index of u, then of d.
+constexpr int kLinkBatch = 2;
 __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, float yh, float zh,
                                             const Consts& k, int32_t& bu_out, int32_t& bd_out) {
   const int r = slot % kRows;
   const float y2 = yh + yh, z2 = zh + zh;
   const float m = 0.01f;
-  int32_t bu = -1, bd = -1, bu_o = 0, bd_o = 0;
+  int32_t bu = -1, bd = -1;
   float best = 0.f;
   for (int d = 1; d <= 2; ++d) {
     if (r - d < 0 || r + d >= kRows) break;
@@ -378,38 +379,69 @@ __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, flo
       if (cz < uz0 || cz > uz1) continue;
       const int32_t c0 = ubase + cz * gu.ny;
       const int32_t a0 = G.cell_off[c0 + uy0], a1 = G.cell_off[c0 + uy1 + 1];
-      for (int32_t u = a0; u < a1; ++u) {
-        const GHit U = ldh(G.gh + u);
-        const float yu = U.y, zu = U.z;
-        if (!(fabsf(yu - yc) <= wy) || !(fabsf(zu - zh) <= wz)) continue;
-        const float py = y2 - yu, pz = z2 - zu;
-        const int32_t uo = U.idx;
-        const int dy0 = cell_of(py - rad - m, gd.ylo, gd.inv_by, gd.ny);
-        const int dy1 = cell_of(py + rad + m, gd.ylo, gd.inv_by, gd.ny);
-        const int dz0 = cell_of(pz - rad - m, gd.zlo, gd.inv_bz, gd.nz);
-        const int dz1 = cell_of(pz + rad + m, gd.zlo, gd.inv_bz, gd.nz);
-        for (int ez = dz0; ez <= dz1; ++ez) {
-          const int32_t e0 = dbase + ez * gd.ny;
-          const int32_t b0 = G.cell_off[e0 + dy0], b1 = G.cell_off[e0 + dy1 + 1];
-          for (int32_t dd = b0; dd < b1; ++dd) {
-            const GHit D = ldh(G.gh + dd);
-            const float ry = (yu + D.y) - y2;
-            const float rz = (zu + D.z) - z2;
-            const float sc = ry * ry + rz * rz;
-            if (!(sc <= k.cut2)) continue;
-            const int32_t dor = D.idx;
-            if (bu < 0 || sc < best || (sc == best && (uo < bu_o || (uo == bu_o && dor < bd_o)))) {
-              best = sc;
-              bu = u;
-              bd = dd;
-              bu_o = uo;
-              bd_o = dor;
+      // candidates are read kLinkBatch at a time (positions only; input indices are read
+      // for exact ties alone), so one memory wait serves several of them; wider batches
+      // measured slower (the kernel is VALU-issue bound, and the predication costs VALU)
+      for (int32_t ub = a0; ub < a1; ub += kLinkBatch) {
+        float2 U[kLinkBatch];
+#pragma unroll
+        for (int i = 0; i < kLinkBatch; ++i) U[i] = ub + i < a1 ? G.yz[ub + i] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kLinkBatch; ++i) {
+          const int32_t u = ub + i;
+          if (u >= a1) break;
+          const float yu = U[i].x, zu = U[i].y;
+          if (!(fabsf(yu - yc) <= wy) || !(fabsf(zu - zh) <= wz)) continue;
+          const float py = y2 - yu, pz = z2 - zu;
+          const int dy0 = cell_of(py - rad - m, gd.ylo, gd.inv_by, gd.ny);
+          const int dy1 = cell_of(py + rad + m, gd.ylo, gd.inv_by, gd.ny);
+          const int dz0 = cell_of(pz - rad - m, gd.zlo, gd.inv_bz, gd.nz);
+          const int dz1 = cell_of(pz + rad + m, gd.zlo, gd.inv_bz, gd.nz);
+          for (int ez0 = dz0; ez0 <= dz1; ez0 += kLinkBatch) {
+            // the candidate ranges of up to kLinkBatch down cell rows at once
+            int32_t B0[kLinkBatch], B1[kLinkBatch];
+#pragma unroll
+            for (int e = 0; e < kLinkBatch; ++e) {
+              B0[e] = B1[e] = 0;
+              if (ez0 + e <= dz1) {
+                const int32_t e0 = dbase + (ez0 + e) * gd.ny;
+                B0[e] = G.cell_off[e0 + dy0];
+                B1[e] = G.cell_off[e0 + dy1 + 1];
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < kLinkBatch; ++e) {
+              for (int32_t db0 = B0[e]; db0 < B1[e]; db0 += kLinkBatch) {
+                float2 D[kLinkBatch];
+#pragma unroll
+                for (int j = 0; j < kLinkBatch; ++j)
+                  D[j] = db0 + j < B1[e] ? G.yz[db0 + j] : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int j = 0; j < kLinkBatch; ++j) {
+                  const int32_t dd = db0 + j;
+                  if (dd >= B1[e]) break;
+                  const float ry = (yu + D[j].x) - y2;
+                  const float rz = (zu + D[j].y) - z2;
+                  const float sc = ry * ry + rz * rz;
+                  if (!(sc <= k.cut2)) continue;
+                  bool win = bu < 0 || sc < best;
+                  if (!win && sc == best) {
+                    const int32_t uo = G.gh[u].idx, bo = G.gh[bu].idx;
+                    win = uo < bo || (uo == bo && G.gh[dd].idx < G.gh[bd].idx);
+                  }
+                  if (win) {
+                    best = sc;
+                    bu = u;
+                    bd = dd;
+                  }
+                }
+              }
             }
           }
+          // (the radius only prunes, so the hardware square root, within a few ulp, does;
+          // the 1e-4 margin keeps it above sqrt(best))
+          if (bu >= 0) rad = fminf(k.link_cut, __builtin_amdgcn_sqrtf(best) * 1.0001f);
         }
-        // (the radius only prunes, so the hardware square root, within a few ulp, does;
-        // the 1e-4 margin keeps it above sqrt(best))
-        if (bu >= 0) rad = fminf(k.link_cut, __builtin_amdgcn_sqrtf(best) * 1.0001f);
       }
     }
     if (bu >= 0) break;
@@ -845,31 +877,55 @@ __global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* 
 
 __global__ void k_select_write(TrackletView V, Bound lo_b, Bound hi_b, const int32_t* accf,
                                const int32_t* kid, const int32_t* hoff, int32_t* sel_from,
-                               int32_t* sel_off, int32_t* sel_hits, int32_t capK, int32_t capH,
-                               int32_t* counters) {
+                               int32_t* sel_off, int32_t capK, int32_t* counters) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), V.capT);
   const int32_t t = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= hi || !accf[t]) return;
   const int32_t kk = kid[t];
-  const int32_t o = hoff[t];
-  const int n = V.nhits[t];
   if (kk >= capK) {
     atomicOr(&counters[kCntStatus], kStatusCapacity);
     return;
   }
   sel_from[kk] = t;
-  sel_off[kk] = o;
-  const uint32_t key = __float_as_uint(V.state[(int64_t)t * kStateStride + 21]);
-  int w = 0;
-  for (int q = 0; q < n; ++q) {
-    const int32_t c = V.hits[(int64_t)t * kHitStride + q];
-    if (V.hitw[c] == key) {
-      if (o + w < capH) sel_hits[o + w] = c;
-      ++w;
+  sel_off[kk] = hoff[t];
+}
+
+// One wave per selected track: its owned hits, in tracklet order, compacted with a
+// ballot per 64 hits (coalesced reads of the hit list, coalesced writes).
+__global__ __launch_bounds__(256) void k_select_hits(TrackletView V, const int32_t* kid, int32_t j0, int32_t j1,
+                                                     const int32_t* sel_from, const int32_t* sel_off,
+                                                     int32_t* sel_hits, int32_t capK, int32_t capH,
+                                                     int32_t* counters) {
+  // selected tracks of jobs j0..j1-1: [kid[T_off[j0]], kid[T_off[j1]])
+  const int32_t lo = kid[min(V.T_off[j0], V.capT)];
+  const int32_t hi = min(kid[min(V.T_off[j1], V.capT)], capK);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w0 = lo + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); w0 < hi; w0 += nw) {
+    const int32_t kk = (int32_t)w0;
+    const int32_t t = sel_from[kk];
+    const int32_t o = sel_off[kk];
+    const int n = V.nhits[t];
+    const uint32_t key = __float_as_uint(V.state[(int64_t)t * kStateStride + 21]);
+    int w = 0;
+    for (int q0 = 0; q0 < n; q0 += 64) {
+      const int q = q0 + lane;
+      int32_t c = 0;
+      bool own = false;
+      if (q < n) {
+        c = V.hits[(int64_t)t * kHitStride + q];
+        own = V.hitw[c] == key;
+      }
+      const uint64_t m = __ballot(own);
+      if (own) {
+        const int pos = o + w + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < capH) sel_hits[pos] = c;
+      }
+      w += __popcll(m);
     }
+    if (lane == 0 && o + w > capH) atomicOr(&counters[kCntStatus], kStatusCapacity);
   }
-  if (o + w > capH) atomicOr(&counters[kCntStatus], kStatusCapacity);
 }
 
 __global__ void k_select_finish(const int32_t* kid, const int32_t* hoff, Bound thi_b, int32_t capT,
@@ -1194,42 +1250,57 @@ __global__ void k_out_count(FitView F, const int32_t* keep, int32_t* outn, Bound
   outn[kk] = n;
 }
 
-__global__ void k_out_write(GridView G, TrackletView V, FitView F, OutView O, const int32_t* keep,
-                            const int32_t* oid, const int32_t* ooff, Bound lo_b, Bound hi_b,
-                            int32_t* counters) {
+// One wave per output track: the hit lists of its pieces copied with the lanes striding
+// over them (coalesced), the per-track fields written by lanes 0..23.
+__global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, FitView F, OutView O,
+                                                   const int32_t* keep, const int32_t* oid, const int32_t* ooff,
+                                                   Bound lo_b, Bound hi_b, int32_t* counters) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
-  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (kk >= hi || !keep[kk]) return;
-  const int32_t o = oid[kk];
-  const int32_t h0 = ooff[kk];
-  if (o >= O.cap_tracks) {
-    atomicOr(&counters[kCntStatus], kStatusCapacity);
-    return;
-  }
-  O.hit_off[o] = h0;
-  int w = 0;
-  const bool walk = F.chain_next && F.chain_prev[kk] < 0;
-  int np = 0;
-  for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1, ++np) {
-    for (int32_t q = F.sel_off[p]; q < F.sel_off[p + 1]; ++q) {
-      if (h0 + w < O.cap_hits) O.hits[h0 + w] = G.gh[F.sel_hits[q]].idx;
-      ++w;
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w0 = lo + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); w0 < hi; w0 += nw) {
+    const int32_t kk = (int32_t)w0;
+    if (!keep[kk]) continue;
+    const int32_t o = oid[kk];
+    const int32_t h0 = ooff[kk];
+    if (o >= O.cap_tracks) {
+      if (lane == 0) atomicOr(&counters[kCntStatus], kStatusCapacity);
+      continue;
+    }
+    int w = 0;
+    const bool walk = F.chain_next && F.chain_prev[kk] < 0;
+    int np = 0;
+    for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1, ++np) {
+      const int32_t q0 = F.sel_off[p], q1 = F.sel_off[p + 1];
+      for (int32_t q = q0 + lane; q < q1; q += 64) {
+        const int32_t pos = h0 + w + (q - q0);
+        if (pos < O.cap_hits) O.hits[pos] = G.gh[F.sel_hits[q]].idx;
+      }
+      w += q1 - q0;
+    }
+    if (lane == 0) {
+      O.hit_off[o] = h0;
+      if (h0 + w > O.cap_hits) atomicOr(&counters[kCntStatus], kStatusCapacity);
+    }
+    if (lane < 5) {
+      O.param[(int64_t)o * 5 + lane] = F.P[(int64_t)lane * F.capK + kk];
+    } else if (lane < 20) {
+      O.cov[(int64_t)o * 15 + (lane - 5)] = F.C[(int64_t)(lane - 5) * F.capK + kk];
+    } else if (lane == 20) {
+      O.x_ref[o] = F.x[kk];
+    } else if (lane == 21) {
+      O.chi2[o] = F.chi2[kk];
+    } else if (lane == 22) {
+      O.ndf[o] = F.ndf[kk];
+    } else if (lane == 23) {
+      const int32_t t = F.sel_from[kk];
+      const int32_t sl = G.gh[V.start[t]].slot;
+      O.sector[o] = (sl / kRows) % kSectors;
+      O.job[o] = sl / (kSectors * kRows);
+      O.tracklet[o] = t;
     }
   }
-  if (h0 + w > O.cap_hits) atomicOr(&counters[kCntStatus], kStatusCapacity);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) O.param[(int64_t)o * 5 + i] = F.P[(int64_t)i * F.capK + kk];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) O.cov[(int64_t)o * 15 + i] = F.C[(int64_t)i * F.capK + kk];
-  O.x_ref[o] = F.x[kk];
-  O.chi2[o] = F.chi2[kk];
-  O.ndf[o] = F.ndf[kk];
-  const int32_t t = F.sel_from[kk];
-  const int32_t sl = G.gh[V.start[t]].slot;
-  O.sector[o] = (sl / kRows) % kSectors;
-  O.job[o] = sl / (kSectors * kRows);
-  O.tracklet[o] = t;
 }
 
 __global__ void k_out_finish(const int32_t* oid, const int32_t* ooff, Bound hi_b, int32_t capK,
@@ -1582,6 +1653,13 @@ void make_consts(const tpc_params& p, Consts& k) {
 }
 
 Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
+// Workgroups (of 4 waves) for a grid-stride loop with one wave per item: enough to fill
+// the device 8 workgroups deep, no more than the items need.
+int wave_grid(tpc_ctx* c, int64_t items) {
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  return (int)std::max<int64_t>(1, std::min<int64_t>((items + 3) / 4, (int64_t)ncu * 8));
+}
 Bound db(const int32_t* p) { return Bound{p, 0, INT32_MAX}; }
 Bound dbc(const int32_t* p, int32_t cap) { return Bound{p, 0, cap}; }
 
@@ -1754,7 +1832,9 @@ void launch_select(tpc_ctx* c, int j0, int j1) {
   scan(c, L.accf, L.kid, lo, hi, tb, j0 != 0);
   scan(c, L.own, L.hoff, lo, hi, tb, j0 != 0);
   hipLaunchKernelGGL(k_select_write, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
-                     L.accf, L.kid, L.hoff, L.sel_from, L.sel_off, L.sel_hits, L.capK, L.capH, L.counters);
+                     L.accf, L.kid, L.hoff, L.sel_from, L.sel_off, L.capK, L.counters);
+  hipLaunchKernelGGL(k_select_hits, dim3(wave_grid(c, tb)), dim3(256), 0, c->stream, make_tv(c), L.kid, j0, j1,
+                     L.sel_from, L.sel_off, L.sel_hits, L.capK, L.capH, L.counters);
   hipLaunchKernelGGL(k_select_finish, dim3(1), dim3(1), 0, c->stream, L.kid, L.hoff, hi, L.capT, L.sel_off,
                      L.capK, L.counters);
 }
@@ -2048,7 +2128,7 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   scan(c, L.outn, L.ooff, klo, khi, kb, false);
   OutView O{out->cap_tracks, out->cap_hits, out->n_tracks, out->hit_off, out->hits, out->param, out->cov,
             out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet};
-  hipLaunchKernelGGL(k_out_write, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
+  hipLaunchKernelGGL(k_out_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
                      make_fv(c, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters);
   hipLaunchKernelGGL(k_out_finish, dim3(1), dim3(1), 0, c->stream, L.oid, L.ooff, khi, L.capK, O, L.counters);
   prof_end(c, pm);
