@@ -945,9 +945,7 @@ struct FitView {
   const int32_t* sel_hits;
   const int32_t* chain_next;  // merged outer piece of a track, -1 if none (NULL: no merge)
   const int32_t* chain_prev;  // merged inner piece, -1 if none; chains are walked from heads only
-  float* P;                   // [5][capK]
-  float* C;                   // [15][capK]
-  float* x;
+  float* row;                 // [capK][kFitStride]: P[5], C[15], x (one record per track)
   float* chi2;
   int32_t* ndf;
   int32_t capK;
@@ -1000,24 +998,19 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
       ++nh;
     }
   }
-  const int capK = F.capK;
-  if (ok) {
+  float v[kFitStride];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) F.P[(int64_t)i * capK + kk] = S.P[i];
+  for (int i = 0; i < 5; ++i) v[i] = ok ? S.P[i] : __builtin_nanf("");
 #pragma unroll
-    for (int i = 0; i < 15; ++i) F.C[(int64_t)i * capK + kk] = S.C[i];
-    F.x[kk] = x;
-    F.chi2[kk] = chi2;
-    F.ndf[kk] = 2 * nh - 5;
-  } else {
+  for (int i = 0; i < 15; ++i) v[5 + i] = ok ? S.C[i] : 0.f;
+  v[20] = ok ? x : 0.f;
+  v[21] = v[22] = v[23] = 0.f;
+  float* dst = F.row + (int64_t)kk * kFitStride;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) F.P[(int64_t)i * capK + kk] = __builtin_nanf("");
-#pragma unroll
-    for (int i = 0; i < 15; ++i) F.C[(int64_t)i * capK + kk] = 0.f;
-    F.x[kk] = 0.f;
-    F.chi2[kk] = 0.f;
-    F.ndf[kk] = -1;
-  }
+  for (int i = 0; i < kFitStride; i += 4)
+    *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+  F.chi2[kk] = ok ? chi2 : 0.f;
+  F.ndf[kk] = ok ? 2 * nh - 5 : -1;
 }
 
 __global__ __launch_bounds__(256) void k_fit(GridView G, TrackletView V, FitView F, Bound lo_b,
@@ -1166,12 +1159,23 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
     const int32_t b = M.bucket_trk[q];
     State S = R;
     float x = xr;
-    if (!propagate(S, x, F.x[b], k)) continue;
+    // B's fitted record: 21 consecutive floats
+    float rb[kFitStride];
+    const float* src = F.row + (int64_t)b * kFitStride;
+#pragma unroll
+    for (int i = 0; i < kFitStride; i += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src + i);
+      rb[i] = v.x;
+      rb[i + 1] = v.y;
+      rb[i + 2] = v.z;
+      rb[i + 3] = v.w;
+    }
+    if (!propagate(S, x, rb[20], k)) continue;
     float PB[5], CB[15];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) PB[i] = F.P[(int64_t)i * F.capK + b];
+    for (int i = 0; i < 5; ++i) PB[i] = rb[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) CB[i] = F.C[(int64_t)i * F.capK + b];
+    for (int i = 0; i < 15; ++i) CB[i] = rb[5 + i];
     const float c = merge_chi2(S.P, S.C, PB, CB);
     if (!(c <= k.chi2_merge)) continue;
     atomicMin((unsigned long long*)&M.bestA[a], (unsigned long long)pack_best(c, b));
@@ -1284,11 +1288,11 @@ __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, F
       if (h0 + w > O.cap_hits) atomicOr(&counters[kCntStatus], kStatusCapacity);
     }
     if (lane < 5) {
-      O.param[(int64_t)o * 5 + lane] = F.P[(int64_t)lane * F.capK + kk];
+      O.param[(int64_t)o * 5 + lane] = F.row[(int64_t)kk * kFitStride + lane];
     } else if (lane < 20) {
-      O.cov[(int64_t)o * 15 + (lane - 5)] = F.C[(int64_t)(lane - 5) * F.capK + kk];
+      O.cov[(int64_t)o * 15 + (lane - 5)] = F.row[(int64_t)kk * kFitStride + lane];
     } else if (lane == 20) {
-      O.x_ref[o] = F.x[kk];
+      O.x_ref[o] = F.row[(int64_t)kk * kFitStride + 20];
     } else if (lane == 21) {
       O.chi2[o] = F.chi2[kk];
     } else if (lane == 22) {
@@ -1448,7 +1452,7 @@ struct Layout {
   float* trk_state;
   uint32_t* hitw;
   int32_t *own, *accf, *kid, *hoff, *sel_off, *sel_hits, *sel_from;
-  float *fitP, *fitC, *fitx, *fitchi2;
+  float *fitrow, *fitchi2;
   int32_t* fitndf;
   int32_t *T_off, *K_off, *counters, *bsum;
   // merge
@@ -1515,9 +1519,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.sel_off, L.capK + 1, t, set);
   carve(p, L.sel_hits, L.capH, t, set);
   carve(p, L.sel_from, L.capK, t, set);
-  carve(p, L.fitP, (int64_t)5 * L.capK, t, set);
-  carve(p, L.fitC, (int64_t)15 * L.capK, t, set);
-  carve(p, L.fitx, L.capK, t, set);
+  carve(p, L.fitrow, (int64_t)kFitStride * L.capK, t, set);
   carve(p, L.fitchi2, L.capK, t, set);
   carve(p, L.fitndf, L.capK, t, set);
   carve(p, L.T_off, J + 1, t, set);
@@ -1703,7 +1705,7 @@ TrackletView make_tv(tpc_ctx* c) {
 FitView make_fv(tpc_ctx* c, bool with_chain) {
   Layout& L = c->L;
   return FitView{L.sel_from, L.sel_off, L.sel_hits, with_chain ? L.chain_next : nullptr,
-                 with_chain ? L.chain_prev : nullptr, L.fitP, L.fitC, L.fitx, L.fitchi2, L.fitndf, L.capK};
+                 with_chain ? L.chain_prev : nullptr, L.fitrow, L.fitchi2, L.fitndf, L.capK};
 }
 
 // ---- stage launch sequences over the job range [j0, j1)
