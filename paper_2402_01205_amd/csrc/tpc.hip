@@ -317,7 +317,7 @@ __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey,
 }
 
 __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
-                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh, float2* gyz) {
+                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
@@ -325,9 +325,17 @@ __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, co
   if (slot < 0) return;
   const int32_t gc = ccell[i];
   const int32_t pos = cell_off[gc] + atomicAdd(&cell_fill[gc], 1);
-  const float y = in.y[i], z = in.z[i];
-  sth(gh + pos, y, z, slot, i);
-  gyz[pos] = make_float2(y, z);
+  sth(gh + pos, in.y[i], in.z[i], slot, i);
+}
+
+// The positions alone, in grid order: one coalesced pass after the scatter (cheaper
+// than a second random write per cluster in it).
+__global__ void k_positions(const GHit* gh, float2* gyz, Bound lo_b, Bound hi_b) {
+  const int32_t lo = lo_b.get(), hi = hi_b.get();
+  const int32_t g = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= hi) return;
+  const GHit H = ldh(gh + g);
+  gyz[g] = make_float2(H.y, H.z);
 }
 
 // ------------------------------------------------------------------ a2: neighbours
@@ -1746,7 +1754,9 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
                      db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.cell_cnt);
   scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh, L.gyz);
+                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh);
+  hipLaunchKernelGGL(k_positions, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.gh, L.gyz,
+                     db(L.slot_off + s0), db(L.slot_off + s1));
 }
 
 void launch_links(tpc_ctx* c, int j0, int j1) {
