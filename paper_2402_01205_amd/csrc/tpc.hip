@@ -302,7 +302,7 @@ __global__ void k_slot_cellbase(SlotGrid* sg, const int32_t* cell_base, int32_t 
 }
 
 __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const SlotGrid* sg,
-                             const int32_t* cell_base, int32_t* ccell, int32_t* cell_cnt) {
+                             const int32_t* cell_base, int32_t* ccell, int32_t* crank, int32_t* cell_cnt) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
@@ -313,18 +313,18 @@ __global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey,
   const int cz = cell_of(in.z[i], g.zlo, g.inv_bz, g.nz);
   const int32_t gc = cell_base[slot] + cz * g.ny + cy;
   ccell[i] = gc;
-  atomicAdd(&cell_cnt[gc], 1);
+  crank[i] = atomicAdd(&cell_cnt[gc], 1);  // the cluster's place within its cell
 }
 
 __global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
-                          const int32_t* cell_off, int32_t* cell_fill, GHit* gh) {
+                          const int32_t* cell_off, const int32_t* crank, GHit* gh) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
   const int32_t slot = ckey[i];
   if (slot < 0) return;
   const int32_t gc = ccell[i];
-  const int32_t pos = cell_off[gc] + atomicAdd(&cell_fill[gc], 1);
+  const int32_t pos = cell_off[gc] + crank[i];
   sth(gh + pos, in.y[i], in.z[i], slot, i);
 }
 
@@ -1450,7 +1450,7 @@ struct Layout {
   int64_t bsumN = 0;
   size_t bytes = 0;
   // arrays
-  int32_t *ckey, *ccell, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_cnt, *cell_off, *cell_fill;
+  int32_t *ckey, *ccell, *crank, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_cnt, *cell_off;
   uint32_t *zmin, *zmax;
   SlotGrid* sg;
   GHit* gh;
@@ -1503,7 +1503,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.cell_base, L.S + 1, t, set);
   carve(p, L.cell_cnt, L.capCells + 1, t, set);
   carve(p, L.cell_off, L.capCells + 1, t, set);
-  carve(p, L.cell_fill, L.capCells + 1, t, set);
+  carve(p, L.crank, N, t, set);
   carve(p, L.gh, N, t, set);
   carve(p, L.gyz, N, t, set);
   carve(p, L.up_raw, N, t, set);
@@ -1748,13 +1748,11 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
   const int64_t cbound = (int64_t)std::ceil((double)nbound * c->tune.cells_per_cluster) + (s1 - s0) + 1;
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_cnt,
                      db(L.cell_base + s0), db(L.cell_base + s1), 0);
-  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_fill,
-                     db(L.cell_base + s0), db(L.cell_base + s1), 0);
   hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.cell_cnt);
+                     db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.crank, L.cell_cnt);
   scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.cell_fill, L.gh);
+                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.crank, L.gh);
   hipLaunchKernelGGL(k_positions, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.gh, L.gyz,
                      db(L.slot_off + s0), db(L.slot_off + s1));
 }
