@@ -471,26 +471,30 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
   dn_raw[h] = bd;
 }
 
-// Mutual cleaning, evaluated on the raw links only.
-__global__ void k_clean(const int32_t* up_raw, const int32_t* dn_raw, int32_t* up, int32_t* dn,
-                        Bound lo_b, Bound hi_b) {
+
+// Cleaning and starts in one pass: the clean links of h, and whether h starts a chain
+// (no clean down link, a clean up link whose own clean up link exists; the latter is
+// evaluated from the raw links too), flagged at h's input index and, for the grid-ordered
+// work list, at h itself.  Also clears h's hit weight for the tracklet stage.
+__global__ void k_clean_starts(const int32_t* up_raw, const int32_t* dn_raw, const GHit* gh, int32_t* up,
+                               int32_t* dn, int32_t* flag, int32_t* flagg, uint32_t* hitw, Bound lo_b,
+                               Bound hi_b) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
   const int32_t u = up_raw[h], d = dn_raw[h];
-  up[h] = (u >= 0 && dn_raw[u] == h) ? u : -1;
-  dn[h] = (d >= 0 && up_raw[d] == h) ? d : -1;
-}
-
-// Chain starts flagged at their input index: no clean down link, a clean up link whose
-// own clean up link exists.
-__global__ void k_start_flags(const int32_t* up, const int32_t* dn, const GHit* gh, int32_t* flag,
-                              Bound lo_b, Bound hi_b) {
-  const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= hi) return;
-  const int32_t u = up[h];
-  if (dn[h] < 0 && u >= 0 && up[u] >= 0) flag[gh[h].idx] = 1;
+  const int32_t uc = (u >= 0 && dn_raw[u] == h) ? u : -1;
+  const int32_t dc = (d >= 0 && up_raw[d] == h) ? d : -1;
+  up[h] = uc;
+  dn[h] = dc;
+  bool start = false;
+  if (dc < 0 && uc >= 0) {
+    const int32_t u2 = up_raw[uc];
+    start = u2 >= 0 && dn_raw[u2] == uc;
+  }
+  if (start) flag[gh[h].idx] = 1;
+  if (flagg) flagg[h] = start ? 1 : 0;
+  hitw[h] = 0u;
 }
 
 __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, int32_t* out_off,
@@ -500,15 +504,6 @@ __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, in
   out_off[j] = scanned[min(job_off[j], cap)];
 }
 
-// Start flags in grid order (for the grid-ordered work list of the tracklet kernel).
-__global__ void k_start_flags_grid(const int32_t* up, const int32_t* dn, int32_t* flagg, Bound lo_b,
-                                   Bound hi_b) {
-  const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= hi) return;
-  const int32_t u = up[h];
-  flagg[h] = (dn[h] < 0 && u >= 0 && up[u] >= 0) ? 1 : 0;
-}
 
 // start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order
 __global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit* gh,
@@ -1767,29 +1762,20 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
   hipLaunchKernelGGL(k_links, dim3(blocks_for(nbound, bl)), dim3(bl), 0, c->stream, make_grid(c), lo, hi,
                      L.up_raw, L.dn_raw, c->k);
   prof_end(c, pm);
-  hipLaunchKernelGGL(k_clean, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up_raw, L.dn_raw,
-                     L.up, L.dn, lo, hi);
-  // starts: flags in input order -> ranked ids
+  // clean links, starts flagged in input order (-> ranked ids) and grid order, weights cleared
   const int32_t* jo = c->jobs.job_off;
+  const bool grid_order = c->tune.tracklet_order == 1;
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.flag,
                      db(jo + j0), db(jo + j1), 0);
-  hipLaunchKernelGGL(k_start_flags, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gh, L.flag, lo, hi);
+  hipLaunchKernelGGL(k_clean_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up_raw, L.dn_raw,
+                     L.gh, L.up, L.dn, L.flag, grid_order ? L.flagg : nullptr, L.hitw, lo, hi);
   scan(c, L.flag, L.fid, db(jo + j0), db(jo + j1), nbound, j0 != 0);
   hipLaunchKernelGGL(k_job_offsets, dim3(blocks_for(j1 - j0, 256)), dim3(256), 0, c->stream, L.fid, jo,
                      L.T_off, j0, j1, (int32_t)L.N);
-  const bool grid_order = c->tune.tracklet_order == 1;
-  if (grid_order) {
-    hipLaunchKernelGGL(k_start_flags_grid, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                       L.flagg, lo, hi);
-    scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
-  }
+  if (grid_order) scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
                      L.gh, L.fid, grid_order ? L.posg : nullptr, L.T_off, L.start,
                      grid_order ? L.order : nullptr, L.capT, lo, hi, L.counters);
-  // tracklet hit weights of this range start at zero
-  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream,
-                     (int32_t*)L.hitw, lo, hi, 0);
 }
 
 int64_t tbound(tpc_ctx* c, int j0, int j1) {
