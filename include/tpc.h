@@ -72,8 +72,8 @@ typedef struct {
 /* Tunable launch shapes.  Results are identical for every valid setting.     */
 typedef struct {
   float cells_per_cluster;  /* grid cells per cluster of a row (search accelerator) */
-  int32_t block_links;      /* threads per workgroup of the neighbour kernel         */
-  int32_t block_tracklets;  /* threads per workgroup of the tracklet kernel          */
+  int32_t block_links;      /* threads per workgroup of the neighbour kernel (64..256)*/
+  int32_t block_tracklets;  /* threads per workgroup of the tracklet kernel (64..256)*/
   int32_t persistent_waves; /* resident waves per CU of persistent kernels (0 = off)  */
   int32_t use_graph;        /* capture the batched stage chain into a hipGraph        */
   int32_t tracklet_order;   /* work order of the tracklet kernel: 0 = tracklet id,    */

@@ -1945,7 +1945,7 @@ int tpc_set_mode(tpc_ctx* c, int mode) {
 
 int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (!c || !t || !(t->cells_per_cluster > 0.f) || t->cells_per_cluster > 8.f) return TPC_E_ARG;
-  if (t->block_links % 64 || t->block_links <= 0 || t->block_links > 1024) return TPC_E_ARG;
+  if (t->block_links % 64 || t->block_links <= 0 || t->block_links > 256) return TPC_E_ARG;
   if (t->block_tracklets % 64 || t->block_tracklets <= 0 || t->block_tracklets > 256) return TPC_E_ARG;
   if (t->tracklet_order != 0 && t->tracklet_order != 1) return TPC_E_ARG;
   if (t->persistent_refill != 0 && t->persistent_refill != 1) return TPC_E_ARG;
