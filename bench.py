@@ -77,6 +77,32 @@ def traffic_record(kernel: str, workload: str):
     return None
 
 
+def _oracle_job(args):
+    """One job of the sample through the oracle (in a worker process)."""
+    import oracle.oracle as O
+    sub = args
+    r = O.Run.from_set(sub)
+    return len(r.tracks()["tracklet"])
+
+
+def cpu_baseline_parallel(cs, workers):
+    """The same oracle on the same sample, one job per worker process (jobs are independent).
+    Run before any GPU use, so the pool may fork."""
+    import multiprocessing as mp
+    if cs.n_jobs <= 1:
+        return None
+    jobs = list(range(0, cs.n_jobs, 32))
+    subs = [cs.job(j) for j in jobs]
+    n = sum(s.n for s in subs)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        ntr = sum(pool.map(_oracle_job, subs, chunksize=1))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "clusters/s", "cores": workers, "kind": "oracle",
+            "sample": f"the same {len(jobs)} jobs ({n} clusters), one job per process; {ntr} tracks; {dt:.1f} s"}
+
+
 def cpu_baseline(cs, cfg, budget_s):
     """The oracle (single thread, as it stands) on a bounded sample of the same workload."""
     import oracle.oracle as O
@@ -186,6 +212,15 @@ def main():
     cs = g.make_config(args.config, seed, workers=args.workers)  # before any GPU use
     log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
         f"in {time.perf_counter() - t0:.1f}s")
+    # the oracle baselines first, before any GPU use
+    cpu = cpu_par = None
+    if not args.no_cpu and not args.profile_only:
+        cpu = cpu_baseline(cs, args.config, args.cpu_budget)
+        cpu["cores"] = 1
+        log(f"cpu baseline (1 core): {cpu['value']:.3e} clusters/s")
+        cpu_par = cpu_baseline_parallel(cs, min(args.workers, os.cpu_count() or 1))
+        if cpu_par:
+            log(f"cpu baseline ({cpu_par['cores']} processes): {cpu_par['value']:.3e} clusters/s")
     others = {}
     if not args.profile_only:
         for name in [x for x in args.also.split(",") if x and x != args.config]:
@@ -344,9 +379,9 @@ def main():
         "tracklets": int(T),
         "quality": q,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cs, args.config, args.cpu_budget)
-        out["cpu_baseline"]["cores"] = 1
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_baseline_all_cores"] = cpu_par
     print(json.dumps(out), flush=True)
 
 
