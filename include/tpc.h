@@ -142,6 +142,8 @@ void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_set_stream(tpc_ctx* ctx, void* hip_stream);
 int tpc_set_mode(tpc_ctx* ctx, int mode);
 int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);
+/* Text of the context's last failure; with ctx = NULL, the reason of this thread's
+ * last failed tpc_ctx_create.                                                  */
 const char* tpc_last_error(const tpc_ctx* ctx);
 
 /* Device bytes of the workspace for n_clusters clusters in n_jobs jobs [host].

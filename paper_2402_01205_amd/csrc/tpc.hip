@@ -1885,6 +1885,9 @@ static bool params_ok(const tpc_params& p) {
          p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f;
 }
 
+// the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))
+static thread_local char g_create_err[256] = "null context";
+
 int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p) {
   if (!out) return TPC_E_ARG;
   if (p && !params_ok(*p)) return TPC_E_ARG;
@@ -1894,11 +1897,11 @@ int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p)
   if (p) c->p = *p; else tpc_params_default(&c->p);
   tpc_tuning_default(&c->tune);
   make_consts(c->p, c->k);
-  if (hipSetDevice(device) != hipSuccess) {
-    delete c;
-    return TPC_E_HIP;
-  }
-  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 64 * sizeof(int32_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    std::snprintf(g_create_err, sizeof(g_create_err), "tpc_ctx_create on device %d: %s", device,
+                  hipGetErrorString(e));
     delete c;
     return TPC_E_HIP;
   }
@@ -1954,7 +1957,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   return TPC_OK;
 }
 
-const char* tpc_last_error(const tpc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* tpc_last_error(const tpc_ctx* c) { return c ? c->err.c_str() : g_create_err; }
 
 size_t tpc_workspace_size(const tpc_ctx* c, int64_t n, int32_t J) {
   if (!c || n < 0 || J <= 0) return 0;

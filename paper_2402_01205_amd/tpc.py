@@ -66,6 +66,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_2402_01205_amd/build.py")
+        # torch's HIP runtime is loaded and initialised before the library is, so the
+        # library binds to that runtime; loaded the other way round, two runtimes can end
+        # up in the process and the library's finds no device.
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = C.CDLL(LIB_PATH)
         V, P, I = C.c_void_p, C.POINTER, C.c_int
         L.tpc_params_default.argtypes = [P(tpc_params)]
@@ -190,7 +196,7 @@ class Tracker:
 
     def _check(self, rc, what=""):
         if rc != TPC_OK:
-            msg = lib().tpc_last_error(self.ctx).decode() if self.ctx.value else ""
+            msg = lib().tpc_last_error(self.ctx if self.ctx.value else None).decode()
             raise TpcError(rc, f"{what}: {msg}")
 
     def set_mode(self, mode: str):
