@@ -107,7 +107,11 @@ typedef struct {
 
 /* Output tracks (after tpc_fit_merge).  Capacities are [host] values; counts
  * are written on the device.  hits: CSR of cluster indices ordered along the
- * track (inner piece rows ascending, then the outer piece).                  */
+ * track (inner piece rows ascending, then the outer piece).  When a capacity
+ * is too small, tpc_sync returns TPC_E_CAPACITY, n_tracks still holds the
+ * number of tracks found, the tracks and hits that fit are written and nothing
+ * beyond the capacities; if the tracks fit, hit_off[n_tracks] holds the number
+ * of hits needed.                                                            */
 typedef struct {
   int32_t cap_tracks, cap_hits;   /* [host] */
   int32_t* n_tracks;              /* [1] */

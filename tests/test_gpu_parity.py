@@ -239,3 +239,57 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
     srv = Server(pool, 0, n_slots=2)
     res = srv.run(make_stream(8, 12, rate_hz=200.0, coll_range=(2, 6), seed=63), realtime=False)
     assert res["n_chunks"] == 12 and res["p99_ms"] >= res["p50_ms"] > 0
+
+
+def test_output_capacity_reports_required_sizes_and_truncates():
+    """Outputs smaller than needed: TPC_E_CAPACITY, n_tracks = the required count, the
+    tracks and hits that fit equal the full result's, nothing beyond the capacities is
+    written (guard values survive)."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2402_01205_amd import tpc as T
+    cs = g.make_config("c1", 12)
+    full = gpu_run(cs, stages=False)["tracks"]
+    K, H = full["n"], int(full["off"][-1])
+    assert K > 40
+    for cap_t, cap_h in ((40, H + 10), (K + 5, 1000)):
+        tr = T.Tracker(0)
+        ev = T.DeviceClusters.from_set(cs, "cuda:0")
+        tr.tpc_grid_build(ev)
+        tr.tpc_find_neighbours()
+        tr.tpc_construct_tracklets()
+        tr.tpc_select_tracks()
+        dev = "cuda:0"
+        guard = 7
+        o = dict(n_tracks=torch.zeros(1, dtype=torch.int32, device=dev),
+                 hit_off=torch.full((cap_t + 1 + guard,), -7, dtype=torch.int32, device=dev),
+                 hits=torch.full((cap_h + guard,), -7, dtype=torch.int32, device=dev),
+                 param=torch.full((cap_t + guard, 5), -7.0, device=dev),
+                 cov=torch.full((cap_t + guard, 15), -7.0, device=dev),
+                 x_ref=torch.full((cap_t + guard,), -7.0, device=dev),
+                 chi2=torch.full((cap_t + guard,), -7.0, device=dev),
+                 ndf=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
+                 sector=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
+                 job=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
+                 tracklet=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev))
+        out = T.tpc_tracks(cap_t, cap_h, *[C.c_void_p(o[k].data_ptr()) for k in (
+            "n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet")])
+        assert T.lib().tpc_fit_merge(tr.ctx, C.byref(out)) == T.TPC_OK
+        assert T.lib().tpc_sync(tr.ctx) == T.TPC_E_CAPACITY
+        torch.cuda.synchronize()
+        assert int(o["n_tracks"].item()) == K
+        kt = min(K, cap_t)
+        assert np.array_equal(o["param"][:kt].cpu().numpy().view(np.uint32), full["param"][:kt].view(np.uint32))
+        assert np.array_equal(o["hit_off"][:kt].cpu().numpy(), full["off"][:kt])
+        if K <= cap_t:
+            assert int(o["hit_off"][K].item()) == H
+        hits = o["hits"].cpu().numpy()
+        nh = min(cap_h, int(full["off"][kt]))
+        assert np.array_equal(hits[:nh], full["hits"][:nh])
+        for k in ("param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet"):
+            assert bool((o[k][cap_t:] == -7).all()), k
+        assert bool((o["hit_off"][cap_t + 1:] == -7).all())
+        assert (hits[cap_h:] == -7).all()
+
