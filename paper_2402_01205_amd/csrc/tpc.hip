@@ -505,10 +505,13 @@ __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, in
 }
 
 
-// start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order
+// start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order.
+// When the starts up to this batch's end (thi) exceed the capacity, ids and positions below
+// capT no longer pair up, so order[] becomes the identity: every kept id is then built.
 __global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit* gh,
                                const int32_t* fid, const int32_t* posg, const int32_t* T_off, int32_t* start,
-                               int32_t* order, int32_t capT, Bound lo_b, Bound hi_b, int32_t* counters) {
+                               int32_t* order, int32_t capT, Bound lo_b, Bound hi_b, Bound thi_b,
+                               int32_t* counters) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
@@ -522,7 +525,7 @@ __global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit*
   if (t - T_off[H.slot / kSlotsPerJob] > kLocalIdMax) atomicOr(&counters[kCntStatus], kStatusCapacity);
   if (order) {
     const int32_t p = posg[h];
-    if (p < capT) order[p] = t < capT ? t : -1;
+    if (p < capT) order[p] = thi_b.get() > capT ? p : t;
   }
 }
 
@@ -1775,7 +1778,7 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
   if (grid_order) scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
                      L.gh, L.fid, grid_order ? L.posg : nullptr, L.T_off, L.start,
-                     grid_order ? L.order : nullptr, L.capT, lo, hi, L.counters);
+                     grid_order ? L.order : nullptr, L.capT, lo, hi, db(L.T_off + j1), L.counters);
 }
 
 int64_t tbound(tpc_ctx* c, int j0, int j1) {

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import tpcsynth as g
-from tests.gpu_helpers import compare_all, gpu_run, oracle_run, say
+from tests.gpu_helpers import bits, compare_all, gpu_run, oracle_run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -293,3 +293,46 @@ def test_output_capacity_reports_required_sizes_and_truncates():
         assert bool((o["hit_off"][cap_t + 1:] == -7).all())
         assert (hits[cap_h:] == -7).all()
 
+
+def test_tracklet_capacity_overflow_is_reported_without_faults():
+    """More chain starts than the workspace holds (capT = N/8 + 1024): straight
+    five-cluster tracks, well apart, give one start per five clusters.  The library
+    reports TPC_E_CAPACITY, drops the tracklets beyond its capacity and stays within
+    bounds."""
+    from paper_2402_01205_amd.tpc import TPC_E_CAPACITY, default_tuning
+    x = 85 + np.arange(152) * 160 / 151
+    sec, row, y, z = [], [], [], []
+    for t, r0 in enumerate(range(0, 147, 6)):          # five rows, then one empty row
+        zs = np.arange(4.0, 246.0, 8.0) + (4.0 if t % 2 else 0.0)
+        half = x[r0] * np.tan(np.radians(10)) - 0.5
+        y0 = np.arange(-half, half, 4.0)
+        for k in range(5):
+            r = r0 + k
+            Y, Z = np.meshgrid(y0 * (x[r] / x[r0]), zs)   # radial lines: y proportional to x
+            sec.append(np.zeros(Y.size, np.uint8)); row.append(np.full(Y.size, r, np.int16))
+            y.append(Y.ravel().astype(np.float32)); z.append(Z.ravel().astype(np.float32))
+    n = sum(len(a) for a in y)
+    assert n // 5 > n // 8 + 1024
+    cs = g.ClusterSet(np.concatenate(sec), np.concatenate(row), np.concatenate(y), np.concatenate(z),
+                      np.zeros(n, np.float32), np.full(n, -1, np.int32), np.array([0, n], np.int32),
+                      np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                      np.zeros(0, np.int8), np.array([0, 0]), {})
+    o = oracle_run(cs)
+    ot = o["trk"]
+    # five-hit tracklets are below the ten hits of a track: no tracks
+    assert len(o["tracks"]["tracklet"]) == 0
+    for mode, tune in (("batched", None), ("persistent", dict(tracklet_order=0)),
+                       ("persistent", dict(persistent_refill=1))):
+        say("mode", mode, tune)
+        r = gpu_run(cs, mode=mode, tuning=tune and default_tuning(**tune))
+        assert r["status"] == TPC_E_CAPACITY
+        assert np.array_equal(r["up"], o["links"]["up"]) and np.array_equal(r["down"], o["links"]["down"])
+        gt = r["trk"]
+        T = len(gt["start"])
+        assert T == n // 8 + 1024 < len(ot["start"])        # the oracle has no such capacity
+        # the tracklets kept are the first ones in start order, and equal the oracle's
+        assert np.array_equal(gt["start"], ot["start"][:T])
+        assert np.array_equal(gt["off"], ot["off"][:T + 1])
+        assert np.array_equal(gt["hits"], ot["hits"][:gt["off"][-1]])
+        assert np.array_equal(bits(gt["P"]), bits(ot["P"][:T]))
+        assert r["tracks"]["n"] == 0
