@@ -97,6 +97,13 @@ def lib():
         L.orc_fit_hits_f64.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.orc_fit_hits_f32.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.orc_rotate_f64.argtypes = [P, P, P, P, C.c_int32, C.c_int32]
+        L.orc_compress.restype = C.c_int32
+        L.orc_compress.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, C.c_int32] + [P] * 6 + [
+            C.c_float, C.c_float, P, P, P, P]
+        L.orc_decompress.argtypes = [C.POINTER(Params), C.c_int32] + [P] * 5 + [C.c_int32, P, P, P] + [
+            C.c_float, C.c_float, P, P, P, P]
+        L.orc_predict.restype = C.c_int32
+        L.orc_predict.argtypes = [C.POINTER(Params), P, C.c_float, C.c_int32, C.c_int32, C.c_int32, P]
         _lib = L
     return _lib
 
@@ -262,3 +269,57 @@ def tri_to_full(Cv):
 
 def full_to_tri(M):
     return np.array([M[i, j] for i in range(5) for j in range(i + 1)], dtype=M.dtype)
+
+
+# ----------------------------------------------------------------- track-model compression
+
+def _headers(tracks):
+    K = len(tracks["off"]) - 1
+    g = lambda k, dt: np.ascontiguousarray(tracks[k], dt)
+    return K, g("off", np.int32), g("P", np.float32), g("x", np.float32), g("sector", np.int32), g("ndf", np.int32)
+
+
+def compress(sector, row, y, z, tracks, q_y, q_z, prm=None):
+    """C2-C4: records (rs, ey, ez) of every track hit in track order, then of the clusters in
+    no track in input order; returns dict(rs, ey, ez, n_attached, status).  `tracks` has the
+    keys of Run.tracks(): off, hits, P, x, sector, ndf."""
+    prm = prm or params()
+    sector = np.ascontiguousarray(sector, np.uint8)
+    row = np.ascontiguousarray(row, np.int16)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    K, off, P, x, ts, ndf = _headers(tracks)
+    hits = np.ascontiguousarray(tracks["hits"], np.int32)
+    n = len(y)
+    cap = int(off[-1]) + n
+    rs = np.zeros(cap, np.uint16)
+    ey = np.zeros(cap, np.int16)
+    ez = np.zeros(cap, np.int16)
+    st = np.zeros(1, np.int32)
+    m = lib().orc_compress(C.byref(prm), n, _p(sector), _p(row), _p(y), _p(z), K, _p(off), _p(hits), _p(P),
+                           _p(x), _p(ts), _p(ndf), q_y, q_z, _p(rs), _p(ey), _p(ez), _p(st))
+    return dict(rs=rs[:m], ey=ey[:m], ez=ez[:m], n_attached=int(off[-1]), status=int(st[0]))
+
+
+def decompress(tracks, codes, q_y, q_z, prm=None):
+    """C5: (sector, row, y, z) of every record, in stream order."""
+    prm = prm or params()
+    K, off, P, x, ts, ndf = _headers(tracks)
+    rs = np.ascontiguousarray(codes["rs"], np.uint16)
+    ey = np.ascontiguousarray(codes["ey"], np.int16)
+    ez = np.ascontiguousarray(codes["ez"], np.int16)
+    m = len(rs)
+    out = dict(sector=np.zeros(m, np.uint8), row=np.zeros(m, np.int16), y=np.zeros(m, np.float32),
+               z=np.zeros(m, np.float32))
+    lib().orc_decompress(C.byref(prm), K, _p(off), _p(P), _p(x), _p(ts), _p(ndf), m, _p(rs), _p(ey), _p(ez),
+                         q_y, q_z, *[_p(out[k]) for k in ("sector", "row", "y", "z")])
+    return out
+
+
+def predict(P, x_ref, sector_ref, sector, row, prm=None):
+    """C1: (ok, py, pz) for a cluster at (sector, row) of a track with state P at x_ref."""
+    prm = prm or params()
+    P = np.ascontiguousarray(P, np.float32)
+    yz = np.zeros(2, np.float32)
+    ok = lib().orc_predict(C.byref(prm), _p(P), x_ref, sector_ref, sector, row, _p(yz))
+    return bool(ok), yz[0], yz[1]

@@ -12,7 +12,8 @@
 // that reading (O1 frame/track model, O2 helix propagation, O3 grid (not
 // needed here: rows are searched in full or by binary search in z), O4
 // neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
-// O9 selection and fit, O10 merge).
+// O9 selection and fit, O10 merge), and C1-C5 for the track-model compression that
+// consumes the tracks (section 5).
 //
 // Only tests/, the smoke check and the CPU baseline leg of the benchmark may
 // load this library.  It shares no code, header, table or constant generator
@@ -32,7 +33,10 @@
 // brute-force triple search; chain/ownership invariants; zero-smear fits
 // recovering the truth.  The hit-picking heuristic of the tracklet following
 // (O7 window search) and the merge pairing (O10) are pinned only by invariants
-// and special cases: parity unpinned beyond those.
+// and special cases: parity unpinned beyond those.  Compression: the prediction
+// against an FP64 closed-form circle in the rotated frame, zero residual codes for
+// clusters placed exactly on the fitted helix, absolute codes against numpy's rint,
+// and the round trip within half a quantisation step.
 
 #include <algorithm>
 #include <cmath>
@@ -753,6 +757,119 @@ struct Oracle {
   }
 };
 
+// ---------------------------------------------------------------- C: track-model compression
+// Section 5: the clusters are stored as residuals to the fitted tracks instead of as
+// absolute coordinates, so that the entropy coder that follows sees small numbers.
+// The paper gives no format; the reading written out here (C1-C5):
+//  C1 The prediction for a cluster of track i at (sector s, row r) starts from the
+//     fitted state (y, z, sin phi, tan lambda, q/pT) at x_ref in the frame of the
+//     track's sector, turns it one sector at a time towards s (O10 rotation, state
+//     only, on the same side of the membrane, the shorter way round), then transports
+//     it to the plane x_r (O2, state only).  There is no prediction when the fit
+//     failed (ndf < 0), the sides differ, or a rotation or the transport fails.
+//  C2 With a prediction (py, pz) the codes are e = rint((v - p) * (1/q)) per coordinate,
+//     in FP32; if |e| > 32767 for either coordinate, or without prediction, the cluster
+//     takes absolute codes e = rint(v * (1/q)) and the flag "absolute".
+//  C3 Absolute codes saturate at +-32767 and raise the range status; an invalid cluster
+//     (sector >= 36, row outside 0..151, non-finite y or z, or a hit index outside the
+//     cluster list) is written as the record 0x7FFF with zero codes and raises it too.
+//  C4 Stream order: the hits of every track in track order, then every cluster that is
+//     in no track, in input order, with absolute codes.
+//  C5 Decoding: v = p + e*q for residual codes, v = e*q for absolute ones (FP32, each
+//     operation rounded once); the record gives sector and row.
+// The record of a cluster: rs = row | sector << 8 | absolute << 15, plus the two codes.
+constexpr uint16_t kRecInvalid = 0x7FFF;
+constexpr int kCodeMax = 32767;
+
+// C1, rotation step: the state part of O10 (rotate() above without the covariance).
+bool rotate_state(const Params& p, float* P, float& x, int from, int to) {
+  if (from / kRowsPerSide != to / kRowsPerSide) return false;
+  const int df = ((to % kRowsPerSide) - (from % kRowsPerSide) + kRowsPerSide) % kRowsPerSide;
+  if (df != 1 && df != kRowsPerSide - 1) return false;
+  const float ca = kGeo.cos20;
+  const float sa = df == 1 ? kGeo.sin20 : -kGeo.sin20;
+  const float s = P[2];
+  const float c = std::sqrt((1.f - s) * (1.f + s));
+  const float xn = x * ca + P[0] * sa;
+  const float yn = P[0] * ca - x * sa;
+  const float sn = s * ca - c * sa;
+  const float cn = c * ca + s * sa;
+  if (!(cn > 0.f) || !(std::fabs(sn) < p.smax)) return false;
+  P[0] = yn;
+  P[2] = sn;
+  x = xn;
+  for (int i = 0; i < 5; ++i)
+    if (!(P[i] - P[i] == 0.f)) return false;
+  return true;
+}
+
+// C1, transport: the state part of O2 (propagate() above without Jacobian and covariance).
+bool transport_state(const Params& p, float* P, float x1, float x2) {
+  const float dx = x2 - x1;
+  if (dx == 0.f) return true;
+  const float curv = P[4] * curvature_factor<float>(p);
+  const float s1 = P[2];
+  const float s2 = s1 + curv * dx;
+  if (!(std::fabs(s2) < p.smax)) return false;
+  const float c1 = std::sqrt((1.f - s1) * (1.f + s1));
+  const float c2 = std::sqrt((1.f - s2) * (1.f + s2));
+  const float f = (s1 + s2) / (c1 + c2);
+  const float dy = dx * f;
+  float ch = std::sqrt(dx * dx + dy * dy);
+  if (dx < 0.f) ch = -ch;
+  const float u = curv * ch * 0.5f;
+  if (!(std::fabs(u) < 1.f)) return false;
+  float A, B;
+  asinc(u, A, B);
+  P[0] = P[0] + dy;
+  P[1] = P[1] + P[3] * (ch * A);
+  P[2] = P[2] + curv * dx;
+  return true;
+}
+
+// C1: the predicted (y, z) of a cluster at (sec, row) of a track with fitted state Pfit.
+bool predict(const Params& p, const float* Pfit, float xref, int sref, int sec, int row, float& py,
+             float& pz) {
+  if (sref < 0 || sref >= kSectors || sec / kRowsPerSide != sref / kRowsPerSide) return false;
+  float P[5];
+  for (int i = 0; i < 5; ++i) P[i] = Pfit[i];
+  float x = xref;
+  const int steps = ((sec % kRowsPerSide) - (sref % kRowsPerSide) + kRowsPerSide) % kRowsPerSide;
+  const int dir = steps <= kRowsPerSide / 2 ? 1 : -1;
+  const int nst = dir == 1 ? steps : kRowsPerSide - steps;
+  int cur = sref;
+  for (int k = 0; k < nst; ++k) {
+    const int nxt = (cur / kRowsPerSide) * kRowsPerSide + (cur % kRowsPerSide + dir + kRowsPerSide) % kRowsPerSide;
+    if (!rotate_state(p, P, x, cur, nxt)) return false;
+    cur = nxt;
+  }
+  if (!transport_state(p, P, x, kGeo.x[row])) return false;
+  py = P[0];
+  pz = P[1];
+  return true;
+}
+
+bool cluster_ok(uint8_t sec, int16_t row, float y, float z) {
+  return sec < kSectors && row >= 0 && row < kRows && y - y == 0.f && z - z == 0.f;
+}
+
+// C3: absolute code with saturation.
+int16_t abs_code(float v, float iq, int32_t& status) {
+  float e = std::rint(v * iq);
+  if (e > (float)kCodeMax) { e = (float)kCodeMax; status |= 1; }
+  if (e < -(float)kCodeMax) { e = -(float)kCodeMax; status |= 1; }
+  return (int16_t)e;
+}
+
+struct TrackHeaders {
+  int32_t K;
+  const int32_t* off;
+  const float* param;
+  const float* x_ref;
+  const int32_t* sector;
+  const int32_t* ndf;
+};
+
 }  // namespace
 
 // ============================================================== C interface (ctypes)
@@ -927,6 +1044,89 @@ int32_t orc_fit_hits_f32(void* h, int32_t nh, const int32_t* hits, const float* 
   for (int i = 0; i < nh; ++i) hs[i] = o->sector[hits[i]];
   int32_t ndf;
   return o->fit<float>(v, stk, hs.back(), hs, P, C, *x, *chi2, ndf);
+}
+
+// C2-C4: encode n clusters against K tracks.  Writes H + U records (H = off[K] track
+// hits, U = clusters in no track); returns that count; *status gets 1 for C3's cases.
+int32_t orc_compress(const Params* p, int32_t n, const uint8_t* sector, const int16_t* row,
+                     const float* y, const float* z, int32_t K, const int32_t* off, const int32_t* hits,
+                     const float* param, const float* x_ref, const int32_t* tsec, const int32_t* ndf,
+                     float q_y, float q_z, uint16_t* rs, int16_t* ey, int16_t* ez, int32_t* status) {
+  const float iy = 1.0f / q_y, iz = 1.0f / q_z;
+  int32_t st = 0;
+  std::vector<uint8_t> in_track(n, 0);
+  int32_t m = 0;
+  auto put_abs = [&](int32_t h) {
+    if (!cluster_ok(sector[h], row[h], y[h], z[h])) {
+      rs[m] = kRecInvalid; ey[m] = 0; ez[m] = 0; st |= 1;
+      return;
+    }
+    rs[m] = (uint16_t)(row[h] | (sector[h] << 8) | (1 << 15));
+    ey[m] = abs_code(y[h], iy, st);
+    ez[m] = abs_code(z[h], iz, st);
+  };
+  for (int32_t i = 0; i < K; ++i) {
+    for (int32_t j = off[i]; j < off[i + 1]; ++j, ++m) {
+      const int32_t h = hits[j];
+      if (h < 0 || h >= n) { rs[m] = kRecInvalid; ey[m] = 0; ez[m] = 0; st |= 1; continue; }
+      in_track[h] = 1;
+      if (!cluster_ok(sector[h], row[h], y[h], z[h])) { put_abs(h); continue; }
+      float py, pz;
+      if (ndf[i] >= 0 && predict(*p, param + 5 * i, x_ref[i], tsec[i], sector[h], row[h], py, pz)) {
+        const float e1 = std::rint((y[h] - py) * iy);
+        const float e2 = std::rint((z[h] - pz) * iz);
+        if (std::fabs(e1) <= (float)kCodeMax && std::fabs(e2) <= (float)kCodeMax) {
+          rs[m] = (uint16_t)(row[h] | (sector[h] << 8));
+          ey[m] = (int16_t)e1;
+          ez[m] = (int16_t)e2;
+          continue;
+        }
+      }
+      put_abs(h);
+    }
+  }
+  for (int32_t h = 0; h < n; ++h)
+    if (!in_track[h]) { put_abs(h); ++m; }
+  *status = st;
+  return m;
+}
+
+// C5: decode m records; the first off[K] belong to the tracks in order.
+void orc_decompress(const Params* p, int32_t K, const int32_t* off, const float* param,
+                    const float* x_ref, const int32_t* tsec, const int32_t* ndf, int32_t m,
+                    const uint16_t* rs, const int16_t* ey, const int16_t* ez, float q_y, float q_z,
+                    uint8_t* sector, int16_t* row, float* y, float* z) {
+  int32_t i = 0;
+  for (int32_t j = 0; j < m; ++j) {
+    while (i < K && j >= off[i + 1]) ++i;
+    const int r = rs[j] & 0xFF, s = (rs[j] >> 8) & 0x7F;
+    const bool absolute = (rs[j] >> 15) != 0;
+    if (r >= kRows || s >= kSectors) {
+      sector[j] = 255; row[j] = -1; y[j] = NAN; z[j] = NAN;
+      continue;
+    }
+    sector[j] = (uint8_t)s;
+    row[j] = (int16_t)r;
+    const float dy = (float)ey[j] * q_y, dz = (float)ez[j] * q_z;
+    float py = 0.f, pz = 0.f;
+    if (!absolute) {
+      if (!(i < K && ndf[i] >= 0 && predict(*p, param + 5 * i, x_ref[i], tsec[i], s, r, py, pz))) {
+        y[j] = NAN; z[j] = NAN;
+        continue;
+      }
+      y[j] = py + dy;
+      z[j] = pz + dz;
+    } else {
+      y[j] = dy;
+      z[j] = dz;
+    }
+  }
+}
+
+// C1 alone (pins): returns 1 and (py, pz) when there is a prediction.
+int32_t orc_predict(const Params* p, const float* P, float xref, int32_t sref, int32_t sec, int32_t row,
+                    float* pyz) {
+  return predict(*p, P, xref, sref, sec, row, pyz[0], pyz[1]);
 }
 
 }  // extern "C"
