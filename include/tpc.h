@@ -174,7 +174,8 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 
 /* Per-kernel timing with HIP events recorded on the context's stream around the
  * launches of: the neighbour kernel (index 0), the tracklet kernel (1), the grid
- * build (2), the selection (3) and fit + merge (4).  While enabled, tpc_run does
+ * build (2), the selection (3), fit + merge (4), tpc_compress (5) and
+ * tpc_decompress (6).  While enabled, tpc_run does
  * not use a graph.  tpc_profile_read waits for the stream and returns the summed
  * milliseconds and the number of timed launches per index since the last reset. */
 #define TPC_PROF_LINKS 0
@@ -182,9 +183,58 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 #define TPC_PROF_GRID 2
 #define TPC_PROF_SELECT 3
 #define TPC_PROF_FIT_MERGE 4
-#define TPC_PROF_KERNELS 5
+#define TPC_PROF_COMPRESS 5   /* tpc_compress (all its kernels)   */
+#define TPC_PROF_DECOMPRESS 6 /* tpc_decompress (all its kernels) */
+#define TPC_PROF_KERNELS 7
 int tpc_profile(tpc_ctx* ctx, int enable);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
+
+/* Track-model compression (section 5: the clusters are stored as residuals to
+ * the fitted tracks instead of as absolute coordinates, which is why every
+ * collision must be tracked).  One record per stored cluster:
+ *   rs = row | sector << 8 | absolute << 15, and codes ey, ez (int16) in units
+ *   of the quantisation steps q_y, q_z (cm).
+ * Records 0 .. H-1 (H = hit_off[n_tracks]) are the track hits in track order:
+ * residual codes e = rint((v - p) / q) against the track's predicted position p
+ * at the cluster's pad row (the fitted state turned sector by sector to the
+ * cluster's sector, same side only, then transported along the helix to the
+ * row's plane; all FP32, round-half-even, q applied as the FP32 product with
+ * 1/q).  A hit whose track fit failed (ndf < 0), whose prediction fails, or
+ * whose residual code exceeds +-32767 is stored with absolute codes
+ * e = rint(v / q) and the absolute bit.  Records H .. are the clusters in no
+ * track, in input order, with absolute codes.  Absolute codes saturate at
+ * +-32767; an invalid cluster (sector >= 36, row outside 0..151, non-finite y
+ * or z) or a hit index outside 0..n-1 is stored as rs = 0x7FFF with zero codes.
+ * Both raise TPC_E_RANGE at tpc_sync.
+ * Decoding gives v = p + e*q for residual codes and v = e*q for absolute ones
+ * (each operation rounded once in FP32), so |v' - v| <= q/2 up to FP32
+ * rounding; the decoded clusters come in record order.                     */
+typedef struct {
+  int32_t cap;          /* [host] capacity of the record arrays                     */
+  int32_t* n_codes;     /* [1] records needed: track hits + clusters in no track    */
+  int32_t* n_attached;  /* [1] records of track hits, H                             */
+  uint16_t* rs;         /* [cap]                                                   */
+  int16_t* ey;          /* [cap]                                                   */
+  int16_t* ez;          /* [cap]                                                   */
+} tpc_codes;
+
+/* Encodes the clusters `c` (device) against tracks `t` (device arrays as written
+ * by tpc_fit_merge; n_tracks is read on the device and clamped to cap_tracks).
+ * Uses the context's workspace, so it needs a preceding tracking run (any
+ * stage) over at least c->n clusters; TPC_E_ARG otherwise, or for q <= 0.
+ * When the records exceed out->cap, nothing is written beyond it, *n_codes
+ * still holds the number needed and tpc_sync returns TPC_E_CAPACITY; track
+ * hits beyond t->cap_hits are not read (TPC_E_CAPACITY as well, and their
+ * clusters count as clusters in no track).  Runs on the context's stream.    */
+int tpc_compress(tpc_ctx* ctx, const tpc_clusters* c, const tpc_tracks* t, float q_y, float q_z,
+                 tpc_codes* out);
+/* Decodes min(*n_codes, cap) records of `in` against the same tracks (only
+ * n_tracks, hit_off, param, x_ref, sector and ndf are read) into sector, row,
+ * y, z [in->cap] (device).  An invalid record decodes to sector 255, row -1,
+ * y = z = NaN; a residual record without a prediction (a stream that does not
+ * belong to these tracks) to NaN coordinates and TPC_E_RANGE at tpc_sync.    */
+int tpc_decompress(tpc_ctx* ctx, const tpc_tracks* t, const tpc_codes* in, float q_y, float q_z,
+                   uint8_t* sector, int16_t* row, float* y, float* z);
 
 /* Wait for the context's stream; returns TPC_E_RANGE / TPC_E_CAPACITY if the
  * kernels reported one since the last tpc_grid_build, else TPC_OK.           */

@@ -1323,6 +1323,239 @@ __global__ void k_out_finish(const int32_t* oid, const int32_t* ooff, Bound hi_b
   if (K <= O.cap_tracks) O.hit_off[K] = H;
 }
 
+// ------------------------------------------------------------------ track-model compression
+// Clusters are stored as residuals to the fitted tracks (section 5): a record per cluster,
+// rs = row | sector << 8 | absolute << 15 and two int16 codes in units of the quantisation
+// steps.  Track hits come first, in track order, with residual codes against the track's
+// predicted position where it exists and fits in 16 bits, else absolute codes; then the
+// clusters in no track, in input order, with absolute codes.  0x7FFF marks an invalid
+// cluster (or a hit index outside the cluster list).
+constexpr uint32_t kRecInvalid = 0x7FFFu;
+constexpr float kCodeMax = 32767.f;
+
+struct CmpClusters {
+  const uint8_t* sector;
+  const int16_t* row;
+  const float* y;
+  const float* z;
+  int32_t n;
+};
+struct CmpTracks {
+  const int32_t* n_tracks;
+  int32_t cap_tracks, cap_hits;
+  const int32_t* off;
+  const int32_t* hits;
+  const float* param;
+  const float* x_ref;
+  const int32_t* sector;
+  const int32_t* ndf;
+};
+struct CmpCodes {
+  int32_t cap;
+  int32_t* n_codes;
+  int32_t* n_attached;
+  uint16_t* rs;
+  int16_t* ey;
+  int16_t* ez;
+};
+struct CmpOut {
+  uint8_t* sector;
+  int16_t* row;
+  float* y;
+  float* z;
+};
+
+__device__ __forceinline__ int32_t cmp_tracks(const CmpTracks& T) {
+  const int32_t k = *T.n_tracks;
+  return k < 0 ? 0 : min(k, T.cap_tracks);
+}
+__device__ __forceinline__ bool cmp_cluster_ok(int s, int r, float y, float z) {
+  return s < kSectors && r >= 0 && r < kRows && finite_f(y) && finite_f(z);
+}
+__device__ __forceinline__ int16_t abs_code(float v, float iq, int32_t& st) {
+  float e = rintf(v * iq);
+  if (e > kCodeMax) {
+    e = kCodeMax;
+    st |= kStatusRange;
+  }
+  if (e < -kCodeMax) {
+    e = -kCodeMax;
+    st |= kStatusRange;
+  }
+  return (int16_t)e;
+}
+// Absolute record of cluster h (or the invalid record).
+__device__ __forceinline__ void encode_abs(const CmpClusters& in, int32_t h, float iqy, float iqz, uint32_t& rs,
+                                           int16_t& ey, int16_t& ez, int32_t& st) {
+  const int s = in.sector[h], r = in.row[h];
+  const float yv = in.y[h], zv = in.z[h];
+  if (!cmp_cluster_ok(s, r, yv, zv)) {
+    rs = kRecInvalid;
+    ey = ez = 0;
+    st |= kStatusRange;
+    return;
+  }
+  rs = (uint32_t)r | ((uint32_t)s << 8) | (1u << 15);
+  ey = abs_code(yv, iqy, st);
+  ez = abs_code(zv, iqz, st);
+}
+
+// Track hits: one wave per track (grid-stride), one lane per hit; flag[h] = 0 marks the
+// cluster as stored.
+__global__ __launch_bounds__(256) void k_cmp_tracks(CmpClusters in, CmpTracks T, CmpCodes O, int32_t* flag,
+                                                    Consts k, float iqy, float iqz, int32_t* counters) {
+  const int32_t K = cmp_tracks(T);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t w_first = xcd_tile(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+  int32_t st = 0;
+  for (int64_t w = w_first; w < K; w += nw) {
+    const int32_t i = (int32_t)w;
+    const int32_t a = max(T.off[i], 0);
+    int32_t b = T.off[i + 1];
+    if (b > T.cap_hits) {
+      b = T.cap_hits;
+      st |= kStatusCapacity;
+    }
+    float P[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) P[q] = T.param[(int64_t)i * 5 + q];
+    const float xr = T.x_ref[i];
+    const int sref = T.sector[i];
+    const bool fit_ok = T.ndf[i] >= 0;
+    for (int32_t j = a + lane; j < b; j += 64) {
+      // every hit is marked, also beyond the record capacity: the count of records needed
+      // must not depend on it
+      const int32_t h = T.hits[j];
+      const bool valid = (uint32_t)h < (uint32_t)in.n;
+      if (valid) flag[h] = 0;
+      if (j >= O.cap) {
+        st |= kStatusCapacity;
+        continue;
+      }
+      uint32_t rs;
+      int16_t ey = 0, ez = 0;
+      if (!valid) {
+        rs = kRecInvalid;
+        st |= kStatusRange;
+      } else {
+        const int s = in.sector[h], r = in.row[h];
+        const float yv = in.y[h], zv = in.z[h];
+        bool done = false;
+        float py, pz;
+        if (cmp_cluster_ok(s, r, yv, zv) && fit_ok && predict_yz(P, xr, sref, s, r, k, py, pz)) {
+          const float e1 = rintf((yv - py) * iqy);
+          const float e2 = rintf((zv - pz) * iqz);
+          if (fabsf(e1) <= kCodeMax && fabsf(e2) <= kCodeMax) {
+            rs = (uint32_t)r | ((uint32_t)s << 8);
+            ey = (int16_t)e1;
+            ez = (int16_t)e2;
+            done = true;
+          }
+        }
+        if (!done) encode_abs(in, h, iqy, iqz, rs, ey, ez, st);
+      }
+      O.rs[j] = (uint16_t)rs;
+      O.ey[j] = ey;
+      O.ez[j] = ez;
+    }
+  }
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
+// Clusters in no track: record H + (rank among them in input order), absolute codes.
+__global__ __launch_bounds__(256) void k_cmp_free(CmpClusters in, CmpTracks T, CmpCodes O, const int32_t* flag,
+                                                  const int32_t* rank, float iqy, float iqz, int32_t* counters) {
+  const int32_t K = cmp_tracks(T);
+  const int32_t H = K > 0 ? max(T.off[K], 0) : 0;
+  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *O.n_codes = H + rank[in.n];
+    *O.n_attached = H;
+  }
+  if (i >= in.n || !flag[i]) return;
+  const int64_t pos = (int64_t)H + rank[i];
+  int32_t st = 0;
+  if (pos >= O.cap) {
+    st |= kStatusCapacity;
+  } else {
+    uint32_t rs;
+    int16_t ey, ez;
+    encode_abs(in, (int32_t)i, iqy, iqz, rs, ey, ez, st);
+    O.rs[pos] = (uint16_t)rs;
+    O.ey[pos] = ey;
+    O.ez[pos] = ez;
+  }
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
+// One record back to (sector, row, y, z); P == nullptr: no track.
+__device__ __forceinline__ void decode_one(const CmpCodes& C, const CmpOut& D, int32_t j, const float* P, float xr,
+                                           int sref, bool fit_ok, float qy, float qz, const Consts& k, int32_t& st) {
+  const uint32_t rs = C.rs[j];
+  const int r = rs & 0xFF, s = (rs >> 8) & 0x7F;
+  const bool absolute = (rs >> 15) != 0;
+  const float nan = __builtin_nanf("");
+  if (r >= kRows || s >= kSectors) {
+    D.sector[j] = 255;
+    D.row[j] = -1;
+    D.y[j] = nan;
+    D.z[j] = nan;
+    return;
+  }
+  D.sector[j] = (uint8_t)s;
+  D.row[j] = (int16_t)r;
+  const float dy = (float)C.ey[j] * qy, dz = (float)C.ez[j] * qz;
+  if (absolute) {
+    D.y[j] = dy;
+    D.z[j] = dz;
+    return;
+  }
+  float py, pz;
+  if (P && fit_ok && predict_yz(P, xr, sref, s, r, k, py, pz)) {
+    D.y[j] = py + dy;
+    D.z[j] = pz + dz;
+  } else {
+    D.y[j] = nan;
+    D.z[j] = nan;
+    st |= kStatusRange;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dcmp_tracks(CmpTracks T, CmpCodes C, CmpOut D, Consts k, float qy,
+                                                     float qz, int32_t* counters) {
+  const int32_t K = cmp_tracks(T);
+  const int32_t m = min(min(*C.n_codes, *C.n_attached), C.cap);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t w_first = xcd_tile(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+  int32_t st = 0;
+  for (int64_t w = w_first; w < K; w += nw) {
+    const int32_t i = (int32_t)w;
+    const int32_t a = T.off[i], b = min(T.off[i + 1], m);
+    float P[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) P[q] = T.param[(int64_t)i * 5 + q];
+    const float xr = T.x_ref[i];
+    const int sref = T.sector[i];
+    const bool fit_ok = T.ndf[i] >= 0;
+    for (int32_t j = max(a, 0) + lane; j < b; j += 64) decode_one(C, D, j, P, xr, sref, fit_ok, qy, qz, k, st);
+  }
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
+__global__ __launch_bounds__(256) void k_dcmp_free(CmpCodes C, CmpOut D, Consts k, float qy, float qz,
+                                                   int32_t* counters) {
+  const int32_t m = min(*C.n_codes, C.cap);
+  const int64_t j = (int64_t)max(*C.n_attached, 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  int32_t st = 0;
+  decode_one(C, D, (int32_t)j, nullptr, 0.f, 0, false, qy, qz, k, st);
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
 // ------------------------------------------------------------------ test hooks
 __global__ void k_links_to_input(const int32_t* a, const int32_t* b, const GHit* gh, int32_t* oa,
                                  int32_t* ob, Bound hi_b) {
@@ -2331,6 +2564,78 @@ int tpc_get_selected(tpc_ctx* c, int32_t* tr, int32_t* off, int32_t* hits) {
                      c->L.sel_off, c->L.sel_hits, c->L.gh, K, tr, off, hits);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPC_OK;
+}
+
+namespace {
+bool cmp_tracks_ok(const tpc_tracks* t) {
+  return t && t->cap_tracks >= 0 && t->cap_hits >= 0 && t->n_tracks && t->hit_off &&
+         (t->cap_hits == 0 || t->hits) &&
+         (t->cap_tracks == 0 || (t->param && t->x_ref && t->sector && t->ndf));
+}
+bool cmp_codes_ok(const tpc_codes* o) {
+  return o && o->cap >= 0 && o->n_codes && o->n_attached && (o->cap == 0 || (o->rs && o->ey && o->ez));
+}
+bool steps_ok(float q_y, float q_z) {
+  return q_y > 0.f && q_z > 0.f && std::isfinite(q_y) && std::isfinite(q_z) && std::isfinite(1.0f / q_y) &&
+         std::isfinite(1.0f / q_z);
+}
+CmpTracks tracks_view(const tpc_tracks* t) {
+  return CmpTracks{t->n_tracks, t->cap_tracks, t->cap_hits, t->hit_off, t->hits, t->param, t->x_ref, t->sector,
+                   t->ndf};
+}
+CmpCodes codes_view(const tpc_codes* o) {
+  return CmpCodes{o->cap, o->n_codes, o->n_attached, o->rs, o->ey, o->ez};
+}
+}  // namespace
+
+int tpc_compress(tpc_ctx* c, const tpc_clusters* in, const tpc_tracks* t, float q_y, float q_z, tpc_codes* out) {
+  if (!c) return TPC_E_ARG;
+  if (!in || !cmp_tracks_ok(t) || !cmp_codes_ok(out)) return fail(c, TPC_E_ARG, "tpc_compress: null or negative argument");
+  if (!steps_ok(q_y, q_z)) return fail(c, TPC_E_ARG, "tpc_compress: quantisation steps must be positive and finite");
+  if (in->n < 0 || (in->n > 0 && (!in->sector || !in->row || !in->y || !in->z)))
+    return fail(c, TPC_E_ARG, "tpc_compress: invalid cluster list");
+  if (!c->laid_out || (int64_t)in->n > c->L.N)
+    return fail(c, TPC_E_ARG, "tpc_compress: needs the workspace of a tracking run over at least n clusters");
+  HIPCHK(c, hipSetDevice(c->device));
+  Layout& L = c->L;
+  const float iqy = 1.0f / q_y, iqz = 1.0f / q_z;
+  const CmpClusters cl{in->sector, in->row, in->y, in->z, in->n};
+  const CmpTracks T = tracks_view(t);
+  const CmpCodes O = codes_view(out);
+  const int pm = prof_begin(c, TPC_PROF_COMPRESS);
+  fill_i32(c, L.flag, in->n, 1);
+  if (t->cap_tracks > 0)
+    hipLaunchKernelGGL(k_cmp_tracks, dim3(wave_grid(c, t->cap_tracks)), dim3(256), 0, c->stream, cl, T, O, L.flag,
+                       c->k, iqy, iqz, L.counters);
+  scan(c, L.flag, L.fid, Bound{nullptr, 0, INT32_MAX}, Bound{nullptr, in->n, INT32_MAX}, in->n, false);
+  hipLaunchKernelGGL(k_cmp_free, dim3(blocks_for(std::max(in->n, 1), 256)), dim3(256), 0, c->stream, cl, T, O,
+                     L.flag, L.fid, iqy, iqz, L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_decompress(tpc_ctx* c, const tpc_tracks* t, const tpc_codes* in, float q_y, float q_z, uint8_t* sector,
+                   int16_t* row, float* y, float* z) {
+  if (!c) return TPC_E_ARG;
+  if (!cmp_tracks_ok(t) || !cmp_codes_ok(in) || (in->cap > 0 && (!sector || !row || !y || !z)))
+    return fail(c, TPC_E_ARG, "tpc_decompress: null or negative argument");
+  if (!steps_ok(q_y, q_z)) return fail(c, TPC_E_ARG, "tpc_decompress: quantisation steps must be positive and finite");
+  if (!c->laid_out) return fail(c, TPC_E_ARG, "tpc_decompress: needs a context that has run a tracking stage");
+  HIPCHK(c, hipSetDevice(c->device));
+  const CmpTracks T = tracks_view(t);
+  const CmpCodes C = codes_view(in);
+  const CmpOut D{sector, row, y, z};
+  const int pm = prof_begin(c, TPC_PROF_DECOMPRESS);
+  if (t->cap_tracks > 0 && in->cap > 0)
+    hipLaunchKernelGGL(k_dcmp_tracks, dim3(wave_grid(c, t->cap_tracks)), dim3(256), 0, c->stream, T, C, D, c->k,
+                       q_y, q_z, c->L.counters);
+  if (in->cap > 0)
+    hipLaunchKernelGGL(k_dcmp_free, dim3(blocks_for(in->cap, 256)), dim3(256), 0, c->stream, C, D, c->k, q_y, q_z,
+                       c->L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
   return TPC_OK;
 }
 

@@ -300,6 +300,81 @@ __device__ __forceinline__ bool rotate(State& S, float& x, int from, int to, con
   return fin;
 }
 
+// ---- track-model compression: the predicted position of a cluster on a fitted track
+// (the state parts of rotate() and propagate(), same operations in the same order).
+
+// One sector turn of the state (y, z, sin phi, tan lambda, q/pT) at plane x; same side only.
+__device__ __forceinline__ bool rotate_state(float* P, float& x, int from, int to, const Consts& k) {
+  if (from / kHalf != to / kHalf) return false;
+  const int df = ((to % kHalf) - (from % kHalf) + kHalf) % kHalf;
+  if (df != 1 && df != kHalf - 1) return false;
+  const float ca = k.cos20;
+  const float sa = df == 1 ? k.sin20 : -k.sin20;
+  const float s = P[2];
+  const float c = sqrt_rn((1.f - s) * (1.f + s));
+  const float xn = x * ca + P[0] * sa;
+  const float yn = P[0] * ca - x * sa;
+  const float sn = s * ca - c * sa;
+  const float cn = c * ca + s * sa;
+  if (!(cn > 0.f) || !(fabsf(sn) < k.smax)) return false;
+  P[0] = yn;
+  P[2] = sn;
+  x = xn;
+  bool fin = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) fin = fin && finite_f(P[i]);
+  return fin;
+}
+
+// Helix transport of the state alone from plane x1 to plane x2.
+__device__ __forceinline__ bool transport_state(float* P, float x1, float x2, const Consts& k) {
+  const float dx = x2 - x1;
+  if (dx == 0.f) return true;
+  const float curv = P[4] * k.cb;
+  const float s1 = P[2];
+  const float s2 = s1 + curv * dx;
+  if (!(fabsf(s2) < k.smax)) return false;
+  const float c1 = sqrt_rn((1.f - s1) * (1.f + s1));
+  const float c2 = sqrt_rn((1.f - s2) * (1.f + s2));
+  const float f = div_rn(s1 + s2, c1 + c2);
+  const float dy = dx * f;
+  float ch = sqrt_rn(dx * dx + dy * dy);
+  if (dx < 0.f) ch = -ch;
+  const float u = curv * ch * 0.5f;
+  if (!(fabsf(u) < 1.f)) return false;
+  float A, B;
+  asinc(u, A, B);
+  P[0] = P[0] + dy;
+  P[1] = P[1] + P[3] * (ch * A);
+  P[2] = P[2] + curv * dx;
+  return true;
+}
+
+// Predicted (y, z) at pad row `row` of sector `sec` for a track fitted to state Pf at plane
+// xref in the frame of sector sref: the state is turned one sector at a time towards `sec`
+// (the shorter way round, same side of the membrane), then transported to the row's plane.
+__device__ __forceinline__ bool predict_yz(const float* Pf, float xref, int sref, int sec, int row,
+                                           const Consts& k, float& py, float& pz) {
+  if (sref < 0 || sref >= kSectors || sec / kHalf != sref / kHalf) return false;
+  float P[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) P[i] = Pf[i];
+  float x = xref;
+  const int steps = ((sec % kHalf) - (sref % kHalf) + kHalf) % kHalf;
+  const int dir = steps <= kHalf / 2 ? 1 : -1;
+  const int nst = dir == 1 ? steps : kHalf - steps;
+  int cur = sref;
+  for (int i = 0; i < nst; ++i) {
+    const int nxt = (cur / kHalf) * kHalf + (cur % kHalf + dir + kHalf) % kHalf;
+    if (!rotate_state(P, x, cur, nxt, k)) return false;
+    cur = nxt;
+  }
+  if (!transport_state(P, x, k.x[row], k)) return false;
+  py = P[0];
+  pz = P[1];
+  return true;
+}
+
 // chi2 = d^T (CA + CB)^-1 d by a 5x5 Cholesky factorisation in fixed order.
 __device__ __forceinline__ float merge_chi2(const float* PA, const float* CA, const float* PB,
                                             const float* CB) {

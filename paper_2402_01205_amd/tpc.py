@@ -58,6 +58,14 @@ class tpc_tracks(C.Structure):
                                   "ndf", "sector", "job", "tracklet")]
 
 
+class tpc_codes(C.Structure):
+    _fields_ = [("cap", C.c_int32)] + [(n, C.c_void_p) for n in ("n_codes", "n_attached", "rs", "ey", "ez")]
+
+
+# Default quantisation step of the compressed coordinates (cm): a power of two, so that
+# 1/q and e*q are exact in FP32; q/sqrt(12) = 0.009 cm against 0.1 cm cluster errors.
+Q_STEP = 1.0 / 32.0
+
 _lib = None
 
 
@@ -105,6 +113,8 @@ def lib():
         L.tpc_profile.argtypes = [V, I]
         L.tpc_copy_probe.argtypes = [V, V, V, C.c_size_t]
         L.tpc_profile_read.argtypes = [V, V, V, C.c_int32, C.c_int32]
+        L.tpc_compress.argtypes = [V, P(tpc_clusters), P(tpc_tracks), C.c_float, C.c_float, P(tpc_codes)]
+        L.tpc_decompress.argtypes = [V, P(tpc_tracks), P(tpc_codes), C.c_float, C.c_float, V, V, V, V]
         _lib = L
     return _lib
 
@@ -115,8 +125,8 @@ EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_c
             "tpc_construct_tracklets", "tpc_select_tracks", "tpc_fit_merge", "tpc_run", "tpc_sync",
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
-            "tpc_profile", "tpc_profile_read", "tpc_copy_probe"]
-PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge"]
+            "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress"]
+PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress"]
 
 
 def default_params(**over) -> tpc_params:
@@ -272,6 +282,54 @@ class Tracker:
 
     def tpc_sync(self):
         self._check(lib().tpc_sync(self.ctx), "tpc_sync")
+
+    # ---- track-model compression of the current clusters against the current tracks
+    def tpc_compress(self, q_y: float = Q_STEP, q_z: float = Q_STEP, cap: int | None = None) -> dict:
+        """Enqueues tpc_compress; returns the record buffers (device tensors, rs stored as int16)."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        cap = max(self._keep.n, 1) if cap is None else cap
+        cd = getattr(self, "codes", None)
+        if cd is None or cd["cap"] != cap:
+            i32, i16 = torch.int32, torch.int16
+            cd = dict(cap=cap, n_codes=torch.zeros(1, dtype=i32, device=dev),
+                      n_attached=torch.zeros(1, dtype=i32, device=dev),
+                      rs=torch.zeros(max(cap, 1), dtype=i16, device=dev),
+                      ey=torch.zeros(max(cap, 1), dtype=i16, device=dev),
+                      ez=torch.zeros(max(cap, 1), dtype=i16, device=dev))
+            self.codes = cd
+        cd["q"] = (q_y, q_z)
+        self._codes = tpc_codes(cap, *[_ptr(cd[k]) for k in ("n_codes", "n_attached", "rs", "ey", "ez")])
+        self._check(lib().tpc_compress(self.ctx, C.byref(self._cl), C.byref(self._tracks), q_y, q_z,
+                                       C.byref(self._codes)), "tpc_compress")
+        return cd
+
+    def tpc_decompress(self, out: dict | None = None) -> dict:
+        """Enqueues tpc_decompress of the last records against the current tracks into device
+        tensors sector, row, y, z [cap]."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        cd = self.codes
+        cap = max(cd["cap"], 1)
+        if out is None:
+            out = dict(sector=torch.zeros(cap, dtype=torch.uint8, device=dev),
+                       row=torch.zeros(cap, dtype=torch.int16, device=dev),
+                       y=torch.zeros(cap, dtype=torch.float32, device=dev),
+                       z=torch.zeros(cap, dtype=torch.float32, device=dev))
+        q_y, q_z = cd["q"]
+        self._check(lib().tpc_decompress(self.ctx, C.byref(self._tracks), C.byref(self._codes), q_y, q_z,
+                                         *[_ptr(out[k]) for k in ("sector", "row", "y", "z")]),
+                    "tpc_decompress")
+        return out
+
+    def codes_numpy(self) -> dict:
+        """The records of the last tpc_compress (waits for the stream; no error check)."""
+        self.torch.cuda.synchronize(self.device)
+        cd = self.codes
+        m = min(int(cd["n_codes"].item()), cd["cap"])
+        return dict(n_codes=int(cd["n_codes"].item()), n_attached=int(cd["n_attached"].item()),
+                    rs=cd["rs"][:m].cpu().numpy().view(np.uint16), ey=cd["ey"][:m].cpu().numpy(),
+                    ez=cd["ez"][:m].cpu().numpy())
 
     run = tpc_run
     sync = tpc_sync

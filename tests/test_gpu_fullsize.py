@@ -37,9 +37,10 @@ def _properties(cs, t):
             assert np.all(np.diff(cs.row[h[a:b]]) > 0)
 
 
-def test_batched_workload_full_size_sampled_jobs():
+@pytest.fixture(scope="module")
+def c4():
+    """The 512-job workload tracked once in the benchmark's launch configuration."""
     from paper_2402_01205_amd.tpc import DeviceClusters
-    sizes = g.c4_job_sizes(41)
     say("generating the 512-job workload")
     cs = g.make_config("c4", 41)
     say("clusters", cs.n)
@@ -49,11 +50,20 @@ def test_batched_workload_full_size_sampled_jobs():
     tr.run(ev)          # graph replay
     t = tr.tracks()
     say("tracks", t["n"])
-    _properties(cs, t)
+    sizes = g.c4_job_sizes(41)
     jobs = sorted({0, 137, 511, int(np.argmax(sizes)), int(np.argmin(sizes))})
+    refs = {}
     for j in jobs:
-        sub = cs.job(j)
-        ref = O.Run.from_set(sub).tracks()
+        refs[j] = O.Run.from_set(cs.job(j)).tracks()
+        say("oracle job", j, "tracks", len(refs[j]["tracklet"]))
+    return dict(cs=cs, tr=tr, ev=ev, t=t, jobs=jobs, refs=refs)
+
+
+def test_batched_workload_full_size_sampled_jobs(c4):
+    cs, t = c4["cs"], c4["t"]
+    _properties(cs, t)
+    for j in c4["jobs"]:
+        ref = c4["refs"][j]
         sel = np.nonzero(t["job"] == j)[0]
         a = cs.job_off[j]
         assert len(sel) == len(ref["tracklet"]), (j, len(sel), len(ref["tracklet"]))
@@ -65,6 +75,46 @@ def test_batched_workload_full_size_sampled_jobs():
         assert np.array_equal(bits(t["param"][sel][good]), bits(ref["P"][good]))
         check_fp64(dict(ndf=t["ndf"][sel], param=t["param"][sel]), ref)
         say("job", j, "tracks", len(sel), "bit-exact")
+
+
+def test_compression_full_size(c4):
+    """Track-model compression of the whole workload: records of the sampled jobs' tracks
+    bit-exact with the oracle's compression of those jobs; the records of clusters in no
+    track are the rounded absolute values (numpy); every cluster decodes within q/2."""
+    cs, tr, t = c4["cs"], c4["tr"], c4["t"]
+    q = 1.0 / 32.0
+    tr.tpc_compress(q, q)
+    tr.sync()
+    gc = tr.codes_numpy()
+    H = int(t["off"][-1])
+    assert gc["n_codes"] == cs.n and gc["n_attached"] == H
+    for j in c4["jobs"]:
+        ref = c4["refs"][j]
+        sub = cs.job(j)
+        oc = O.compress(sub.sector, sub.row, sub.y, sub.z, ref, q, q)
+        sel = np.nonzero(t["job"] == j)[0]
+        pos = np.concatenate([np.arange(t["off"][i], t["off"][i + 1]) for i in sel]) if len(sel) else np.zeros(0, int)
+        Hj = oc["n_attached"]
+        assert len(pos) == Hj
+        assert np.array_equal(gc["rs"][pos], oc["rs"][:Hj]) and np.array_equal(gc["ey"][pos], oc["ey"][:Hj])
+        assert np.array_equal(gc["ez"][pos], oc["ez"][:Hj])
+        say("job", j, "track-hit records", Hj, "bit-exact")
+    free = np.ones(cs.n, bool)
+    free[t["hits"]] = False
+    rest = np.nonzero(free)[0]
+    iq = np.float32(1.0) / np.float32(q)
+    assert np.array_equal(gc["ey"][H:], np.rint(cs.y[rest] * iq).astype(np.int16))
+    assert np.array_equal(gc["ez"][H:], np.rint(cs.z[rest] * iq).astype(np.int16))
+    assert np.all(gc["rs"][H:] >> 15 == 1)
+    d = tr.tpc_decompress()
+    tr.sync()
+    perm = np.concatenate([t["hits"], rest]).astype(np.int64)
+    for k, v in (("sector", cs.sector), ("row", cs.row)):
+        assert np.array_equal(d[k][:cs.n].cpu().numpy(), v[perm])
+    for k, v in (("y", cs.y), ("z", cs.z)):
+        assert np.abs(d[k][:cs.n].cpu().numpy() - v[perm]).max() <= q / 2 + 1e-4
+    res = (gc["rs"][:H] >> 15) == 0
+    say("records", gc["n_codes"], "residual", int(res.sum()), "absolute", int(cs.n - res.sum()))
 
 
 def test_timeframe_full_size_sampled_sectors():
