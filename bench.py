@@ -6,7 +6,9 @@ selection, fit and sector merge) over the workload's clusters, already resident
 in HBM.  The default workload is the batched form: 512 single-sector jobs of
 100..20000 primaries (log-uniform), ~89M clusters, tracked by one chain of
 persistent launches captured in a hipGraph; the same data is also run through
-the plain path (one launch sequence per sector-job) for comparison.
+the plain path (one launch sequence per sector-job) for comparison.  After the
+tracking, the track-model compression of the same clusters against the tracks
+found (and its decoding) is timed on its own; it is not part of the step.
 
 Prints one JSON line (see the keys below).  Only --gpus 1 is supported.
 """
@@ -41,6 +43,14 @@ SEEDS = {"c1": 11, "c2": 21, "c3": 31, "c4": 41}
 LINK_BYTES_PER_CLUSTER = 26
 TRK_BYTES_PER_HIT = 36
 TRK_BYTES_PER_TRACKLET = 88
+#  compression     : per cluster: sector, row, y, z read (11) + record written (6); per track
+#                    hit: its cluster index (4); per track: hit offset, state, x_ref, sector,
+#                    ndf (36)
+#  decompression   : per cluster: record read (6) + sector, row, y, z written (11); per track 36
+CMP_BYTES_PER_CLUSTER = 17
+CMP_BYTES_PER_HIT = 4
+CMP_BYTES_PER_TRACK = 36
+Q_STEP = 1.0 / 32.0
 
 
 def log(*a):
@@ -168,6 +178,57 @@ def default_tuning_from(t):
     return default_tuning(**{k: getattr(t, k) for k, _ in t._fields_})
 
 
+def _entropy_bits(v) -> float:
+    """Order-0 entropy (bits per value) of an int16 stream."""
+    if len(v) == 0:
+        return 0.0
+    c = np.bincount(v.astype(np.int64) + 32768, minlength=65536)
+    p = c[c > 0] / len(v)
+    return float(-(p * np.log2(p)).sum())
+
+
+def compression_run(tr, cs, tracks, steps, log):
+    """Track-model compression of the clusters against the tracks just found, and decoding:
+    times (HIP events on the library's stream), roofline of the compression call, and the
+    order-0 entropy of the record streams against all-absolute records at the same step."""
+    tr.profile(True)
+    tr.profile_read(reset=True)
+    for _ in range(steps):
+        tr.tpc_compress(Q_STEP, Q_STEP)
+    for _ in range(steps):
+        tr.tpc_decompress()
+    prof = tr.profile_read(reset=True)
+    tr.profile(False)
+    tr.sync()
+    c_ms = prof["compress"][0] / max(1, prof["compress"][1])
+    d_ms = prof["decompress"][0] / max(1, prof["decompress"][1])
+    rec = tr.codes_numpy()
+    n, H, K = cs.n, rec["n_attached"], int(tracks["n"])
+    c_bytes = CMP_BYTES_PER_CLUSTER * n + CMP_BYTES_PER_HIT * H + CMP_BYTES_PER_TRACK * K
+    d_bytes = CMP_BYTES_PER_CLUSTER * n + CMP_BYTES_PER_TRACK * K
+    rs, ey, ez = rec["rs"], rec["ey"], rec["ez"]
+    res = (rs >> 15) == 0
+    streams = [rs.view(np.int16), ey[res], ez[res], ey[~res], ez[~res]]
+    bits = sum(_entropy_bits(v) * len(v) for v in streams) / max(n, 1)
+    iq = np.float32(1.0) / np.float32(Q_STEP)
+    ay = np.clip(np.rint(cs.y * iq), -32767, 32767).astype(np.int16)
+    az = np.clip(np.rint(cs.z * iq), -32767, 32767).astype(np.int16)
+    ars = (cs.row.astype(np.uint16) | (cs.sector.astype(np.uint16) << 8) | np.uint16(1 << 15)).view(np.int16)
+    bits_abs = _entropy_bits(ars) + _entropy_bits(ay) + _entropy_bits(az)
+    gbs = c_bytes / c_ms / 1e6
+    out = {"q_cm": Q_STEP, "ms": c_ms, "clusters_per_s": n / (c_ms / 1e3), "decompress_ms": d_ms,
+           "decompress_clusters_per_s": n / (d_ms / 1e3), "records": rec["n_codes"], "track_hit_records": H,
+           "residual_records": int(res.sum()),
+           "roofline": {"bound": "hbm", "kernel": "tpc_compress (all its kernels)", "achieved": gbs,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "algorithmic_bytes": c_bytes, "traffic": None},
+           "decompress_GBs": d_bytes / d_ms / 1e6,
+           "entropy_bits_per_cluster": bits, "entropy_bits_per_cluster_absolute": bits_abs,
+           "entropy_ratio": bits_abs / bits if bits else None}
+    log("compression: " + json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +329,13 @@ def main():
     tr.sync()
     log(f"batched ({args.mode}{'' if args.no_graph else ' + graph'}): {ms:.2f} ms/step")
     if args.profile_only:
+        # the compression kernels in the same trace, after the tracking steps
+        for _ in range(args.steps):
+            tr.tpc_compress(Q_STEP, Q_STEP)
+        for _ in range(args.steps):
+            tr.tpc_decompress()
+        tr.sync()
+        log(f"compression: {args.steps} encode and {args.steps} decode calls")
         print(json.dumps({"ms_per_step": ms, "sources": source_digest(),
                           "tuning": {k: getattr(tuning, k) for k, _ in tuning._fields_}}), flush=True)
         return
@@ -295,8 +363,9 @@ def main():
     traffic = None
     if trec and trec.get("read_bytes") is not None and trec.get("write_bytes") is not None:
         traffic = trec["read_bytes"] + trec["write_bytes"]
-    log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items()))
+    log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items() if v[1]))
     log("kernels: " + json.dumps(kern))
+    compression = compression_run(tr, cs, tracks, args.steps, log)
 
     # plain path on the same data
     plain_ms = None
@@ -374,7 +443,8 @@ def main():
         "serving": serving,
         "other_workloads": also,
         "tuning": tune_report["best"] if tune_report else None,
-        "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items() if v[1]},
+        "compression": compression,
         "tracks": int(tracks["n"]),
         "tracklets": int(T),
         "quality": q,

@@ -1384,26 +1384,40 @@ __device__ __forceinline__ int16_t abs_code(float v, float iq, int32_t& st) {
   }
   return (int16_t)e;
 }
-// Absolute record of cluster h (or the invalid record).
-__device__ __forceinline__ void encode_abs(const CmpClusters& in, int32_t h, float iqy, float iqz, uint32_t& rs,
-                                           int16_t& ey, int16_t& ez, int32_t& st) {
-  const int s = in.sector[h], r = in.row[h];
-  const float yv = in.y[h], zv = in.z[h];
-  if (!cmp_cluster_ok(s, r, yv, zv)) {
+// Packed copy of the clusters, written in one coalesced pass: (y, z, record word) in 16
+// bytes, so that a track hit costs one gather.  The record word is row | sector << 8, or
+// the invalid record.  The one-byte marks (1 = in no track) are set in the same pass and
+// cleared by the track hits: a byte array small enough to stay in the last-level cache
+// while the hits scatter into it.
+__global__ __launch_bounds__(256) void k_cmp_pack(CmpClusters in, int4* rec, uint8_t* free_mark) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= in.n) return;
+  const int s = in.sector[i], r = in.row[i];
+  const float yv = in.y[i], zv = in.z[i];
+  const uint32_t w = cmp_cluster_ok(s, r, yv, zv) ? ((uint32_t)r | ((uint32_t)s << 8)) : kRecInvalid;
+  rec[i] = make_int4(__float_as_int(yv), __float_as_int(zv), (int32_t)w, 0);
+  free_mark[i] = 1;
+}
+
+// Absolute record of a packed cluster (or the invalid record).
+__device__ __forceinline__ void encode_abs(const int4& R, float iqy, float iqz, uint32_t& rs, int16_t& ey,
+                                           int16_t& ez, int32_t& st) {
+  const uint32_t w = (uint32_t)R.z;
+  if (w == kRecInvalid) {
     rs = kRecInvalid;
     ey = ez = 0;
     st |= kStatusRange;
     return;
   }
-  rs = (uint32_t)r | ((uint32_t)s << 8) | (1u << 15);
-  ey = abs_code(yv, iqy, st);
-  ez = abs_code(zv, iqz, st);
+  rs = w | (1u << 15);
+  ey = abs_code(__int_as_float(R.x), iqy, st);
+  ez = abs_code(__int_as_float(R.y), iqz, st);
 }
 
-// Track hits: one wave per track (grid-stride), one lane per hit; flag[h] = 0 marks the
-// cluster as stored.
-__global__ __launch_bounds__(256) void k_cmp_tracks(CmpClusters in, CmpTracks T, CmpCodes O, int32_t* flag,
-                                                    Consts k, float iqy, float iqz, int32_t* counters) {
+// Track hits: one wave per track (grid-stride), one lane per hit.
+__global__ __launch_bounds__(256) void k_cmp_tracks(int32_t n, const int4* rec, uint8_t* free_mark, CmpTracks T,
+                                                    CmpCodes O, Consts k, float iqy, float iqz,
+                                                    int32_t* counters) {
   const int32_t K = cmp_tracks(T);
   const int lane = threadIdx.x & 63;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1425,36 +1439,41 @@ __global__ __launch_bounds__(256) void k_cmp_tracks(CmpClusters in, CmpTracks T,
     const int sref = T.sector[i];
     const bool fit_ok = T.ndf[i] >= 0;
     for (int32_t j = a + lane; j < b; j += 64) {
-      // every hit is marked, also beyond the record capacity: the count of records needed
-      // must not depend on it
       const int32_t h = T.hits[j];
-      const bool valid = (uint32_t)h < (uint32_t)in.n;
-      if (valid) flag[h] = 0;
+      const bool valid = (uint32_t)h < (uint32_t)n;
+      int4 R = make_int4(0, 0, (int32_t)kRecInvalid, 0);
+      if (valid) {
+        R = rec[h];
+        // every hit is marked, also beyond the record capacity: the count of records
+        // needed must not depend on it
+        free_mark[h] = 0;
+      }
       if (j >= O.cap) {
         st |= kStatusCapacity;
         continue;
       }
       uint32_t rs;
       int16_t ey = 0, ez = 0;
+      const uint32_t wd = (uint32_t)R.z;
       if (!valid) {
         rs = kRecInvalid;
         st |= kStatusRange;
       } else {
-        const int s = in.sector[h], r = in.row[h];
-        const float yv = in.y[h], zv = in.z[h];
+        const int r = wd & 0xFF, s = (wd >> 8) & 0x7F;
+        const float yv = __int_as_float(R.x), zv = __int_as_float(R.y);
         bool done = false;
         float py, pz;
-        if (cmp_cluster_ok(s, r, yv, zv) && fit_ok && predict_yz(P, xr, sref, s, r, k, py, pz)) {
+        if (wd != kRecInvalid && fit_ok && predict_yz(P, xr, sref, s, r, k, py, pz)) {
           const float e1 = rintf((yv - py) * iqy);
           const float e2 = rintf((zv - pz) * iqz);
           if (fabsf(e1) <= kCodeMax && fabsf(e2) <= kCodeMax) {
-            rs = (uint32_t)r | ((uint32_t)s << 8);
+            rs = wd;
             ey = (int16_t)e1;
             ez = (int16_t)e2;
             done = true;
           }
         }
-        if (!done) encode_abs(in, h, iqy, iqz, rs, ey, ez, st);
+        if (!done) encode_abs(R, iqy, iqz, rs, ey, ez, st);
       }
       O.rs[j] = (uint16_t)rs;
       O.ey[j] = ey;
@@ -1464,28 +1483,58 @@ __global__ __launch_bounds__(256) void k_cmp_tracks(CmpClusters in, CmpTracks T,
   if (st) atomicOr(&counters[kCntStatus], st);
 }
 
-// Clusters in no track: record H + (rank among them in input order), absolute codes.
-__global__ __launch_bounds__(256) void k_cmp_free(CmpClusters in, CmpTracks T, CmpCodes O, const int32_t* flag,
-                                                  const int32_t* rank, float iqy, float iqz, int32_t* counters) {
+// Clusters in no track (mark still set), counted per tile of kScanTile input indices; item q
+// of thread t is index tile * kScanTile + q * kScanThreads + t, so that the loads coalesce.
+__global__ __launch_bounds__(kScanThreads) void k_cmp_count(int32_t n, const uint8_t* free_mark, int32_t* bsum) {
+  __shared__ int lds[40];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t k = base + (int64_t)q * kScanThreads;
+    if (k < n && free_mark[k]) ++c;
+  }
+  int total;
+  block_excl_scan(c, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Their records: H + (rank among them in input order), absolute codes; bsum holds the
+// exclusive tile offsets and *n_free their sum.
+__global__ __launch_bounds__(kScanThreads) void k_cmp_free(int32_t n, const int4* rec, const uint8_t* free_mark,
+                                                          CmpTracks T, CmpCodes O, const int32_t* bsum,
+                                                          const int32_t* n_free, float iqy, float iqz,
+                                                          int32_t* counters) {
+  __shared__ int lds[40];
   const int32_t K = cmp_tracks(T);
   const int32_t H = K > 0 ? max(T.off[K], 0) : 0;
-  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    *O.n_codes = H + rank[in.n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *O.n_codes = H + *n_free;
     *O.n_attached = H;
   }
-  if (i >= in.n || !flag[i]) return;
-  const int64_t pos = (int64_t)H + rank[i];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  int64_t rank = (int64_t)H + bsum[blockIdx.x];
   int32_t st = 0;
-  if (pos >= O.cap) {
-    st |= kStatusCapacity;
-  } else {
-    uint32_t rs;
-    int16_t ey, ez;
-    encode_abs(in, (int32_t)i, iqy, iqz, rs, ey, ez, st);
-    O.rs[pos] = (uint16_t)rs;
-    O.ey[pos] = ey;
-    O.ez[pos] = ez;
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t k = base + (int64_t)q * kScanThreads;
+    const int m = (k < n && free_mark[k]) ? 1 : 0;
+    int tot;
+    const int r = block_excl_scan(m, lds, tot);
+    if (m) {
+      const int4 R = rec[k];
+      const int64_t pos = rank + r;
+      if (pos >= O.cap) {
+        st |= kStatusCapacity;
+      } else {
+        uint32_t rs;
+        int16_t ey, ez;
+        encode_abs(R, iqy, iqz, rs, ey, ez, st);
+        O.rs[pos] = (uint16_t)rs;
+        O.ey[pos] = ey;
+        O.ez[pos] = ez;
+      }
+    }
+    rank += tot;
   }
   if (st) atomicOr(&counters[kCntStatus], st);
 }
@@ -1694,6 +1743,8 @@ struct Layout {
   float *fitrow, *fitchi2;
   int32_t* fitndf;
   int32_t *T_off, *K_off, *counters, *bsum;
+  int4* cmp;         // compression: (y, z, record word, unused) per cluster
+  uint8_t* cmp_free;  // compression: 1 while no track holds the cluster
   // merge
   float* bucket_z;
   int32_t *trk_event, *bucket_cnt, *bucket_off, *bucket_fill, *bucket_trk, *chain_next, *chain_prev,
@@ -1780,6 +1831,8 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.ooff, L.capK + 1, t, set);
   carve(p, L.bestA, L.capK, t, set);
   carve(p, L.bestB, L.capK, t, set);
+  carve(p, L.cmp, N, t, set);
+  carve(p, L.cmp_free, N, t, set);
   L.bytes = t + 256;
 }
 
@@ -2604,13 +2657,18 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* in, const tpc_tracks* t, float 
   const CmpTracks T = tracks_view(t);
   const CmpCodes O = codes_view(out);
   const int pm = prof_begin(c, TPC_PROF_COMPRESS);
-  fill_i32(c, L.flag, in->n, 1);
+  const int nb = blocks_for(std::max(in->n, 1), 256);
+  hipLaunchKernelGGL(k_cmp_pack, dim3(nb), dim3(256), 0, c->stream, cl, L.cmp, L.cmp_free);
   if (t->cap_tracks > 0)
-    hipLaunchKernelGGL(k_cmp_tracks, dim3(wave_grid(c, t->cap_tracks)), dim3(256), 0, c->stream, cl, T, O, L.flag,
-                       c->k, iqy, iqz, L.counters);
-  scan(c, L.flag, L.fid, Bound{nullptr, 0, INT32_MAX}, Bound{nullptr, in->n, INT32_MAX}, in->n, false);
-  hipLaunchKernelGGL(k_cmp_free, dim3(blocks_for(std::max(in->n, 1), 256)), dim3(256), 0, c->stream, cl, T, O,
-                     L.flag, L.fid, iqy, iqz, L.counters);
+    hipLaunchKernelGGL(k_cmp_tracks, dim3(wave_grid(c, t->cap_tracks)), dim3(256), 0, c->stream, in->n, L.cmp,
+                       L.cmp_free, T, O, c->k, iqy, iqz, L.counters);
+  // clusters in no track: counts per tile, tile offsets (their sum in fid[n]), records
+  const int nt = blocks_for(std::max(in->n, 1), kScanTile);
+  hipLaunchKernelGGL(k_cmp_count, dim3(nt), dim3(kScanThreads), 0, c->stream, in->n, L.cmp_free, L.bsum);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c->stream, L.bsum, Bound{nullptr, 0, INT32_MAX},
+                     Bound{nullptr, in->n, INT32_MAX}, 0, L.fid);
+  hipLaunchKernelGGL(k_cmp_free, dim3(nt), dim3(kScanThreads), 0, c->stream, in->n, L.cmp, L.cmp_free, T, O,
+                     L.bsum, L.fid + in->n, iqy, iqz, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
   return TPC_OK;
