@@ -103,6 +103,14 @@ def lib():
         L.orc_decompress.argtypes = [C.POINTER(Params), C.c_int32] + [P] * 5 + [C.c_int32, P, P, P] + [
             C.c_float, C.c_float, P, P, P, P]
         L.orc_predict.restype = C.c_int32
+        L.orc_rans_model.argtypes = [P, C.c_int32, P]
+        L.orc_rans_model.restype = None
+        L.orc_rans_encode.argtypes = [P, C.c_int32, P, P, P]
+        L.orc_rans_encode.restype = C.c_int32
+        L.orc_rans_decode.argtypes = [P, P, P, C.c_int32, P]
+        L.orc_rans_decode.restype = None
+        L.orc_rans_lanes.argtypes = [C.c_int64]
+        L.orc_rans_lanes.restype = C.c_int64
         L.orc_predict.argtypes = [C.POINTER(Params), P, C.c_float, C.c_int32, C.c_int32, C.c_int32, P]
         _lib = L
     return _lib
@@ -323,3 +331,44 @@ def predict(P, x_ref, sector_ref, sector, row, prm=None):
     yz = np.zeros(2, np.float32)
     ok = lib().orc_predict(C.byref(prm), _p(P), x_ref, sector_ref, sector, row, _p(yz))
     return bool(ok), yz[0], yz[1]
+
+
+# ----------------------------------------------------------------- rANS entropy coding
+
+RANS_LANE_SYMBOLS = 512
+
+
+def rans_lanes(n: int) -> int:
+    return int(lib().orc_rans_lanes(n))
+
+
+def rans_model(sym):
+    """E1: normalised frequencies (uint32[65536], sum 2^16 unless the stream is empty)."""
+    sym = np.ascontiguousarray(sym, np.uint16)
+    f = np.zeros(1 << 16, np.uint32)
+    lib().orc_rans_model(_p(sym), len(sym), _p(f))
+    return f
+
+
+def rans_encode(sym, freq=None):
+    """E2, E4, E5: dict(freq, lane_off, words)."""
+    sym = np.ascontiguousarray(sym, np.uint16)
+    n = len(sym)
+    freq = rans_model(sym) if freq is None else np.ascontiguousarray(freq, np.uint32)
+    lanes = rans_lanes(n)
+    off = np.zeros(lanes + 1, np.uint32)
+    words = np.zeros(max(1, lanes * (RANS_LANE_SYMBOLS + 2)), np.uint16)
+    m = lib().orc_rans_encode(_p(sym), n, _p(freq), _p(off), _p(words))
+    return dict(freq=freq, lane_off=off, words=words[:m])
+
+
+def rans_decode(enc, n):
+    """E3: the n symbols back."""
+    out = np.zeros(max(n, 1), np.uint16)
+    f = np.ascontiguousarray(enc["freq"], np.uint32)
+    off = np.ascontiguousarray(enc["lane_off"], np.uint32)
+    w = np.ascontiguousarray(enc["words"], np.uint16)
+    if len(w) == 0:
+        w = np.zeros(1, np.uint16)
+    lib().orc_rans_decode(_p(f), _p(off), _p(w), n, _p(out))
+    return out[:n]

@@ -12,8 +12,8 @@
 // that reading (O1 frame/track model, O2 helix propagation, O3 grid (not
 // needed here: rows are searched in full or by binary search in z), O4
 // neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
-// O9 selection and fit, O10 merge), and C1-C5 for the track-model compression that
-// consumes the tracks (section 5).
+// O9 selection and fit, O10 merge), C1-C5 for the track-model compression that
+// consumes the tracks, and E1-E5 for the rANS entropy coder after it (section 5).
 //
 // Only tests/, the smoke check and the CPU baseline leg of the benchmark may
 // load this library.  It shares no code, header, table or constant generator
@@ -36,7 +36,9 @@
 // and special cases: parity unpinned beyond those.  Compression: the prediction
 // against an FP64 closed-form circle in the rotated frame, zero residual codes for
 // clusters placed exactly on the fitted helix, absolute codes against numpy's rint,
-// and the round trip within half a quantisation step.
+// and the round trip within half a quantisation step.  rANS: exact round trips, the
+// model's normalisation rule and closed forms, lane sizes within a few words of the
+// information content under the model.
 
 #include <algorithm>
 #include <cmath>
@@ -870,6 +872,41 @@ struct TrackHeaders {
   const int32_t* ndf;
 };
 
+// ---------------------------------------------------------------- E: entropy coding (rANS)
+// Section 5: every detector's data, the TPC's after the track-model compression, goes
+// through a common rANS entropy coder (Table 1: TPC rANS encoding; Table 2: decoding).  The
+// paper names the coder only; the reading (E1-E5) is static range ANS as Duda defined it:
+//  E1 One model per stream of 16-bit symbols: counts c_s over the stream, K = symbols that
+//     occur, M = 2^16; f_s = max(1, floor(c_s (M - K) / n)) for those, 0 for the others;
+//     the remainder M - sum f goes to the most frequent symbol (ties: the smaller symbol).
+//     C_s = sum of f_t over t < s.
+//  E2 Coder: 32-bit state x in [2^16, 2^32), 16-bit words.  Encoding s: if x >= f_s 2^16,
+//     emit x mod 2^16 and x <- floor(x / 2^16); then x <- floor(x / f_s) 2^16 +
+//     (x mod f_s) + C_s.  The state starts at 2^16.
+//  E3 Decoding: slot = x mod 2^16, s the symbol with C_s <= slot < C_s + f_s,
+//     x <- f_s floor(x / 2^16) + slot - C_s, and if x < 2^16, x <- x 2^16 + next word.
+//  E4 Lanes: the stream is cut into chunks of 64 S symbols (S = 512); lane l of chunk k
+//     codes the symbols k 64 S + l + 64 m that exist, with its own state, last symbol
+//     first, so that its decoder reads them first to last.  A lane's words in decoding
+//     order: the final state (high word, low word), then the emitted words, last emitted
+//     first.  A lane without symbols has no words.
+//  E5 The lanes' words are concatenated in lane order; lane_off[l] is the offset of lane l.
+constexpr int kRansLaneSymbols = 512;
+constexpr int kRansLanesPerChunk = 64;
+constexpr uint32_t kRansM = 1u << 16;
+constexpr uint32_t kRansL = 1u << 16;
+
+int64_t rans_lanes(int64_t n) {
+  const int64_t chunk = (int64_t)kRansLanesPerChunk * kRansLaneSymbols;
+  return (n + chunk - 1) / chunk * kRansLanesPerChunk;
+}
+// symbols of lane l (chunk l / 64, lane l % 64): indices first + 64 m, m < count
+void rans_lane(int64_t n, int64_t l, int64_t& first, int64_t& count) {
+  const int64_t k = l / kRansLanesPerChunk, j = l % kRansLanesPerChunk;
+  first = k * kRansLanesPerChunk * kRansLaneSymbols + j;
+  count = first < n ? std::min<int64_t>(kRansLaneSymbols, (n - first + kRansLanesPerChunk - 1) / kRansLanesPerChunk) : 0;
+}
+
 }  // namespace
 
 // ============================================================== C interface (ctypes)
@@ -1122,6 +1159,83 @@ void orc_decompress(const Params* p, int32_t K, const int32_t* off, const float*
     }
   }
 }
+
+// E1: the normalised frequencies freq[65536] of a stream of n symbols.
+void orc_rans_model(const uint16_t* sym, int32_t n, uint32_t* freq) {
+  std::vector<int64_t> c(kRansM, 0);
+  for (int32_t i = 0; i < n; ++i) ++c[sym[i]];
+  int64_t K = 0;
+  uint32_t top = 0;
+  for (uint32_t v = 0; v < kRansM; ++v) {
+    if (c[v] > 0) ++K;
+    if (c[v] > c[top]) top = v;
+  }
+  uint64_t sum = 0;
+  for (uint32_t v = 0; v < kRansM; ++v) {
+    freq[v] = c[v] > 0 ? (uint32_t)std::max<int64_t>(1, c[v] * ((int64_t)kRansM - K) / n) : 0;
+    sum += freq[v];
+  }
+  if (n > 0) freq[top] += (uint32_t)(kRansM - sum);
+}
+
+// E2, E4, E5: encodes with the given model; returns the number of words and fills
+// lane_off[lanes + 1] and words[] (capacity: lanes * (S + 2)).
+int32_t orc_rans_encode(const uint16_t* sym, int32_t n, const uint32_t* freq, uint32_t* lane_off,
+                        uint16_t* words) {
+  std::vector<uint32_t> C(kRansM + 1, 0);
+  for (uint32_t v = 0; v < kRansM; ++v) C[v + 1] = C[v] + freq[v];
+  const int64_t lanes = rans_lanes(n);
+  int64_t pos = 0;
+  std::vector<uint16_t> out;
+  for (int64_t l = 0; l < lanes; ++l) {
+    lane_off[l] = (uint32_t)pos;
+    int64_t first, count;
+    rans_lane(n, l, first, count);
+    if (count == 0) continue;
+    uint32_t x = kRansL;
+    out.clear();
+    for (int64_t m = count - 1; m >= 0; --m) {
+      const uint16_t s = sym[first + kRansLanesPerChunk * m];
+      const uint32_t f = freq[s];
+      if ((uint64_t)x >= (uint64_t)f << 16) {
+        out.push_back((uint16_t)(x & 0xFFFF));
+        x >>= 16;
+      }
+      x = ((x / f) << 16) + (x % f) + C[s];
+    }
+    words[pos++] = (uint16_t)(x >> 16);
+    words[pos++] = (uint16_t)(x & 0xFFFF);
+    for (auto it = out.rbegin(); it != out.rend(); ++it) words[pos++] = *it;
+  }
+  lane_off[lanes] = (uint32_t)pos;
+  return (int32_t)pos;
+}
+
+// E3: decodes n symbols.
+void orc_rans_decode(const uint32_t* freq, const uint32_t* lane_off, const uint16_t* words, int32_t n,
+                     uint16_t* sym) {
+  std::vector<uint32_t> C(kRansM + 1, 0);
+  for (uint32_t v = 0; v < kRansM; ++v) C[v + 1] = C[v] + freq[v];
+  const int64_t lanes = rans_lanes(n);
+  for (int64_t l = 0; l < lanes; ++l) {
+    int64_t first, count;
+    rans_lane(n, l, first, count);
+    if (count == 0) continue;
+    int64_t p = lane_off[l];
+    uint32_t x = ((uint32_t)words[p] << 16) | words[p + 1];
+    p += 2;
+    for (int64_t m = 0; m < count; ++m) {
+      const uint32_t slot = x & 0xFFFF;
+      // the symbol whose interval [C_s, C_s + f_s) holds the slot
+      const uint32_t s = (uint32_t)(std::upper_bound(C.begin(), C.end() - 1, slot) - C.begin()) - 1;
+      sym[first + kRansLanesPerChunk * m] = (uint16_t)s;
+      x = freq[s] * (x >> 16) + slot - C[s];
+      if (x < kRansL) x = (x << 16) | words[p++];
+    }
+  }
+}
+
+int64_t orc_rans_lanes(int64_t n) { return rans_lanes(n); }
 
 // C1 alone (pins): returns 1 and (py, pz) when there is a prediction.
 int32_t orc_predict(const Params* p, const float* P, float xref, int32_t sref, int32_t sec, int32_t row,
