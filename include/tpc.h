@@ -174,8 +174,9 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 
 /* Per-kernel timing with HIP events recorded on the context's stream around the
  * launches of: the neighbour kernel (index 0), the tracklet kernel (1), the grid
- * build (2), the selection (3), fit + merge (4), tpc_compress (5) and
- * tpc_decompress (6).  While enabled, tpc_run does
+ * build (2), the selection (3), fit + merge (4), tpc_compress (5),
+ * tpc_decompress (6), tpc_rans_encode (7) and tpc_rans_decode (8).  While
+ * enabled, tpc_run does
  * not use a graph.  tpc_profile_read waits for the stream and returns the summed
  * milliseconds and the number of timed launches per index since the last reset. */
 #define TPC_PROF_LINKS 0
@@ -185,7 +186,9 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 #define TPC_PROF_FIT_MERGE 4
 #define TPC_PROF_COMPRESS 5   /* tpc_compress (all its kernels)   */
 #define TPC_PROF_DECOMPRESS 6 /* tpc_decompress (all its kernels) */
-#define TPC_PROF_KERNELS 7
+#define TPC_PROF_RANS_ENCODE 7
+#define TPC_PROF_RANS_DECODE 8
+#define TPC_PROF_KERNELS 9
 int tpc_profile(tpc_ctx* ctx, int enable);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
 
@@ -235,6 +238,40 @@ int tpc_compress(tpc_ctx* ctx, const tpc_clusters* c, const tpc_tracks* t, float
  * belong to these tracks) to NaN coordinates and TPC_E_RANGE at tpc_sync.    */
 int tpc_decompress(tpc_ctx* ctx, const tpc_tracks* t, const tpc_codes* in, float q_y, float q_z,
                    uint8_t* sector, int16_t* row, float* y, float* z);
+
+/* rANS entropy coding (section 5: every detector's data, the TPC's after the
+ * track-model compression, goes through a common rANS coder; Tables 1 and 2
+ * time the TPC encoding and decoding).  Static range ANS on a stream of n
+ * 16-bit symbols (e.g. one field of the compression records):
+ *  - model: freq[s] over 2^16 slots, f_s = max(1, floor(c_s (2^16 - K) / n))
+ *    for the K symbols that occur (c_s = count), 0 for the others, and the
+ *    remainder 2^16 - sum to the most frequent symbol (ties: the smaller).
+ *  - coder: 32-bit state in [2^16, 2^32) starting at 2^16, 16-bit words;
+ *    encoding s emits the low word and shifts when x >= f_s 2^16, then sets
+ *    x = floor(x / f_s) 2^16 + (x mod f_s) + C_s (C_s = sum of f below s).
+ *  - lanes: chunks of 64 x 512 symbols; lane l of chunk k codes symbols
+ *    k*32768 + l + 64 m with its own state, last symbol first.  A lane's words
+ *    in decoding order: final state (high, low word), then the emitted words,
+ *    last emitted first; a lane without symbols has none.  lane_off[l] is the
+ *    word offset of lane l, lane_off[lanes] the total.
+ * tpc_rans_lanes(n) = 64 * ceil(n / 32768) is the number of lanes.  The words
+ * needed are at most n + 2 * lanes.  Both calls use the context's workspace, so
+ * they need a preceding tracking run over at least n clusters (TPC_E_ARG
+ * otherwise); they run on the context's stream.  Encoding writes freq,
+ * lane_off and *n_words in full and the words that fit in cap_words (else
+ * TPC_E_CAPACITY at tpc_sync).  Decoding reads only what lane_off and
+ * cap_words bound; a stream that runs short raises TPC_E_RANGE.             */
+#define TPC_RANS_LANE_SYMBOLS 512
+typedef struct {
+  int32_t cap_words;   /* [host] capacity of words                              */
+  int32_t* n_words;    /* [1] words of the coded stream                         */
+  uint32_t* freq;      /* [65536] model (written by encode, read by decode)     */
+  uint32_t* lane_off;  /* [tpc_rans_lanes(n) + 1]                               */
+  uint16_t* words;     /* [cap_words]                                           */
+} tpc_rans;
+int64_t tpc_rans_lanes(int64_t n);
+int tpc_rans_encode(tpc_ctx* ctx, const uint16_t* sym, int32_t n, tpc_rans* out);
+int tpc_rans_decode(tpc_ctx* ctx, const tpc_rans* in, int32_t n, uint16_t* sym);
 
 /* Wait for the context's stream; returns TPC_E_RANGE / TPC_E_CAPACITY if the
  * kernels reported one since the last tpc_grid_build, else TPC_OK.           */

@@ -1605,6 +1605,221 @@ __global__ __launch_bounds__(256) void k_dcmp_free(CmpCodes C, CmpOut D, Consts 
   if (st) atomicOr(&counters[kCntStatus], st);
 }
 
+// ------------------------------------------------------------------ rANS entropy coding
+// Static range ANS (section 5: the common entropy coder after the TPC-specific steps) on
+// streams of 16-bit symbols: a model of 2^16 slots per stream (every occurring symbol keeps
+// a slot, the remainder to the most frequent), a 32-bit state with 16-bit renormalisation,
+// and the stream cut into chunks of 64 lanes x 512 symbols, lane l of a chunk coding the
+// chunk's symbols l, l + 64, ... with its own state, so that a wave codes a chunk with
+// coalesced symbol loads and every lane is independent.
+constexpr uint32_t kRansL = 1u << 16;
+
+__host__ __device__ inline int64_t rans_chunk_first(int64_t l) {
+  return (l / kRansLanesPerChunk) * (int64_t)kRansLanesPerChunk * kRansLaneSymbols + l % kRansLanesPerChunk;
+}
+__host__ __device__ inline int32_t rans_lane_count(int64_t n, int64_t l) {
+  const int64_t first = rans_chunk_first(l);
+  if (first >= n) return 0;
+  const int64_t c = (n - first + kRansLanesPerChunk - 1) / kRansLanesPerChunk;
+  return (int32_t)(c < kRansLaneSymbols ? c : kRansLaneSymbols);
+}
+
+// Symbol counts: the int16 window [-2048, 2048) (where residual codes live) in LDS, one
+// global atomic per touched bin and block; other symbols straight to global memory.
+constexpr int kRansHot = 4096;
+__global__ __launch_bounds__(256) void k_rans_hist(const uint16_t* sym, int32_t n, uint32_t* cnt) {
+  __shared__ uint32_t hot[kRansHot];
+  for (int i = threadIdx.x; i < kRansHot; i += blockDim.x) hot[i] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = sym[i];
+    const uint32_t b = (v + kRansHot / 2) & 0xFFFFu;
+    if (b < (uint32_t)kRansHot)
+      atomicAdd(&hot[b], 1u);
+    else
+      atomicAdd(&cnt[v], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRansHot; i += blockDim.x)
+    if (hot[i]) atomicAdd(&cnt[(i - kRansHot / 2) & 0xFFFF], hot[i]);
+}
+
+// cum[v] = sum of freq[u], u < v, over the 2^16 symbols (one block of 1024 threads, 64
+// consecutive symbols per thread); cum[2^16] = the total.
+__device__ __forceinline__ void rans_cumulate(const uint32_t* freq, uint32_t* cum, int* lds) {
+  const int t = threadIdx.x;
+  uint32_t local = 0;
+  for (int i = 0; i < 64; ++i) local += freq[t * 64 + i];
+  int total;
+  uint32_t run = (uint32_t)block_excl_scan((int)local, lds, total);
+  for (int i = 0; i < 64; ++i) {
+    cum[t * 64 + i] = run;
+    run += freq[t * 64 + i];
+  }
+  if (t == 0) cum[kRansM] = (uint32_t)total;
+}
+
+// The model: f_s = max(1, floor(c_s (2^16 - K) / n)) for the K occurring symbols, the
+// remainder to the most frequent one (ties: the smaller symbol); then the cumulative table.
+__global__ __launch_bounds__(1024) void k_rans_model(const uint32_t* cnt, int32_t n, uint32_t* freq,
+                                                     uint32_t* cum) {
+  __shared__ int lds[40];
+  __shared__ unsigned long long best[1024];
+  __shared__ uint32_t ksum[1024];
+  const int t = threadIdx.x;
+  uint32_t k = 0;
+  unsigned long long key = 0;
+  for (int i = 0; i < 64; ++i) {
+    const uint32_t v = t * 64 + i;
+    const uint32_t c = cnt[v];
+    if (c) ++k;
+    const unsigned long long kv = ((unsigned long long)c << 16) | (0xFFFFu - v);
+    if (c && kv > key) key = kv;
+  }
+  ksum[t] = k;
+  best[t] = key;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) {
+      ksum[t] += ksum[t + o];
+      if (best[t + o] > best[t]) best[t] = best[t + o];
+    }
+    __syncthreads();
+  }
+  const uint64_t K = ksum[0];
+  const uint32_t top = 0xFFFFu - (uint32_t)(best[0] & 0xFFFFu);
+  __syncthreads();
+  uint32_t local = 0;
+  for (int i = 0; i < 64; ++i) {
+    const uint32_t v = t * 64 + i;
+    const uint64_t c = cnt[v];
+    uint32_t f = 0;
+    if (c) {
+      const uint64_t q = c * ((uint64_t)kRansM - K) / (uint64_t)n;
+      f = q > 0 ? (uint32_t)q : 1u;
+    }
+    freq[v] = f;
+    local += f;
+  }
+  ksum[t] = local;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) ksum[t] += ksum[t + o];
+    __syncthreads();
+  }
+  if (t == 0 && n > 0) freq[top] += kRansM - ksum[0];
+  __syncthreads();
+  rans_cumulate(freq, cum, lds);
+}
+
+__global__ __launch_bounds__(1024) void k_rans_cum(const uint32_t* freq, uint32_t* cum) {
+  __shared__ int lds[40];
+  rans_cumulate(freq, cum, lds);
+}
+
+// One thread per lane: the lane's symbols last to first, words written backwards into the
+// lane's own buffer of S + 2 words; len[l] = words written.
+__global__ __launch_bounds__(256) void k_rans_enc(const uint16_t* sym, int32_t n, int64_t lanes,
+                                                  const uint32_t* freq, const uint32_t* cum, uint16_t* buf,
+                                                  int32_t* len) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= lanes) return;
+  const int32_t count = rans_lane_count(n, l);
+  const int64_t first = rans_chunk_first(l);
+  uint16_t* out = buf + l * (kRansLaneSymbols + 2);
+  int p = kRansLaneSymbols + 2;
+  uint32_t x = kRansL;
+  for (int m = count - 1; m >= 0; --m) {
+    const uint32_t s = sym[first + (int64_t)kRansLanesPerChunk * m];
+    const uint32_t f = freq[s];
+    if ((uint64_t)x >= ((uint64_t)f << 16)) {
+      out[--p] = (uint16_t)(x & 0xFFFFu);
+      x >>= 16;
+    }
+    x = ((x / f) << 16) + (x % f) + cum[s];
+  }
+  if (count > 0) {
+    out[--p] = (uint16_t)(x & 0xFFFFu);
+    out[--p] = (uint16_t)(x >> 16);
+  }
+  len[l] = kRansLaneSymbols + 2 - p;
+}
+
+// One wave per lane: its words to words[lane_off[l] ...]; nothing beyond the capacity.
+__global__ __launch_bounds__(256) void k_rans_copy(const uint16_t* buf, const int32_t* len,
+                                                   const uint32_t* lane_off, int64_t lanes, uint16_t* words,
+                                                   int32_t cap, int32_t* n_words, int32_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_words = (int32_t)lane_off[lanes];
+  int32_t st = 0;
+  for (int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; l < lanes; l += nw) {
+    const int32_t k = len[l];
+    const uint16_t* src = buf + l * (kRansLaneSymbols + 2) + (kRansLaneSymbols + 2 - k);
+    const int64_t dst = lane_off[l];
+    for (int32_t i = lane; i < k; i += 64) {
+      if (dst + i < cap)
+        words[dst + i] = src[i];
+      else
+        st |= kStatusCapacity;
+    }
+  }
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
+// slot -> symbol: the last s with cum[s] <= slot (the symbol whose interval holds it).
+__global__ __launch_bounds__(256) void k_rans_table(const uint32_t* cum, uint16_t* tab) {
+  const uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= kRansM) return;
+  uint32_t lo = 0, hi = kRansM;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cum[mid] <= slot)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  tab[slot] = (uint16_t)lo;
+}
+
+// One thread per lane: reads the lane's words first to last, writes its symbols.
+__global__ __launch_bounds__(256) void k_rans_dec(const uint32_t* freq, const uint32_t* cum, const uint16_t* tab,
+                                                  const uint32_t* lane_off, const uint16_t* words, int32_t cap,
+                                                  int32_t n, int64_t lanes, uint16_t* sym, int32_t* counters) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= lanes) return;
+  const int32_t count = rans_lane_count(n, l);
+  if (count == 0) return;
+  const int64_t first = rans_chunk_first(l);
+  int64_t p = lane_off[l];
+  const int64_t end = min((int64_t)lane_off[l + 1], (int64_t)cap);
+  int32_t st = 0;
+  if (p < 0 || p + 2 > end) {
+    st |= kStatusRange;
+    p = end;
+  }
+  uint32_t x = kRansL;
+  if (p + 2 <= end) {
+    x = ((uint32_t)words[p] << 16) | words[p + 1];
+    p += 2;
+  }
+  for (int m = 0; m < count; ++m) {
+    const uint32_t slot = x & 0xFFFFu;
+    const uint32_t s = tab[slot];
+    sym[first + (int64_t)kRansLanesPerChunk * m] = (uint16_t)s;
+    x = freq[s] * (x >> 16) + slot - cum[s];
+    if (x < kRansL) {
+      uint32_t w = 0;
+      if (p < end)
+        w = words[p++];
+      else
+        st |= kStatusRange;
+      x = (x << 16) | w;
+    }
+  }
+  if (st) atomicOr(&counters[kCntStatus], st);
+}
+
 // ------------------------------------------------------------------ test hooks
 __global__ void k_links_to_input(const int32_t* a, const int32_t* b, const GHit* gh, int32_t* oa,
                                  int32_t* ob, Bound hi_b) {
@@ -1745,6 +1960,13 @@ struct Layout {
   int32_t *T_off, *K_off, *counters, *bsum;
   int4* cmp;         // compression: (y, z, record word, unused) per cluster
   uint8_t* cmp_free;  // compression: 1 while no track holds the cluster
+  // rANS: symbol counts, cumulative frequencies, slot -> symbol table, lane lengths and
+  // the lanes' word buffers (each lane writes backwards into its own S + 2 words)
+  uint32_t *rans_cnt, *rans_cum;
+  uint16_t* rans_tab;
+  int32_t* rans_len;
+  uint16_t* rans_buf;
+  int64_t rans_lanesN = 0;
   // merge
   float* bucket_z;
   int32_t *trk_event, *bucket_cnt, *bucket_off, *bucket_fill, *bucket_trk, *chain_next, *chain_prev,
@@ -1833,6 +2055,12 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.bestB, L.capK, t, set);
   carve(p, L.cmp, N, t, set);
   carve(p, L.cmp_free, N, t, set);
+  L.rans_lanesN = rans_lanes(N);
+  carve(p, L.rans_cnt, kRansM, t, set);
+  carve(p, L.rans_cum, kRansM + 1, t, set);
+  carve(p, L.rans_tab, kRansM, t, set);
+  carve(p, L.rans_len, L.rans_lanesN + 1, t, set);
+  carve(p, L.rans_buf, L.rans_lanesN * (kRansLaneSymbols + 2), t, set);
   L.bytes = t + 256;
 }
 
@@ -2692,6 +2920,61 @@ int tpc_decompress(tpc_ctx* c, const tpc_tracks* t, const tpc_codes* in, float q
   if (in->cap > 0)
     hipLaunchKernelGGL(k_dcmp_free, dim3(blocks_for(in->cap, 256)), dim3(256), 0, c->stream, C, D, c->k, q_y, q_z,
                        c->L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int64_t tpc_rans_lanes(int64_t n) { return n < 0 ? -1 : rans_lanes(n); }
+
+int tpc_rans_encode(tpc_ctx* c, const uint16_t* sym, int32_t n, tpc_rans* out) {
+  if (!c) return TPC_E_ARG;
+  if (!out || n < 0 || (n > 0 && !sym) || out->cap_words < 0 || !out->n_words || !out->freq || !out->lane_off ||
+      (out->cap_words > 0 && !out->words))
+    return fail(c, TPC_E_ARG, "tpc_rans_encode: null or negative argument");
+  if (!c->laid_out || (int64_t)n > c->L.N)
+    return fail(c, TPC_E_ARG, "tpc_rans_encode: needs the workspace of a tracking run over at least n clusters");
+  HIPCHK(c, hipSetDevice(c->device));
+  Layout& L = c->L;
+  const int64_t lanes = rans_lanes(n);
+  const int pm = prof_begin(c, TPC_PROF_RANS_ENCODE);
+  fill_i32(c, reinterpret_cast<int32_t*>(L.rans_cnt), kRansM, 0);
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (n > 0)
+    hipLaunchKernelGGL(k_rans_hist, dim3(std::min(blocks_for(n, 256), ncu * 4)), dim3(256), 0, c->stream, sym, n,
+                       L.rans_cnt);
+  hipLaunchKernelGGL(k_rans_model, dim3(1), dim3(1024), 0, c->stream, L.rans_cnt, n, out->freq, L.rans_cum);
+  if (lanes > 0) {
+    hipLaunchKernelGGL(k_rans_enc, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, sym, n, lanes, out->freq,
+                       L.rans_cum, L.rans_buf, L.rans_len);
+    scan(c, L.rans_len, reinterpret_cast<int32_t*>(out->lane_off), Bound{nullptr, 0, INT32_MAX},
+         Bound{nullptr, (int32_t)lanes, INT32_MAX}, lanes, false);
+  } else {
+    fill_i32(c, reinterpret_cast<int32_t*>(out->lane_off), 1, 0);
+  }
+  hipLaunchKernelGGL(k_rans_copy, dim3(std::max(1, wave_grid(c, lanes))), dim3(256), 0, c->stream, L.rans_buf,
+                     L.rans_len, out->lane_off, lanes, out->words, out->cap_words, out->n_words, L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_rans_decode(tpc_ctx* c, const tpc_rans* in, int32_t n, uint16_t* sym) {
+  if (!c) return TPC_E_ARG;
+  if (!in || n < 0 || (n > 0 && !sym) || in->cap_words < 0 || !in->freq || !in->lane_off ||
+      (in->cap_words > 0 && !in->words))
+    return fail(c, TPC_E_ARG, "tpc_rans_decode: null or negative argument");
+  if (!c->laid_out) return fail(c, TPC_E_ARG, "tpc_rans_decode: needs a context that has run a tracking stage");
+  HIPCHK(c, hipSetDevice(c->device));
+  Layout& L = c->L;
+  const int64_t lanes = rans_lanes(n);
+  const int pm = prof_begin(c, TPC_PROF_RANS_DECODE);
+  hipLaunchKernelGGL(k_rans_cum, dim3(1), dim3(1024), 0, c->stream, in->freq, L.rans_cum);
+  hipLaunchKernelGGL(k_rans_table, dim3(kRansM / 256), dim3(256), 0, c->stream, L.rans_cum, L.rans_tab);
+  if (lanes > 0)
+    hipLaunchKernelGGL(k_rans_dec, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, in->freq, L.rans_cum,
+                       L.rans_tab, in->lane_off, in->words, in->cap_words, n, lanes, sym, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
   return TPC_OK;

@@ -68,6 +68,15 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 // status bits
+// rANS: slots of the model, symbols per lane, lanes per chunk (one wave)
+constexpr uint32_t kRansM = 1u << 16;
+constexpr int kRansLaneSymbols = 512;
+constexpr int kRansLanesPerChunk = 64;
+__host__ __device__ inline int64_t rans_lanes(int64_t n) {
+  const int64_t chunk = (int64_t)kRansLanesPerChunk * kRansLaneSymbols;
+  return (n + chunk - 1) / chunk * kRansLanesPerChunk;
+}
+
 constexpr int32_t kStatusRange = 1;
 constexpr int32_t kStatusCapacity = 2;
 

@@ -62,6 +62,12 @@ class tpc_codes(C.Structure):
     _fields_ = [("cap", C.c_int32)] + [(n, C.c_void_p) for n in ("n_codes", "n_attached", "rs", "ey", "ez")]
 
 
+class tpc_rans(C.Structure):
+    _fields_ = [("cap_words", C.c_int32)] + [(n, C.c_void_p) for n in ("n_words", "freq", "lane_off", "words")]
+
+
+RANS_LANE_SYMBOLS = 512
+
 # Default quantisation step of the compressed coordinates (cm): a power of two, so that
 # 1/q and e*q are exact in FP32; q/sqrt(12) = 0.009 cm against 0.1 cm cluster errors.
 Q_STEP = 1.0 / 32.0
@@ -115,6 +121,10 @@ def lib():
         L.tpc_profile_read.argtypes = [V, V, V, C.c_int32, C.c_int32]
         L.tpc_compress.argtypes = [V, P(tpc_clusters), P(tpc_tracks), C.c_float, C.c_float, P(tpc_codes)]
         L.tpc_decompress.argtypes = [V, P(tpc_tracks), P(tpc_codes), C.c_float, C.c_float, V, V, V, V]
+        L.tpc_rans_lanes.argtypes = [C.c_int64]
+        L.tpc_rans_lanes.restype = C.c_int64
+        L.tpc_rans_encode.argtypes = [V, V, C.c_int32, P(tpc_rans)]
+        L.tpc_rans_decode.argtypes = [V, P(tpc_rans), C.c_int32, V]
         _lib = L
     return _lib
 
@@ -125,8 +135,10 @@ EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_c
             "tpc_construct_tracklets", "tpc_select_tracks", "tpc_fit_merge", "tpc_run", "tpc_sync",
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
-            "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress"]
-PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress"]
+            "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress",
+            "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode"]
+PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress",
+              "rans_encode", "rans_decode"]
 
 
 def default_params(**over) -> tpc_params:
@@ -321,6 +333,39 @@ class Tracker:
                                          *[_ptr(out[k]) for k in ("sector", "row", "y", "z")]),
                     "tpc_decompress")
         return out
+
+    # ---- rANS entropy coding of a device stream of 16-bit symbols
+    def tpc_rans_encode(self, sym, cap_words: int | None = None) -> dict:
+        """Enqueues tpc_rans_encode of `sym` (device tensor of 2-byte elements); returns the
+        coded stream's device buffers."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        n = int(sym.numel())
+        lanes = int(lib().tpc_rans_lanes(n))
+        cap = n + 2 * lanes if cap_words is None else cap_words
+        enc = dict(n=n, cap_words=cap, n_words=torch.zeros(1, dtype=torch.int32, device=dev),
+                   freq=torch.zeros(1 << 16, dtype=torch.int32, device=dev),
+                   lane_off=torch.zeros(lanes + 1, dtype=torch.int32, device=dev),
+                   words=torch.zeros(max(cap, 1), dtype=torch.int16, device=dev))
+        enc["_s"] = tpc_rans(cap, *[_ptr(enc[k]) for k in ("n_words", "freq", "lane_off", "words")])
+        self._check(lib().tpc_rans_encode(self.ctx, _ptr(sym), n, C.byref(enc["_s"])), "tpc_rans_encode")
+        return enc
+
+    def tpc_rans_decode(self, enc: dict, out=None):
+        """Enqueues tpc_rans_decode of a stream from tpc_rans_encode into `out` (device, int16)."""
+        torch = self.torch
+        n = enc["n"]
+        if out is None:
+            out = torch.zeros(max(n, 1), dtype=torch.int16, device=f"cuda:{self.device}")
+        self._check(lib().tpc_rans_decode(self.ctx, C.byref(enc["_s"]), n, _ptr(out)), "tpc_rans_decode")
+        return out
+
+    def rans_numpy(self, enc: dict) -> dict:
+        self.torch.cuda.synchronize(self.device)
+        m = min(int(enc["n_words"].item()), enc["cap_words"])
+        return dict(n_words=int(enc["n_words"].item()), freq=enc["freq"].cpu().numpy().view(np.uint32),
+                    lane_off=enc["lane_off"].cpu().numpy().view(np.uint32),
+                    words=enc["words"][:m].cpu().numpy().view(np.uint16))
 
     def codes_numpy(self) -> dict:
         """The records of the last tpc_compress (waits for the stream; no error check)."""

@@ -117,6 +117,43 @@ def test_compression_full_size(c4):
     say("records", gc["n_codes"], "residual", int(res.sum()), "absolute", int(cs.n - res.sum()))
 
 
+def test_rans_full_size(c4):
+    """rANS on a stream of the batched workload's size (88.7M symbols, residual-like codes
+    with a third of absolute-like ones) in the context the benchmark uses: bit-exact with the
+    oracle's coder over the whole stream, and decoded exactly; then the workload's own
+    compression records, field by field, decoded exactly."""
+    import torch
+    tr, cs = c4["tr"], c4["cs"]
+    n = cs.n
+    rng = np.random.default_rng(41)
+    s = np.clip(np.rint(rng.normal(0, 3.2, n)), -32767, 32767).astype(np.int16)
+    tail = rng.random(n) < 0.33
+    s[tail] = rng.integers(-8000, 8000, int(tail.sum())).astype(np.int16)
+    d = torch.from_numpy(s).to("cuda:0")
+    enc = tr.tpc_rans_encode(d)
+    tr.sync()
+    out = tr.tpc_rans_decode(enc)
+    tr.sync()
+    gr = tr.rans_numpy(enc)
+    ref = O.rans_encode(s.view(np.uint16))
+    assert np.array_equal(gr["freq"], ref["freq"]) and np.array_equal(gr["lane_off"], ref["lane_off"])
+    assert np.array_equal(gr["words"], ref["words"])
+    assert torch.equal(out[:n], d)
+    say("synthetic stream", n, "bits/symbol", 16 * gr["n_words"] / n)
+    tr.tpc_compress(1.0 / 32.0, 1.0 / 32.0)
+    tr.sync()
+    cd = tr.codes
+    H = int(cd["n_attached"].item())
+    for k in ("rs", "ey", "ez"):
+        for a, b in ((0, H), (H, n)):
+            part = cd[k][a:b].contiguous()
+            e = tr.tpc_rans_encode(part)
+            o = tr.tpc_rans_decode(e)
+            tr.sync()
+            assert torch.equal(o[:b - a], part)
+            say(k, a, b, "bits/symbol", 16 * int(e["n_words"].item()) / max(b - a, 1))
+
+
 def test_timeframe_full_size_sampled_sectors():
     from paper_2402_01205_amd.tpc import DeviceClusters
     say("generating the full time-frame slice")
