@@ -51,6 +51,8 @@ CMP_BYTES_PER_CLUSTER = 17
 CMP_BYTES_PER_HIT = 4
 CMP_BYTES_PER_TRACK = 36
 Q_STEP = 1.0 / 32.0
+#  rANS encode     : per symbol 2 B read; per coded word 2 B written; per lane 4 B (offset)
+#  rANS decode     : per coded word 2 B read; per symbol 2 B written; per lane 8 B (offsets)
 
 
 def log(*a):
@@ -225,8 +227,65 @@ def compression_run(tr, cs, tracks, steps, log):
            "decompress_GBs": d_bytes / d_ms / 1e6,
            "entropy_bits_per_cluster": bits, "entropy_bits_per_cluster_absolute": bits_abs,
            "entropy_ratio": bits_abs / bits if bits else None}
+    out["rans"] = rans_run(tr, rec["n_attached"], n, steps)
     log("compression: " + json.dumps(out))
     return out
+
+
+def record_streams(tr, H, n):
+    """The six fields of the compression records as device streams: rs, ey, ez, each split
+    into the track hits (residual codes) and the clusters in no track (absolute codes)."""
+    cd = tr.codes
+    return {f"{k}_{part}": cd[k][a:b].contiguous()
+            for k in ("rs", "ey", "ez") for part, a, b in (("tracks", 0, H), ("free", H, n))}
+
+
+def rans_run(tr, H, n, steps):
+    """rANS coding of the compression records, field by field: time per pass over the six
+    streams (HIP events on the library's stream), coded size and roofline."""
+    streams = record_streams(tr, H, n)
+    tr.profile(True)
+    tr.profile_read(reset=True)
+    encs = {}
+    for _ in range(steps):
+        for k, v in streams.items():
+            encs[k] = tr.tpc_rans_encode(v)
+    outs = {k: None for k in streams}
+    for _ in range(steps):
+        for k in streams:
+            outs[k] = tr.tpc_rans_decode(encs[k], outs[k])
+    prof = tr.profile_read(reset=True)
+    tr.profile(False)
+    tr.sync()
+    e_ms = prof["rans_encode"][0] / steps
+    d_ms = prof["rans_decode"][0] / steps
+    per, words, lanes, model = {}, 0, 0, 0
+    exact = True
+    for k, v in streams.items():
+        r = tr.rans_numpy(encs[k])
+        nl = len(r["lane_off"]) - 1
+        nz = int((r["freq"] > 0).sum())
+        words += r["n_words"]
+        lanes += nl
+        model += nz
+        exact &= bool(outs[k][:v.numel()].equal(v))
+        per[k] = {"symbols": int(v.numel()), "words": r["n_words"], "symbols_in_model": nz,
+                  "bits_per_symbol": 16.0 * r["n_words"] / max(1, v.numel())}
+    sym = 3 * n
+    coded_bytes = 2 * words + 4 * lanes + 4 * model   # words, lane offsets, sparse model
+    e_bytes = 2 * sym + 2 * words + 4 * lanes
+    d_bytes = 2 * sym + 2 * words + 8 * lanes
+    return {"encode_ms": e_ms, "decode_ms": d_ms, "symbols": sym,
+            "encode_symbols_per_s": sym / (e_ms / 1e3), "decode_symbols_per_s": sym / (d_ms / 1e3),
+            "round_trip_exact": exact, "coded_bytes": coded_bytes,
+            "coded_bits_per_cluster": 8.0 * coded_bytes / max(n, 1),
+            "record_bits_per_cluster": 48.0, "ratio_vs_records": 48.0 * n / max(8.0 * coded_bytes, 1),
+            "ratio_vs_float_clusters": 88.0 * n / max(8.0 * coded_bytes, 1),
+            "roofline_encode": {"bound": "hbm", "achieved": e_bytes / e_ms / 1e6, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": e_bytes / e_ms / 1e6 / HBM_PEAK_GBS},
+            "roofline_decode": {"bound": "hbm", "achieved": d_bytes / d_ms / 1e6, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": d_bytes / d_ms / 1e6 / HBM_PEAK_GBS},
+            "streams": per}
 
 
 def main():
@@ -335,7 +394,15 @@ def main():
         for _ in range(args.steps):
             tr.tpc_decompress()
         tr.sync()
-        log(f"compression: {args.steps} encode and {args.steps} decode calls")
+        H = int(tr.codes["n_attached"].item())
+        streams = record_streams(tr, H, cs.n)
+        for _ in range(args.steps):
+            encs = {k: tr.tpc_rans_encode(v) for k, v in streams.items()}
+        for _ in range(args.steps):
+            for e in encs.values():
+                tr.tpc_rans_decode(e)
+        tr.sync()
+        log(f"compression: {args.steps} encode and {args.steps} decode calls, then rANS of its six streams")
         print(json.dumps({"ms_per_step": ms, "sources": source_digest(),
                           "tuning": {k: getattr(tuning, k) for k, _ in tuning._fields_}}), flush=True)
         return

@@ -1644,37 +1644,93 @@ __global__ __launch_bounds__(256) void k_rans_hist(const uint16_t* sym, int32_t 
     if (hot[i]) atomicAdd(&cnt[(i - kRansHot / 2) & 0xFFFF], hot[i]);
 }
 
-// cum[v] = sum of freq[u], u < v, over the 2^16 symbols (one block of 1024 threads, 64
-// consecutive symbols per thread); cum[2^16] = the total.
-__device__ __forceinline__ void rans_cumulate(const uint32_t* freq, uint32_t* cum, int* lds) {
+// Symbol counts with the whole alphabet privatised in LDS: two passes over the stream, each
+// counting one half of the 16-bit range in 32768 LDS bins (128 KiB), then one global
+// atomic per non-empty bin and workgroup.  Used where the device grants that much LDS.
+constexpr int kRansHalf = 1 << 15;
+__global__ __launch_bounds__(1024) void k_rans_hist_lds(const uint16_t* sym, int32_t n, uint32_t* cnt) {
+  extern __shared__ uint32_t bins[];
+  for (uint32_t half = 0; half < 2; ++half) {
+    for (int i = threadIdx.x; i < kRansHalf; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const uint32_t v = sym[i];
+      if ((v >> 15) == half) atomicAdd(&bins[v & (kRansHalf - 1)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kRansHalf; i += blockDim.x)
+      if (bins[i]) atomicAdd(&cnt[(half << 15) | (uint32_t)i], bins[i]);
+    __syncthreads();
+  }
+}
+
+// Thread t of the one 1024-thread workgroup owns the 64 consecutive symbols 64 t .. 64 t + 63,
+// read and written as 16 four-symbol (16-byte) groups.
+__device__ __forceinline__ uint4 rans_group(const uint32_t* a, int g) {
+  return reinterpret_cast<const uint4*>(a + threadIdx.x * 64)[g];
+}
+
+// cum[v] = sum of freq[u], u < v, over the 2^16 symbols; cum[2^16] = the total; with enc_tab
+// also the encoder's (f_s, C_s) entries (one 8-byte gather per coded symbol).
+__device__ __forceinline__ void rans_cumulate(const uint32_t* freq, uint32_t* cum, int* lds,
+                                              uint64_t* enc_tab = nullptr) {
   const int t = threadIdx.x;
   uint32_t local = 0;
-  for (int i = 0; i < 64; ++i) local += freq[t * 64 + i];
+#pragma unroll
+  for (int g = 0; g < 16; ++g) {
+    const uint4 q = rans_group(freq, g);
+    local += q.x + q.y + q.z + q.w;
+  }
   int total;
   uint32_t run = (uint32_t)block_excl_scan((int)local, lds, total);
-  for (int i = 0; i < 64; ++i) {
-    cum[t * 64 + i] = run;
-    run += freq[t * 64 + i];
+  uint4* out = reinterpret_cast<uint4*>(cum + t * 64);
+  ulonglong2* eo = reinterpret_cast<ulonglong2*>(enc_tab + t * 64);
+  for (int g = 0; g < 16; ++g) {
+    const uint4 q = rans_group(freq, g);
+    const uint4 c = make_uint4(run, run + q.x, run + q.x + q.y, run + q.x + q.y + q.z);
+    run = c.w + q.w;
+    out[g] = c;
+    if (enc_tab) {
+      eo[2 * g] = make_ulonglong2((uint64_t)q.x | ((uint64_t)c.x << 32), (uint64_t)q.y | ((uint64_t)c.y << 32));
+      eo[2 * g + 1] = make_ulonglong2((uint64_t)q.z | ((uint64_t)c.z << 32), (uint64_t)q.w | ((uint64_t)c.w << 32));
+    }
   }
   if (t == 0) cum[kRansM] = (uint32_t)total;
 }
 
+// floor(c (2^16 - K) / n) for c > 0, at least 1: an estimate from a double reciprocal made
+// exact by integer correction steps (c (2^16 - K) < 2^47: the products stay in 64 bits).
+__device__ __forceinline__ uint32_t rans_norm(uint32_t c, uint64_t mk, int32_t n, double r) {
+  if (!c) return 0u;
+  const uint64_t num = (uint64_t)c * mk;
+  uint64_t q = (uint64_t)((double)c * r);
+  while (q > 0 && q * (uint64_t)n > num) --q;
+  while ((q + 1) * (uint64_t)n <= num) ++q;
+  return q > 0 ? (uint32_t)q : 1u;
+}
+
 // The model: f_s = max(1, floor(c_s (2^16 - K) / n)) for the K occurring symbols, the
-// remainder to the most frequent one (ties: the smaller symbol); then the cumulative table.
+// remainder to the most frequent one (ties: the smaller symbol); then the cumulative table
+// and the encoder's entries.
 __global__ __launch_bounds__(1024) void k_rans_model(const uint32_t* cnt, int32_t n, uint32_t* freq,
-                                                     uint32_t* cum) {
+                                                     uint32_t* cum, uint64_t* enc_tab) {
   __shared__ int lds[40];
   __shared__ unsigned long long best[1024];
   __shared__ uint32_t ksum[1024];
   const int t = threadIdx.x;
   uint32_t k = 0;
   unsigned long long key = 0;
-  for (int i = 0; i < 64; ++i) {
-    const uint32_t v = t * 64 + i;
-    const uint32_t c = cnt[v];
-    if (c) ++k;
-    const unsigned long long kv = ((unsigned long long)c << 16) | (0xFFFFu - v);
-    if (c && kv > key) key = kv;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) {
+    const uint4 q = rans_group(cnt, g);
+    const uint32_t c4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t v = t * 64 + g * 4 + j;
+      k += c4[j] ? 1u : 0u;
+      const unsigned long long kv = ((unsigned long long)c4[j] << 16) | (0xFFFFu - v);
+      if (c4[j] && kv > key) key = kv;
+    }
   }
   ksum[t] = k;
   best[t] = key;
@@ -1686,20 +1742,18 @@ __global__ __launch_bounds__(1024) void k_rans_model(const uint32_t* cnt, int32_
     }
     __syncthreads();
   }
-  const uint64_t K = ksum[0];
+  const uint64_t mk = (uint64_t)kRansM - ksum[0];
   const uint32_t top = 0xFFFFu - (uint32_t)(best[0] & 0xFFFFu);
+  const double r = n > 0 ? (double)mk / (double)n : 0.0;
   __syncthreads();
   uint32_t local = 0;
-  for (int i = 0; i < 64; ++i) {
-    const uint32_t v = t * 64 + i;
-    const uint64_t c = cnt[v];
-    uint32_t f = 0;
-    if (c) {
-      const uint64_t q = c * ((uint64_t)kRansM - K) / (uint64_t)n;
-      f = q > 0 ? (uint32_t)q : 1u;
-    }
-    freq[v] = f;
-    local += f;
+  uint4* fo = reinterpret_cast<uint4*>(freq + t * 64);
+  for (int g = 0; g < 16; ++g) {
+    const uint4 q = rans_group(cnt, g);
+    const uint4 f = make_uint4(rans_norm(q.x, mk, n, r), rans_norm(q.y, mk, n, r), rans_norm(q.z, mk, n, r),
+                               rans_norm(q.w, mk, n, r));
+    local += f.x + f.y + f.z + f.w;
+    fo[g] = f;
   }
   ksum[t] = local;
   __syncthreads();
@@ -1709,7 +1763,7 @@ __global__ __launch_bounds__(1024) void k_rans_model(const uint32_t* cnt, int32_
   }
   if (t == 0 && n > 0) freq[top] += kRansM - ksum[0];
   __syncthreads();
-  rans_cumulate(freq, cum, lds);
+  rans_cumulate(freq, cum, lds, enc_tab);
 }
 
 __global__ __launch_bounds__(1024) void k_rans_cum(const uint32_t* freq, uint32_t* cum) {
@@ -1718,10 +1772,12 @@ __global__ __launch_bounds__(1024) void k_rans_cum(const uint32_t* freq, uint32_
 }
 
 // One thread per lane: the lane's symbols last to first, words written backwards into the
-// lane's own buffer of S + 2 words; len[l] = words written.
+// lane's own buffer of S + 2 words; len[l] = words written.  Symbols and their (f, C)
+// entries are loaded kRansBatch at a time, so the memory latency is paid once per batch
+// and not on the state's dependency chain.
+constexpr int kRansBatch = 8;
 __global__ __launch_bounds__(256) void k_rans_enc(const uint16_t* sym, int32_t n, int64_t lanes,
-                                                  const uint32_t* freq, const uint32_t* cum, uint16_t* buf,
-                                                  int32_t* len) {
+                                                  const uint64_t* enc_tab, uint16_t* buf, int32_t* len) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= lanes) return;
   const int32_t count = rans_lane_count(n, l);
@@ -1729,14 +1785,27 @@ __global__ __launch_bounds__(256) void k_rans_enc(const uint16_t* sym, int32_t n
   uint16_t* out = buf + l * (kRansLaneSymbols + 2);
   int p = kRansLaneSymbols + 2;
   uint32_t x = kRansL;
-  for (int m = count - 1; m >= 0; --m) {
-    const uint32_t s = sym[first + (int64_t)kRansLanesPerChunk * m];
-    const uint32_t f = freq[s];
-    if ((uint64_t)x >= ((uint64_t)f << 16)) {
-      out[--p] = (uint16_t)(x & 0xFFFFu);
-      x >>= 16;
+  for (int m0 = count - 1; m0 >= 0; m0 -= kRansBatch) {
+    uint32_t sb[kRansBatch];
+    uint64_t eb[kRansBatch];
+#pragma unroll
+    for (int u = 0; u < kRansBatch; ++u) {
+      const int m = m0 - u;
+      sb[u] = m >= 0 ? sym[first + (int64_t)kRansLanesPerChunk * m] : 0u;
     }
-    x = ((x / f) << 16) + (x % f) + cum[s];
+#pragma unroll
+    for (int u = 0; u < kRansBatch; ++u) eb[u] = m0 - u >= 0 ? enc_tab[sb[u]] : 1ull;
+#pragma unroll
+    for (int u = 0; u < kRansBatch; ++u) {
+      if (m0 - u < 0) break;
+      const uint32_t f = (uint32_t)eb[u];
+      const uint32_t c = (uint32_t)(eb[u] >> 32);
+      if ((uint64_t)x >= ((uint64_t)f << 16)) {
+        out[--p] = (uint16_t)(x & 0xFFFFu);
+        x >>= 16;
+      }
+      x = ((x / f) << 16) + (x % f) + c;
+    }
   }
   if (count > 0) {
     out[--p] = (uint16_t)(x & 0xFFFFu);
@@ -1767,8 +1836,9 @@ __global__ __launch_bounds__(256) void k_rans_copy(const uint16_t* buf, const in
   if (st) atomicOr(&counters[kCntStatus], st);
 }
 
-// slot -> symbol: the last s with cum[s] <= slot (the symbol whose interval holds it).
-__global__ __launch_bounds__(256) void k_rans_table(const uint32_t* cum, uint16_t* tab) {
+// slot -> (s, f_s, slot - C_s) with s the last symbol with C_s <= slot (the symbol whose
+// interval holds the slot): one gather per decoded symbol.
+__global__ __launch_bounds__(256) void k_rans_table(const uint32_t* freq, const uint32_t* cum, uint64_t* tab) {
   const uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= kRansM) return;
   uint32_t lo = 0, hi = kRansM;
@@ -1779,13 +1849,13 @@ __global__ __launch_bounds__(256) void k_rans_table(const uint32_t* cum, uint16_
     else
       hi = mid;
   }
-  tab[slot] = (uint16_t)lo;
+  tab[slot] = (uint64_t)lo | ((uint64_t)freq[lo] << 16) | ((uint64_t)(slot - cum[lo]) << 33);
 }
 
 // One thread per lane: reads the lane's words first to last, writes its symbols.
-__global__ __launch_bounds__(256) void k_rans_dec(const uint32_t* freq, const uint32_t* cum, const uint16_t* tab,
-                                                  const uint32_t* lane_off, const uint16_t* words, int32_t cap,
-                                                  int32_t n, int64_t lanes, uint16_t* sym, int32_t* counters) {
+__global__ __launch_bounds__(256) void k_rans_dec(const uint64_t* tab, const uint32_t* lane_off,
+                                                  const uint16_t* words, int32_t cap, int32_t n, int64_t lanes,
+                                                  uint16_t* sym, int32_t* counters) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= lanes) return;
   const int32_t count = rans_lane_count(n, l);
@@ -1804,10 +1874,9 @@ __global__ __launch_bounds__(256) void k_rans_dec(const uint32_t* freq, const ui
     p += 2;
   }
   for (int m = 0; m < count; ++m) {
-    const uint32_t slot = x & 0xFFFFu;
-    const uint32_t s = tab[slot];
-    sym[first + (int64_t)kRansLanesPerChunk * m] = (uint16_t)s;
-    x = freq[s] * (x >> 16) + slot - cum[s];
+    const uint64_t e = tab[x & 0xFFFFu];
+    sym[first + (int64_t)kRansLanesPerChunk * m] = (uint16_t)(e & 0xFFFFu);
+    x = (uint32_t)((e >> 16) & 0x1FFFFu) * (x >> 16) + (uint32_t)(e >> 33);
     if (x < kRansL) {
       uint32_t w = 0;
       if (p < end)
@@ -1963,7 +2032,7 @@ struct Layout {
   // rANS: symbol counts, cumulative frequencies, slot -> symbol table, lane lengths and
   // the lanes' word buffers (each lane writes backwards into its own S + 2 words)
   uint32_t *rans_cnt, *rans_cum;
-  uint16_t* rans_tab;
+  uint64_t* rans_t64;  // encode: (f_s, C_s) per symbol; decode: (s, f_s, slot - C_s) per slot
   int32_t* rans_len;
   uint16_t* rans_buf;
   int64_t rans_lanesN = 0;
@@ -2058,7 +2127,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   L.rans_lanesN = rans_lanes(N);
   carve(p, L.rans_cnt, kRansM, t, set);
   carve(p, L.rans_cum, kRansM + 1, t, set);
-  carve(p, L.rans_tab, kRansM, t, set);
+  carve(p, L.rans_t64, kRansM, t, set);
   carve(p, L.rans_len, L.rans_lanesN + 1, t, set);
   carve(p, L.rans_buf, L.rans_lanesN * (kRansLaneSymbols + 2), t, set);
   L.bytes = t + 256;
@@ -2091,6 +2160,7 @@ struct tpc_ctx {
   std::string err;
   int32_t* pinned = nullptr;  // host-pinned counters for tpc_sync
   bool lds_count_ok = false;  // the device grants the LDS of k_grid_count_lds
+  bool lds_hist_ok = false;   // ... and the 128 KiB of k_rans_hist_lds
   // graph cache (batched modes): the chain is captured once per set of buffers
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -2430,6 +2500,10 @@ int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p)
       c->lds_count_ok = hipFuncSetAttribute((const void*)k_grid_count_lds,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, need) == hipSuccess;
     }
+    const int need_h = kRansHalf * (int)sizeof(uint32_t);
+    if (lds_max >= need_h)
+      c->lds_hist_ok = hipFuncSetAttribute((const void*)k_rans_hist_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           need_h) == hipSuccess;
     (void)hipGetLastError();
   }
   *out = c;
@@ -2932,6 +3006,8 @@ int tpc_rans_encode(tpc_ctx* c, const uint16_t* sym, int32_t n, tpc_rans* out) {
   if (!out || n < 0 || (n > 0 && !sym) || out->cap_words < 0 || !out->n_words || !out->freq || !out->lane_off ||
       (out->cap_words > 0 && !out->words))
     return fail(c, TPC_E_ARG, "tpc_rans_encode: null or negative argument");
+  if (reinterpret_cast<uintptr_t>(out->freq) % 16)
+    return fail(c, TPC_E_ARG, "tpc_rans_encode: freq must be 16-byte aligned");
   if (!c->laid_out || (int64_t)n > c->L.N)
     return fail(c, TPC_E_ARG, "tpc_rans_encode: needs the workspace of a tracking run over at least n clusters");
   HIPCHK(c, hipSetDevice(c->device));
@@ -2941,13 +3017,17 @@ int tpc_rans_encode(tpc_ctx* c, const uint16_t* sym, int32_t n, tpc_rans* out) {
   fill_i32(c, reinterpret_cast<int32_t*>(L.rans_cnt), kRansM, 0);
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-  if (n > 0)
+  if (n > 0 && c->lds_hist_ok)
+    hipLaunchKernelGGL(k_rans_hist_lds, dim3(std::min(blocks_for(n, 1024), ncu)), dim3(1024),
+                       kRansHalf * sizeof(uint32_t), c->stream, sym, n, L.rans_cnt);
+  else if (n > 0)
     hipLaunchKernelGGL(k_rans_hist, dim3(std::min(blocks_for(n, 256), ncu * 4)), dim3(256), 0, c->stream, sym, n,
                        L.rans_cnt);
-  hipLaunchKernelGGL(k_rans_model, dim3(1), dim3(1024), 0, c->stream, L.rans_cnt, n, out->freq, L.rans_cum);
+  hipLaunchKernelGGL(k_rans_model, dim3(1), dim3(1024), 0, c->stream, L.rans_cnt, n, out->freq, L.rans_cum,
+                     L.rans_t64);
   if (lanes > 0) {
-    hipLaunchKernelGGL(k_rans_enc, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, sym, n, lanes, out->freq,
-                       L.rans_cum, L.rans_buf, L.rans_len);
+    hipLaunchKernelGGL(k_rans_enc, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, sym, n, lanes,
+                       L.rans_t64, L.rans_buf, L.rans_len);
     scan(c, L.rans_len, reinterpret_cast<int32_t*>(out->lane_off), Bound{nullptr, 0, INT32_MAX},
          Bound{nullptr, (int32_t)lanes, INT32_MAX}, lanes, false);
   } else {
@@ -2965,16 +3045,19 @@ int tpc_rans_decode(tpc_ctx* c, const tpc_rans* in, int32_t n, uint16_t* sym) {
   if (!in || n < 0 || (n > 0 && !sym) || in->cap_words < 0 || !in->freq || !in->lane_off ||
       (in->cap_words > 0 && !in->words))
     return fail(c, TPC_E_ARG, "tpc_rans_decode: null or negative argument");
+  if (reinterpret_cast<uintptr_t>(in->freq) % 16)
+    return fail(c, TPC_E_ARG, "tpc_rans_decode: freq must be 16-byte aligned");
   if (!c->laid_out) return fail(c, TPC_E_ARG, "tpc_rans_decode: needs a context that has run a tracking stage");
   HIPCHK(c, hipSetDevice(c->device));
   Layout& L = c->L;
   const int64_t lanes = rans_lanes(n);
   const int pm = prof_begin(c, TPC_PROF_RANS_DECODE);
   hipLaunchKernelGGL(k_rans_cum, dim3(1), dim3(1024), 0, c->stream, in->freq, L.rans_cum);
-  hipLaunchKernelGGL(k_rans_table, dim3(kRansM / 256), dim3(256), 0, c->stream, L.rans_cum, L.rans_tab);
+  hipLaunchKernelGGL(k_rans_table, dim3(kRansM / 256), dim3(256), 0, c->stream, in->freq, L.rans_cum,
+                     L.rans_t64);
   if (lanes > 0)
-    hipLaunchKernelGGL(k_rans_dec, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, in->freq, L.rans_cum,
-                       L.rans_tab, in->lane_off, in->words, in->cap_words, n, lanes, sym, L.counters);
+    hipLaunchKernelGGL(k_rans_dec, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, L.rans_t64,
+                       in->lane_off, in->words, in->cap_words, n, lanes, sym, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
   return TPC_OK;
