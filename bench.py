@@ -129,11 +129,38 @@ def cpu_baseline(cs, cfg, budget_s):
     t0 = time.perf_counter()
     r = O.Run.from_set(sample)
     dt = time.perf_counter() - t0
-    ntr = len(r.tracks()["tracklet"])
+    t = r.tracks()
+    ntr = len(t["tracklet"])
     if dt > budget_s * 3:
         log(f"cpu baseline took {dt:.1f}s (budget {budget_s}s)")
-    return {"value": sample.n / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-            "sample": desc + f"; {ntr} tracks; {dt:.1f} s single-threaded incl. FP64 refit"}
+    out = {"value": sample.n / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+           "sample": desc + f"; {ntr} tracks; {dt:.1f} s single-threaded incl. FP64 refit"}
+    # the compression and rANS rows' oracles on the same sample, against its own tracks
+    t0 = time.perf_counter()
+    c = O.compress(sample.sector, sample.row, sample.y, sample.z, t, Q_STEP, Q_STEP)
+    dc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.decompress(t, c, Q_STEP, Q_STEP)
+    dd = time.perf_counter() - t0
+    H = c["n_attached"]
+    streams = [np.ascontiguousarray(c[k][a:b]).view(np.uint16) for k in ("rs", "ey", "ez")
+               for a, b in ((0, H), (H, len(c["rs"])))]
+    t0 = time.perf_counter()
+    encs = [O.rans_encode(v) for v in streams]
+    de = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for v, e in zip(streams, encs):
+        O.rans_decode(e, len(v))
+    dr = time.perf_counter() - t0
+    nsym = sum(len(v) for v in streams)
+    out["compression"] = {"value": sample.n / dc, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+                          "decompress_clusters_per_s": sample.n / dd,
+                          "sample": f"the same sample and its oracle tracks; {dc:.2f} s encode, {dd:.2f} s decode"}
+    out["rans"] = {"value": nsym / de, "unit": "symbols/s", "cores": 1, "kind": "oracle",
+                   "decode_symbols_per_s": nsym / dr,
+                   "sample": f"the six record streams of that sample ({nsym} symbols); {de:.2f} s encode, "
+                             f"{dr:.2f} s decode"}
+    return out
 
 
 def copy_probe(tr, torch, mib, reps):
@@ -517,6 +544,8 @@ def main():
         "quality": q,
     }
     if cpu is not None:
+        compression["cpu_baseline"] = cpu.pop("compression", None)
+        compression["rans"]["cpu_baseline"] = cpu.pop("rans", None)
         out["cpu_baseline"] = cpu
         out["cpu_baseline_all_cores"] = cpu_par
     print(json.dumps(out), flush=True)
