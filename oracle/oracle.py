@@ -109,6 +109,10 @@ def lib():
         L.orc_rans_encode.restype = C.c_int32
         L.orc_rans_decode.argtypes = [P, P, P, C.c_int32, P]
         L.orc_rans_decode.restype = None
+        L.orc_find_clusters.restype = C.c_int32
+        L.orc_find_clusters.argtypes = [C.c_int32] + [P] * 5 + [C.c_float, C.c_float, C.c_int32, C.c_int32] + [P] * 10
+        L.orc_cf_pads.restype = C.c_int32
+        L.orc_cf_pads.argtypes = [C.c_int32, C.c_float]
         L.orc_rans_lanes.argtypes = [C.c_int64]
         L.orc_rans_lanes.restype = C.c_int64
         L.orc_predict.argtypes = [C.POINTER(Params), P, C.c_float, C.c_int32, C.c_int32, C.c_int32, P]
@@ -372,3 +376,31 @@ def rans_decode(enc, n):
         w = np.zeros(1, np.uint16)
     lib().orc_rans_decode(_p(f), _p(off), _p(w), n, _p(out))
     return out[:n]
+
+
+# ----------------------------------------------------------------- cluster finding
+
+CF_DEFAULTS = dict(pitch=0.5, bin=0.5, n_time=500, q_min=10)
+
+
+def cf_pads(r: int, pitch: float = 0.5) -> int:
+    return int(lib().orc_cf_pads(r, pitch))
+
+
+def find_clusters(sector, row, pad, time, adc, pitch=0.5, bin=0.5, n_time=500, q_min=10):
+    """F1-F6: dict(digit, sector, row, y, z, q_tot, q_max, sigma_pad, sigma_time, status)."""
+    a = [np.ascontiguousarray(sector, np.uint8), np.ascontiguousarray(row, np.int16),
+         np.ascontiguousarray(pad, np.int16), np.ascontiguousarray(time, np.int16),
+         np.ascontiguousarray(adc, np.uint16)]
+    n = len(a[0])
+    m0 = max(n, 1)
+    out = dict(digit=np.zeros(m0, np.int32), sector=np.zeros(m0, np.uint8), row=np.zeros(m0, np.int16),
+               y=np.zeros(m0, np.float32), z=np.zeros(m0, np.float32), q_tot=np.zeros(m0, np.uint32),
+               q_max=np.zeros(m0, np.uint32), sigma_pad=np.zeros(m0, np.float32),
+               sigma_time=np.zeros(m0, np.float32))
+    st = np.zeros(1, np.int32)
+    keys = ["digit", "sector", "row", "y", "z", "q_tot", "q_max", "sigma_pad", "sigma_time"]
+    m = lib().orc_find_clusters(n, *map(_p, a), pitch, bin, n_time, q_min, *[_p(out[k]) for k in keys], _p(st))
+    res = {k: v[:m] for k, v in out.items()}
+    res["status"] = int(st[0])
+    return res

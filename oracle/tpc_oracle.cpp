@@ -13,7 +13,8 @@
 // needed here: rows are searched in full or by binary search in z), O4
 // neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
 // O9 selection and fit, O10 merge), C1-C5 for the track-model compression that
-// consumes the tracks, and E1-E5 for the rANS entropy coder after it (section 5).
+// consumes the tracks, E1-E5 for the rANS entropy coder after it, and F1-F6 for the
+// cluster finding before the tracking (section 5).
 //
 // Only tests/, the smoke check and the CPU baseline leg of the benchmark may
 // load this library.  It shares no code, header, table or constant generator
@@ -36,7 +37,9 @@
 // and special cases: parity unpinned beyond those.  Compression: the prediction
 // against an FP64 closed-form circle in the rotated frame, zero residual codes for
 // clusters placed exactly on the fitted helix, absolute codes against numpy's rint,
-// and the round trip within half a quantisation step.  rANS: exact round trips, the
+// and the round trip within half a quantisation step.  Cluster finding: exact centroids
+// of symmetric and hand-computed charge patterns, the tie rule, translation invariance,
+// and the generator's clusters recovered from its digits.  rANS: exact round trips, the
 // model's normalisation rule and closed forms, lane sizes within a few words of the
 // information content under the model.
 
@@ -44,6 +47,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 namespace {
@@ -907,6 +911,31 @@ void rans_lane(int64_t n, int64_t l, int64_t& first, int64_t& count) {
   count = first < n ? std::min<int64_t>(kRansLaneSymbols, (n - first + kRansLanesPerChunk - 1) / kRansLanesPerChunk) : 0;
 }
 
+// ---------------------------------------------------------------- F: cluster finding
+// Section 5: the TPC clusters are found on the GPUs from the zero-suppressed digits, before
+// the tracking.  The paper gives neither the pad plane nor the finder; the reading (F1-F6):
+//  F1 Pad plane: row r holds P_r = 2 ceil(x_r tan 10 deg / pitch) pads (x_r in double),
+//     pad p centred at y = (p + 1/2) pitch - P_r pitch / 2; time bins of `bin` cm of |z|,
+//     bin t centred at |z| = (t + 1/2) bin, t < n_time.
+//  F2 Charge map: each cell (sector, row, pad, time) holds the sum of the ADC counts of the
+//     digits in it; digits outside the sector/row/pad/time ranges are dropped and raise the
+//     range status.
+//  F3 Peak: a digit whose cell charge q >= q_min and, over the 8 neighbouring cells of its
+//     row (cells outside the pad or time range count as 0), q > q_n for the neighbours that
+//     come before it in (pad, time) order and q >= q_n for those after (so of two equal
+//     neighbouring maxima the earlier one is the peak).
+//  F4 Cluster of a peak at (p, t): over its 3 x 3 cells, Q = sum q, S_p = sum q dp,
+//     S_t = sum q dt, S_pp = sum q dp^2, S_tt = sum q dt^2 (integers, exact); in FP32
+//     pad = p + S_p / Q, time = t + S_t / Q, sigma_pad = sqrt(max(0, S_pp / Q - (S_p / Q)^2))
+//     and likewise in time; y = (pad + 1/2) pitch - P_r pitch / 2 (the last term rounded
+//     once from double), z = (time + 1/2) bin, negative on side C; q_max = the peak's q.
+//  F5 Clusters come in the order of their peak digits in the input.
+//  F6 Duplicated digits add up in the map; each copy of a peak digit reports the cluster.
+int32_t cf_pads(int r, float pitch) {
+  const double x = 85.0 + (double)r * 160.0 / 151.0;
+  return 2 * (int32_t)std::ceil(x * std::tan(10.0 * 3.14159265358979323846 / 180.0) / (double)pitch);
+}
+
 }  // namespace
 
 // ============================================================== C interface (ctypes)
@@ -1236,6 +1265,77 @@ void orc_rans_decode(const uint32_t* freq, const uint32_t* lane_off, const uint1
 }
 
 int64_t orc_rans_lanes(int64_t n) { return rans_lanes(n); }
+
+// F1-F6: the clusters of n digits; returns their number (<= n).
+int32_t orc_find_clusters(int32_t n, const uint8_t* sector, const int16_t* row, const int16_t* pad,
+                          const int16_t* time, const uint16_t* adc, float pitch, float bin, int32_t n_time,
+                          int32_t q_min, int32_t* digit, uint8_t* csec, int16_t* crow, float* y, float* z,
+                          uint32_t* qtot, uint32_t* qmax, float* spad, float* stime, int32_t* status) {
+  int32_t P[kRows];
+  for (int r = 0; r < kRows; ++r) P[r] = cf_pads(r, pitch);
+  auto in_range = [&](int s, int r, int p, int t) {
+    return s >= 0 && s < kSectors && r >= 0 && r < kRows && p >= 0 && p < P[r] && t >= 0 && t < n_time;
+  };
+  auto key = [&](int s, int r, int p, int t) {
+    return (((uint64_t)s * kRows + (uint64_t)r) * 1024 + (uint64_t)p) * 65536 + (uint64_t)t;
+  };
+  std::unordered_map<uint64_t, uint32_t> map;
+  int32_t st = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!in_range(sector[i], row[i], pad[i], time[i])) { st |= 1; continue; }
+    map[key(sector[i], row[i], pad[i], time[i])] += adc[i];
+  }
+  auto charge = [&](int s, int r, int p, int t) -> uint32_t {
+    if (!in_range(s, r, p, t)) return 0;
+    auto it = map.find(key(s, r, p, t));
+    return it == map.end() ? 0 : it->second;
+  };
+  int32_t m = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int s = sector[i], r = row[i], p = pad[i], t = time[i];
+    if (!in_range(s, r, p, t)) continue;
+    const uint32_t q = charge(s, r, p, t);
+    if (q < (uint32_t)q_min) continue;
+    bool peak = true;
+    for (int dp = -1; dp <= 1 && peak; ++dp)
+      for (int dt = -1; dt <= 1 && peak; ++dt) {
+        if (dp == 0 && dt == 0) continue;
+        const uint32_t qn = charge(s, r, p + dp, t + dt);
+        const bool before = dp < 0 || (dp == 0 && dt < 0);
+        if (before ? !(q > qn) : !(q >= qn)) peak = false;
+      }
+    if (!peak) continue;
+    int64_t Q = 0, Sp = 0, St = 0, Spp = 0, Stt = 0;
+    for (int dp = -1; dp <= 1; ++dp)
+      for (int dt = -1; dt <= 1; ++dt) {
+        const int64_t qn = charge(s, r, p + dp, t + dt);
+        Q += qn;
+        Sp += qn * dp;
+        St += qn * dt;
+        Spp += qn * dp * dp;
+        Stt += qn * dt * dt;
+      }
+    const float fq = (float)Q;
+    const float mp = (float)Sp / fq, mt = (float)St / fq;
+    const float vp = (float)Spp / fq - mp * mp, vt = (float)Stt / fq - mt * mt;
+    const float half = (float)((double)P[r] * (double)pitch / 2.0);
+    digit[m] = i;
+    csec[m] = (uint8_t)s;
+    crow[m] = (int16_t)r;
+    y[m] = ((float)p + mp + 0.5f) * pitch - half;
+    const float az = ((float)t + mt + 0.5f) * bin;
+    z[m] = s < kRowsPerSide ? az : -az;
+    qtot[m] = (uint32_t)Q;
+    qmax[m] = q;
+    spad[m] = std::sqrt(std::max(vp, 0.f));
+    stime[m] = std::sqrt(std::max(vt, 0.f));
+    ++m;
+  }
+  *status = st;
+  return m;
+}
+
+int32_t orc_cf_pads(int32_t r, float pitch) { return cf_pads(r, pitch); }
 
 // C1 alone (pins): returns 1 and (py, pz) when there is a prediction.
 int32_t orc_predict(const Params* p, const float* P, float xref, int32_t sref, int32_t sec, int32_t row,
