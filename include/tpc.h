@@ -175,7 +175,8 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 /* Per-kernel timing with HIP events recorded on the context's stream around the
  * launches of: the neighbour kernel (index 0), the tracklet kernel (1), the grid
  * build (2), the selection (3), fit + merge (4), tpc_compress (5),
- * tpc_decompress (6), tpc_rans_encode (7) and tpc_rans_decode (8).  While
+ * tpc_decompress (6), tpc_rans_encode (7), tpc_rans_decode (8) and
+ * tpc_find_clusters (9).  While
  * enabled, tpc_run does
  * not use a graph.  tpc_profile_read waits for the stream and returns the summed
  * milliseconds and the number of timed launches per index since the last reset. */
@@ -188,7 +189,8 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 #define TPC_PROF_DECOMPRESS 6 /* tpc_decompress (all its kernels) */
 #define TPC_PROF_RANS_ENCODE 7
 #define TPC_PROF_RANS_DECODE 8
-#define TPC_PROF_KERNELS 9
+#define TPC_PROF_CLUSTERS 9   /* tpc_find_clusters (all its kernels) */
+#define TPC_PROF_KERNELS 10
 int tpc_profile(tpc_ctx* ctx, int enable);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
 
@@ -272,6 +274,63 @@ typedef struct {
 int64_t tpc_rans_lanes(int64_t n);
 int tpc_rans_encode(tpc_ctx* ctx, const uint16_t* sym, int32_t n, tpc_rans* out);
 int tpc_rans_decode(tpc_ctx* ctx, const tpc_rans* in, int32_t n, uint16_t* sym);
+
+/* Cluster finding (section 5: the TPC clusters are found on the GPUs from the
+ * zero-suppressed digits, ahead of the tracking).  Pad plane: row r holds
+ * P_r = 2 ceil(x_r tan 10 deg / pad_pitch) pads (x_r = 85 + r 160/151 cm, in
+ * double), pad p centred at y = (p + 1/2) pad_pitch - P_r pad_pitch / 2; time
+ * bins of time_bin cm of |z|, bin t centred at |z| = (t + 1/2) time_bin.
+ * The ADC counts of the digits are summed per (sector, row, pad, time) cell
+ * (digits outside the plane are dropped: TPC_E_RANGE in *status).  A digit is
+ * a peak when its cell's charge q >= q_min and, over the 8 neighbouring cells
+ * of its row (cells off the plane count 0), q > q_n for the neighbours that
+ * come earlier in (pad, time) order and q >= q_n for the later ones.  Its
+ * cluster, over the 3 x 3 cells: Q = sum q and the integer moments
+ * S_p = sum q dp, S_pp = sum q dp^2 (and in time); in FP32
+ * pad = p + S_p / Q, sigma_pad = sqrt(max(0, S_pp / Q - (S_p / Q)^2)),
+ * y = (pad + 1/2) pad_pitch - P_r pad_pitch / 2 (last term rounded once),
+ * z = (time + 1/2) time_bin, negative on side C (sectors 18..35).
+ * Clusters come in the order of their peak digits; each copy of a duplicated
+ * peak digit reports it.  Errors found on the device go to out->status
+ * (TPC_E_RANGE / TPC_E_CAPACITY bits as in TPC_STATUS_*), not to tpc_sync;
+ * beyond out->cap nothing is written and *n_clusters holds the number found.
+ * The caller provides a 256-byte aligned device workspace of at least
+ * tpc_cf_workspace_size() bytes (a uint32 charge map of all cells, about
+ * 1.3 GB for the defaults); the call needs no tracking run before it.       */
+#define TPC_STATUS_RANGE 1
+#define TPC_STATUS_CAPACITY 2
+typedef struct {
+  float pad_pitch;  /* cm, >= 0.05                         */
+  float time_bin;   /* cm of drift per time bin            */
+  int32_t n_time;   /* time bins per row, 1..32767         */
+  int32_t q_min;    /* minimum charge of a peak, ADC, >= 1 */
+} tpc_cf_params;
+typedef struct {
+  int32_t n;
+  const uint8_t* sector;
+  const int16_t* row;
+  const int16_t* pad;
+  const int16_t* time;
+  const uint16_t* adc;
+} tpc_digits;
+typedef struct {
+  int32_t cap;            /* [host] */
+  int32_t* n_clusters;    /* [1] */
+  int32_t* status;        /* [1] TPC_STATUS_* bits */
+  int32_t* digit;         /* [cap] index of the peak digit */
+  uint8_t* sector;        /* [cap] */
+  int16_t* row;           /* [cap] */
+  float* y;               /* [cap] cm, sector frame */
+  float* z;               /* [cap] cm */
+  uint32_t* q_tot;        /* [cap] ADC over the 3 x 3 cells */
+  uint32_t* q_max;        /* [cap] ADC of the peak cell */
+  float* sigma_pad;       /* [cap] pads */
+  float* sigma_time;      /* [cap] time bins */
+} tpc_cf_clusters;
+int tpc_cf_params_default(tpc_cf_params* p);  /* 0.5 cm, 0.5 cm, 500 bins, 10 ADC */
+size_t tpc_cf_workspace_size(const tpc_cf_params* p, int32_t n_digits);  /* 0: invalid */
+int tpc_find_clusters(tpc_ctx* ctx, const tpc_cf_params* p, const tpc_digits* d, void* ws, size_t ws_bytes,
+                      tpc_cf_clusters* out);
 
 /* Wait for the context's stream; returns TPC_E_RANGE / TPC_E_CAPACITY if the
  * kernels reported one since the last tpc_grid_build, else TPC_OK.           */

@@ -927,6 +927,7 @@ void rans_lane(int64_t n, int64_t l, int64_t& first, int64_t& count) {
 //  F4 Cluster of a peak at (p, t): over its 3 x 3 cells, Q = sum q, S_p = sum q dp,
 //     S_t = sum q dt, S_pp = sum q dp^2, S_tt = sum q dt^2 (integers, exact); in FP32
 //     pad = p + S_p / Q, time = t + S_t / Q, sigma_pad = sqrt(max(0, S_pp / Q - (S_p / Q)^2))
+//     (q_min >= 1, so Q > 0)
 //     and likewise in time; y = (pad + 1/2) pitch - P_r pitch / 2 (the last term rounded
 //     once from double), z = (time + 1/2) bin, negative on side C; q_max = the peak's q.
 //  F5 Clusters come in the order of their peak digits in the input.
@@ -1327,8 +1328,8 @@ int32_t orc_find_clusters(int32_t n, const uint8_t* sector, const int16_t* row, 
     z[m] = s < kRowsPerSide ? az : -az;
     qtot[m] = (uint32_t)Q;
     qmax[m] = q;
-    spad[m] = std::sqrt(std::max(vp, 0.f));
-    stime[m] = std::sqrt(std::max(vt, 0.f));
+    spad[m] = std::sqrt(vp > 0.f ? vp : 0.f);
+    stime[m] = std::sqrt(vt > 0.f ? vt : 0.f);
     ++m;
   }
   *status = st;

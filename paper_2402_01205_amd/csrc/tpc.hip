@@ -1889,6 +1889,174 @@ __global__ __launch_bounds__(256) void k_rans_dec(const uint64_t* tab, const uin
   if (st) atomicOr(&counters[kCntStatus], st);
 }
 
+// ------------------------------------------------------------------ cluster finding
+// Clusters from zero-suppressed digits (section 5: cluster finding runs on the GPUs before
+// the tracking).  The digits' charges are summed into a dense map of every (sector, row,
+// pad, time) cell; a digit is a peak if its cell's charge reaches q_min and is a local
+// maximum over the 8 neighbouring cells of its row (strictly above the neighbours that come
+// earlier in (pad, time) order, at least equal to the later ones); its cluster is the
+// charge-weighted centroid and width over the 3 x 3 cells.  Clusters come in the order of
+// their peak digits.
+struct CfGeo {
+  int32_t pads[kRows];        // pads of each row
+  int32_t rowoff[kRows + 1];  // first cell of each row within a sector (pads x n_time each)
+  float half[kRows];          // half the row width, pads * pitch / 2
+  int64_t per_sector;         // cells per sector
+  int32_t n_time, q_min;
+  float pitch, bin;
+};
+struct CfDigits {
+  int32_t n;
+  const uint8_t* sector;
+  const int16_t* row;
+  const int16_t* pad;
+  const int16_t* time;
+  const uint16_t* adc;
+};
+struct CfOut {
+  int32_t cap;
+  int32_t* n_clusters;
+  int32_t* status;
+  int32_t* digit;
+  uint8_t* sector;
+  int16_t* row;
+  float *y, *z;
+  uint32_t *q_tot, *q_max;
+  float *sigma_pad, *sigma_time;
+};
+
+// cell index of digit i, or -1 if it lies outside the pad plane
+__device__ __forceinline__ int64_t cf_cell(const CfGeo& G, const CfDigits& D, int64_t i, int& s, int& r, int& p,
+                                           int& t) {
+  s = D.sector[i];
+  r = D.row[i];
+  p = D.pad[i];
+  t = D.time[i];
+  if (s >= kSectors || r < 0 || r >= kRows || p < 0 || p >= G.pads[r] || t < 0 || t >= G.n_time) return -1;
+  return (int64_t)s * G.per_sector + G.rowoff[r] + (int64_t)p * G.n_time + t;
+}
+
+__device__ __forceinline__ uint32_t cf_at(const uint32_t* map, const CfGeo& G, int64_t base, int r, int p, int t) {
+  return (p >= 0 && p < G.pads[r] && t >= 0 && t < G.n_time) ? map[base + (int64_t)p * G.n_time + t] : 0u;
+}
+
+__device__ __forceinline__ bool cf_peak(const uint32_t* map, const CfGeo& G, int64_t base, int r, int p, int t) {
+  const uint32_t q = cf_at(map, G, base, r, p, t);
+  if (q < (uint32_t)G.q_min) return false;
+#pragma unroll
+  for (int dp = -1; dp <= 1; ++dp)
+#pragma unroll
+    for (int dt = -1; dt <= 1; ++dt) {
+      if (dp == 0 && dt == 0) continue;
+      const uint32_t qn = cf_at(map, G, base, r, p + dp, t + dt);
+      const bool before = dp < 0 || (dp == 0 && dt < 0);
+      if (before ? !(q > qn) : !(q >= qn)) return false;
+    }
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_cf_fill(CfGeo G, CfDigits D, uint32_t* map, int32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  int s, r, p, t;
+  const int64_t c = cf_cell(G, D, i, s, r, p, t);
+  if (c < 0)
+    atomicOr(status, kStatusRange);
+  else
+    atomicAdd(map + c, (uint32_t)D.adc[i]);
+}
+
+// peaks per tile of kScanTile digits (item q of thread j: digit tile * kScanTile + q * 256 + j)
+__global__ __launch_bounds__(kScanThreads) void k_cf_count(CfGeo G, CfDigits D, const uint32_t* map,
+                                                           int32_t* bsum) {
+  __shared__ int lds[40];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  int c = 0;
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = base + (int64_t)q * kScanThreads;
+    if (i >= D.n) break;
+    int s, r, p, t;
+    const int64_t cell = cf_cell(G, D, i, s, r, p, t);
+    if (cell >= 0 && cf_peak(map, G, cell - (int64_t)p * G.n_time - t, r, p, t)) ++c;
+  }
+  int total;
+  block_excl_scan(c, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// exclusive offsets of the tiles' peaks; *total = all peaks
+__global__ __launch_bounds__(1024) void k_cf_tiles(int32_t* bsum, int32_t ntiles, int32_t* total) {
+  __shared__ int lds[40];
+  int carry = 0;
+  for (int c = 0; c < ntiles; c += blockDim.x) {
+    const int i = c + threadIdx.x;
+    const int v = i < ntiles ? bsum[i] : 0;
+    int tot;
+    const int e = block_excl_scan(v, lds, tot);
+    if (i < ntiles) bsum[i] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_cf_write(CfGeo G, CfDigits D, const uint32_t* map,
+                                                           const int32_t* bsum, const int32_t* total, CfOut O) {
+  __shared__ int lds[40];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *O.n_clusters = *total;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  int64_t rank = bsum[blockIdx.x];
+  int32_t st = 0;
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = base + (int64_t)q * kScanThreads;
+    int s = 0, r = 0, p = 0, t = 0;
+    int64_t rb = 0;
+    bool peak = false;
+    if (i < D.n) {
+      const int64_t cell = cf_cell(G, D, i, s, r, p, t);
+      if (cell >= 0) {
+        rb = cell - (int64_t)p * G.n_time - t;
+        peak = cf_peak(map, G, rb, r, p, t);
+      }
+    }
+    int tot;
+    const int k = block_excl_scan(peak ? 1 : 0, lds, tot);
+    if (peak) {
+      const int64_t pos = rank + k;
+      if (pos >= O.cap) {
+        st |= kStatusCapacity;
+      } else {
+        int64_t Q = 0, Sp = 0, St = 0, Spp = 0, Stt = 0;
+#pragma unroll
+        for (int dp = -1; dp <= 1; ++dp)
+#pragma unroll
+          for (int dt = -1; dt <= 1; ++dt) {
+            const int64_t qn = cf_at(map, G, rb, r, p + dp, t + dt);
+            Q += qn;
+            Sp += qn * dp;
+            St += qn * dt;
+            Spp += qn * dp * dp;
+            Stt += qn * dt * dt;
+          }
+        const float fq = (float)Q;
+        const float mp = div_rn((float)Sp, fq), mt = div_rn((float)St, fq);
+        const float vp = div_rn((float)Spp, fq) - mp * mp, vt = div_rn((float)Stt, fq) - mt * mt;
+        const float az = ((float)t + mt + 0.5f) * G.bin;
+        O.digit[pos] = (int32_t)i;
+        O.sector[pos] = (uint8_t)s;
+        O.row[pos] = (int16_t)r;
+        O.y[pos] = ((float)p + mp + 0.5f) * G.pitch - G.half[r];
+        O.z[pos] = s < kHalf ? az : -az;
+        O.q_tot[pos] = (uint32_t)Q;
+        O.q_max[pos] = cf_at(map, G, rb, r, p, t);
+        O.sigma_pad[pos] = sqrt_rn(vp > 0.f ? vp : 0.f);
+        O.sigma_time[pos] = sqrt_rn(vt > 0.f ? vt : 0.f);
+      }
+    }
+    rank += tot;
+  }
+  if (st) atomicOr(O.status, st);
+}
+
 // ------------------------------------------------------------------ test hooks
 __global__ void k_links_to_input(const int32_t* a, const int32_t* b, const GHit* gh, int32_t* oa,
                                  int32_t* ob, Bound hi_b) {
@@ -3058,6 +3226,90 @@ int tpc_rans_decode(tpc_ctx* c, const tpc_rans* in, int32_t n, uint16_t* sym) {
   if (lanes > 0)
     hipLaunchKernelGGL(k_rans_dec, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, L.rans_t64,
                        in->lane_off, in->words, in->cap_words, n, lanes, sym, L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+int tpc_cf_params_default(tpc_cf_params* p) {
+  if (!p) return TPC_E_ARG;
+  p->pad_pitch = 0.5f;
+  p->time_bin = 0.5f;
+  p->n_time = 500;
+  p->q_min = 10;
+  return TPC_OK;
+}
+
+namespace {
+bool cf_params_ok(const tpc_cf_params* p) {
+  return p && p->pad_pitch > 0.f && p->time_bin > 0.f && std::isfinite(p->pad_pitch) &&
+         std::isfinite(p->time_bin) && p->n_time >= 1 && p->n_time <= 32767 && p->q_min >= 1 &&
+         p->pad_pitch >= 0.05f;
+}
+// F1: 2 ceil(x_r tan 10 deg / pitch) pads per row, x_r in double
+CfGeo cf_geometry(const tpc_cf_params* p) {
+  CfGeo G{};
+  const double tan10 = std::tan(10.0 * 3.14159265358979323846 / 180.0);
+  int64_t off = 0;
+  for (int r = 0; r < kRows; ++r) {
+    const double x = 85.0 + (double)r * 160.0 / 151.0;
+    G.pads[r] = 2 * (int32_t)std::ceil(x * tan10 / (double)p->pad_pitch);
+    G.half[r] = (float)((double)G.pads[r] * (double)p->pad_pitch / 2.0);
+    G.rowoff[r] = (int32_t)off;
+    off += (int64_t)G.pads[r] * p->n_time;
+  }
+  G.rowoff[kRows] = (int32_t)off;
+  G.per_sector = off;
+  G.n_time = p->n_time;
+  G.q_min = p->q_min;
+  G.pitch = p->pad_pitch;
+  G.bin = p->time_bin;
+  return G;
+}
+size_t cf_map_bytes(const CfGeo& G) { return ((size_t)G.per_sector * kSectors * sizeof(uint32_t) + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t tpc_cf_workspace_size(const tpc_cf_params* p, int32_t n_digits) {
+  if (!cf_params_ok(p) || n_digits < 0) return 0;
+  const CfGeo G = cf_geometry(p);
+  const int64_t tiles = ((int64_t)n_digits + kScanTile - 1) / kScanTile + 1;
+  return cf_map_bytes(G) + (size_t)(tiles + 64) * sizeof(int32_t);
+}
+
+int tpc_find_clusters(tpc_ctx* c, const tpc_cf_params* p, const tpc_digits* d, void* ws, size_t ws_bytes,
+                      tpc_cf_clusters* out) {
+  if (!c) return TPC_E_ARG;
+  if (!cf_params_ok(p)) return fail(c, TPC_E_ARG, "tpc_find_clusters: invalid parameters");
+  if (!d || d->n < 0 || (d->n > 0 && (!d->sector || !d->row || !d->pad || !d->time || !d->adc)))
+    return fail(c, TPC_E_ARG, "tpc_find_clusters: invalid digit list");
+  if (!out || out->cap < 0 || !out->n_clusters || !out->status ||
+      (out->cap > 0 && (!out->digit || !out->sector || !out->row || !out->y || !out->z || !out->q_tot ||
+                        !out->q_max || !out->sigma_pad || !out->sigma_time)))
+    return fail(c, TPC_E_ARG, "tpc_find_clusters: invalid output");
+  const size_t need = tpc_cf_workspace_size(p, d->n);
+  if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(c, TPC_E_ARG, "tpc_find_clusters: workspace missing, unaligned or smaller than tpc_cf_workspace_size");
+  HIPCHK(c, hipSetDevice(c->device));
+  const CfGeo G = cf_geometry(p);
+  uint32_t* map = static_cast<uint32_t*>(ws);
+  int32_t* bsum = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + cf_map_bytes(G));
+  const int32_t ntiles = (int32_t)(((int64_t)d->n + kScanTile - 1) / kScanTile);
+  int32_t* total = bsum + ntiles + 1;
+  const CfDigits D{d->n, d->sector, d->row, d->pad, d->time, d->adc};
+  const CfOut O{out->cap, out->n_clusters, out->status, out->digit, out->sector, out->row, out->y, out->z,
+                out->q_tot, out->q_max, out->sigma_pad, out->sigma_time};
+  const int pm = prof_begin(c, TPC_PROF_CLUSTERS);
+  fill_i32(c, reinterpret_cast<int32_t*>(map), G.per_sector * kSectors, 0);
+  fill_i32(c, out->status, 1, 0);
+  fill_i32(c, total, 1, 0);
+  if (d->n > 0) {
+    hipLaunchKernelGGL(k_cf_fill, dim3(blocks_for(d->n, 256)), dim3(256), 0, c->stream, G, D, map, out->status);
+    hipLaunchKernelGGL(k_cf_count, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, bsum);
+    hipLaunchKernelGGL(k_cf_tiles, dim3(1), dim3(1024), 0, c->stream, bsum, ntiles, total);
+    hipLaunchKernelGGL(k_cf_write, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, bsum, total, O);
+  } else {
+    fill_i32(c, out->n_clusters, 1, 0);
+  }
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
   return TPC_OK;

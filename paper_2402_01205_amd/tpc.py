@@ -68,6 +68,22 @@ class tpc_rans(C.Structure):
 
 RANS_LANE_SYMBOLS = 512
 
+
+class tpc_cf_params(C.Structure):
+    _fields_ = [("pad_pitch", C.c_float), ("time_bin", C.c_float), ("n_time", C.c_int32), ("q_min", C.c_int32)]
+
+
+class tpc_digits(C.Structure):
+    _fields_ = [("n", C.c_int32)] + [(k, C.c_void_p) for k in ("sector", "row", "pad", "time", "adc")]
+
+
+CF_KEYS = ("digit", "sector", "row", "y", "z", "q_tot", "q_max", "sigma_pad", "sigma_time")
+
+
+class tpc_cf_clusters(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("n_clusters", C.c_void_p), ("status", C.c_void_p)] + [
+        (k, C.c_void_p) for k in CF_KEYS]
+
 # Default quantisation step of the compressed coordinates (cm): a power of two, so that
 # 1/q and e*q are exact in FP32; q/sqrt(12) = 0.009 cm against 0.1 cm cluster errors.
 Q_STEP = 1.0 / 32.0
@@ -121,6 +137,10 @@ def lib():
         L.tpc_profile_read.argtypes = [V, V, V, C.c_int32, C.c_int32]
         L.tpc_compress.argtypes = [V, P(tpc_clusters), P(tpc_tracks), C.c_float, C.c_float, P(tpc_codes)]
         L.tpc_decompress.argtypes = [V, P(tpc_tracks), P(tpc_codes), C.c_float, C.c_float, V, V, V, V]
+        L.tpc_cf_params_default.argtypes = [P(tpc_cf_params)]
+        L.tpc_cf_workspace_size.argtypes = [P(tpc_cf_params), C.c_int32]
+        L.tpc_cf_workspace_size.restype = C.c_size_t
+        L.tpc_find_clusters.argtypes = [V, P(tpc_cf_params), P(tpc_digits), V, C.c_size_t, P(tpc_cf_clusters)]
         L.tpc_rans_lanes.argtypes = [C.c_int64]
         L.tpc_rans_lanes.restype = C.c_int64
         L.tpc_rans_encode.argtypes = [V, V, C.c_int32, P(tpc_rans)]
@@ -136,9 +156,10 @@ EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_c
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
             "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress",
-            "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode"]
+            "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode", "tpc_cf_params_default",
+            "tpc_cf_workspace_size", "tpc_find_clusters"]
 PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress",
-              "rans_encode", "rans_decode"]
+              "rans_encode", "rans_decode", "find_clusters"]
 
 
 def default_params(**over) -> tpc_params:
@@ -366,6 +387,49 @@ class Tracker:
         return dict(n_words=int(enc["n_words"].item()), freq=enc["freq"].cpu().numpy().view(np.uint32),
                     lane_off=enc["lane_off"].cpu().numpy().view(np.uint32),
                     words=enc["words"][:m].cpu().numpy().view(np.uint16))
+
+    # ---- cluster finding from digits (device tensors)
+    def tpc_find_clusters(self, digits: dict, params: tpc_cf_params | None = None, cap: int | None = None) -> dict:
+        """Enqueues tpc_find_clusters on digits {sector u8, row i16, pad i16, time i16, adc i16
+        (read as uint16)}; returns the output device tensors (kept until the next call)."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        if params is None:
+            params = tpc_cf_params()
+            lib().tpc_cf_params_default(C.byref(params))
+        n = int(digits["adc"].numel())
+        need = int(lib().tpc_cf_workspace_size(C.byref(params), n))
+        if need == 0:
+            raise TpcError(TPC_E_ARG, "tpc_cf_workspace_size: invalid parameters")
+        if getattr(self, "cf_ws", None) is None or self.cf_ws.numel() < need:
+            self.cf_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        cap = max(n, 1) if cap is None else cap
+        i32, f32 = torch.int32, torch.float32
+        o = dict(cap=cap, n_clusters=torch.zeros(1, dtype=i32, device=dev), status=torch.zeros(1, dtype=i32, device=dev),
+                 digit=torch.zeros(max(cap, 1), dtype=i32, device=dev),
+                 sector=torch.zeros(max(cap, 1), dtype=torch.uint8, device=dev),
+                 row=torch.zeros(max(cap, 1), dtype=torch.int16, device=dev),
+                 y=torch.zeros(max(cap, 1), dtype=f32, device=dev), z=torch.zeros(max(cap, 1), dtype=f32, device=dev),
+                 q_tot=torch.zeros(max(cap, 1), dtype=i32, device=dev),
+                 q_max=torch.zeros(max(cap, 1), dtype=i32, device=dev),
+                 sigma_pad=torch.zeros(max(cap, 1), dtype=f32, device=dev),
+                 sigma_time=torch.zeros(max(cap, 1), dtype=f32, device=dev))
+        dg = tpc_digits(n, *[_ptr(digits[k]) for k in ("sector", "row", "pad", "time", "adc")])
+        cl = tpc_cf_clusters(cap, _ptr(o["n_clusters"]), _ptr(o["status"]), *[_ptr(o[k]) for k in CF_KEYS])
+        self._check(lib().tpc_find_clusters(self.ctx, C.byref(params), C.byref(dg), _ptr(self.cf_ws), need,
+                                            C.byref(cl)), "tpc_find_clusters")
+        return o
+
+    def clusters_numpy(self, o: dict) -> dict:
+        """The found clusters as numpy arrays (waits for the stream); status as TPC_STATUS_* bits."""
+        self.torch.cuda.synchronize(self.device)
+        m = min(int(o["n_clusters"].item()), o["cap"])
+        r = {k: o[k][:m].cpu().numpy() for k in CF_KEYS}
+        r["q_tot"] = r["q_tot"].view(np.uint32)
+        r["q_max"] = r["q_max"].view(np.uint32)
+        r["n"] = int(o["n_clusters"].item())
+        r["status"] = int(o["status"].item())
+        return r
 
     def codes_numpy(self) -> dict:
         """The records of the last tpc_compress (waits for the stream; no error check)."""
