@@ -53,6 +53,9 @@ CMP_BYTES_PER_TRACK = 36
 Q_STEP = 1.0 / 32.0
 #  rANS encode     : per symbol 2 B read; per coded word 2 B written; per lane 4 B (offset)
 #  rANS decode     : per coded word 2 B read; per symbol 2 B written; per lane 8 B (offsets)
+#  cluster finding : per digit 9 B read (sector, row, pad, time, adc); per cluster 35 B written
+CF_BYTES_PER_DIGIT = 9
+CF_BYTES_PER_CLUSTER = 35
 
 
 def log(*a):
@@ -259,6 +262,50 @@ def compression_run(tr, cs, tracks, steps, log):
     return out
 
 
+def cf_cpu_baseline(dg):
+    """The oracle's cluster finder on the digits of sectors 0-3 of the digit workload."""
+    import oracle.oracle as O
+    m = dg.sector < 4
+    args = [dg.sector[m], dg.row[m], dg.pad[m], dg.time[m], dg.adc[m]]
+    t0 = time.perf_counter()
+    c = O.find_clusters(*args, n_time=dg.n_time)
+    dt = time.perf_counter() - t0
+    return {"value": int(m.sum()) / dt, "unit": "digits/s", "cores": 1, "kind": "oracle",
+            "sample": f"sectors 0-3 of the digit workload ({int(m.sum())} digits, {len(c['y'])} clusters); "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def cf_run(tr, dg, steps, torch):
+    """Cluster finding on the digit workload: time per call (HIP events on the library's
+    stream, on a workspace the previous call left clean), roofline."""
+    from paper_2402_01205_amd.tpc import lib, tpc_cf_params
+    import ctypes as C
+    p = tpc_cf_params()
+    lib().tpc_cf_params_default(C.byref(p))
+    p.n_time = dg.n_time
+    f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to("cuda:0")
+    dd = dict(sector=f(dg.sector, np.uint8), row=f(dg.row, np.int16), pad=f(dg.pad, np.int16),
+              time=f(dg.time, np.int16), adc=f(dg.adc.view(np.int16), np.int16))
+    out = tr.tpc_find_clusters(dd, p)           # warm-up: clears the map once
+    torch.cuda.synchronize()
+    tr.profile(True)
+    tr.profile_read(reset=True)
+    for _ in range(steps):
+        out = tr.tpc_find_clusters(dd, p)
+    prof = tr.profile_read(reset=True)
+    tr.profile(False)
+    res = tr.clusters_numpy(out)
+    ms = prof["find_clusters"][0] / max(1, prof["find_clusters"][1])
+    nb = CF_BYTES_PER_DIGIT * dg.n + CF_BYTES_PER_CLUSTER * res["n"]
+    gbs = nb / ms / 1e6
+    r = {"workload": dg.desc, "digits": dg.n, "clusters": res["n"], "status": res["status"], "ms": ms,
+         "digits_per_s": dg.n / (ms / 1e3), "clusters_per_s": res["n"] / (ms / 1e3),
+         "roofline": {"bound": "hbm", "kernel": "tpc_find_clusters (all its kernels)", "achieved": gbs,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nb}}
+    log("cluster finding: " + json.dumps(r))
+    return r
+
+
 def record_streams(tr, H, n):
     """The six fields of the compression records as device streams: rs, ey, ez, each split
     into the track hits (residual codes) and the clusters in no track (absolute codes)."""
@@ -339,6 +386,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=64,
                     help="collisions in the serving pool; the workload states 512")
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--cf-config", default="d3", choices=["d1", "d2", "d3", ""],
+                    help="digit workload of the cluster-finding row ('' = skip)")
     ap.add_argument("--also", default="c2,c3",
                     help="other workloads timed in the same launch configuration (comma list, '' = none)")
     args = ap.parse_args()
@@ -368,6 +417,16 @@ def main():
         cpu_par = cpu_baseline_parallel(cs, min(args.workers, os.cpu_count() or 1))
         if cpu_par:
             log(f"cpu baseline ({cpu_par['cores']} processes): {cpu_par['value']:.3e} clusters/s")
+    dg = None
+    if args.cf_config:
+        from tpcsynth import digits as D
+        t0 = time.perf_counter()
+        _, dg, nt = D.digit_config(args.cf_config, 7)
+        dg.n_time = nt
+        dg.desc = {"d1": "one sector of one event", "d2": "one full-TPC event (8000 primaries)",
+                   "d3": "8 full-TPC events at uniform times over two drift lengths (1000 time bins)"}[args.cf_config]
+        log(f"digits {args.cf_config}: {dg.n} in {time.perf_counter() - t0:.1f}s")
+    cf_cpu = cf_cpu_baseline(dg) if (dg is not None and not args.no_cpu and not args.profile_only) else None
     others = {}
     if not args.profile_only:
         for name in [x for x in args.also.split(",") if x and x != args.config]:
@@ -430,6 +489,8 @@ def main():
                 tr.tpc_rans_decode(e)
         tr.sync()
         log(f"compression: {args.steps} encode and {args.steps} decode calls, then rANS of its six streams")
+        if dg is not None:
+            cf_run(tr, dg, args.steps, torch)
         print(json.dumps({"ms_per_step": ms, "sources": source_digest(),
                           "tuning": {k: getattr(tuning, k) for k, _ in tuning._fields_}}), flush=True)
         return
@@ -460,6 +521,9 @@ def main():
     log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items() if v[1]))
     log("kernels: " + json.dumps(kern))
     compression = compression_run(tr, cs, tracks, args.steps, log)
+    clusters_row = cf_run(tr, dg, args.steps, torch) if dg is not None else None
+    if clusters_row is not None:
+        clusters_row["cpu_baseline"] = cf_cpu
 
     # plain path on the same data
     plain_ms = None
@@ -539,6 +603,7 @@ def main():
         "tuning": tune_report["best"] if tune_report else None,
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items() if v[1]},
         "compression": compression,
+        "cluster_finding": clusters_row,
         "tracks": int(tracks["n"]),
         "tracklets": int(T),
         "quality": q,

@@ -296,7 +296,10 @@ int tpc_rans_decode(tpc_ctx* ctx, const tpc_rans* in, int32_t n, uint16_t* sym);
  * beyond out->cap nothing is written and *n_clusters holds the number found.
  * The caller provides a 256-byte aligned device workspace of at least
  * tpc_cf_workspace_size() bytes (a uint32 charge map of all cells, about
- * 1.3 GB for the defaults); the call needs no tracking run before it.       */
+ * 1.3 GB for the defaults); the call needs no tracking run before it.  The
+ * call leaves the map zero: a following call on the same context with the
+ * same workspace pointer and pad plane skips clearing it, so the caller must
+ * not write to the workspace between such calls.                           */
 #define TPC_STATUS_RANGE 1
 #define TPC_STATUS_CAPACITY 2
 typedef struct {

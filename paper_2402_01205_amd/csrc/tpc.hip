@@ -1955,6 +1955,16 @@ __device__ __forceinline__ bool cf_peak(const uint32_t* map, const CfGeo& G, int
   return true;
 }
 
+// The cells the digits touched back to zero, so that the next call on the same workspace
+// need not clear the whole map.
+__global__ __launch_bounds__(256) void k_cf_clear(CfGeo G, CfDigits D, uint32_t* map) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  int s, r, p, t;
+  const int64_t c = cf_cell(G, D, i, s, r, p, t);
+  if (c >= 0) map[c] = 0u;
+}
+
 __global__ __launch_bounds__(256) void k_cf_fill(CfGeo G, CfDigits D, uint32_t* map, int32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
@@ -1966,9 +1976,10 @@ __global__ __launch_bounds__(256) void k_cf_fill(CfGeo G, CfDigits D, uint32_t* 
     atomicAdd(map + c, (uint32_t)D.adc[i]);
 }
 
-// peaks per tile of kScanTile digits (item q of thread j: digit tile * kScanTile + q * 256 + j)
+// Peaks per tile of kScanTile digits (item q of thread j: digit tile * kScanTile + q * 256 + j,
+// so the digit loads coalesce); peak[i] = 1 marks them for the write pass.
 __global__ __launch_bounds__(kScanThreads) void k_cf_count(CfGeo G, CfDigits D, const uint32_t* map,
-                                                           int32_t* bsum) {
+                                                           uint8_t* peak, int32_t* bsum) {
   __shared__ int lds[40];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
   int c = 0;
@@ -1977,7 +1988,9 @@ __global__ __launch_bounds__(kScanThreads) void k_cf_count(CfGeo G, CfDigits D, 
     if (i >= D.n) break;
     int s, r, p, t;
     const int64_t cell = cf_cell(G, D, i, s, r, p, t);
-    if (cell >= 0 && cf_peak(map, G, cell - (int64_t)p * G.n_time - t, r, p, t)) ++c;
+    const bool pk = cell >= 0 && cf_peak(map, G, cell - (int64_t)p * G.n_time - t, r, p, t);
+    peak[i] = pk ? 1 : 0;
+    c += pk ? 1 : 0;
   }
   int total;
   block_excl_scan(c, lds, total);
@@ -1999,60 +2012,55 @@ __global__ __launch_bounds__(1024) void k_cf_tiles(int32_t* bsum, int32_t ntiles
   if (threadIdx.x == 0) *total = carry;
 }
 
+// The clusters of a tile's peaks: thread j takes the tile's digits 8 j .. 8 j + 7 (one block
+// scan gives each thread the rank of its first peak) and writes a cluster per marked digit.
 __global__ __launch_bounds__(kScanThreads) void k_cf_write(CfGeo G, CfDigits D, const uint32_t* map,
-                                                           const int32_t* bsum, const int32_t* total, CfOut O) {
+                                                           const uint8_t* peak, const int32_t* bsum,
+                                                           const int32_t* total, CfOut O) {
   __shared__ int lds[40];
   if (blockIdx.x == 0 && threadIdx.x == 0) *O.n_clusters = *total;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
-  int64_t rank = bsum[blockIdx.x];
+  const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q)
+    if (first + q < D.n && peak[first + q]) mask |= 1u << q;
+  int tot;
+  int64_t pos = (int64_t)bsum[blockIdx.x] + block_excl_scan(__popc(mask), lds, tot);
   int32_t st = 0;
-  for (int q = 0; q < kScanItems; ++q) {
-    const int64_t i = base + (int64_t)q * kScanThreads;
-    int s = 0, r = 0, p = 0, t = 0;
-    int64_t rb = 0;
-    bool peak = false;
-    if (i < D.n) {
-      const int64_t cell = cf_cell(G, D, i, s, r, p, t);
-      if (cell >= 0) {
-        rb = cell - (int64_t)p * G.n_time - t;
-        peak = cf_peak(map, G, rb, r, p, t);
-      }
+  for (; mask; mask &= mask - 1, ++pos) {
+    const int64_t i = first + __ffs(mask) - 1;
+    if (pos >= O.cap) {
+      st |= kStatusCapacity;
+      continue;
     }
-    int tot;
-    const int k = block_excl_scan(peak ? 1 : 0, lds, tot);
-    if (peak) {
-      const int64_t pos = rank + k;
-      if (pos >= O.cap) {
-        st |= kStatusCapacity;
-      } else {
-        int64_t Q = 0, Sp = 0, St = 0, Spp = 0, Stt = 0;
+    int s, r, p, t;
+    const int64_t cell = cf_cell(G, D, i, s, r, p, t);
+    const int64_t rb = cell - (int64_t)p * G.n_time - t;
+    int64_t Q = 0, Sp = 0, St = 0, Spp = 0, Stt = 0;
 #pragma unroll
-        for (int dp = -1; dp <= 1; ++dp)
+    for (int dp = -1; dp <= 1; ++dp)
 #pragma unroll
-          for (int dt = -1; dt <= 1; ++dt) {
-            const int64_t qn = cf_at(map, G, rb, r, p + dp, t + dt);
-            Q += qn;
-            Sp += qn * dp;
-            St += qn * dt;
-            Spp += qn * dp * dp;
-            Stt += qn * dt * dt;
-          }
-        const float fq = (float)Q;
-        const float mp = div_rn((float)Sp, fq), mt = div_rn((float)St, fq);
-        const float vp = div_rn((float)Spp, fq) - mp * mp, vt = div_rn((float)Stt, fq) - mt * mt;
-        const float az = ((float)t + mt + 0.5f) * G.bin;
-        O.digit[pos] = (int32_t)i;
-        O.sector[pos] = (uint8_t)s;
-        O.row[pos] = (int16_t)r;
-        O.y[pos] = ((float)p + mp + 0.5f) * G.pitch - G.half[r];
-        O.z[pos] = s < kHalf ? az : -az;
-        O.q_tot[pos] = (uint32_t)Q;
-        O.q_max[pos] = cf_at(map, G, rb, r, p, t);
-        O.sigma_pad[pos] = sqrt_rn(vp > 0.f ? vp : 0.f);
-        O.sigma_time[pos] = sqrt_rn(vt > 0.f ? vt : 0.f);
+      for (int dt = -1; dt <= 1; ++dt) {
+        const int64_t qn = cf_at(map, G, rb, r, p + dp, t + dt);
+        Q += qn;
+        Sp += qn * dp;
+        St += qn * dt;
+        Spp += qn * dp * dp;
+        Stt += qn * dt * dt;
       }
-    }
-    rank += tot;
+    const float fq = (float)Q;
+    const float mp = div_rn((float)Sp, fq), mt = div_rn((float)St, fq);
+    const float vp = div_rn((float)Spp, fq) - mp * mp, vt = div_rn((float)Stt, fq) - mt * mt;
+    const float az = ((float)t + mt + 0.5f) * G.bin;
+    O.digit[pos] = (int32_t)i;
+    O.sector[pos] = (uint8_t)s;
+    O.row[pos] = (int16_t)r;
+    O.y[pos] = ((float)p + mp + 0.5f) * G.pitch - G.half[r];
+    O.z[pos] = s < kHalf ? az : -az;
+    O.q_tot[pos] = (uint32_t)Q;
+    O.q_max[pos] = cf_at(map, G, rb, r, p, t);
+    O.sigma_pad[pos] = sqrt_rn(vp > 0.f ? vp : 0.f);
+    O.sigma_time[pos] = sqrt_rn(vt > 0.f ? vt : 0.f);
   }
   if (st) atomicOr(O.status, st);
 }
@@ -2329,6 +2337,8 @@ struct tpc_ctx {
   int32_t* pinned = nullptr;  // host-pinned counters for tpc_sync
   bool lds_count_ok = false;  // the device grants the LDS of k_grid_count_lds
   bool lds_hist_ok = false;   // ... and the 128 KiB of k_rans_hist_lds
+  void* cf_clean_ws = nullptr;  // cluster-finding workspace whose charge map this context left zero
+  int64_t cf_clean_cells = 0;
   // graph cache (batched modes): the chain is captured once per set of buffers
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -3273,7 +3283,7 @@ size_t tpc_cf_workspace_size(const tpc_cf_params* p, int32_t n_digits) {
   if (!cf_params_ok(p) || n_digits < 0) return 0;
   const CfGeo G = cf_geometry(p);
   const int64_t tiles = ((int64_t)n_digits + kScanTile - 1) / kScanTile + 1;
-  return cf_map_bytes(G) + (size_t)(tiles + 64) * sizeof(int32_t);
+  return cf_map_bytes(G) + (size_t)(tiles + 64) * sizeof(int32_t) + (size_t)n_digits;
 }
 
 int tpc_find_clusters(tpc_ctx* c, const tpc_cf_params* p, const tpc_digits* d, void* ws, size_t ws_bytes,
@@ -3295,23 +3305,30 @@ int tpc_find_clusters(tpc_ctx* c, const tpc_cf_params* p, const tpc_digits* d, v
   int32_t* bsum = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + cf_map_bytes(G));
   const int32_t ntiles = (int32_t)(((int64_t)d->n + kScanTile - 1) / kScanTile);
   int32_t* total = bsum + ntiles + 1;
+  uint8_t* peak = reinterpret_cast<uint8_t*>(bsum + ntiles + 64);
   const CfDigits D{d->n, d->sector, d->row, d->pad, d->time, d->adc};
   const CfOut O{out->cap, out->n_clusters, out->status, out->digit, out->sector, out->row, out->y, out->z,
                 out->q_tot, out->q_max, out->sigma_pad, out->sigma_time};
   const int pm = prof_begin(c, TPC_PROF_CLUSTERS);
-  fill_i32(c, reinterpret_cast<int32_t*>(map), G.per_sector * kSectors, 0);
+  // a workspace this context left clean (same pointer, same plane) needs no full clear
+  const bool clean = c->cf_clean_ws == ws && c->cf_clean_cells == G.per_sector * kSectors;
+  if (!clean) fill_i32(c, reinterpret_cast<int32_t*>(map), G.per_sector * kSectors, 0);
   fill_i32(c, out->status, 1, 0);
   fill_i32(c, total, 1, 0);
   if (d->n > 0) {
     hipLaunchKernelGGL(k_cf_fill, dim3(blocks_for(d->n, 256)), dim3(256), 0, c->stream, G, D, map, out->status);
-    hipLaunchKernelGGL(k_cf_count, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, bsum);
+    hipLaunchKernelGGL(k_cf_count, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, peak, bsum);
     hipLaunchKernelGGL(k_cf_tiles, dim3(1), dim3(1024), 0, c->stream, bsum, ntiles, total);
-    hipLaunchKernelGGL(k_cf_write, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, bsum, total, O);
+    hipLaunchKernelGGL(k_cf_write, dim3(ntiles), dim3(kScanThreads), 0, c->stream, G, D, map, peak, bsum, total,
+                       O);
+    hipLaunchKernelGGL(k_cf_clear, dim3(blocks_for(d->n, 256)), dim3(256), 0, c->stream, G, D, map);
   } else {
     fill_i32(c, out->n_clusters, 1, 0);
   }
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
+  c->cf_clean_ws = ws;
+  c->cf_clean_cells = G.per_sector * kSectors;
   return TPC_OK;
 }
 

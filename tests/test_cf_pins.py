@@ -89,7 +89,7 @@ def test_threshold_edges_and_separation():
 
 
 def test_translation_moves_clusters_by_whole_cells():
-    cs, d = D.digit_config("d1", 11)
+    cs, d, _ = D.digit_config("d1", 11)
     a = O.find_clusters(d.sector, d.row, d.pad, d.time, d.adc)
     b = O.find_clusters(d.sector, d.row, d.pad, d.time + 7, d.adc)
     # near the time edge the shifted copy keeps clusters the original cut
@@ -116,7 +116,7 @@ def test_generator_clusters_are_recovered():
     """Single-sector event: every isolated generated cluster (no other within 3 pads and
     3 bins) is found within 0.35 pad / bin of where its charge was deposited, with an RMS
     residual well below the 0.6-cell charge spread."""
-    cs, d = D.digit_config("d1", 11)
+    cs, d, _ = D.digit_config("d1", 11)
     c = O.find_clusters(d.sector, d.row, d.pad, d.time, d.adc)
     u_f = (c["y"] + D.PADS[c["row"]] * PITCH / 2) / PITCH - 0.5
     v_f = np.abs(c["z"]) / BIN - 0.5

@@ -62,7 +62,7 @@ def _arrays(d):
 
 @pytest.mark.parametrize("cfg,seed", [("d1", 11), ("d1", 12), ("d2", 21)])
 def test_digits_of_generated_events_bit_exact(tracker, cfg, seed):
-    cs, d = D.digit_config(cfg, seed)
+    cs, d, _ = D.digit_config(cfg, seed)
     say(cfg, seed, "digits", d.n)
     g = _gpu(tracker, _arrays(d))
     assert g["status"] == 0
@@ -72,7 +72,7 @@ def test_digits_of_generated_events_bit_exact(tracker, cfg, seed):
 
 
 def test_shuffled_digits_and_other_parameters(tracker):
-    cs, d = D.digit_config("d1", 13)
+    cs, d, _ = D.digit_config("d1", 13)
     a = _arrays(d)
     perm = np.random.default_rng(1).permutation(d.n)
     sh = [x[perm] for x in a]
@@ -87,7 +87,7 @@ def test_shuffled_digits_and_other_parameters(tracker):
 
 def test_invalid_duplicated_and_empty(tracker):
     from paper_2402_01205_amd.tpc import TPC_E_RANGE
-    cs, d = D.digit_config("d1", 11)
+    cs, d, _ = D.digit_config("d1", 11)
     a = [x.copy() for x in _arrays(d)]
     a[1][3] = 152
     a[2][4] = 500
@@ -104,18 +104,36 @@ def test_invalid_duplicated_and_empty(tracker):
 
 
 def test_output_capacity(tracker):
+    """Too small an output: TPC_STATUS_CAPACITY, the number found reported, the first cap
+    clusters written and nothing beyond them (guard values)."""
+    import ctypes as C
     import torch
-    cs, d = D.digit_config("d1", 12)
+    from paper_2402_01205_amd.tpc import CF_KEYS, lib, tpc_cf_clusters, tpc_cf_params, tpc_digits
+    cs, d, _ = D.digit_config("d1", 12)
     o = O.find_clusters(*_arrays(d))
     n = len(o["y"])
+    dd = _dev(_arrays(d))
+    p = tpc_cf_params()
+    lib().tpc_cf_params_default(C.byref(p))
+    need = int(lib().tpc_cf_workspace_size(C.byref(p), d.n))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    dg = tpc_digits(d.n, *[C.c_void_p(dd[k].data_ptr()) for k in ("sector", "row", "pad", "time", "adc")])
+    types = dict(digit=torch.int32, sector=torch.uint8, row=torch.int16, y=torch.float32, z=torch.float32,
+                 q_tot=torch.int32, q_max=torch.int32, sigma_pad=torch.float32, sigma_time=torch.float32)
     for cap in (n - 1, n // 2, 0):
-        out = tracker.tpc_find_clusters(_dev(_arrays(d)), None, cap)
-        guard = out["y"][cap:].clone() if cap > 0 else None
-        g = tracker.clusters_numpy(out)
-        assert g["status"] == 2 and g["n"] == n
-        for k in KEYS:
-            assert np.array_equal(g[k], o[k][:cap]), k
+        guard = 64
+        out = {k: torch.full((cap + guard,), 7, dtype=t, device="cuda:0") for k, t in types.items()}
+        cnt = torch.zeros(2, dtype=torch.int32, device="cuda:0")
+        cl = tpc_cf_clusters(cap, C.c_void_p(cnt.data_ptr()), C.c_void_p(cnt.data_ptr() + 4),
+                             *[C.c_void_p(out[k].data_ptr()) for k in CF_KEYS])
+        assert lib().tpc_find_clusters(tracker.ctx, C.byref(p), C.byref(dg), C.c_void_p(ws.data_ptr()), need,
+                                       C.byref(cl)) == 0
+        torch.cuda.synchronize()
+        assert int(cnt[0]) == n and int(cnt[1]) == 2
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in ("digit", "sector", "row"):
+            assert np.array_equal(g[k][:cap], o[k][:cap]), k
+            assert np.all(g[k][cap:] == 7), k
         for k in FKEYS:
-            assert np.array_equal(bits(g[k]), bits(o[k][:cap])), k
-        if cap > 0:
-            assert torch.equal(out["y"][cap:], guard)
+            assert np.array_equal(bits(g[k][:cap]), bits(o[k][:cap])), k
+            assert np.all(g[k][cap:] == 7), k

@@ -60,19 +60,21 @@ def _cdf(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0)))
 
 
-ROW_CELLS = PADS * N_TIME
-ROW_OFF = np.concatenate([[0], np.cumsum(ROW_CELLS)])   # cell offset of each row in a sector
 
 
-def make_digits(cs, seed: int) -> Digits:
+def make_digits(cs, seed: int, n_time: int = N_TIME, shift=None) -> Digits:
+    """``shift`` (time bins per cluster) places collisions later in the read-out window."""
     rng = np.random.default_rng(seed)
     n = cs.n
     q = 30.0 + rng.gamma(2.0, 30.0, n)
     u, v = cluster_coordinates(cs.sector, cs.row, cs.y, cs.z)
+    if shift is not None:
+        v = v + shift
+    row_off = np.concatenate([[0], np.cumsum(PADS * n_time)])   # first cell of each row in a sector
     row_all = cs.row.astype(np.int64)
     by_sector = np.argsort(cs.sector, kind="stable")
     bounds = np.searchsorted(cs.sector[by_sector], np.arange(N_SECTORS + 1))
-    charge = np.zeros(int(ROW_OFF[-1]))          # one sector's cells, reused
+    charge = np.zeros(int(row_off[-1]))          # one sector's cells, reused
     out = {k: [] for k in ("sector", "row", "pad", "time", "adc")}
     for s in range(N_SECTORS):
         idx = by_sector[bounds[s]:bounds[s + 1]]
@@ -88,10 +90,10 @@ def make_digits(cs, seed: int) -> Digits:
         for dt in range(-2, 3):
             tt = vc + dt
             wt = _cdf((tt + 0.5 - vs) / SIGMA_TIME) - _cdf((tt - 0.5 - vs) / SIGMA_TIME)
-            okt = (tt >= 0) & (tt < N_TIME)
+            okt = (tt >= 0) & (tt < n_time)
             for pp, wp in wps:
                 ok = okt & (pp >= 0) & (pp < PADS[row])
-                cells.append((ROW_OFF[row] + pp * N_TIME + tt)[ok])
+                cells.append((row_off[row] + pp * n_time + tt)[ok])
                 vals.append((qs * wp * wt)[ok])
         cell = np.concatenate(cells)
         np.add.at(charge, cell, np.concatenate(vals))
@@ -100,12 +102,12 @@ def make_digits(cs, seed: int) -> Digits:
         charge[c] = 0.0
         keep = adc >= ZS_THRESHOLD
         c, adc = c[keep], adc[keep]
-        r = np.searchsorted(ROW_OFF, c, side="right") - 1
-        w = c - ROW_OFF[r]
+        r = np.searchsorted(row_off, c, side="right") - 1
+        w = c - row_off[r]
         out["sector"].append(np.full(len(c), s, np.uint8))
         out["row"].append(r.astype(np.int16))
-        out["pad"].append((w // N_TIME).astype(np.int16))
-        out["time"].append((w % N_TIME).astype(np.int16))
+        out["pad"].append((w // n_time).astype(np.int16))
+        out["time"].append((w % n_time).astype(np.int16))
         out["adc"].append(adc.astype(np.uint16))
     cat = {k: (np.concatenate(v) if v else np.zeros(0, dt)) for (k, v), dt in
            zip(out.items(), (np.uint8, np.int16, np.int16, np.int16, np.uint16))}
@@ -113,8 +115,16 @@ def make_digits(cs, seed: int) -> Digits:
 
 
 def digit_config(cfg: str, seed: int):
-    """(clusters, digits) of a workload: 'd1' one sector, 'd2' the full TPC event."""
-    from . import make_config
-    cs = make_config({"d1": "c1", "d2": "c2"}[cfg], seed)
-    assert np.all(cs.sector < N_SECTORS)
-    return cs, make_digits(cs, seed + 1000)
+    """(clusters, digits, n_time) of a workload: 'd1' one sector of one event, 'd2' the full
+    TPC event, 'd3' eight such events at uniform times over two drift lengths (1000 bins)."""
+    from . import concat, make_config
+    if cfg in ("d1", "d2"):
+        cs = make_config({"d1": "c1", "d2": "c2"}[cfg], seed)
+        return cs, make_digits(cs, seed + 1000), N_TIME
+    assert cfg == "d3"
+    rng = np.random.default_rng(seed)
+    evs = [make_config("c2", seed * 100 + k) for k in range(8)]
+    cs = concat(evs, {})
+    offs = rng.uniform(0.0, N_TIME, len(evs))
+    shift = np.repeat(offs, [e.n for e in evs])
+    return cs, make_digits(cs, seed + 1000, n_time=2 * N_TIME, shift=shift), 2 * N_TIME
