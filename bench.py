@@ -392,7 +392,7 @@ def main():
                     help="other workloads timed in the same launch configuration (comma list, '' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "only one GPU is measured; run with --gpus 1"}))
         sys.exit(2)
 
     if args.probe_only:
