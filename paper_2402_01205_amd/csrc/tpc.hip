@@ -91,18 +91,20 @@ __global__ void k_fill_range_i32(int32_t* p, Bound lo, Bound hi, int32_t v) {
     p[k] = v;
 }
 
-// Exclusive scan of in[lo..hi) into out[lo..hi], out[lo] = base (base = *base_p or 0).
+// Exclusive scan of in[lo..hi) into out[lo..hi], out[lo] = base (base = *base_p or 0), in
+// tiles of kScanTile elements.  Loads and stores are striped (element q * 256 + j of a tile
+// goes to thread j, so a wave touches 64 consecutive ints); the apply pass turns the tile
+// into 8 consecutive elements per thread through LDS for the per-thread scan.
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, Bound lo_b, Bound hi_b,
                                                               int32_t* bsum) {
   __shared__ int lds[40];
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int64_t start = (int64_t)lo + (int64_t)blockIdx.x * kScanTile;
   int s = 0;
-  if (start < hi) {
-    const int64_t base = start + (int64_t)threadIdx.x * kScanItems;
 #pragma unroll
-    for (int q = 0; q < kScanItems; ++q)
-      if (base + q < hi) s += in[base + q];
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = start + (int64_t)q * kScanThreads + threadIdx.x;
+    if (i < hi) s += in[i];
   }
   int total;
   block_excl_scan(s, lds, total);
@@ -126,26 +128,42 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* bsum, Bound lo_b,
   }
   if (threadIdx.x == 0) out[hi > lo ? hi : lo] = carry;
 }
+// LDS slot of tile element i: one padding word per 32 keeps the per-thread reads of 8
+// consecutive elements from piling onto the same banks.
+__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int32_t* out, Bound lo_b,
                                                              Bound hi_b, const int32_t* bsum) {
   __shared__ int lds[40];
+  __shared__ int tile[kScanTile + kScanTile / 32];
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int64_t start = (int64_t)lo + (int64_t)blockIdx.x * kScanTile;
   if (start >= hi) return;
-  const int64_t base = start + (int64_t)threadIdx.x * kScanItems;
+  const int j = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = start + (int64_t)q * kScanThreads + j;
+    tile[scan_slot(q * kScanThreads + j)] = i < hi ? in[i] : 0;
+  }
+  __syncthreads();
   int v[kScanItems];
   int s = 0;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    v[q] = (base + q < hi) ? in[base + q] : 0;
+    v[q] = tile[scan_slot(j * kScanItems + q)];
     s += v[q];
   }
   int total;
   int e = block_excl_scan(s, lds, total) + bsum[blockIdx.x];
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    if (base + q < hi) out[base + q] = e;
+    tile[scan_slot(j * kScanItems + q)] = e;
     e += v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = start + (int64_t)q * kScanThreads + j;
+    if (i < hi) out[i] = tile[scan_slot(q * kScanThreads + j)];
   }
 }
 
