@@ -104,3 +104,42 @@ def test_c4_job_sizes_law():
     assert 700 < np.median(s) < 2300
     one = g.make_config("c4", 41, jobs=[3], scale=0.05)
     assert np.all(one.sector == 3)
+
+
+# ------------------------------------------------------------------ digit simulator
+def test_digits_layout_and_charge():
+    """Digits are unique cells in read-out order inside the pad plane, 10-bit, above the
+    zero-suppression threshold; an isolated deposit keeps its charge up to the suppressed
+    tails and the rounding."""
+    from tpcsynth import digits as D
+    cs, d, nt = D.digit_config("d1", 11)
+    assert nt == D.N_TIME
+    key = ((d.sector.astype(np.int64) * 152 + d.row) * 256 + d.pad) * 1024 + d.time
+    assert np.all(np.diff(key) > 0)
+    assert np.all(d.pad >= 0) and np.all(d.pad < D.PADS[d.row])
+    assert np.all(d.time >= 0) and np.all(d.time < nt)
+    assert d.adc.min() >= D.ZS_THRESHOLD and d.adc.max() <= D.ADC_MAX
+    # one cluster alone: its 5 x 5 deposit sums to Q within the suppressed and rounded part
+    one = g.ClusterSet(np.zeros(1, np.uint8), np.array([70], np.int16), np.array([1.3], np.float32),
+                       np.array([100.2], np.float32), np.zeros(1, np.float32), np.zeros(1, np.int32),
+                       np.array([0, 1], np.int32), np.zeros(0), np.zeros(0), np.zeros(0),
+                       np.zeros(0, np.int8), np.array([0, 0]), {})
+    d1 = D.make_digits(one, 5)
+    q = float(d1.true_q[0])
+    assert abs(float(d1.adc.sum()) - q) < 25 * (D.ZS_THRESHOLD + 0.5)
+    # the charge-weighted centre of its digits is the deposit's centre
+    u, v = D.cluster_coordinates(one.sector, one.row, one.y, one.z)
+    w = d1.adc.astype(np.float64)
+    assert abs((w * d1.pad).sum() / w.sum() - u[0]) < 0.1
+    assert abs((w * d1.time).sum() / w.sum() - v[0]) < 0.1
+
+
+def test_digits_time_shift():
+    """A collision placed later in the read-out window moves its digits by whole bins."""
+    from tpcsynth import digits as D
+    cs = g.make_config("c1", 11)
+    a = D.make_digits(cs, 3)
+    b = D.make_digits(cs, 3, n_time=2 * D.N_TIME, shift=np.full(cs.n, 200.0))
+    m = (b.time >= 200) & (b.time < 200 + D.N_TIME)   # the cells the shorter window also has
+    assert np.array_equal(a.adc, b.adc[m]) and np.array_equal(a.pad, b.pad[m])
+    assert np.array_equal(a.time.astype(np.int32) + 200, b.time[m].astype(np.int32))
