@@ -3283,10 +3283,10 @@ CfGeo cf_geometry(const tpc_cf_params* p) {
     const double x = 85.0 + (double)r * 160.0 / 151.0;
     G.pads[r] = 2 * (int32_t)std::ceil(x * tan10 / (double)p->pad_pitch);
     G.half[r] = (float)((double)G.pads[r] * (double)p->pad_pitch / 2.0);
-    G.rowoff[r] = (int32_t)off;
+    G.rowoff[r] = (int32_t)std::min<int64_t>(off, INT32_MAX);
     off += (int64_t)G.pads[r] * p->n_time;
   }
-  G.rowoff[kRows] = (int32_t)off;
+  G.rowoff[kRows] = (int32_t)std::min<int64_t>(off, INT32_MAX);
   G.per_sector = off;
   G.n_time = p->n_time;
   G.q_min = p->q_min;
@@ -3300,6 +3300,7 @@ size_t cf_map_bytes(const CfGeo& G) { return ((size_t)G.per_sector * kSectors * 
 size_t tpc_cf_workspace_size(const tpc_cf_params* p, int32_t n_digits) {
   if (!cf_params_ok(p) || n_digits < 0) return 0;
   const CfGeo G = cf_geometry(p);
+  if (G.per_sector > INT32_MAX) return 0;  // the row offsets are 32-bit
   const int64_t tiles = ((int64_t)n_digits + kScanTile - 1) / kScanTile + 1;
   return cf_map_bytes(G) + (size_t)(tiles + 64) * sizeof(int32_t) + (size_t)n_digits;
 }
@@ -3315,6 +3316,7 @@ int tpc_find_clusters(tpc_ctx* c, const tpc_cf_params* p, const tpc_digits* d, v
                         !out->q_max || !out->sigma_pad || !out->sigma_time)))
     return fail(c, TPC_E_ARG, "tpc_find_clusters: invalid output");
   const size_t need = tpc_cf_workspace_size(p, d->n);
+  if (need == 0) return fail(c, TPC_E_ARG, "tpc_find_clusters: pad plane too large for 32-bit row offsets");
   if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(c, TPC_E_ARG, "tpc_find_clusters: workspace missing, unaligned or smaller than tpc_cf_workspace_size");
   HIPCHK(c, hipSetDevice(c->device));
