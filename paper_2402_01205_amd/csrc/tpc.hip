@@ -2446,7 +2446,7 @@ Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
 int wave_grid(tpc_ctx* c, int64_t items) {
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-  return (int)std::max<int64_t>(1, std::min<int64_t>((items + 3) / 4, (int64_t)ncu * 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((items + 3) / 4, (int64_t)ncu * 32));
 }
 Bound db(const int32_t* p) { return Bound{p, 0, INT32_MAX}; }
 Bound dbc(const int32_t* p, int32_t cap) { return Bound{p, 0, cap}; }
