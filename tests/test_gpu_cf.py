@@ -137,3 +137,16 @@ def test_output_capacity(tracker):
         for k in FKEYS:
             assert np.array_equal(bits(g[k][:cap]), bits(o[k][:cap])), k
             assert np.all(g[k][cap:] == 7), k
+
+
+def test_workspace_reuse_across_digit_sets(tracker):
+    """The charge map is left clean after each call: different digit sets one after the other
+    on the same workspace each give the oracle's clusters."""
+    sets = []
+    for seed in (11, 12, 13):
+        _, d, _ = D.digit_config("d1", seed)
+        sets.append(_arrays(d))
+    for a in (sets[0], sets[1], sets[2], sets[0]):
+        g = _gpu(tracker, a)
+        assert g["status"] == 0
+        _compare(g, O.find_clusters(*a))

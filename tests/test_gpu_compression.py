@@ -233,3 +233,24 @@ def test_arguments_are_checked():
         fresh._tracks = tr._tracks
         fresh._keep = tr._keep
         fresh.tpc_compress(Q, Q)
+
+
+def test_compression_between_graph_replays():
+    """Compression reuses scratch of the tracking workspace: a tracking run replayed from its
+    captured graph after it gives the same tracks, and compressing again the same records."""
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker, default_tuning
+    cs = g.make_config("c2", 21, scale=0.5)
+    tr = Tracker(0, mode="persistent", tuning=default_tuning(use_graph=1))
+    ev = DeviceClusters.from_set(cs, "cuda:0")
+    tr.run(ev)
+    t0 = tr.tracks()
+    tr.tpc_compress(Q, Q)
+    c0 = tr.codes_numpy()
+    tr.run(ev)
+    tr.run(ev)
+    t1 = tr.tracks()
+    assert np.array_equal(t0["hits"], t1["hits"]) and np.array_equal(bits(t0["param"]), bits(t1["param"]))
+    tr.tpc_compress(Q, Q)
+    c1 = tr.codes_numpy()
+    for k in ("rs", "ey", "ez"):
+        assert np.array_equal(c0[k], c1[k])
