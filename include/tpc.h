@@ -11,7 +11,11 @@
  * (section 5), that its cost is linear in the number of TPC hits (section 6), and
  * that it runs on GPUs (sections 6-7).  The paper does not spell the algorithm
  * out; the library implements a fixed reading of it whose constants are the
- * fields of tpc_params.
+ * fields of tpc_params.  The rest of the paper's GPU chain for the TPC is here
+ * too (section 5): cluster finding from zero-suppressed digits before the
+ * tracking (tpc_find_clusters), and after it the track-model compression of
+ * the clusters against the tracks (tpc_compress / tpc_decompress) and the rANS
+ * entropy coder (tpc_rans_encode / tpc_rans_decode).
  *
  * Conventions
  *  - Pointers are DEVICE pointers unless marked [host].  The caller owns every
