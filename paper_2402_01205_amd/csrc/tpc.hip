@@ -3,8 +3,9 @@
 // Stages (see include/tpc.h): grid build (counting sort into per-row cell grids),
 // neighbour links + cleaning + chain starts, tracklet construction (one lane per
 // tracklet, FP32 Kalman filter), selection (max-key ownership), refit and
-// sector merge.  No stage uses MFMA: nothing on this path is a dense contraction;
-// every kernel is bound by HBM traffic or by dependent-load latency.
+// sector merge; around them, cluster finding from digits, track-model compression
+// and the rANS coder.  No stage uses MFMA: nothing here is a dense contraction;
+// every kernel is bound by HBM traffic, instruction issue or dependent-load latency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
