@@ -188,8 +188,9 @@ __device__ __forceinline__ int job_of(const int32_t* job_off, int n_jobs, int32_
 }
 
 // Validate each input cluster, compute its slot, count clusters per slot and the
-// per-slot z range (order-preserving integer min/max).
-__global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32_t* slot_cnt,
+// per-slot z range (order-preserving integer min/max); each cluster's rank in its slot
+// comes from the count.
+__global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32_t* srank, int32_t* slot_cnt,
                              uint32_t* zmin, uint32_t* zmax, int32_t* counters) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,7 +207,7 @@ __global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32
   const int j = job_of(in.job_off, in.n_jobs, i);
   const int32_t slot = (j * kSectors + s) * kRows + r;
   ckey[i] = slot;
-  atomicAdd(&slot_cnt[slot], 1);
+  srank[i] = atomicAdd(&slot_cnt[slot], 1);
   const uint32_t oz = f2ord(z);
   atomicMin(&zmin[slot], oz);
   atomicMax(&zmax[slot], oz);
@@ -215,11 +216,13 @@ __global__ void k_grid_count(In in, Bound lo_b, Bound hi_b, int32_t* ckey, int32
 // Same as k_grid_count, with the per-slot counters and z ranges of the block's job
 // privatised in LDS (a block covers kCountTile consecutive input clusters, almost
 // always of one job) and flushed with one global atomic per touched slot.  Clusters
-// of another job (at a job boundary) update global memory directly.
+// of another job (at a job boundary) update global memory directly.  A cluster's rank in
+// its slot is its rank in the block's LDS count plus the block's base, which the flush's
+// atomic returns.
 constexpr int kCountThreads = 1024;
 constexpr int kCountTile = kCountThreads * 4;
 __global__ __launch_bounds__(kCountThreads) void k_grid_count_lds(In in, Bound lo_b, Bound hi_b, int32_t* ckey,
-                                                                   int32_t* slot_cnt, uint32_t* zmin,
+                                                                   int32_t* srank, int32_t* slot_cnt, uint32_t* zmin,
                                                                    uint32_t* zmax, int32_t* counters) {
   extern __shared__ uint32_t lds[];
   uint32_t* s_cnt = lds;
@@ -238,8 +241,12 @@ __global__ __launch_bounds__(kCountThreads) void k_grid_count_lds(In in, Bound l
   }
   __syncthreads();
   bool bad = false;
+  constexpr int kQ = kCountTile / kCountThreads;
+  int lslot[kQ], lrank[kQ];  // LDS slot (-1: none) and rank in the block's count
 #pragma unroll
-  for (int q = 0; q < kCountTile / kCountThreads; ++q) {
+  for (int q = 0; q < kQ; ++q) lslot[q] = -1;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
     const int32_t i = (int32_t)base + q * kCountThreads + threadIdx.x;
     if (i >= end) break;
     const int s = in.sector[i];
@@ -256,11 +263,12 @@ __global__ __launch_bounds__(kCountThreads) void k_grid_count_lds(In in, Bound l
     ckey[i] = slot;
     const uint32_t oz = f2ord(z);
     if (j == job0) {
-      atomicAdd(&s_cnt[local], 1u);
+      lslot[q] = local;
+      lrank[q] = (int)atomicAdd(&s_cnt[local], 1u);
       atomicMin(&s_zmin[local], oz);
       atomicMax(&s_zmax[local], oz);
     } else {
-      atomicAdd(&slot_cnt[slot], 1);
+      srank[i] = atomicAdd(&slot_cnt[slot], 1);
       atomicMin(&zmin[slot], oz);
       atomicMax(&zmax[slot], oz);
     }
@@ -271,21 +279,28 @@ __global__ __launch_bounds__(kCountThreads) void k_grid_count_lds(In in, Bound l
     const uint32_t c = s_cnt[s];
     if (c) {
       const int32_t slot = job0 * kSlotsPerJob + s;
-      atomicAdd(&slot_cnt[slot], (int32_t)c);
+      s_cnt[s] = (uint32_t)atomicAdd(&slot_cnt[slot], (int32_t)c);
       atomicMin(&zmin[slot], s_zmin[s]);
       atomicMax(&zmax[slot], s_zmax[s]);
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    if (lslot[q] >= 0) srank[base + q * kCountThreads + threadIdx.x] = (int32_t)s_cnt[lslot[q]] + lrank[q];
 }
 
 // Cell geometry of every slot: roughly cells_per_cluster cells per cluster, square
-// cells in (y, z) over the row's acceptance in y and the slot's z range.
+// cells in (y, z) over the row's acceptance in y and the slot's z range.  Non-empty
+// slots are appended (in no particular order) to slot_list, whose count sits in front.
+constexpr int kListCount = 0, kListFirst = 1;
 __global__ void k_slot_geometry(const int32_t* slot_cnt, const uint32_t* zmin, const uint32_t* zmax,
-                                SlotGrid* sg, int32_t* ncell, int32_t s0, int32_t s1, Consts k,
-                                float cpc) {
+                                SlotGrid* sg, int32_t* ncell, int32_t* slot_list, int32_t s0, int32_t s1,
+                                Consts k, float cpc) {
   const int32_t s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= s1) return;
   const int n = slot_cnt[s];
+  if (n > 0) slot_list[kListFirst + atomicAdd(&slot_list[kListCount], 1)] = s;
   SlotGrid g;
   g.cbase = 0;
   if (n == 0) {
@@ -320,31 +335,139 @@ __global__ void k_slot_cellbase(SlotGrid* sg, const int32_t* cell_base, int32_t 
   if (s < s1) sg[s].cbase = cell_base[s];
 }
 
-__global__ void k_cell_count(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const SlotGrid* sg,
-                             const int32_t* cell_base, int32_t* ccell, int32_t* crank, int32_t* cell_cnt) {
+// Clusters in slot order: each valid cluster goes to slot_off[slot] + its rank in the
+// slot (positions and input index, the input of the per-slot cell sort).
+__global__ void k_slot_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* srank,
+                               const int32_t* slot_off, float2* syz, int32_t* sidx) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hi) return;
   const int32_t slot = ckey[i];
   if (slot < 0) return;
-  const SlotGrid g = sg[slot];
-  const int cy = cell_of(in.y[i], g.ylo, g.inv_by, g.ny);
-  const int cz = cell_of(in.z[i], g.zlo, g.inv_bz, g.nz);
-  const int32_t gc = cell_base[slot] + cz * g.ny + cy;
-  ccell[i] = gc;
-  crank[i] = atomicAdd(&cell_cnt[gc], 1);  // the cluster's place within its cell
+  const int32_t p = slot_off[slot] + srank[i];
+  syz[p] = make_float2(in.y[i], in.z[i]);
+  sidx[p] = i;
 }
 
-__global__ void k_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* ccell,
-                          const int32_t* cell_off, const int32_t* crank, GHit* gh) {
-  const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= hi) return;
-  const int32_t slot = ckey[i];
-  if (slot < 0) return;
-  const int32_t gc = ccell[i];
-  const int32_t pos = cell_off[gc] + crank[i];
-  sth(gh + pos, in.y[i], in.z[i], slot, i);
+// Counting sort of one slot's clusters by cell, one workgroup per slot, in LDS.  The
+// slot's cells are taken in ranges of kSortWords counters; each range is counted, turned
+// into offsets within the slot (continuing over the ranges) and its clusters placed.
+// Counters are 16 bits wide, two per word, when the slot holds fewer than 2^16 clusters
+// (no count or offset within the slot reaches that, so a low half never carries into its
+// high half), 32 bits otherwise.  Loads are batched kSortBatch per thread ahead of the
+// LDS atomics.
+constexpr int kSortThreads = 256;
+constexpr int kSortWords = 8192;
+constexpr int kSortBatch = 4;
+struct SlotSort {
+  const float2* syz;    // positions, slot order
+  const int32_t* sidx;  // input index, slot order
+  int32_t* cell_off;
+  GHit* gh;
+};
+
+__device__ __forceinline__ int slot_cell(const SlotGrid& g, float2 v) {
+  return cell_of(v.y, g.zlo, g.inv_bz, g.nz) * g.ny + cell_of(v.x, g.ylo, g.inv_by, g.ny);
+}
+
+template <bool kWide>
+__device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, int32_t n, int32_t base,
+                          uint32_t* cnt, int* lds) {
+  constexpr int kPer = kWide ? 1 : 2;  // counters per word
+  constexpr int kRange = kSortWords * kPer;
+  constexpr uint32_t kMask = kWide ? 0xFFFFFFFFu : 0xFFFFu;
+  int carry = 0;
+  for (int r0 = 0; r0 < g.ncell; r0 += kRange) {
+    const int nc = min(kRange, g.ncell - r0);
+    const int nw = (nc + kPer - 1) / kPer;
+    for (int w = threadIdx.x; w < nw; w += kSortThreads) cnt[w] = 0u;
+    __syncthreads();
+    for (int p0 = 0; p0 < n; p0 += kSortThreads * kSortBatch) {
+      int c[kSortBatch];
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        const int p = p0 + k * kSortThreads + threadIdx.x;
+        c[k] = p < n ? slot_cell(g, S.syz[base + p]) - r0 : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k)
+        if ((unsigned)c[k] < (unsigned)nc) atomicAdd(&cnt[c[k] / kPer], 1u << ((c[k] % kPer) * 16));
+    }
+    __syncthreads();
+    // offsets, 4 words per thread and pass (w + 3 < kSortWords always)
+    for (int w0 = 0; w0 < nw; w0 += kSortThreads * 4) {
+      const int w = w0 + threadIdx.x * 4;
+      const uint4 q = *reinterpret_cast<const uint4*>(cnt + w);
+      const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+      int sum = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (w + k < nw) sum += kWide ? (int)v[k] : (int)((v[k] & kMask) + (v[k] >> 16));
+      int total;
+      int e = carry + block_excl_scan(sum, lds, total);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (w + k >= nw) break;
+        const int c = r0 + kPer * (w + k);
+        const int a = e;
+        e += (int)(v[k] & kMask);
+        S.cell_off[g.cbase + c] = base + a;
+        if (kWide) {
+          cnt[w + k] = (uint32_t)a;
+        } else {
+          const int b = e;
+          e += (int)(v[k] >> 16);
+          cnt[w + k] = (uint32_t)a | ((uint32_t)b << 16);
+          if (c + 1 < r0 + nc) S.cell_off[g.cbase + c + 1] = base + b;
+        }
+      }
+      carry += total;
+    }
+    __syncthreads();
+    for (int p0 = 0; p0 < n; p0 += kSortThreads * kSortBatch) {
+      float2 v[kSortBatch];
+      int32_t idx[kSortBatch];
+      int c[kSortBatch];
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        const int p = p0 + k * kSortThreads + threadIdx.x;
+        c[k] = -1;
+        if (p < n) {
+          v[k] = S.syz[base + p];
+          idx[k] = S.sidx[base + p];
+          c[k] = slot_cell(g, v[k]) - r0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        if ((unsigned)c[k] >= (unsigned)nc) continue;
+        const uint32_t sh = (uint32_t)(c[k] % kPer) * 16;
+        const uint32_t old = atomicAdd(&cnt[c[k] / kPer], 1u << sh);
+        sth(S.gh + base + (int32_t)((old >> sh) & kMask), v[k].x, v[k].y, slot, idx[k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Workgroups take the non-empty slots of the list in turn; the cell offsets end with
+// the total at the range's last cell.
+__global__ __launch_bounds__(kSortThreads) void k_cell_sort(SlotSort S, const int32_t* slot_list,
+                                                           const int32_t* slot_cnt, const int32_t* slot_off,
+                                                           const SlotGrid* sg, const int32_t* cell_base,
+                                                           int32_t s1) {
+  __shared__ __align__(16) uint32_t cnt[kSortWords];
+  __shared__ int lds[40];
+  const int32_t n_list = slot_list[kListCount];
+  for (int32_t k = blockIdx.x; k < n_list; k += gridDim.x) {
+    const int32_t s = slot_list[kListFirst + k];
+    const int32_t n = slot_cnt[s];
+    const SlotGrid g = sg[s];
+    const int32_t base = slot_off[s];
+    if (n < 65536) sort_slot<false>(S, g, s, n, base, cnt, lds);
+    else sort_slot<true>(S, g, s, n, base, cnt, lds);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.cell_off[cell_base[s1]] = slot_off[s1];
 }
 
 // The positions alone, in grid order: one coalesced pass after the scatter (cheaper
@@ -2209,7 +2332,9 @@ struct Layout {
   int64_t bsumN = 0;
   size_t bytes = 0;
   // arrays
-  int32_t *ckey, *ccell, *crank, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_cnt, *cell_off;
+  // grid build: slot of each input cluster and its rank there, input index in slot order,
+  // the non-empty slots (count first)
+  int32_t *ckey, *srank, *sidx, *slot_list, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_off;
   uint32_t *zmin, *zmax;
   SlotGrid* sg;
   GHit* gh;
@@ -2261,7 +2386,8 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   char* p = base;
   size_t t = 0;
   carve(p, L.ckey, N, t, set);
-  carve(p, L.ccell, N, t, set);
+  carve(p, L.sidx, N, t, set);
+  carve(p, L.slot_list, L.S + 1, t, set);
   carve(p, L.slot_cnt, L.S + 1, t, set);
   carve(p, L.slot_off, L.S + 1, t, set);
   carve(p, L.zmin, L.S, t, set);
@@ -2269,9 +2395,8 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.sg, L.S, t, set);
   carve(p, L.ncell, L.S + 1, t, set);
   carve(p, L.cell_base, L.S + 1, t, set);
-  carve(p, L.cell_cnt, L.capCells + 1, t, set);
   carve(p, L.cell_off, L.capCells + 1, t, set);
-  carve(p, L.crank, N, t, set);
+  carve(p, L.srank, N, t, set);
   carve(p, L.gh, N, t, set);
   carve(p, L.gyz, N, t, set);
   carve(p, L.up_raw, N, t, set);
@@ -2512,26 +2637,29 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
   if (c->lds_count_ok) {
     hipLaunchKernelGGL(k_grid_count_lds, dim3(blocks_for(nbound, kCountTile)), dim3(kCountThreads),
                        3 * kSlotsPerJob * sizeof(uint32_t), c->stream, in, db(jo + j0), db(jo + j1), L.ckey,
-                       L.slot_cnt, L.zmin, L.zmax, L.counters);
+                       L.srank, L.slot_cnt, L.zmin, L.zmax, L.counters);
   } else {
     hipLaunchKernelGGL(k_grid_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in,
-                       db(jo + j0), db(jo + j1), L.ckey, L.slot_cnt, L.zmin, L.zmax, L.counters);
+                       db(jo + j0), db(jo + j1), L.ckey, L.srank, L.slot_cnt, L.zmin, L.zmax, L.counters);
   }
   // slot offsets in grid order (base: clusters of earlier jobs)
   scan(c, L.slot_cnt, L.slot_off, hb(s0), hb(s1), s1 - s0, j0 != 0);
+  hipLaunchKernelGGL(k_fill_range_i32, dim3(1), dim3(64), 0, c->stream, L.slot_list, hb(kListCount),
+                     hb(kListCount + 1), 0);
   hipLaunchKernelGGL(k_slot_geometry, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.slot_cnt,
-                     L.zmin, L.zmax, L.sg, L.ncell, s0, s1, c->k, c->tune.cells_per_cluster);
+                     L.zmin, L.zmax, L.sg, L.ncell, L.slot_list, s0, s1, c->k, c->tune.cells_per_cluster);
   scan(c, L.ncell, L.cell_base, hb(s0), hb(s1), s1 - s0, j0 != 0);
   hipLaunchKernelGGL(k_slot_cellbase, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.sg, L.cell_base,
                      s0, s1);
-  const int64_t cbound = (int64_t)std::ceil((double)nbound * c->tune.cells_per_cluster) + (s1 - s0) + 1;
-  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(cbound, 256)), dim3(256), 0, c->stream, L.cell_cnt,
-                     db(L.cell_base + s0), db(L.cell_base + s1), 0);
-  hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.sg, L.cell_base, L.ccell, L.crank, L.cell_cnt);
-  scan(c, L.cell_cnt, L.cell_off, db(L.cell_base + s0), db(L.cell_base + s1), cbound, j0 != 0);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.ccell, L.cell_off, L.crank, L.gh);
+  // clusters in slot order (positions staged in gyz), then each slot sorted by cell
+  hipLaunchKernelGGL(k_slot_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
+                     db(jo + j1), L.ckey, L.srank, L.slot_off, L.gyz, L.sidx);
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  const SlotSort ss{L.gyz, L.sidx, L.cell_off, L.gh};
+  hipLaunchKernelGGL(k_cell_sort, dim3((int)std::max<int64_t>(1, std::min<int64_t>(s1 - s0, (int64_t)ncu * 4))),
+                     dim3(kSortThreads), 0, c->stream, ss, L.slot_list, L.slot_cnt, L.slot_off, L.sg, L.cell_base,
+                     s1);
   hipLaunchKernelGGL(k_positions, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.gh, L.gyz,
                      db(L.slot_off + s0), db(L.slot_off + s1));
 }

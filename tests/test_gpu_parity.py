@@ -174,6 +174,26 @@ def test_empty_and_tiny_inputs():
     compare_all(gpu_run(both), oracle_run(both))
 
 
+def test_dense_rows_beyond_the_per_slot_counter_range():
+    """Rows far denser than any workload's: 70,000 noise clusters in one row (past the 16-bit
+    cell counters of the per-slot cell sort) and 12,000 in another (more cells than one LDS
+    range at the default cell size), on top of a single-sector event; same results as the
+    oracle."""
+    cs = g.make_config("c1", 11)
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([np.full(70000, 60), np.full(12000, 100)]).astype(np.int16)
+    m = len(rows)
+    y = (rng.uniform(-1.0, 1.0, m) * g.ROW_X[rows] * g.TAN_HALF).astype(np.float32)
+    z = rng.uniform(0.0, g.DRIFT_LENGTH, m).astype(np.float32)
+    cat = lambda a, b: np.concatenate([a, b.astype(a.dtype)])
+    dense = g.ClusterSet(cat(cs.sector, np.zeros(m)), cat(cs.row, rows), cat(cs.y, y), cat(cs.z, z),
+                         cat(cs.time, (g.DRIFT_LENGTH - z) / g.V_DRIFT), cat(cs.label, np.full(m, -1)),
+                         np.array([0, cs.n + m], np.int32), cs.part_pt, cs.part_eta, cs.part_phi, cs.part_q,
+                         np.array([0, len(cs.part_pt)]), {})
+    say("dense rows n", dense.n)
+    compare_all(gpu_run(dense), oracle_run(dense))
+
+
 def test_graph_replays_match_eager():
     """The captured stage chain, replayed several times with eager work and synchronisations
     in between, reproduces the eager result every time."""
