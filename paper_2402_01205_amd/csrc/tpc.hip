@@ -335,18 +335,25 @@ __global__ void k_slot_cellbase(SlotGrid* sg, const int32_t* cell_base, int32_t 
   if (s < s1) sg[s].cbase = cell_base[s];
 }
 
-// Clusters in slot order: each valid cluster goes to slot_off[slot] + its rank in the
-// slot (positions and input index, the input of the per-slot cell sort).
-__global__ void k_slot_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* ckey, const int32_t* srank,
-                               const int32_t* slot_off, float2* syz, int32_t* sidx) {
+// Clusters in slot order: each valid cluster's {y, z, input index} goes to
+// slot_off[slot] + its rank in the slot (the input of the per-slot cell sort).  Blocks
+// take the count's tiles, so the clusters that one count block ranked in a slot (one
+// contiguous run of destinations) are written by one block, whose L2 joins the run's
+// lines before they go out.
+__global__ __launch_bounds__(kCountThreads) void k_slot_scatter(In in, Bound lo_b, Bound hi_b,
+                                                                 const int32_t* ckey, const int32_t* srank,
+                                                                 const int32_t* slot_off, int4* srec) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= hi) return;
-  const int32_t slot = ckey[i];
-  if (slot < 0) return;
-  const int32_t p = slot_off[slot] + srank[i];
-  syz[p] = make_float2(in.y[i], in.z[i]);
-  sidx[p] = i;
+  const int64_t base = (int64_t)lo + (int64_t)blockIdx.x * kCountTile;
+#pragma unroll
+  for (int q = 0; q < kCountTile / kCountThreads; ++q) {
+    const int64_t i = base + q * kCountThreads + threadIdx.x;
+    if (i >= hi) break;
+    const int32_t slot = ckey[i];
+    if (slot < 0) continue;
+    const int32_t p = slot_off[slot] + srank[i];
+    srec[p] = make_int4(__float_as_int(in.y[i]), __float_as_int(in.z[i]), (int32_t)i, 0);
+  }
 }
 
 // Counting sort of one slot's clusters by cell, one workgroup per slot, in LDS.  The
@@ -355,16 +362,19 @@ __global__ void k_slot_scatter(In in, Bound lo_b, Bound hi_b, const int32_t* cke
 // Counters are 16 bits wide, two per word, when the slot holds fewer than 2^16 clusters
 // (no count or offset within the slot reaches that, so a low half never carries into its
 // high half), 32 bits otherwise.  Loads are batched kSortBatch per thread ahead of the
-// LDS atomics.
-constexpr int kSortThreads = 256;
+// LDS atomics.  Each placed cluster is written twice in grid order: the 16-byte record
+// and its position alone.
+constexpr int kSortThreads = 512;
 constexpr int kSortWords = 8192;
-constexpr int kSortBatch = 4;
+constexpr int kSortBatch = 2;
+static_assert(kSortWords % (4 * kSortThreads) == 0, "offset passes read 4 words per thread");
 struct SlotSort {
-  const float2* syz;    // positions, slot order
-  const int32_t* sidx;  // input index, slot order
+  const int4* srec;  // {y, z, input index, unused}, slot order
   int32_t* cell_off;
   GHit* gh;
+  float2* gyz;
 };
+__device__ __forceinline__ float2 srec_yz(const int4* r) { return *reinterpret_cast<const float2*>(r); }
 
 __device__ __forceinline__ int slot_cell(const SlotGrid& g, float2 v) {
   return cell_of(v.y, g.zlo, g.inv_bz, g.nz) * g.ny + cell_of(v.x, g.ylo, g.inv_by, g.ny);
@@ -387,14 +397,15 @@ __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, in
 #pragma unroll
       for (int k = 0; k < kSortBatch; ++k) {
         const int p = p0 + k * kSortThreads + threadIdx.x;
-        c[k] = p < n ? slot_cell(g, S.syz[base + p]) - r0 : -1;
+        c[k] = p < n ? slot_cell(g, srec_yz(S.srec + base + p)) - r0 : -1;
       }
 #pragma unroll
       for (int k = 0; k < kSortBatch; ++k)
         if ((unsigned)c[k] < (unsigned)nc) atomicAdd(&cnt[c[k] / kPer], 1u << ((c[k] % kPer) * 16));
     }
     __syncthreads();
-    // offsets, 4 words per thread and pass (w + 3 < kSortWords always)
+    // offsets, 4 words per thread and pass (w + 3 < kSortWords always: kSortWords is a
+    // multiple of 4 kSortThreads)
     for (int w0 = 0; w0 < nw; w0 += kSortThreads * 4) {
       const int w = w0 + threadIdx.x * 4;
       const uint4 q = *reinterpret_cast<const uint4*>(cnt + w);
@@ -425,17 +436,15 @@ __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, in
     }
     __syncthreads();
     for (int p0 = 0; p0 < n; p0 += kSortThreads * kSortBatch) {
-      float2 v[kSortBatch];
-      int32_t idx[kSortBatch];
+      int4 v[kSortBatch];
       int c[kSortBatch];
 #pragma unroll
       for (int k = 0; k < kSortBatch; ++k) {
         const int p = p0 + k * kSortThreads + threadIdx.x;
         c[k] = -1;
         if (p < n) {
-          v[k] = S.syz[base + p];
-          idx[k] = S.sidx[base + p];
-          c[k] = slot_cell(g, v[k]) - r0;
+          v[k] = S.srec[base + p];
+          c[k] = slot_cell(g, make_float2(__int_as_float(v[k].x), __int_as_float(v[k].y))) - r0;
         }
       }
 #pragma unroll
@@ -443,7 +452,10 @@ __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, in
         if ((unsigned)c[k] >= (unsigned)nc) continue;
         const uint32_t sh = (uint32_t)(c[k] % kPer) * 16;
         const uint32_t old = atomicAdd(&cnt[c[k] / kPer], 1u << sh);
-        sth(S.gh + base + (int32_t)((old >> sh) & kMask), v[k].x, v[k].y, slot, idx[k]);
+        const int32_t q = base + (int32_t)((old >> sh) & kMask);
+        const float y = __int_as_float(v[k].x), z = __int_as_float(v[k].y);
+        sth(S.gh + q, y, z, slot, v[k].z);
+        S.gyz[q] = make_float2(y, z);
       }
     }
     __syncthreads();
@@ -468,16 +480,6 @@ __global__ __launch_bounds__(kSortThreads) void k_cell_sort(SlotSort S, const in
     else sort_slot<true>(S, g, s, n, base, cnt, lds);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) S.cell_off[cell_base[s1]] = slot_off[s1];
-}
-
-// The positions alone, in grid order: one coalesced pass after the scatter (cheaper
-// than a second random write per cluster in it).
-__global__ void k_positions(const GHit* gh, float2* gyz, Bound lo_b, Bound hi_b) {
-  const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t g = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= hi) return;
-  const GHit H = ldh(gh + g);
-  gyz[g] = make_float2(H.y, H.z);
 }
 
 // ------------------------------------------------------------------ a2: neighbours
@@ -2332,9 +2334,10 @@ struct Layout {
   int64_t bsumN = 0;
   size_t bytes = 0;
   // arrays
-  // grid build: slot of each input cluster and its rank there, input index in slot order,
-  // the non-empty slots (count first)
-  int32_t *ckey, *srank, *sidx, *slot_list, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_off;
+  // grid build: slot of each input cluster and its rank there, the non-empty slots
+  // (count first), the clusters in slot order
+  int32_t *ckey, *srank, *slot_list, *slot_cnt, *slot_off, *ncell, *cell_base, *cell_off;
+  int4* srec;
   uint32_t *zmin, *zmax;
   SlotGrid* sg;
   GHit* gh;
@@ -2386,7 +2389,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   char* p = base;
   size_t t = 0;
   carve(p, L.ckey, N, t, set);
-  carve(p, L.sidx, N, t, set);
+  carve(p, L.srec, N, t, set);
   carve(p, L.slot_list, L.S + 1, t, set);
   carve(p, L.slot_cnt, L.S + 1, t, set);
   carve(p, L.slot_off, L.S + 1, t, set);
@@ -2651,17 +2654,15 @@ void launch_grid(tpc_ctx* c, int j0, int j1) {
   scan(c, L.ncell, L.cell_base, hb(s0), hb(s1), s1 - s0, j0 != 0);
   hipLaunchKernelGGL(k_slot_cellbase, dim3(blocks_for(s1 - s0, 256)), dim3(256), 0, c->stream, L.sg, L.cell_base,
                      s0, s1);
-  // clusters in slot order (positions staged in gyz), then each slot sorted by cell
-  hipLaunchKernelGGL(k_slot_scatter, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, in, db(jo + j0),
-                     db(jo + j1), L.ckey, L.srank, L.slot_off, L.gyz, L.sidx);
+  // clusters in slot order, then each slot sorted by cell
+  hipLaunchKernelGGL(k_slot_scatter, dim3(blocks_for(nbound, kCountTile)), dim3(kCountThreads), 0, c->stream, in,
+                     db(jo + j0), db(jo + j1), L.ckey, L.srank, L.slot_off, L.srec);
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-  const SlotSort ss{L.gyz, L.sidx, L.cell_off, L.gh};
+  const SlotSort ss{L.srec, L.cell_off, L.gh, L.gyz};
   hipLaunchKernelGGL(k_cell_sort, dim3((int)std::max<int64_t>(1, std::min<int64_t>(s1 - s0, (int64_t)ncu * 4))),
                      dim3(kSortThreads), 0, c->stream, ss, L.slot_list, L.slot_cnt, L.slot_off, L.sg, L.cell_base,
                      s1);
-  hipLaunchKernelGGL(k_positions, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.gh, L.gyz,
-                     db(L.slot_off + s0), db(L.slot_off + s1));
 }
 
 void launch_links(tpc_ctx* c, int j0, int j1) {
