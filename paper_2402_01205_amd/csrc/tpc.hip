@@ -363,9 +363,13 @@ __global__ __launch_bounds__(kCountThreads) void k_slot_scatter(In in, Bound lo_
 // (no count or offset within the slot reaches that, so a low half never carries into its
 // high half), 32 bits otherwise.  Loads are batched kSortBatch per thread ahead of the
 // LDS atomics.  Each placed cluster is written twice in grid order: the 16-byte record
-// and its position alone.
+// and its position alone.  A slot of up to kSortPerm clusters places only its slot-order
+// index in LDS and then writes both arrays in one coalesced pass (random placements
+// straight into HBM leave partly written lines: twice the bytes); larger slots write
+// each cluster where the counter puts it.
 constexpr int kSortThreads = 512;
-constexpr int kSortWords = 8192;
+constexpr int kSortWords = 4096;
+constexpr int kSortPerm = 8192;
 constexpr int kSortBatch = 2;
 static_assert(kSortWords % (4 * kSortThreads) == 0, "offset passes read 4 words per thread");
 struct SlotSort {
@@ -380,9 +384,9 @@ __device__ __forceinline__ int slot_cell(const SlotGrid& g, float2 v) {
   return cell_of(v.y, g.zlo, g.inv_bz, g.nz) * g.ny + cell_of(v.x, g.ylo, g.inv_by, g.ny);
 }
 
-template <bool kWide>
+template <bool kWide, bool kStage>
 __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, int32_t n, int32_t base,
-                          uint32_t* cnt, int* lds) {
+                          uint32_t* cnt, uint16_t* perm, int* lds) {
   constexpr int kPer = kWide ? 1 : 2;  // counters per word
   constexpr int kRange = kSortWords * kPer;
   constexpr uint32_t kMask = kWide ? 0xFFFFFFFFu : 0xFFFFu;
@@ -452,10 +456,33 @@ __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, in
         if ((unsigned)c[k] >= (unsigned)nc) continue;
         const uint32_t sh = (uint32_t)(c[k] % kPer) * 16;
         const uint32_t old = atomicAdd(&cnt[c[k] / kPer], 1u << sh);
-        const int32_t q = base + (int32_t)((old >> sh) & kMask);
+        const int32_t q = (int32_t)((old >> sh) & kMask);
+        if (kStage) {
+          perm[q] = (uint16_t)(p0 + k * kSortThreads + threadIdx.x);
+        } else {
+          const float y = __int_as_float(v[k].x), z = __int_as_float(v[k].y);
+          sth(S.gh + base + q, y, z, slot, v[k].z);
+          S.gyz[base + q] = make_float2(y, z);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (kStage) {
+    for (int q0 = 0; q0 < n; q0 += kSortThreads * kSortBatch) {
+      int4 v[kSortBatch];
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        const int q = q0 + k * kSortThreads + threadIdx.x;
+        if (q < n) v[k] = S.srec[base + perm[q]];
+      }
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        const int q = q0 + k * kSortThreads + threadIdx.x;
+        if (q >= n) break;
         const float y = __int_as_float(v[k].x), z = __int_as_float(v[k].y);
-        sth(S.gh + q, y, z, slot, v[k].z);
-        S.gyz[q] = make_float2(y, z);
+        sth(S.gh + base + q, y, z, slot, v[k].z);
+        S.gyz[base + q] = make_float2(y, z);
       }
     }
     __syncthreads();
@@ -464,11 +491,11 @@ __device__ void sort_slot(const SlotSort& S, const SlotGrid& g, int32_t slot, in
 
 // Workgroups take the non-empty slots of the list in turn; the cell offsets end with
 // the total at the range's last cell.
-__global__ __launch_bounds__(kSortThreads) void k_cell_sort(SlotSort S, const int32_t* slot_list,
-                                                           const int32_t* slot_cnt, const int32_t* slot_off,
-                                                           const SlotGrid* sg, const int32_t* cell_base,
-                                                           int32_t s1) {
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_cell_sort(
+    SlotSort S, const int32_t* slot_list, const int32_t* slot_cnt, const int32_t* slot_off, const SlotGrid* sg,
+    const int32_t* cell_base, int32_t s1) {
   __shared__ __align__(16) uint32_t cnt[kSortWords];
+  __shared__ uint16_t perm[kSortPerm];
   __shared__ int lds[40];
   const int32_t n_list = slot_list[kListCount];
   for (int32_t k = blockIdx.x; k < n_list; k += gridDim.x) {
@@ -476,8 +503,9 @@ __global__ __launch_bounds__(kSortThreads) void k_cell_sort(SlotSort S, const in
     const int32_t n = slot_cnt[s];
     const SlotGrid g = sg[s];
     const int32_t base = slot_off[s];
-    if (n < 65536) sort_slot<false>(S, g, s, n, base, cnt, lds);
-    else sort_slot<true>(S, g, s, n, base, cnt, lds);
+    if (n <= kSortPerm) sort_slot<false, true>(S, g, s, n, base, cnt, perm, lds);
+    else if (n < 65536) sort_slot<false, false>(S, g, s, n, base, cnt, perm, lds);
+    else sort_slot<true, false>(S, g, s, n, base, cnt, perm, lds);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) S.cell_off[cell_base[s1]] = slot_off[s1];
 }
