@@ -1027,17 +1027,77 @@ __global__ __launch_bounds__(256) void k_tracklets_chunked(
 }
 
 // ------------------------------------------------------------------ a5: selection
-// Owned-hit counts from one coalesced pass over the clusters: a cluster's weight is the
-// key of the tracklet that owns it, whose low 32 bits are 2^32-1 - id.
-__global__ void k_own_count(const uint32_t* hitw, const GHit* gh, const int32_t* T_off, int32_t* own,
-                            Bound lo_b, Bound hi_b, int32_t capT) {
+// Owned-hit counts from one coalesced pass over the clusters in grid order: a cluster's
+// weight is the key of the tracklet that owns it, whose low 24 bits are 2^24-1 - its id
+// within the job.  A block takes kOwnChunk consecutive grid positions.  When they all
+// belong to one job of at most kOwnLocal tracklets, it counts them in LDS (8-bit counters,
+// four to a word: a tracklet holds fewer than 256 clusters) and adds each non-zero count
+// with one atomic; otherwise every owned cluster adds its own.
+constexpr int kOwnThreads = 1024;
+constexpr int kOwnChunk = 65536;
+constexpr int kOwnLocal = 65536;
+constexpr int kOwnBatch = 4;
+static_assert(kHitStride < 256, "8-bit ownership counters");
+__global__ __launch_bounds__(kOwnThreads) void k_own_count(const uint32_t* hitw, const GHit* gh,
+                                                           const int32_t* T_off, const int32_t* slot_off,
+                                                           int32_t* own, int32_t j0, int32_t j1, Bound lo_b,
+                                                           Bound hi_b, int32_t capT) {
+  __shared__ uint32_t cnt[kOwnLocal / 4];
+  __shared__ int32_t s_job;
   const int32_t lo = lo_b.get(), hi = hi_b.get();
-  const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= hi) return;
-  const uint32_t w = hitw[h];
-  if (w == 0u) return;
-  const int32_t t = key_tracklet(w, T_off, gh[h].slot);
-  if ((uint32_t)t < (uint32_t)capT) atomicAdd(&own[t], 1);
+  const int64_t a = (int64_t)lo + (int64_t)blockIdx.x * kOwnChunk;
+  if (a >= hi) return;
+  const int32_t b = (int32_t)std::min<int64_t>(a + kOwnChunk, hi);
+  if (threadIdx.x == 0) {  // the job holding position a: slot_off[j K] <= a < slot_off[(j+1) K]
+    int x = j0, y = j1;
+    while (y - x > 1) {
+      const int m = (x + y) >> 1;
+      if (slot_off[(int64_t)m * kSlotsPerJob] <= a) x = m; else y = m;
+    }
+    s_job = x;
+  }
+  __syncthreads();
+  const int32_t j = s_job;
+  const int32_t t0 = T_off[j], ntr = T_off[j + 1] - t0;
+  if (slot_off[(int64_t)(j + 1) * kSlotsPerJob] < b || ntr > kOwnLocal) {
+    for (int64_t h0 = a; h0 < b; h0 += kOwnThreads * kOwnBatch) {
+      uint32_t w[kOwnBatch];
+#pragma unroll
+      for (int k = 0; k < kOwnBatch; ++k) {
+        const int64_t h = h0 + k * kOwnThreads + threadIdx.x;
+        w[k] = h < b ? hitw[h] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < kOwnBatch; ++k) {
+        if (w[k] == 0u) continue;
+        const int32_t t = key_tracklet(w[k], T_off, gh[h0 + k * kOwnThreads + threadIdx.x].slot);
+        if ((uint32_t)t < (uint32_t)capT) atomicAdd(&own[t], 1);
+      }
+    }
+    return;
+  }
+  const int nw = (ntr + 3) >> 2;
+  for (int q = threadIdx.x; q < nw; q += kOwnThreads) cnt[q] = 0u;
+  __syncthreads();
+  for (int64_t h0 = a; h0 < b; h0 += kOwnThreads * kOwnBatch) {
+    uint32_t w[kOwnBatch];
+#pragma unroll
+    for (int k = 0; k < kOwnBatch; ++k) {
+      const int64_t h = h0 + k * kOwnThreads + threadIdx.x;
+      w[k] = h < b ? hitw[h] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kOwnBatch; ++k) {
+      if (w[k] == 0u) continue;
+      const int32_t id = kLocalIdMax - (int32_t)(w[k] & (uint32_t)kLocalIdMax);
+      if ((uint32_t)id < (uint32_t)ntr) atomicAdd(&cnt[id >> 2], 1u << ((id & 3) << 3));
+    }
+  }
+  __syncthreads();
+  for (int32_t id = threadIdx.x; id < ntr; id += kOwnThreads) {
+    const int32_t c = (int32_t)((cnt[id >> 2] >> ((id & 3) << 3)) & 0xFFu);
+    if (c && (uint32_t)(t0 + id) < (uint32_t)capT) atomicAdd(&own[t0 + id], c);
+  }
 }
 
 __global__ void k_select_count(TrackletView V, Bound lo_b, Bound hi_b, int32_t* own, int32_t* accf,
@@ -2761,8 +2821,8 @@ void launch_select(tpc_ctx* c, int j0, int j1) {
   const int64_t nbound = c->job_off_h[j1] - c->job_off_h[j0];
   const int32_t s0 = j0 * kSlotsPerJob, s1 = j1 * kSlotsPerJob;
   hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, L.own, lo, hi, 0);
-  hipLaunchKernelGGL(k_own_count, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.hitw, L.gh,
-                     L.T_off, L.own, db(L.slot_off + s0), db(L.slot_off + s1), L.capT);
+  hipLaunchKernelGGL(k_own_count, dim3(blocks_for(nbound, kOwnChunk)), dim3(kOwnThreads), 0, c->stream, L.hitw,
+                     L.gh, L.T_off, L.slot_off, L.own, j0, j1, db(L.slot_off + s0), db(L.slot_off + s1), L.capT);
   hipLaunchKernelGGL(k_select_count, dim3(blocks_for(tb, 256)), dim3(256), 0, c->stream, make_tv(c), lo, hi,
                      L.own, L.accf, c->k);
   // the scans run over [T_off[j0], min(T_off[j1], capT)); clamp via a copy of the bound
