@@ -85,6 +85,12 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < n; k += stride) p[k] = v;
 }
+__global__ void k_fill_range_u8(uint8_t* p, Bound lo, Bound hi, uint8_t v) {
+  const int32_t a = lo.get(), b = hi.get();
+  for (int64_t k = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
 __global__ void k_fill_range_i32(int32_t* p, Bound lo, Bound hi, int32_t v) {
   const int32_t a = lo.get(), b = hi.get();
   for (int64_t k = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b;
@@ -96,8 +102,9 @@ __global__ void k_fill_range_i32(int32_t* p, Bound lo, Bound hi, int32_t v) {
 // tiles of kScanTile elements.  Loads and stores are striped (element q * 256 + j of a tile
 // goes to thread j, so a wave touches 64 consecutive ints); the apply pass turns the tile
 // into 8 consecutive elements per thread through LDS for the per-thread scan.
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, Bound lo_b, Bound hi_b,
-                                                              int32_t* bsum) {
+// The scanned input is int32 or bytes (0/1 flags); sums are int32.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T* in, Bound lo_b, Bound hi_b, int32_t* bsum) {
   __shared__ int lds[40];
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int64_t start = (int64_t)lo + (int64_t)blockIdx.x * kScanTile;
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in,
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const int64_t i = start + (int64_t)q * kScanThreads + threadIdx.x;
-    if (i < hi) s += in[i];
+    if (i < hi) s += (int)in[i];
   }
   int total;
   block_excl_scan(s, lds, total);
@@ -132,8 +139,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* bsum, Bound lo_b,
 // LDS slot of tile element i: one padding word per 32 keeps the per-thread reads of 8
 // consecutive elements from piling onto the same banks.
 __device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int32_t* out, Bound lo_b,
-                                                             Bound hi_b, const int32_t* bsum) {
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T* in, int32_t* out, Bound lo_b, Bound hi_b,
+                                                             const int32_t* bsum) {
   __shared__ int lds[40];
   __shared__ int tile[kScanTile + kScanTile / 32];
   const int32_t lo = lo_b.get(), hi = hi_b.get();
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, 
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const int64_t i = start + (int64_t)q * kScanThreads + j;
-    tile[scan_slot(q * kScanThreads + j)] = i < hi ? in[i] : 0;
+    tile[scan_slot(q * kScanThreads + j)] = i < hi ? (int)in[i] : 0;
   }
   __syncthreads();
   int v[kScanItems];
@@ -649,7 +657,7 @@ __global__ __launch_bounds__(256) void k_links(GridView G, Bound lo_b, Bound hi_
 // evaluated from the raw links too), flagged at h's input index and, for the grid-ordered
 // work list, at h itself.  Also clears h's hit weight for the tracklet stage.
 __global__ void k_clean_starts(const int32_t* up_raw, const int32_t* dn_raw, const GHit* gh, int32_t* up,
-                               int32_t* dn, int32_t* flag, int32_t* flagg, uint32_t* hitw, Bound lo_b,
+                               int32_t* dn, uint8_t* flag, uint8_t* flagg, uint32_t* hitw, Bound lo_b,
                                Bound hi_b) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -664,8 +672,8 @@ __global__ void k_clean_starts(const int32_t* up_raw, const int32_t* dn_raw, con
     const int32_t u2 = up_raw[uc];
     start = u2 >= 0 && dn_raw[u2] == uc;
   }
-  if (start) flag[gh[h].idx] = 1;
-  if (flagg) flagg[h] = start ? 1 : 0;
+  if (start) flag[gh[h].idx] = 1u;
+  if (flagg) flagg[h] = start ? 1u : 0u;
   hitw[h] = 0u;
 }
 
@@ -2430,7 +2438,8 @@ struct Layout {
   SlotGrid* sg;
   GHit* gh;
   float2* gyz;
-  int32_t *up_raw, *dn_raw, *up, *dn, *flag, *fid, *start, *flagg, *posg, *order;
+  int32_t *up_raw, *dn_raw, *up, *dn, *fid, *start, *posg, *order;
+  uint8_t *flag, *flagg;  // chain starts in input and grid order
   int32_t *trk_hits, *trk_n;
   float* trk_state;
   uint32_t* hitw;
@@ -2676,14 +2685,14 @@ void fill_i32(tpc_ctx* c, int32_t* p, int64_t n, int32_t v) {
 
 // exclusive scan over [lo, hi) (bound <= host upper bound of hi-lo)
 // base_from_out: continue from the total a previous scan left in out[lo]
-void scan(tpc_ctx* c, const int32_t* in, int32_t* out, Bound lo, Bound hi, int64_t bound,
-          bool base_from_out) {
+template <typename T>
+void scan(tpc_ctx* c, const T* in, int32_t* out, Bound lo, Bound hi, int64_t bound, bool base_from_out) {
   Layout& L = c->L;
   const int nb = (int)std::max<int64_t>(1, (bound + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, c->stream, in, lo, hi, L.bsum);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, lo, hi, L.bsum);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c->stream, L.bsum, lo, hi,
                      (int32_t)base_from_out, out);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, lo, hi, L.bsum);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, lo, hi, L.bsum);
 }
 
 In make_in(tpc_ctx* c) {
@@ -2766,8 +2775,8 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
   // clean links, starts flagged in input order (-> ranked ids) and grid order, weights cleared
   const int32_t* jo = c->jobs.job_off;
   const bool grid_order = c->tune.tracklet_order == 1;
-  hipLaunchKernelGGL(k_fill_range_i32, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.flag,
-                     db(jo + j0), db(jo + j1), 0);
+  hipLaunchKernelGGL(k_fill_range_u8, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.flag,
+                     db(jo + j0), db(jo + j1), (uint8_t)0);
   hipLaunchKernelGGL(k_clean_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up_raw, L.dn_raw,
                      L.gh, L.up, L.dn, L.flag, grid_order ? L.flagg : nullptr, L.hitw, lo, hi);
   scan(c, L.flag, L.fid, db(jo + j0), db(jo + j1), nbound, j0 != 0);
