@@ -688,15 +688,21 @@ __global__ void k_job_offsets(const int32_t* scanned, const int32_t* job_off, in
 // start[t] = grid index of tracklet t's start; order[p] = id of the p-th start in grid order.
 // When the starts up to this batch's end (thi) exceed the capacity, ids and positions below
 // capT no longer pair up, so order[] becomes the identity: every kept id is then built.
-__global__ void k_write_starts(const int32_t* up, const int32_t* dn, const GHit* gh,
+// Starts are read from the grid-order flags when there are any (one byte per cluster),
+// else tested on the clean links.
+__global__ void k_write_starts(const int32_t* up, const int32_t* dn, const uint8_t* flagg, const GHit* gh,
                                const int32_t* fid, const int32_t* posg, const int32_t* T_off, int32_t* start,
                                int32_t* order, int32_t capT, Bound lo_b, Bound hi_b, Bound thi_b,
                                int32_t* counters) {
   const int32_t lo = lo_b.get(), hi = hi_b.get();
   const int32_t h = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= hi) return;
-  const int32_t u = up[h];
-  if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
+  if (flagg) {
+    if (!flagg[h]) return;
+  } else {
+    const int32_t u = up[h];
+    if (!(dn[h] < 0 && u >= 0 && up[u] >= 0)) return;
+  }
   const GHit H = ldh(gh + h);
   const int32_t t = fid[H.idx];
   if (t < capT) start[t] = h;
@@ -2784,7 +2790,7 @@ void launch_links(tpc_ctx* c, int j0, int j1) {
                      L.T_off, j0, j1, (int32_t)L.N);
   if (grid_order) scan(c, L.flagg, L.posg, lo, hi, nbound, j0 != 0);
   hipLaunchKernelGGL(k_write_starts, dim3(blocks_for(nbound, 256)), dim3(256), 0, c->stream, L.up, L.dn,
-                     L.gh, L.fid, grid_order ? L.posg : nullptr, L.T_off, L.start,
+                     grid_order ? L.flagg : nullptr, L.gh, L.fid, grid_order ? L.posg : nullptr, L.T_off, L.start,
                      grid_order ? L.order : nullptr, L.capT, lo, hi, db(L.T_off + j1), L.counters);
 }
 
