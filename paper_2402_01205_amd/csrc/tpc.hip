@@ -1043,12 +1043,13 @@ __global__ __launch_bounds__(256) void k_tracklets_chunked(
 // ------------------------------------------------------------------ a5: selection
 // Owned-hit counts from one coalesced pass over the clusters in grid order: a cluster's
 // weight is the key of the tracklet that owns it, whose low 24 bits are 2^24-1 - its id
-// within the job.  A block takes kOwnChunk consecutive grid positions.  When they all
-// belong to one job of at most kOwnLocal tracklets, it counts them in LDS (8-bit counters,
-// four to a word: a tracklet holds fewer than 256 clusters) and adds each non-zero count
-// with one atomic; otherwise every owned cluster adds its own.
+// within the job.  A block takes kOwnChunk consecutive grid positions (small enough that
+// few chunks straddle a job boundary, large enough that few tracklets are split between
+// chunks).  When they all belong to one job of at most kOwnLocal tracklets, it counts them
+// in LDS (8-bit counters, four to a word: a tracklet holds fewer than 256 clusters) and adds
+// each non-zero count with one atomic; otherwise every owned cluster adds its own.
 constexpr int kOwnThreads = 1024;
-constexpr int kOwnChunk = 65536;
+constexpr int kOwnChunk = 16384;
 constexpr int kOwnLocal = 65536;
 constexpr int kOwnBatch = 4;
 static_assert(kHitStride < 256, "8-bit ownership counters");
