@@ -96,7 +96,8 @@ def lib():
         L.orc_merge_chi2.argtypes = [P, P, P, P]
         L.orc_fit_hits_f64.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.orc_fit_hits_f32.argtypes = [P, C.c_int32, P, P, P, P, P, P]
-        L.orc_rotate_f64.argtypes = [P, P, P, P, C.c_int32, C.c_int32]
+        L.orc_rotate_f64.argtypes = [P, P, P, C.c_int32, C.c_int32, C.POINTER(Params)]
+        L.orc_rotate_f32.argtypes = [P, P, P, C.c_int32, C.c_int32, C.POINTER(Params)]
         L.orc_compress.restype = C.c_int32
         L.orc_compress.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, C.c_int32] + [P] * 6 + [
             C.c_float, C.c_float, P, P, P, P]
@@ -238,6 +239,18 @@ def propagate(P, Cv, x1, x2, prm=None, fp64=False):
     fn = lib().orc_propagate_f64 if fp64 else lib().orc_propagate_f32
     ok = fn(_p(P), _p(Cv), x1, x2, C.byref(prm))
     return bool(ok), P, Cv
+
+
+def rotate(P, Cv, x, sec_from, sec_to, prm=None, fp64=False):
+    """Sector rotation of a state at plane x (O10).  Returns (ok, state[10], C[15], x')."""
+    dt = np.float64 if fp64 else np.float32
+    P = _state(P, dt)
+    Cv = np.array(Cv, dt)
+    xx = np.array([x], dt)
+    prm = prm or params()
+    fn = lib().orc_rotate_f64 if fp64 else lib().orc_rotate_f32
+    ok = fn(_p(P), _p(Cv), _p(xx), int(sec_from), int(sec_to), C.byref(prm))
+    return bool(ok), P, Cv, float(xx[0])
 
 
 def update(P, Cv, my, mz, prm=None, fp64=False):

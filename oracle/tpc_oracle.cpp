@@ -332,6 +332,55 @@ struct Track {
   std::vector<int32_t> pieces;  // chain head: its absorbed pieces, inner -> outer
 };
 
+// O10: re-express a state in the frame of the adjacent sector `to` (same side; the
+// sector angle changes by d = +-20 degrees).  The point keeps its global position:
+// x' = x cos d + y sin d, y' = -x sin d + y cos d; the direction turns by -d:
+// s' = s cos d - c sin d, c' = c cos d + s sin d; z, t, k are unchanged.  The new
+// reference plane is x' = const, so a shift dy of y at fixed x moves the point by
+// dy sin d off that plane; moving it back along the helix by dx' = -dy sin d changes
+// y' by dx' s'/c', z by dx' t/c' and sin(phi) by dx' times the curvature k cb:
+// dy'/dy = (cos d c' - sin d s')/c' = c/c', dz'/dy = -t sin d / c',
+// ds'/dy = -k cb sin d.  A change of s at fixed point turns only the direction:
+// ds'/ds = cos d + sin d s/c = c'/c.  Fails unless c' > 0 and |s'| < smax.
+template <class T> bool rotate_sector(T* P, T* L, T* C, T& x, int from, int to, T cb, T smax) {
+  const int df = ((to % kRowsPerSide) - (from % kRowsPerSide) + kRowsPerSide) % kRowsPerSide;
+  if (df != 1 && df != kRowsPerSide - 1) return false;
+  const T ca = (T)kGeo.cos20;
+  const T sa = df == 1 ? (T)kGeo.sin20 : -(T)kGeo.sin20;
+  const T s = P[2];
+  const T c = std::sqrt((T(1) - s) * (T(1) + s));
+  const T xn = x * ca + P[0] * sa;
+  const T yn = P[0] * ca - x * sa;
+  const T sn = s * ca - c * sa;
+  const T cn = c * ca + s * sa;
+  if (!(cn > T(0)) || !(std::fabs(sn) < smax)) return false;
+  const T ja = c / cn;                 // dy'/dy
+  const T jb = -(P[3] * sa / cn);      // dz'/dy
+  const T jc = -(P[4] * cb * sa);      // ds'/dy
+  const T je = cn / c;                 // ds'/ds
+  T c5[5][5];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) c5[i][j] = C[tri(i, j)];
+  T M[5][5];
+  for (int j = 0; j < 5; ++j) {
+    M[0][j] = ja * c5[0][j];
+    M[1][j] = jb * c5[0][j] + c5[1][j];
+    M[2][j] = jc * c5[0][j] + je * c5[2][j];
+    M[3][j] = c5[3][j];
+    M[4][j] = c5[4][j];
+  }
+  for (int i = 0; i < 5; ++i) {
+    const T n[5] = {ja * M[i][0], jb * M[i][0] + M[i][1], jc * M[i][0] + je * M[i][2], M[i][3], M[i][4]};
+    for (int j = 0; j <= i; ++j) C[tri(i, j)] = n[j];
+  }
+  P[0] = yn;
+  P[2] = sn;
+  L[0] = T(0);
+  L[2] = T(0);
+  x = xn;
+  return all_finite(P, C);
+}
+
 struct Oracle {
   Params p;
   int32_t n = 0, J = 0;
@@ -602,49 +651,8 @@ struct Oracle {
     return true;
   }
 
-  // O10: re-express a state in the frame of the adjacent sector `to` (same side; the
-  // sector angle changes by d = +-20 degrees).  The point keeps its global position:
-  // x' = x cos d + y sin d, y' = -x sin d + y cos d; the direction turns by -d:
-  // s' = s cos d - c sin d, c' = c cos d + s sin d; z, t, k are unchanged.  The new
-  // reference plane is x' = const, so a shift of y at fixed x moves the point off that
-  // plane; moving it back along the track gives dy'/dy = c/c' and dz'/dy = -t sin d / c'.
-  // Also ds'/ds = c'/c.  Fails unless c' > 0 and |s'| < smax.
   template <class T> bool rotate(T* P, T* L, T* C, T& x, int from, int to) {
-    const int df = ((to % kRowsPerSide) - (from % kRowsPerSide) + kRowsPerSide) % kRowsPerSide;
-    if (df != 1 && df != kRowsPerSide - 1) return false;
-    const T ca = (T)kGeo.cos20;
-    const T sa = df == 1 ? (T)kGeo.sin20 : -(T)kGeo.sin20;
-    const T s = P[2];
-    const T c = std::sqrt((T(1) - s) * (T(1) + s));
-    const T xn = x * ca + P[0] * sa;
-    const T yn = P[0] * ca - x * sa;
-    const T sn = s * ca - c * sa;
-    const T cn = c * ca + s * sa;
-    if (!(cn > T(0)) || !(std::fabs(sn) < (T)p.smax)) return false;
-    const T ja = c / cn;                 // dy'/dy
-    const T jb = -(P[3] * sa / cn);      // dz'/dy
-    const T je = cn / c;                 // ds'/ds
-    T c5[5][5];
-    for (int i = 0; i < 5; ++i)
-      for (int j = 0; j < 5; ++j) c5[i][j] = C[tri(i, j)];
-    T M[5][5];
-    for (int j = 0; j < 5; ++j) {
-      M[0][j] = ja * c5[0][j];
-      M[1][j] = jb * c5[0][j] + c5[1][j];
-      M[2][j] = je * c5[2][j];
-      M[3][j] = c5[3][j];
-      M[4][j] = c5[4][j];
-    }
-    for (int i = 0; i < 5; ++i) {
-      const T n[5] = {ja * M[i][0], jb * M[i][0] + M[i][1], je * M[i][2], M[i][3], M[i][4]};
-      for (int j = 0; j <= i; ++j) C[tri(i, j)] = n[j];
-    }
-    P[0] = yn;
-    P[2] = sn;
-    L[0] = T(0);
-    L[2] = T(0);
-    x = xn;
-    return all_finite(P, C);
+    return rotate_sector(P, L, C, x, from, to, curvature_factor<T>(p), (T)p.smax);
   }
 
   void fit_all() {
@@ -1084,8 +1092,11 @@ int32_t orc_update_f64(double* P, double* C, double my, double mz, const Params*
   const double sy = p->sigma_y, sz = p->sigma_z;
   return kf_update<double>(P, P + 5, C, my, mz, sy * sy, sz * sz, (double)p->smax, chi2);
 }
-int32_t orc_rotate_f64(void* h, double* P, double* C, double* x, int32_t from, int32_t to) {
-  return ((Oracle*)h)->rotate<double>(P, P + 5, C, *x, from, to);
+int32_t orc_rotate_f64(double* P, double* C, double* x, int32_t from, int32_t to, const Params* p) {
+  return rotate_sector<double>(P, P + 5, C, *x, from, to, curvature_factor<double>(*p), (double)p->smax);
+}
+int32_t orc_rotate_f32(float* P, float* C, float* x, int32_t from, int32_t to, const Params* p) {
+  return rotate_sector<float>(P, P + 5, C, *x, from, to, curvature_factor<float>(*p), p->smax);
 }
 void orc_asinc_f32(float u, float* A, float* B) { asinc(u, *A, *B); }
 void orc_asinc_f64(double u, double* A, double* B) { asinc(u, *A, *B); }

@@ -252,6 +252,9 @@ __device__ __forceinline__ bool kf_update(State& S, float my, float mz, const Co
 
 // Re-express the state in the frame of the adjacent sector `to` (same side; the
 // sector angle changes by d = +-20 deg).  x is updated to the rotated plane.
+// Covariance by the first-order Jacobian of "rotate, then move along the helix
+// back to the rotated plane": dy'/dy = c/c', dz'/dy = -t sin d / c',
+// ds'/dy = -k cb sin d (the direction turns while moving back), ds'/ds = c'/c.
 __device__ __forceinline__ bool rotate(State& S, float& x, int from, int to, const Consts& k) {
   const int df = ((to % kHalf) - (from % kHalf) + kHalf) % kHalf;
   if (df != 1 && df != kHalf - 1) return false;
@@ -266,6 +269,7 @@ __device__ __forceinline__ bool rotate(State& S, float& x, int from, int to, con
   if (!(cn > 0.f) || !(fabsf(sn) < k.smax)) return false;
   const float ja = div_rn(c, cn);
   const float jb = -div_rn(S.P[3] * sa, cn);
+  const float jc = -(S.P[4] * k.cb * sa);
   const float je = div_rn(cn, c);
   float c5[5][5];
 #pragma unroll
@@ -277,13 +281,13 @@ __device__ __forceinline__ bool rotate(State& S, float& x, int from, int to, con
   for (int j = 0; j < 5; ++j) {
     M[0][j] = ja * c5[0][j];
     M[1][j] = jb * c5[0][j] + c5[1][j];
-    M[2][j] = je * c5[2][j];
+    M[2][j] = jc * c5[0][j] + je * c5[2][j];
     M[3][j] = c5[3][j];
     M[4][j] = c5[4][j];
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    const float n[5] = {ja * M[i][0], jb * M[i][0] + M[i][1], je * M[i][2], M[i][3], M[i][4]};
+    const float n[5] = {ja * M[i][0], jb * M[i][0] + M[i][1], jc * M[i][0] + je * M[i][2], M[i][3], M[i][4]};
 #pragma unroll
     for (int j = 0; j <= i; ++j) S.C[tri(i, j)] = n[j];
   }

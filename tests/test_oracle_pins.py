@@ -139,6 +139,89 @@ def test_transport_is_J_C_Jt():
     assert np.allclose(O.tri_to_full(Cn), J @ Cf @ J.T, rtol=1e-12, atol=1e-12)
 
 
+# ------------------------------------------------------------------ sector rotation (O10)
+def _rotated_at_plane(P, x, frm, to, xn0, prm):
+    """Rotate into sector `to`, then move along the helix to the plane x' = xn0:
+    the state map whose derivative the rotation's covariance transform must be."""
+    ok, Pr, _, xn = O.rotate(P, np.zeros(15), x, frm, to, prm, fp64=True)
+    assert ok
+    ok, Pp, _ = O.propagate(Pr, np.zeros(15), xn, xn0, prm, fp64=True)
+    assert ok
+    return Pp[:5] + Pp[5:]
+
+
+def _jac_from_rotation(P, x, frm, to, prm):
+    """Column a of J from rotating C = e_a e_a^T (every diagonal entry of J is > 0)."""
+    J = np.zeros((5, 5))
+    for a in range(5):
+        E = np.zeros((5, 5))
+        E[a, a] = 1.0
+        ok, _, Cn, _ = O.rotate(P, O.full_to_tri(E), x, frm, to, prm, fp64=True)
+        assert ok
+        M = O.tri_to_full(Cn)
+        J[:, a] = M[:, a] / math.sqrt(M[a, a])
+    return J
+
+
+@pytest.mark.parametrize("state,x,frm,to", [
+    ([30.0, 40.0, 0.3, 0.5, 5.0], 180.0, 0, 1),     # leaves through +y, positive curvature term
+    ([30.0, 40.0, 0.3, 0.5, -5.0], 180.0, 0, 1),
+    ([-35.0, -60.0, -0.4, -0.7, 8.0], 220.0, 19, 18),  # side C, through -y
+    ([-20.0, 10.0, -0.2, 0.1, -9.5], 120.0, 17, 16),
+    ([40.0, 100.0, 0.5, 0.9, 2.0], 240.0, 17, 0),    # wraps 17 -> 0
+    ([-42.0, -5.0, -0.35, -0.2, -3.0], 238.0, 0, 17),   # wraps 0 -> 17
+])
+def test_rotation_jacobian_against_finite_differences(state, x, frm, to):
+    """O10: the covariance transform of the sector rotation is the derivative of the
+    map 'rotate, then move back along the helix to the rotated nominal plane'
+    (central differences of the exact FP64 state map, propagation pinned above)."""
+    prm = O.params(smax=0.999)
+    ok, _, _, xn0 = O.rotate(state, np.zeros(15), x, frm, to, prm, fp64=True)
+    assert ok
+    J = _jac_from_rotation(state, x, frm, to, prm)
+    Jfd = np.zeros((5, 5))
+    for a in range(5):
+        hstep = 1e-6 * max(1.0, abs(state[a]))
+        pp = np.array(state, float); pp[a] += hstep
+        pm = np.array(state, float); pm[a] -= hstep
+        Jfd[:, a] = (_rotated_at_plane(pp, x, frm, to, xn0, prm)
+                     - _rotated_at_plane(pm, x, frm, to, xn0, prm)) / (2 * hstep)
+    assert np.allclose(J, Jfd, rtol=1e-6, atol=1e-8), (J, Jfd)
+    # the curvature term is really there (k != 0 in every case above)
+    assert abs(J[2, 0]) > 1e-4
+
+
+def test_rotation_is_J_C_Jt():
+    prm = O.params(smax=0.999)
+    state, x = [25.0, -30.0, 0.25, -0.6, -4.0], 200.0
+    J = _jac_from_rotation(state, x, 3, 4, prm)
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(5, 5))
+    Cf = A @ A.T + np.eye(5)
+    ok, _, Cn, _ = O.rotate(state, O.full_to_tri(Cf), x, 3, 4, prm, fp64=True)
+    assert ok
+    assert np.allclose(O.tri_to_full(Cn), J @ Cf @ J.T, rtol=1e-12, atol=1e-12)
+
+
+def test_rotation_there_and_back_is_identity():
+    """Turning into the neighbour sector and back returns the state (up to the FP32
+    rounding of the cos 20 / sin 20 table values, ~1e-7 relative)."""
+    prm = O.params(smax=0.999)
+    state, x = np.array([30.0, 40.0, 0.3, 0.5, 5.0]), 180.0
+    ok, P1, _, x1 = O.rotate(state, np.zeros(15), x, 5, 6, prm, fp64=True)
+    ok2, P2, _, x2 = O.rotate(P1, np.zeros(15), x1, 6, 5, prm, fp64=True)
+    assert ok and ok2
+    assert abs(x2 - x) < 1e-6
+    assert np.allclose(P2[:5] + P2[5:], state, rtol=0, atol=1e-6)
+
+
+def test_rotation_rejects_non_adjacent_and_other_side():
+    prm = O.params()
+    for frm, to in [(0, 2), (0, 18), (3, 3), (20, 5)]:
+        ok, *_ = O.rotate([1.0, 1.0, 0.1, 0.1, 1.0], np.eye(5)[np.tril_indices(5)], 150.0, frm, to, prm, fp64=True)
+        assert not ok
+
+
 # ------------------------------------------------------------------ Kalman update
 @pytest.mark.parametrize("seed", range(5))
 def test_update_equals_information_form(seed):
