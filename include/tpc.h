@@ -343,6 +343,16 @@ int tpc_find_clusters(tpc_ctx* ctx, const tpc_cf_params* p, const tpc_digits* d,
  * kernels reported one since the last tpc_grid_build, else TPC_OK.           */
 int tpc_sync(tpc_ctx* ctx);
 
+/* Enqueues on the context's stream a copy of six counters of the last run into
+ * dst[6] (device memory or pinned host memory), without synchronising:
+ *   dst[0] status bits since the last tpc_grid_build (TPC_STATUS_RANGE,
+ *          TPC_STATUS_CAPACITY: the conditions tpc_sync reports),
+ *   dst[1] tracklets, dst[2] selected tracks, dst[3] their hits,
+ *   dst[4] output tracks (= *n_tracks), dst[5] their hits (hit_off[n_tracks]).
+ * For callers with several runs in flight on different streams that check each
+ * run's status when its results arrive.  TPC_E_ARG before the first run.      */
+int tpc_counts(tpc_ctx* ctx, int32_t* dst);
+
 /* Test hooks (stage outputs, device pointers, sizes n or capacities):        */
 /* raw links before cleaning, as cluster indices                             */
 int tpc_get_links_raw(tpc_ctx* ctx, int32_t* up_raw, int32_t* down_raw);

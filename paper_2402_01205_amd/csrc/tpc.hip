@@ -3275,6 +3275,16 @@ int tpc_sync(tpc_ctx* c) {
   return TPC_OK;
 }
 
+int tpc_counts(tpc_ctx* c, int32_t* dst) {
+  if (!c || !dst) return fail(c, TPC_E_ARG, "null argument");
+  if (!c->laid_out) return fail(c, TPC_E_ARG, "no tracking run");
+  static_assert(kCntStatus == 0 && kCntTracklets == 1 && kCntSelected == 2 && kCntSelHits == 3 &&
+                    kCntOut == 4 && kCntOutHits == 5,
+                "tpc_counts copies the first six counters in the order tpc.h states");
+  HIPCHK(c, hipMemcpyAsync(dst, c->L.counters, 6 * sizeof(int32_t), hipMemcpyDefault, c->stream));
+  return TPC_OK;
+}
+
 int tpc_get_links_raw(tpc_ctx* c, int32_t* up_raw, int32_t* down_raw) {
   if (!c || c->stage < 2) return TPC_E_ARG;
   hipLaunchKernelGGL(k_links_to_input, dim3(blocks_for(c->L.N, 256)), dim3(256), 0, c->stream, c->L.up_raw,

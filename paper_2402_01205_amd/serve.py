@@ -9,7 +9,10 @@ overlaps with them.  Admission is sized by free HBM: a batch is launched only if
 its workspace (tpc_workspace_size), its cluster buffers and its outputs fit in
 the budget left by the batches in flight.  Cluster and track state stay on the
 device; each chunk's results are copied to pinned host memory when its batch
-completes, which ends the chunk's latency (measured from its arrival time).
+completes: the library's counters (tpc_counts) first, then exactly the tracks and hits
+found, all copied to pinned host memory; the end of those copies ends the chunk's
+latency (measured from its arrival time).  A batch whose status reports a range or
+capacity condition is an error, not a silently shortened result.
 
 A chunk's tracks depend only on its own clusters (jobs are independent), so a
 chunk gives the same result alone and in any mix.
@@ -153,16 +156,23 @@ def assemble(pool: Pool, chunks, stream, device="cuda:0"):
     return ev
 
 
+OUT_KEYS = ("hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet")
+
+
 @dataclass
 class Slot:
     stream: object
     tracker: Tracker
-    busy: bool = False
+    phase: int = 0              # 0 idle, 1 tracking, 2 copying the results to the host
     batch: list = field(default_factory=list)
-    done_event: object = None
+    event: object = None
     bytes: int = 0
     ev: object = None
-    host: dict = None
+    counts: object = None       # pinned int32[6] (tpc_counts)
+    host: dict = None           # pinned result buffers, grown as needed
+    t_launch: float = 0.0
+    k: int = 0
+    h: int = 0
 
 
 def _bytes_of(tracker: Tracker, n, j):
@@ -171,13 +181,29 @@ def _bytes_of(tracker: Tracker, n, j):
     return tracker.workspace_size(n, j) + 15 * n + 100 * capT + 4 * n
 
 
+class ServingError(RuntimeError):
+    pass
+
+
 class Server:
+    """Continuous batching over `n_slots` HIP streams.
+
+    Each chunk's results (hits as chunk-local cluster indices in CSR form, the fitted
+    parameters, covariance, x_ref, chi2, ndf, sector, tracklet id) are copied to pinned
+    host memory and handed to ``on_result(cid, result)`` when the copy has completed;
+    that moment ends the chunk's latency.  The arrays of ``result`` are views of the
+    slot's pinned buffers, valid during the call only.  A batch whose run reported a
+    range or capacity condition (tpc_counts status bits) raises ServingError with its
+    chunk ids unless ``strict`` is False, in which case its chunks are reported with
+    ``result["status"]`` set."""
+
     def __init__(self, pool: Pool, device=0, n_slots=3, hbm_budget=None, tuning=None, max_batch=64,
-                 max_batch_clusters=150_000_000):
+                 max_batch_clusters=150_000_000, strict=True):
         import torch
         self.torch = torch
         self.pool = pool
         self.device = device
+        self.strict = strict
         torch.cuda.synchronize(device)
         torch.cuda.empty_cache()
         free, total = torch.cuda.mem_get_info(device)
@@ -189,7 +215,8 @@ class Server:
         for _ in range(n_slots):
             s = torch.cuda.Stream(device)
             self.slots.append(Slot(s, Tracker(device, mode="persistent" if tuning.persistent_waves else "batched",
-                                              tuning=tuning, stream=s)))
+                                              tuning=tuning, stream=s),
+                                   counts=torch.zeros(6, dtype=torch.int32, pin_memory=True)))
         self.max_batch = max_batch
         self.in_flight_bytes = 0
 
@@ -198,17 +225,57 @@ class Server:
         ev = assemble(self.pool, batch, slot.stream, f"cuda:{self.device}")
         with torch.cuda.stream(slot.stream):
             slot.tracker.run(ev)
-            o = slot.tracker.out
-            # per-chunk results to pinned host memory
-            host = {k: torch.empty(o[k].shape, dtype=o[k].dtype, pin_memory=True)
-                    for k in ("n_tracks", "hit_off", "job")}
-            for k in host:
-                host[k].copy_(o[k], non_blocking=True)
+            slot.tracker.tpc_counts(slot.counts)
             done = torch.cuda.Event()
             done.record(slot.stream)
-        slot.busy, slot.batch, slot.done_event, slot.ev, slot.host = True, batch, done, ev, host
+        slot.phase, slot.batch, slot.event, slot.ev = 1, batch, done, ev
 
-    def run(self, chunks, realtime=True, log=None, deadline_s=900.0):
+    def _copy_results(self, slot: Slot, status: int):
+        """Tracking done: enqueue the copies of exactly the tracks and hits found (none when
+        the batch reported a range or capacity condition)."""
+        torch = self.torch
+        o = slot.tracker.out
+        c = slot.counts.numpy()
+        K, H = (0, 0) if status else (int(c[4]), int(c[5]))
+        h = slot.host
+        if h is None or h["hit_off"].shape[0] < K + 1 or h["hits"].shape[0] < max(H, 1):
+            cap_k, cap_h = 2 * max(K + 1, 1024), 2 * max(H, 1024)
+            h = {k: torch.empty(((cap_h if k == "hits" else cap_k),) + tuple(o[k].shape[1:]),
+                                dtype=o[k].dtype, pin_memory=True) for k in OUT_KEYS}
+            slot.host = h
+        with torch.cuda.stream(slot.stream):
+            for k in OUT_KEYS:
+                n = (K + 1) if k == "hit_off" else (H if k == "hits" else K)
+                if n:
+                    h[k][:n].copy_(o[k][:n], non_blocking=True)
+            done = torch.cuda.Event()
+            done.record(slot.stream)
+        slot.phase, slot.event, slot.k, slot.h = 2, done, K, H
+
+    def _deliver(self, slot: Slot, status: int, on_result):
+        """Copies done: split the batch's tracks by job (one job per chunk)."""
+        h = slot.host
+        K = slot.k
+        job = h["job"][:K].numpy()
+        off = h["hit_off"][:K + 1].numpy()
+        jo = slot.ev.job_off_host
+        if K and np.any(np.diff(job) < 0):
+            raise ServingError("tracks of a batch are not in job order")
+        bounds = np.searchsorted(job, np.arange(len(slot.batch) + 1), side="left")
+        counts = np.diff(bounds)
+        for i, ch in enumerate(slot.batch):
+            if on_result is None:
+                continue
+            a, b = int(bounds[i]), int(bounds[i + 1])
+            res = dict(status=status, n_tracks=b - a,
+                       hit_off=off[a:b + 1] - off[a],
+                       hits=h["hits"][int(off[a]):int(off[b])].numpy() - jo[i])
+            for k in ("param", "cov", "x_ref", "chi2", "ndf", "sector", "tracklet"):
+                res[k] = h[k][a:b].numpy()
+            on_result(ch.cid, res)
+        return counts
+
+    def run(self, chunks, realtime=True, log=None, deadline_s=900.0, on_result=None):
         """Serve the chunk stream; returns per-chunk latencies and totals."""
         for ch in chunks:
             plan_chunk(self.pool, ch)
@@ -217,38 +284,48 @@ class Server:
         nxt = 0
         lat = {}
         tracks = {}
+        errors = {}
         t0 = time.perf_counter()
-        busy_time = 0.0
         n_batches = 0
         max_conc = 0
+        busy = []          # (start, end) of every batch: tracking through the result copies
         t_start = time.perf_counter()
         while len(lat) < len(chunks):
             if time.perf_counter() - t_start > deadline_s:
                 raise RuntimeError(f"serving did not finish within {deadline_s} s")
             now = time.perf_counter() - t0
-            if not realtime and nxt < len(order) and not pending and all(not s.busy for s in self.slots):
+            if not realtime and nxt < len(order) and not pending and all(s.phase == 0 for s in self.slots):
                 now = order[nxt].arrival  # skip idle gaps when not pacing in real time
                 t0 = time.perf_counter() - now
             while nxt < len(order) and order[nxt].arrival <= now:
                 pending.append(order[nxt])
                 nxt += 1
-            # completions
+            # completions: tracking done -> copy results; copies done -> deliver
             for s in self.slots:
-                if s.busy and s.done_event.query():
+                if s.phase == 1 and s.event.query():
+                    status = int(s.counts[0])
+                    if status:
+                        ids = [ch.cid for ch in s.batch]
+                        if self.strict:
+                            raise ServingError(f"batch of chunks {ids} reported status bits {status} "
+                                               f"(1 = cluster out of range, 2 = capacity exceeded)")
+                        for c in ids:
+                            errors[c] = status
+                    self._copy_results(s, status)
+                elif s.phase == 2 and s.event.query():
                     tdone = time.perf_counter() - t0
-                    K = int(s.host["n_tracks"][0])
-                    jobs = s.host["job"][:K].numpy()
-                    cnt = np.bincount(jobs, minlength=len(s.batch))
+                    cnt = self._deliver(s, errors.get(s.batch[0].cid, 0), on_result)
                     for i, ch in enumerate(s.batch):
                         lat[ch.cid] = tdone - ch.arrival
                         tracks[ch.cid] = int(cnt[i])
+                    busy.append((s.t_launch, tdone))
                     if log:
-                        log(f"t={tdone:7.3f}s done {len(s.batch)} chunks, {K} tracks; served {len(lat)}")
+                        log(f"t={tdone:7.3f}s done {len(s.batch)} chunks, {s.k} tracks; served {len(lat)}")
                     self.in_flight_bytes -= s.bytes
-                    s.busy, s.batch, s.ev, s.host = False, [], None, None
+                    s.phase, s.batch, s.ev, s.event = 0, [], None, None
             # admissions: pack waiting chunks into one launch per free slot
             for s in self.slots:
-                if s.busy or not pending:
+                if s.phase != 0 or not pending:
                     continue
                 batch, n = [], 0
                 for ch in list(pending):
@@ -270,9 +347,10 @@ class Server:
                     pending.remove(ch)
                 s.bytes = _bytes_of(s.tracker, n, len(batch))
                 self.in_flight_bytes += s.bytes
+                s.t_launch = now
                 self._launch(s, batch)
                 n_batches += 1
-                max_conc = max(max_conc, sum(x.busy for x in self.slots))
+                max_conc = max(max_conc, sum(x.phase != 0 for x in self.slots))
                 if log:
                     log(f"t={now:7.3f}s launch {len(batch)} chunks, {n} clusters, pending {len(pending)}")
             time.sleep(0.0002)
@@ -280,7 +358,15 @@ class Server:
         lats = np.array([lat[c.cid] for c in chunks])
         n_cl = sum(c.n_signal + n_noise(c) for c in chunks)
         offered = n_cl / max(order[-1].arrival, 1e-9)
+        # fraction of the wall time with at least one batch in flight
+        busy.sort()
+        covered, end = 0.0, -1e300
+        for a, b in busy:
+            if b > end:
+                covered += b - max(a, end)
+                end = b
         return dict(n_chunks=len(chunks), clusters=n_cl, wall_s=wall, clusters_per_s=n_cl / wall,
                     offered_clusters_per_s=offered, p50_ms=float(np.percentile(lats, 50) * 1e3),
                     p99_ms=float(np.percentile(lats, 99) * 1e3), mean_ms=float(lats.mean() * 1e3),
-                    batches=n_batches, max_concurrent=max_conc, tracks=tracks, latencies=lats)
+                    batches=n_batches, max_concurrent=max_conc, busy_fraction=covered / wall,
+                    errors=len(errors), tracks=tracks, latencies=lats)

@@ -124,6 +124,7 @@ def lib():
         L.tpc_fit_merge.argtypes = [V, P(tpc_tracks)]
         L.tpc_run.argtypes = [V, P(tpc_clusters), P(tpc_jobs), P(tpc_tracks)]
         L.tpc_sync.argtypes = [V]
+        L.tpc_counts.argtypes = [V, V]
         L.tpc_get_links_raw.argtypes = [V, V, V]
         L.tpc_get_rows.argtypes = [V, V, V]
         L.tpc_get_tracklet_counts.argtypes = [V, P(C.c_int32), P(C.c_int64)]
@@ -151,7 +152,7 @@ def lib():
 
 EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_ctx_destroy",
             "tpc_set_stream", "tpc_set_mode", "tpc_set_tuning", "tpc_last_error",
-            "tpc_workspace_size", "tpc_bind_workspace", "tpc_grid_build", "tpc_find_neighbours",
+            "tpc_workspace_size", "tpc_bind_workspace", "tpc_grid_build", "tpc_find_neighbours", "tpc_counts",
             "tpc_construct_tracklets", "tpc_select_tracks", "tpc_fit_merge", "tpc_run", "tpc_sync",
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
@@ -315,6 +316,13 @@ class Tracker:
 
     def tpc_sync(self):
         self._check(lib().tpc_sync(self.ctx), "tpc_sync")
+
+    def tpc_counts(self, dst):
+        """Enqueues the copy of the last run's six counters (status bits, tracklets,
+        selected tracks and hits, output tracks and hits) into `dst` (int32 tensor of 6,
+        device or pinned host)."""
+        assert dst.dtype == self.torch.int32 and dst.numel() >= 6 and dst.is_contiguous()
+        self._check(lib().tpc_counts(self.ctx, _ptr(dst)), "tpc_counts")
 
     # ---- track-model compression of the current clusters against the current tracks
     def tpc_compress(self, q_y: float = Q_STEP, q_z: float = Q_STEP, cap: int | None = None) -> dict:

@@ -234,36 +234,45 @@ def test_autotune_candidates_are_bit_identical():
 
 
 def test_serving_chunk_alone_equals_chunk_in_mix():
-    """A chunk's tracks are the same when it is tracked alone and when it shares a batch."""
+    """Each chunk's full result from the concurrent Server (three slots busy at once,
+    batches of up to two chunks, results copied back from overlapping streams) equals
+    the same chunk tracked alone, bit for bit: hit lists, parameters, covariance,
+    x_ref, chi2, ndf and sector."""
     import torch
 
-    from paper_2402_01205_amd.serve import Pool, Server, assemble, make_stream, plan_chunk
+    from paper_2402_01205_amd.serve import Pool, Server, assemble, make_stream
     from paper_2402_01205_amd.tpc import Tracker
     cols = g.gen_collision_pool(61, 8, mult_range=(100, 400))
     pool = Pool.from_collisions(cols)
-    chunks = [plan_chunk(pool, c) for c in make_stream(8, 5, coll_range=(2, 6), seed=62)]
-    s = torch.cuda.current_stream()
+    got = {}
 
-    def tracks_of(batch, which):
-        ev = assemble(pool, batch, s)
-        tr = Tracker(0, mode="batched")
+    def keep(cid, res):
+        got[cid] = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in res.items()}
+
+    srv = Server(pool, 0, n_slots=3, max_batch=2)
+    chunks = make_stream(8, 14, rate_hz=1e5, coll_range=(2, 6), seed=63)
+    res = srv.run(chunks, realtime=True, on_result=keep)
+    say("server", {k: v for k, v in res.items() if k not in ("tracks", "latencies")})
+    assert res["n_chunks"] == 14 and res["p99_ms"] >= res["p50_ms"] > 0 and res["errors"] == 0
+    assert res["max_concurrent"] == 3 and res["batches"] < 14      # overlap and shared batches
+    assert sorted(got) == list(range(14))
+    s = torch.cuda.current_stream()
+    tr = Tracker(0, mode="batched")
+    n_cmp = 0
+    for ch in chunks:
+        ev = assemble(pool, [ch], s)
         tr.run(ev)
         t = tr.tracks()
-        jo = ev.job_off_host
-        sel = np.nonzero(t["job"] == which)[0]
-        hits = [t["hits"][t["off"][i]:t["off"][i + 1]] - jo[which] for i in sel]
-        return hits, t["param"][sel]
-
-    for i in (0, 2, 4):
-        alone_h, alone_p = tracks_of([chunks[i]], 0)
-        mix_h, mix_p = tracks_of(chunks, i)
-        assert len(alone_h) == len(mix_h) > 0
-        assert all(np.array_equal(a, b) for a, b in zip(alone_h, mix_h))
-        assert np.array_equal(alone_p.view(np.uint32), mix_p.view(np.uint32))
-    # and the scheduler serves every chunk
-    srv = Server(pool, 0, n_slots=2)
-    res = srv.run(make_stream(8, 12, rate_hz=200.0, coll_range=(2, 6), seed=63), realtime=False)
-    assert res["n_chunks"] == 12 and res["p99_ms"] >= res["p50_ms"] > 0
+        m = got[ch.cid]
+        assert m["status"] == 0 and m["n_tracks"] == t["n"] > 0, ch.cid
+        assert np.array_equal(m["hit_off"], t["off"]), ch.cid
+        assert np.array_equal(m["hits"], t["hits"]), ch.cid
+        for k, tk in (("param", "param"), ("cov", "cov"), ("x_ref", "x_ref"), ("chi2", "chi2")):
+            assert np.array_equal(m[k].view(np.uint32), t[tk].view(np.uint32)), (ch.cid, k)
+        for k in ("ndf", "sector"):
+            assert np.array_equal(m[k], t[k]), (ch.cid, k)
+        n_cmp += t["n"]
+    say("tracks compared", n_cmp)
 
 
 def test_output_capacity_reports_required_sizes_and_truncates():

@@ -371,3 +371,37 @@ def make_config(cfg: str, seed: int, *, workers: int = 0, n_jobs: int = 512,
 
 def default_workers() -> int:
     return max(1, min(16, os.cpu_count() or 1))
+
+
+# --------------------------------------------------------------------------------------
+# Inputs with exact ties (test inputs for the method's index tie-breaks)
+# --------------------------------------------------------------------------------------
+
+def with_exact_ties(cs: ClusterSet, q: float, dup_frac: float, seed: int) -> ClusterSet:
+    """A copy of ``cs`` whose y and z are rounded to multiples of ``q`` (a power of two,
+    so the lattice values are exact in FP32; 1/32 cm is the decoded compression step)
+    and in which a fraction ``dup_frac`` of the clusters of every job appears twice with
+    identical coordinates.  Each job's clusters are shuffled afterwards, so a duplicate
+    is as likely to come before its original as after it.  Returns the new set; its
+    ``meta["dup_group"]`` holds, per cluster, the index of the group of identical
+    clusters it belongs to (int64, every cluster in exactly one group)."""
+    assert q > 0 and math.log2(q) == round(math.log2(q))
+    rng = np.random.default_rng(seed)
+    parts, groups, base = [], [], 0
+    for j in range(cs.n_jobs):
+        s = cs.job(j)
+        n = s.n
+        k = int(round(dup_frac * n))
+        src = np.concatenate([np.arange(n), rng.choice(n, k, replace=False)]) if n else np.arange(0)
+        p = rng.permutation(len(src))
+        src = src[p]
+        y = (np.rint(s.y.astype(np.float64) / q) * q).astype(np.float32)
+        z = (np.rint(s.z.astype(np.float64) / q) * q).astype(np.float32)
+        parts.append(ClusterSet(s.sector[src], s.row[src], y[src], z[src], s.time[src], s.label[src],
+                                np.array([0, len(src)], np.int32), s.part_pt, s.part_eta, s.part_phi,
+                                s.part_q, np.array([0, len(s.part_pt)], np.int64), {}))
+        groups.append(src.astype(np.int64) + base)
+        base += n
+    out = concat(parts, dict(cs.meta, ties=dict(q=q, dup_frac=dup_frac, seed=seed)))
+    out.meta["dup_group"] = np.concatenate(groups) if groups else np.zeros(0, np.int64)
+    return out
