@@ -264,7 +264,7 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
         tr.run(ev)
         t = tr.tracks()
         m = got[ch.cid]
-        assert m["status"] == 0 and m["n_tracks"] == t["n"] > 0, ch.cid
+        assert m["status"] == 0 and m["n_tracks"] == t["n"], ch.cid
         assert np.array_equal(m["hit_off"], t["off"]), ch.cid
         assert np.array_equal(m["hits"], t["hits"]), ch.cid
         for k, tk in (("param", "param"), ("cov", "cov"), ("x_ref", "x_ref"), ("chi2", "chi2")):
@@ -273,6 +273,7 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
             assert np.array_equal(m[k], t[k]), (ch.cid, k)
         n_cmp += t["n"]
     say("tracks compared", n_cmp)
+    assert n_cmp > 100
 
 
 def test_output_capacity_reports_required_sizes_and_truncates():
