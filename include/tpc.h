@@ -279,6 +279,22 @@ int64_t tpc_rans_lanes(int64_t n);
 int tpc_rans_encode(tpc_ctx* ctx, const uint16_t* sym, int32_t n, tpc_rans* out);
 int tpc_rans_decode(tpc_ctx* ctx, const tpc_rans* in, int32_t n, uint16_t* sym);
 
+/* tpc_rans_encode for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same model, lanes and words as tpc_rans_encode, bit for bit, but every
+ * intermediate buffer lives in a fixed device array of the library (10 MiB per
+ * device, held until the process ends) instead of the context's workspace, so
+ * it needs no tracking run and calls no hipMalloc, hipFree or allocating
+ * library routine.  The caller still passes the stream and the outputs.
+ * n > TPC_RANS_STATIC_MAX_SYMBOLS: TPC_E_ARG, nothing enqueued.  Capacity:
+ * as tpc_rans_encode (*n_words holds the words needed; TPC_E_CAPACITY at the
+ * context's next tpc_sync).  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams or contexts) race and give
+ * wrong results; serialise them.  TPC_E_HIP if the array's device address
+ * could not be obtained when the context was created.                     */
+#define TPC_RANS_STATIC_MAX_SYMBOLS 4194304
+int tpc_rans_encode_static(tpc_ctx* ctx, const uint16_t* sym, int32_t n, tpc_rans* out);
+
 /* Cluster finding (section 5: the TPC clusters are found on the GPUs from the
  * zero-suppressed digits, ahead of the tracking).  Pad plane: row r holds
  * P_r = 2 ceil(x_r tan 10 deg / pad_pitch) pads (x_r = 85 + r 160/151 cm, in

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2588,6 +2589,7 @@ struct tpc_ctx {
   int32_t* pinned = nullptr;  // host-pinned counters for tpc_sync
   bool lds_count_ok = false;  // the device grants the LDS of k_grid_count_lds
   bool lds_hist_ok = false;   // ... and the 128 KiB of k_rans_hist_lds
+  bool static_pending = false;  // tpc_rans_encode_static ran since the last tpc_sync
   void* cf_clean_ws = nullptr;  // cluster-finding workspace whose charge map this context left zero
   int64_t cf_clean_cells = 0;
   // graph cache (batched modes): the chain is captured once per set of buffers
@@ -2692,14 +2694,16 @@ void fill_i32(tpc_ctx* c, int32_t* p, int64_t n, int32_t v) {
 
 // exclusive scan over [lo, hi) (bound <= host upper bound of hi-lo)
 // base_from_out: continue from the total a previous scan left in out[lo]
+// bsum: block sums, (bound / kScanTile + 1) entries (nullptr: the workspace's)
 template <typename T>
-void scan(tpc_ctx* c, const T* in, int32_t* out, Bound lo, Bound hi, int64_t bound, bool base_from_out) {
-  Layout& L = c->L;
+void scan(tpc_ctx* c, const T* in, int32_t* out, Bound lo, Bound hi, int64_t bound, bool base_from_out,
+          int32_t* bsum = nullptr) {
+  if (!bsum) bsum = c->L.bsum;
   const int nb = (int)std::max<int64_t>(1, (bound + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, lo, hi, L.bsum);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c->stream, L.bsum, lo, hi,
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, lo, hi, bsum);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c->stream, bsum, lo, hi,
                      (int32_t)base_from_out, out);
-  hipLaunchKernelGGL(k_scan_apply<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, lo, hi, L.bsum);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, lo, hi, bsum);
 }
 
 In make_in(tpc_ctx* c) {
@@ -2905,6 +2909,10 @@ static bool params_ok(const tpc_params& p) {
 // the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))
 static thread_local char g_create_err[256] = "null context";
 
+namespace {
+void scratch_setup(int device);
+}
+
 int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p) {
   if (!out) return TPC_E_ARG;
   if (p && !params_ok(*p)) return TPC_E_ARG;
@@ -2936,6 +2944,7 @@ int tpc_ctx_create(tpc_ctx** out, int device, void* stream, const tpc_params* p)
                                            need_h) == hipSuccess;
     (void)hipGetLastError();
   }
+  scratch_setup(device);
   *out = c;
   return TPC_OK;
 }
@@ -3259,17 +3268,30 @@ int tpc_profile_read(tpc_ctx* c, double* ms, int32_t* launches, int32_t n, int32
   return TPC_OK;
 }
 
+namespace {
+int32_t* scratch_status(int device);
+}
+
 int tpc_sync(tpc_ctx* c) {
   if (!c) return TPC_E_ARG;
   HIPCHK(c, hipSetDevice(c->device));
+  c->pinned[kNumCounters] = 0;
+  if (c->static_pending) {
+    // status of the last tpc_rans_encode_static on this device (the scratch's status word)
+    c->static_pending = false;
+    if (int32_t* s = scratch_status(c->device))
+      HIPCHK(c, hipMemcpyAsync(c->pinned + kNumCounters, s, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  }
   if (!c->laid_out) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int32_t st = c->pinned[kNumCounters];
+    if (st & kStatusCapacity) return fail(c, TPC_E_CAPACITY, "capacity exceeded");
     return TPC_OK;
   }
   HIPCHK(c, hipMemcpyAsync(c->pinned, c->L.counters, kNumCounters * sizeof(int32_t), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  const int32_t st = c->pinned[kCntStatus];
+  const int32_t st = c->pinned[kCntStatus] | c->pinned[kNumCounters];
   if (st & kStatusCapacity) return fail(c, TPC_E_CAPACITY, "capacity exceeded");
   if (st & kStatusRange) return fail(c, TPC_E_RANGE, "cluster with sector/row out of range or non-finite y/z");
   return TPC_OK;
@@ -3500,6 +3522,122 @@ int tpc_rans_decode(tpc_ctx* c, const tpc_rans* in, int32_t n, uint16_t* sym) {
                        in->lane_off, in->words, in->cap_words, n, lanes, sym, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+// ---- rANS encoding without allocation
+// A file-scope device array holds everything the encoder needs beyond its inputs and
+// outputs, for streams of up to TPC_RANS_STATIC_MAX_SYMBOLS symbols.  Each device has its
+// own copy; host code never uses the array's name as an address, only the pointer that
+// hipGetSymbolAddress returned on that device (the name is a host-side stand-in).
+constexpr size_t kStaticScratchBytes = size_t(10) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Once per device, with the device current (called from tpc_ctx_create).
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* ptr = nullptr;
+  g_scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (g_scratch_err[device] == hipSuccess) g_scratch[device] = ptr;
+  (void)hipGetLastError();
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch[device];
+}
+
+struct StaticRans {
+  uint32_t* cnt;
+  uint32_t* cum;
+  uint64_t* t64;
+  int32_t* len;
+  uint16_t* buf;
+  int32_t* bsum;
+  int32_t* counters;
+};
+constexpr int64_t kStaticLanes = (TPC_RANS_STATIC_MAX_SYMBOLS / (kRansLanesPerChunk * kRansLaneSymbols)) *
+                                 kRansLanesPerChunk;
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kStaticCntOff = 0;
+constexpr size_t kStaticCumOff = kStaticCntOff + al256(kRansM * 4);
+constexpr size_t kStaticT64Off = kStaticCumOff + al256((kRansM + 1) * 4);
+constexpr size_t kStaticLenOff = kStaticT64Off + al256(kRansM * 8);
+constexpr size_t kStaticBufOff = kStaticLenOff + al256((kStaticLanes + 1) * 4);
+constexpr size_t kStaticBsumOff = kStaticBufOff + al256(kStaticLanes * (kRansLaneSymbols + 2) * 2);
+constexpr size_t kStaticCntrOff = kStaticBsumOff + al256((kStaticLanes / kScanTile + 4) * 4);
+constexpr size_t kStaticEnd = kStaticCntrOff + al256(kNumCounters * 4);
+static_assert(TPC_RANS_STATIC_MAX_SYMBOLS % (kRansLanesPerChunk * kRansLaneSymbols) == 0,
+              "the limit is a whole number of chunks");
+static_assert(kStaticEnd <= kStaticScratchBytes, "the encoder's scratch fits the static array");
+
+StaticRans static_rans(void* base) {
+  char* b = static_cast<char*>(base);
+  return StaticRans{reinterpret_cast<uint32_t*>(b + kStaticCntOff), reinterpret_cast<uint32_t*>(b + kStaticCumOff),
+                    reinterpret_cast<uint64_t*>(b + kStaticT64Off), reinterpret_cast<int32_t*>(b + kStaticLenOff),
+                    reinterpret_cast<uint16_t*>(b + kStaticBufOff), reinterpret_cast<int32_t*>(b + kStaticBsumOff),
+                    reinterpret_cast<int32_t*>(b + kStaticCntrOff)};
+}
+
+int32_t* scratch_status(int device) {
+  void* p = scratch_ptr(device);
+  return p ? static_rans(p).counters + kCntStatus : nullptr;
+}
+}  // namespace
+
+int tpc_rans_encode_static(tpc_ctx* c, const uint16_t* sym, int32_t n, tpc_rans* out) {
+  if (!c) return TPC_E_ARG;
+  if (!out || n < 0 || (n > 0 && !sym) || out->cap_words < 0 || !out->n_words || !out->freq || !out->lane_off ||
+      (out->cap_words > 0 && !out->words))
+    return fail(c, TPC_E_ARG, "tpc_rans_encode_static: null or negative argument");
+  if (reinterpret_cast<uintptr_t>(out->freq) % 16)
+    return fail(c, TPC_E_ARG, "tpc_rans_encode_static: freq must be 16-byte aligned");
+  if ((int64_t)n > TPC_RANS_STATIC_MAX_SYMBOLS)
+    return fail(c, TPC_E_ARG, "tpc_rans_encode_static: n exceeds TPC_RANS_STATIC_MAX_SYMBOLS (4194304)");
+  void* base = scratch_ptr(c->device);
+  if (!base) {
+    const hipError_t e = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_err[c->device] : hipErrorInvalidDevice;
+    c->err = std::string("tpc_rans_encode_static: no scratch address on this device: ") + hipGetErrorString(e);
+    return TPC_E_HIP;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  const StaticRans S = static_rans(base);
+  const int64_t lanes = rans_lanes(n);
+  // the scratch keeps the last call's contents: clear the counts and the status word
+  fill_i32(c, reinterpret_cast<int32_t*>(S.cnt), kRansM, 0);
+  fill_i32(c, S.counters, kNumCounters, 0);
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (n > 0 && c->lds_hist_ok)
+    hipLaunchKernelGGL(k_rans_hist_lds, dim3(std::min(blocks_for(n, 1024), ncu)), dim3(1024),
+                       kRansHalf * sizeof(uint32_t), c->stream, sym, n, S.cnt);
+  else if (n > 0)
+    hipLaunchKernelGGL(k_rans_hist, dim3(std::min(blocks_for(n, 256), ncu * 4)), dim3(256), 0, c->stream, sym, n,
+                       S.cnt);
+  hipLaunchKernelGGL(k_rans_model, dim3(1), dim3(1024), 0, c->stream, S.cnt, n, out->freq, S.cum, S.t64);
+  if (lanes > 0) {
+    hipLaunchKernelGGL(k_rans_enc, dim3(blocks_for(lanes, 256)), dim3(256), 0, c->stream, sym, n, lanes, S.t64,
+                       S.buf, S.len);
+    scan(c, S.len, reinterpret_cast<int32_t*>(out->lane_off), Bound{nullptr, 0, INT32_MAX},
+         Bound{nullptr, (int32_t)lanes, INT32_MAX}, lanes, false, S.bsum);
+  } else {
+    fill_i32(c, reinterpret_cast<int32_t*>(out->lane_off), 1, 0);
+  }
+  hipLaunchKernelGGL(k_rans_copy, dim3(std::max(1, wave_grid(c, lanes))), dim3(256), 0, c->stream, S.buf, S.len,
+                     out->lane_off, lanes, out->words, out->cap_words, out->n_words, S.counters);
+  HIPCHK(c, hipGetLastError());
+  c->static_pending = true;
   return TPC_OK;
 }
 

@@ -146,6 +146,7 @@ def lib():
         L.tpc_rans_lanes.restype = C.c_int64
         L.tpc_rans_encode.argtypes = [V, V, C.c_int32, P(tpc_rans)]
         L.tpc_rans_decode.argtypes = [V, P(tpc_rans), C.c_int32, V]
+        L.tpc_rans_encode_static.argtypes = [V, V, C.c_int32, P(tpc_rans)]
         _lib = L
     return _lib
 
@@ -157,7 +158,8 @@ EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_c
             "tpc_get_links_raw", "tpc_get_rows", "tpc_get_tracklet_counts", "tpc_get_tracklets",
             "tpc_get_selected_counts", "tpc_get_selected", "tpc_debug_propagate", "tpc_debug_update",
             "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress",
-            "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode", "tpc_cf_params_default",
+            "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode", "tpc_rans_encode_static",
+            "tpc_cf_params_default",
             "tpc_cf_workspace_size", "tpc_find_clusters"]
 PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress",
               "rans_encode", "rans_decode", "find_clusters"]
@@ -378,6 +380,31 @@ class Tracker:
                    words=torch.zeros(max(cap, 1), dtype=torch.int16, device=dev))
         enc["_s"] = tpc_rans(cap, *[_ptr(enc[k]) for k in ("n_words", "freq", "lane_off", "words")])
         self._check(lib().tpc_rans_encode(self.ctx, _ptr(sym), n, C.byref(enc["_s"])), "tpc_rans_encode")
+        return enc
+
+    def rans_outputs(self, n: int, cap_words: int | None = None) -> dict:
+        """Device output buffers of a coded stream of n symbols (words for the worst case
+        unless cap_words is given)."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        lanes = int(lib().tpc_rans_lanes(n))
+        cap = n + 2 * lanes if cap_words is None else cap_words
+        enc = dict(n=n, cap_words=cap, n_words=torch.zeros(1, dtype=torch.int32, device=dev),
+                   freq=torch.zeros(1 << 16, dtype=torch.int32, device=dev),
+                   lane_off=torch.zeros(lanes + 1, dtype=torch.int32, device=dev),
+                   words=torch.zeros(max(cap, 1), dtype=torch.int16, device=dev))
+        enc["_s"] = tpc_rans(cap, *[_ptr(enc[k]) for k in ("n_words", "freq", "lane_off", "words")])
+        return enc
+
+    def tpc_rans_encode_static(self, sym, enc: dict) -> dict:
+        """Enqueues tpc_rans_encode_static of `sym` (device tensor of 2-byte elements) into the
+        caller's buffers `enc` (from rans_outputs, for at least sym.numel() symbols)."""
+        n = int(sym.numel())
+        if int(lib().tpc_rans_lanes(n)) + 1 > enc["lane_off"].numel():
+            raise ValueError("lane offset buffer too small for the stream")
+        enc["n"] = n
+        self._check(lib().tpc_rans_encode_static(self.ctx, _ptr(sym), n, C.byref(enc["_s"])),
+                    "tpc_rans_encode_static")
         return enc
 
     def tpc_rans_decode(self, enc: dict, out=None):
