@@ -34,15 +34,14 @@ WORKLOADS = {
     "c4": "batched form: 512 single-sector jobs, 100-20000 primaries each (log-uniform)",
 }
 SEEDS = {"c1": 11, "c2": 21, "c3": 31, "c4": 41}
-# Algorithmic bytes (unique bytes each kernel must move):
-#  neighbour kernel: per cluster y, z (8) + slot (4) + input index for tie-breaks (4)
-#                    + cell offsets (~2) + two links out (8) = 26 B
-#  tracklet kernel : per tracklet hit: next link (4) + y, z (8) + slot (4) + hit write (4)
-#                    + 64-bit weight read-modify-write (16) = 36 B; per tracklet: start (4)
-#                    + state write (21 x 4) = 88 B
-LINK_BYTES_PER_CLUSTER = 26
-TRK_BYTES_PER_HIT = 36
-TRK_BYTES_PER_TRACKLET = 88
+# Algorithmic bytes (unique bytes each kernel must move), as the method's plan prices them:
+#  neighbour kernel: per cluster y, z (8) + cell offsets (2) + raw up/down links written (8)
+#                    = 18 B
+#  tracklet kernel : per tracklet hit: next link (4) + y, z (8) + hit written (4) + hit-weight
+#                    read-modify-write (16) = 32 B; per tracklet: state written = 80 B
+LINK_BYTES_PER_CLUSTER = 18
+TRK_BYTES_PER_HIT = 32
+TRK_BYTES_PER_TRACKLET = 80
 #  compression     : per cluster: sector, row, y, z read (11) + record written (6); per track
 #                    hit: its cluster index (4); per track: hit offset, state, x_ref, sector,
 #                    ndf (36)
@@ -92,53 +91,108 @@ def traffic_record(kernel: str, workload: str):
     return None
 
 
-def _oracle_job(args):
-    """One job of the sample through the oracle (in a worker process)."""
+def host_cpu() -> dict:
+    """The host the oracle runs on: logical CPUs, the CPUs this process may use, model, clock."""
+    info = {"nproc": os.cpu_count(), "cpus_available": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and "model" not in info:
+                    info["model"] = v.strip()
+                elif k == "cpu MHz" and "mhz" not in info:
+                    info["mhz"] = float(v)
+    except OSError:
+        pass
+    return info
+
+
+def c4_sample_jobs(cs):
+    """Every 16th job plus the largest one."""
+    jobs = list(range(0, cs.n_jobs, 16))
+    big = int(np.argmax(np.diff(cs.job_off)))
+    return sorted(set(jobs) | {big})
+
+
+def _oracle_job(sub):
+    """One job of a sample through the oracle (in a worker process): (tracks, seconds)."""
     import oracle.oracle as O
-    sub = args
+    t0 = time.perf_counter()
     r = O.Run.from_set(sub)
-    return len(r.tracks()["tracklet"])
+    return len(r.tracks()["tracklet"]), time.perf_counter() - t0
 
 
-def cpu_baseline_parallel(cs, workers):
-    """The same oracle on the same sample, one job per worker process (jobs are independent).
-    Run before any GPU use, so the pool may fork."""
+def cpu_parallel(subs, workers, desc):
+    """The oracle over independent jobs, one job per worker process.  Run before any GPU use,
+    so the pool may fork."""
     import multiprocessing as mp
-    if cs.n_jobs <= 1:
-        return None
-    jobs = list(range(0, cs.n_jobs, 32))
-    subs = [cs.job(j) for j in jobs]
     n = sum(s.n for s in subs)
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        ntr = sum(pool.map(_oracle_job, subs, chunksize=1))
+        res = pool.map(_oracle_job, sorted(subs, key=lambda s: -s.n), chunksize=1)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "clusters/s", "cores": workers, "kind": "oracle",
-            "sample": f"the same {len(jobs)} jobs ({n} clusters), one job per process; {ntr} tracks; {dt:.1f} s"}
+            "sample": f"{desc} ({n} clusters), one job per process; {sum(r[0] for r in res)} tracks; "
+                      f"{dt:.1f} s wall, {sum(r[1] for r in res):.1f} s summed over the processes"}
 
 
-def cpu_baseline(cs, cfg, budget_s):
-    """The oracle (single thread, as it stands) on a bounded sample of the same workload."""
+def cpu_single(cs, desc):
+    """The oracle (single thread, as it stands) on one cluster set: rate, FP64 refit share."""
     import oracle.oracle as O
-    import tpcsynth as g
-    if cs.n_jobs > 1:
-        jobs = list(range(0, cs.n_jobs, 32))
-        sample = cs.subset_jobs(jobs)
-        desc = f"jobs {jobs[0]}..{jobs[-1]} step 32 ({len(jobs)} of {cs.n_jobs} sector-jobs, {sample.n} clusters)"
-    else:
-        sample = cs
-        desc = f"whole event ({cs.n} clusters)"
     t0 = time.perf_counter()
-    r = O.Run.from_set(sample)
+    r = O.Run.from_set(cs)
     dt = time.perf_counter() - t0
+    ntr = len(r.tracks()["tracklet"])
+    f64 = r.fp64_seconds
+    return r, {"value": cs.n / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle", "seconds": dt,
+               "fp64_refit_seconds": f64, "without_fp64_refit": cs.n / max(dt - f64, 1e-9),
+               "sample": f"{desc} ({cs.n} clusters); {ntr} tracks; {dt:.1f} s single-threaded, "
+                         f"of which {f64:.2f} s FP64 refit"}
+
+
+def cpu_baseline(cs, others, workers):
+    """The oracle on the host: the headline workload's sample on one core (every 16th job plus
+    the largest, with the rate extrapolated to all jobs by cluster count), the smaller
+    workloads in full on one core, and the same samples over `workers` processes."""
+    import tpcsynth as g
+    host = host_cpu()
+    if cs.n_jobs > 1:
+        jobs = c4_sample_jobs(cs)
+        sample = cs.subset_jobs(jobs)
+        desc = f"jobs 0..{cs.n_jobs - 1} step 16 plus the largest ({len(jobs)} of {cs.n_jobs} sector-jobs)"
+    else:
+        jobs, sample, desc = [0], cs, "whole workload"
+    r, out = cpu_single(sample, desc)
+    out["host"] = host
+    if cs.n_jobs > 1:
+        out["extrapolated"] = True
+        out["extrapolation"] = ("cluster-weighted: the sample's clusters/s applied to all "
+                                f"{cs.n} clusters ({cs.n / out['value']:.0f} s estimated for the whole workload)")
+    full = {}
+    for name, ocs in [("c1", g.make_config("c1", 11))] + [(k, v) for k, v in others.items() if k == "c2"]:
+        _, full[name] = cpu_single(ocs, f"{name} in full")
+        log(f"cpu baseline {name} (1 core): {full[name]['value']:.3e} clusters/s")
+    out["full_runs"] = full
+    par = {}
+    if cs.n_jobs > 1:
+        par[cs.meta.get("workload", "main")] = cpu_parallel([cs.job(j) for j in jobs], workers, "the same sample")
+    if "c3" in others:
+        split, _, _ = g.split_by_sector(others["c3"])
+        par["c3"] = cpu_parallel([split.job(j) for j in range(split.n_jobs)], workers,
+                                 "c3 in full as 36 sector jobs (no merge across sectors in this leg)")
+    for k, v in par.items():
+        v["host"] = host
+        v["note"] = f"{workers} worker processes: this GPU's share of the host's CPUs"
+        log(f"cpu baseline {k} ({workers} processes): {v['value']:.3e} clusters/s")
+    return r, sample, out, par
+
+
+def cpu_chain_baseline(r, sample):
+    """The compression and rANS oracles on the sample, against its own oracle tracks."""
+    import oracle.oracle as O
     t = r.tracks()
-    ntr = len(t["tracklet"])
-    if dt > budget_s * 3:
-        log(f"cpu baseline took {dt:.1f}s (budget {budget_s}s)")
-    out = {"value": sample.n / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-           "sample": desc + f"; {ntr} tracks; {dt:.1f} s single-threaded incl. FP64 refit"}
-    # the compression and rANS rows' oracles on the same sample, against its own tracks
     t0 = time.perf_counter()
     c = O.compress(sample.sector, sample.row, sample.y, sample.z, t, Q_STEP, Q_STEP)
     dc = time.perf_counter() - t0
@@ -156,14 +210,14 @@ def cpu_baseline(cs, cfg, budget_s):
         O.rans_decode(e, len(v))
     dr = time.perf_counter() - t0
     nsym = sum(len(v) for v in streams)
-    out["compression"] = {"value": sample.n / dc, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-                          "decompress_clusters_per_s": sample.n / dd,
-                          "sample": f"the same sample and its oracle tracks; {dc:.2f} s encode, {dd:.2f} s decode"}
-    out["rans"] = {"value": nsym / de, "unit": "symbols/s", "cores": 1, "kind": "oracle",
-                   "decode_symbols_per_s": nsym / dr,
-                   "sample": f"the six record streams of that sample ({nsym} symbols); {de:.2f} s encode, "
-                             f"{dr:.2f} s decode"}
-    return out
+    comp = {"value": sample.n / dc, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "decompress_clusters_per_s": sample.n / dd,
+            "sample": f"the same sample and its oracle tracks; {dc:.2f} s encode, {dd:.2f} s decode"}
+    rans = {"value": nsym / de, "unit": "symbols/s", "cores": 1, "kind": "oracle",
+            "decode_symbols_per_s": nsym / dr,
+            "sample": f"the six record streams of that sample ({nsym} symbols); {de:.2f} s encode, "
+                      f"{dr:.2f} s decode"}
+    return comp, rans
 
 
 def copy_probe(tr, torch, mib, reps):
@@ -362,6 +416,31 @@ def rans_run(tr, H, n, steps):
             "streams": per}
 
 
+def kernel_rows(prof, n, T, H):
+    """Time, algorithmic bytes and GB/s of the two hot kernels from a profiled pass."""
+    ms = lambda k: prof[k][0] / max(1, prof[k][1])
+    lb = LINK_BYTES_PER_CLUSTER * n
+    tb = TRK_BYTES_PER_HIT * H + TRK_BYTES_PER_TRACKLET * T
+    return {"k_links": dict(ms=ms("k_links"), bytes=lb, gbs=lb / ms("k_links") / 1e6),
+            "k_tracklets": dict(ms=ms("k_tracklets"), bytes=tb, gbs=tb / ms("k_tracklets") / 1e6,
+                                tracklets=int(T), tracklet_hits=int(H))}
+
+
+def kernel_json(kern):
+    return {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS, "algorithmic_bytes": v["bytes"],
+                **({"tracklets": v["tracklets"], "tracklet_hits": v["tracklet_hits"]} if "tracklets" in v else {})}
+            for k, v in kern.items()}
+
+
+def same_tracks(a, b, perm=None):
+    """Two track outputs hold the same tracks (as sets of hit lists); perm maps b's cluster
+    indices to a's."""
+    def lists(t, p):
+        off, hits = t["off"], t["hits"] if p is None else p[t["hits"]]
+        return sorted(tuple(hits[off[i]:off[i + 1]].tolist()) for i in range(int(t["n"])))
+    return int(a["n"]) == int(b["n"]) and lists(a, None) == lists(b, perm)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,7 +452,6 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the batched path only (for rocprofv3)")
@@ -408,15 +486,18 @@ def main():
     cs = g.make_config(args.config, seed, workers=args.workers)  # before any GPU use
     log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
         f"in {time.perf_counter() - t0:.1f}s")
+    others = {}
+    if not args.profile_only:
+        for name in [x for x in args.also.split(",") if x and x != args.config]:
+            others[name] = g.make_config(name, SEEDS[name], workers=args.workers)
+            log(f"generated {name}: {others[name].n} clusters")
     # the oracle baselines first, before any GPU use
-    cpu = cpu_par = None
+    cpu = cpu_par = cpu_chain = None
     if not args.no_cpu and not args.profile_only:
-        cpu = cpu_baseline(cs, args.config, args.cpu_budget)
-        cpu["cores"] = 1
+        r_cpu, sample, cpu, cpu_par = cpu_baseline(cs, others, args.workers)
         log(f"cpu baseline (1 core): {cpu['value']:.3e} clusters/s")
-        cpu_par = cpu_baseline_parallel(cs, min(args.workers, os.cpu_count() or 1))
-        if cpu_par:
-            log(f"cpu baseline ({cpu_par['cores']} processes): {cpu_par['value']:.3e} clusters/s")
+        cpu_chain = cpu_chain_baseline(r_cpu, sample)
+        del r_cpu, sample
     dg = None
     if args.cf_config:
         from tpcsynth import digits as D
@@ -427,11 +508,6 @@ def main():
                    "d3": "8 full-TPC events at uniform times over two drift lengths (1000 time bins)"}[args.cf_config]
         log(f"digits {args.cf_config}: {dg.n} in {time.perf_counter() - t0:.1f}s")
     cf_cpu = cf_cpu_baseline(dg) if (dg is not None and not args.no_cpu and not args.profile_only) else None
-    others = {}
-    if not args.profile_only:
-        for name in [x for x in args.also.split(",") if x and x != args.config]:
-            others[name] = g.make_config(name, SEEDS[name], workers=args.workers)
-            log(f"generated {name}: {others[name].n} clusters")
 
     import torch
 
@@ -506,15 +582,7 @@ def main():
     prof = tr.profile_read(reset=True)
     tr.profile(False)
     T, H = tr.tracklet_counts()
-    n_valid = cs.n
-    kl_ms = prof["k_links"][0] / max(1, prof["k_links"][1])
-    kt_ms = prof["k_tracklets"][0] / max(1, prof["k_tracklets"][1])
-    link_bytes = LINK_BYTES_PER_CLUSTER * n_valid
-    trk_bytes = TRK_BYTES_PER_HIT * H + TRK_BYTES_PER_TRACKLET * T
-    kern = {
-        "k_links": dict(ms=kl_ms, bytes=link_bytes, gbs=link_bytes / kl_ms / 1e6),
-        "k_tracklets": dict(ms=kt_ms, bytes=trk_bytes, gbs=trk_bytes / kt_ms / 1e6),
-    }
+    kern = kernel_rows(prof, cs.n, T, H)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     trec = traffic_record(dom, args.config)
     traffic = None
@@ -545,26 +613,51 @@ def main():
     q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off, cs.part_pt)
     log("quality: " + json.dumps(q))
     also = {}
-    for name, ocs in others.items():
-        oev = DeviceClusters.from_set(ocs, dev)
-        otr = Tracker(0, mode=args.mode, tuning=tuning)
-        otr.run(oev)
-        otr.sync()
+    def time_run(tracker, dev_set, steps):
+        tracker.run(dev_set)
+        tracker.sync()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
-            otr.run(oev)
+        for _ in range(steps):
+            tracker.run(dev_set)
         e1.record()
         torch.cuda.synchronize()
-        oms = e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / steps
+
+    for name, ocs in others.items():
+        oev = DeviceClusters.from_set(ocs, dev)
+        otr = Tracker(0, mode=args.mode, tuning=tuning)
+        oms = time_run(otr, oev, args.steps)
         ot = otr.tracks()
+        otr.profile(True)
+        otr.profile_read(reset=True)
+        for _ in range(args.steps):
+            otr.run(oev)
+        oprof = otr.profile_read(reset=True)
+        otr.profile(False)
+        oT, oH = otr.tracklet_counts()
         oq = quality(ocs.label, ocs.job_off, ocs.sector, ot["off"], ot["hits"], ocs.part_off, ocs.part_pt)
         also[name] = {"workload": WORKLOADS[name], "n_clusters": ocs.n, "ms_per_step": oms,
-                      "clusters_per_s": ocs.n / (oms / 1e3), "tracks": int(ot["n"]), "quality": oq}
+                      "clusters_per_s": ocs.n / (oms / 1e3), "tracks": int(ot["n"]), "quality": oq,
+                      "kernels": kernel_json(kernel_rows(oprof, ocs.n, oT, oH)),
+                      "stages_ms": {k: v[0] / max(1, v[1]) for k, v in oprof.items() if v[1]}}
         log(f"{name}: {oms:.3f} ms/step, {ocs.n / (oms / 1e3):.3e} clusters/s, quality {oq}")
         del otr, oev
+        if name == "c3" and args.plain_steps > 0:
+            # the per-sector form: every sector its own job, launched one after the other
+            split, perm, jev = g.split_by_sector(ocs)
+            sev = DeviceClusters.from_set(split, dev, jev)
+            ptr = Tracker(0, mode="plain")
+            pms = time_run(ptr, sev, args.plain_steps)
+            same = same_tracks(ot, ptr.tracks(), perm)
+            also[name].update({"plain_per_sector_ms_per_step": pms,
+                               "plain_per_sector_clusters_per_s": ocs.n / (pms / 1e3),
+                               "batched_over_plain": pms / oms, "plain_jobs": split.n_jobs,
+                               "plain_identical_tracks": same})
+            log(f"{name} plain per sector ({split.n_jobs} jobs): {pms:.3f} ms/step; identical tracks: {same}")
+            del ptr, sev
     serving = None
     if args.serve_chunks > 0:
         del tr, ev                 # the serving run sizes its admission by free HBM
@@ -593,10 +686,12 @@ def main():
         "batched_over_plain": (plain_ms / ms) if plain_ms else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_ratio": (traffic / kern[dom]["bytes"]) if traffic else None,
                      "kernel_ms": kern[dom]["ms"], "algorithmic_bytes": kern[dom]["bytes"],
+                     "bytes_per_unit": ({"cluster": LINK_BYTES_PER_CLUSTER} if dom == "k_links" else
+                                        {"tracklet_hit": TRK_BYTES_PER_HIT, "tracklet": TRK_BYTES_PER_TRACKLET}),
                      "traffic_source": trec["file"] if trec else None},
-        "kernels": {k: {"ms": v["ms"], "GB/s": v["gbs"], "frac": v["gbs"] / HBM_PEAK_GBS}
-                    for k, v in kern.items()},
+        "kernels": kernel_json(kern),
         "copy_probe_GBs": probe,
         "p50_chunk_latency_ms": serving["p50_ms"] if serving else None,
         "p99_chunk_latency_ms": serving["p99_ms"] if serving else None,
@@ -611,8 +706,7 @@ def main():
         "quality": q,
     }
     if cpu is not None:
-        compression["cpu_baseline"] = cpu.pop("compression", None)
-        compression["rans"]["cpu_baseline"] = cpu.pop("rans", None)
+        compression["cpu_baseline"], compression["rans"]["cpu_baseline"] = cpu_chain
         out["cpu_baseline"] = cpu
         out["cpu_baseline_all_cores"] = cpu_par
     print(json.dumps(out), flush=True)

@@ -70,6 +70,8 @@ def lib():
         L.orc_destroy.argtypes = [P]
         L.orc_set_brute.argtypes = [P, C.c_int32]
         L.orc_status.argtypes = [P]
+        L.orc_fp64_seconds.argtypes = [P]
+        L.orc_fp64_seconds.restype = C.c_double
         L.orc_run.argtypes = [P, C.c_int32]
         L.orc_num_slot_members.restype = C.c_int64
         L.orc_num_slot_members.argtypes = [P]
@@ -159,6 +161,11 @@ class Run:
     @property
     def status(self) -> int:
         return lib().orc_status(self.h)
+
+    @property
+    def fp64_seconds(self) -> float:
+        """Wall time the last run spent in its FP64 refits."""
+        return float(lib().orc_fp64_seconds(self.h))
 
     def rows(self):
         """(slot_off[J*36*152+1], members) with members of each slot in ascending index."""

@@ -44,6 +44,7 @@
 // information content under the model.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -401,6 +402,7 @@ struct Oracle {
   std::vector<uint64_t> hitw;
   std::vector<Track> tracks;      // selected, in tracklet-id order
   bool brute = false;             // search whole rows instead of the z-sorted range
+  double fp64_seconds = 0.0;      // wall time spent in the FP64 refits (timing only)
 
   int64_t slot(int j, int s, int r) const { return ((int64_t)j * kSectors + s) * kRows + r; }
 
@@ -670,10 +672,12 @@ struct Oracle {
       tr.ndf = -1;
       for (float& v : tr.P) v = NAN;
     }
+    const auto t0 = std::chrono::steady_clock::now();
     if (!fit<double>(tr.hits, sinit, so, hs, tr.Pd, tr.Cd, tr.xd, tr.chi2d, tr.ndfd)) {
       tr.ndfd = -1;
       for (double& v : tr.Pd) v = NAN;
     }
+    fp64_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
   // -------- O10: merge track pieces that continue into an adjacent sector (same side).
@@ -982,6 +986,8 @@ void* orc_create(int32_t n, const uint8_t* sector, const int16_t* row, const flo
 void orc_destroy(void* h) { delete (Oracle*)h; }
 void orc_set_brute(void* h, int32_t b) { ((Oracle*)h)->brute = b != 0; }
 int32_t orc_status(void* h) { return ((Oracle*)h)->status; }
+// seconds spent in the FP64 refits of the last run (fit stage, merged refits included)
+double orc_fp64_seconds(void* h) { return ((Oracle*)h)->fp64_seconds; }
 
 void orc_run(void* h, int32_t last_stage) {
   Oracle* o = (Oracle*)h;

@@ -405,3 +405,29 @@ def with_exact_ties(cs: ClusterSet, q: float, dup_frac: float, seed: int) -> Clu
     out = concat(parts, dict(cs.meta, ties=dict(q=q, dup_frac=dup_frac, seed=seed)))
     out.meta["dup_group"] = np.concatenate(groups) if groups else np.zeros(0, np.int64)
     return out
+
+
+def split_by_sector(cs: ClusterSet):
+    """Every (job, sector) of ``cs`` as a job of its own: the per-sector form of a workload.
+
+    Returns (set, perm, job_event): the clusters grouped by (job, sector), input order kept
+    inside a group; perm[i] = the index in ``cs`` of cluster i of the new set; job_event[k] =
+    the job of ``cs`` that new job k came from (the sector jobs of one job form one event).
+    Only jobs with clusters are kept.  Particles are not split (part_off keeps every
+    particle in the first sector job of its event): evaluate quality on ``cs``."""
+    n = cs.n
+    job_of = np.repeat(np.arange(cs.n_jobs, dtype=np.int64), np.diff(cs.job_off).astype(np.int64))
+    key = job_of * N_SECTORS + cs.sector.astype(np.int64)
+    perm = np.argsort(key, kind="stable")
+    ks = key[perm]
+    uniq, first = np.unique(ks, return_index=True)
+    job_off = np.concatenate([first, [n]]).astype(np.int32)
+    job_event = (uniq // N_SECTORS).astype(np.int32)
+    pcount = np.diff(cs.part_off)
+    part_off = np.zeros(len(uniq) + 1, np.int64)
+    firsts = np.concatenate([[True], job_event[1:] != job_event[:-1]]) if len(uniq) else np.zeros(0, bool)
+    part_off[1:] = np.cumsum(np.where(firsts, pcount[job_event], 0))
+    out = ClusterSet(cs.sector[perm], cs.row[perm], cs.y[perm], cs.z[perm], cs.time[perm], cs.label[perm],
+                     job_off, cs.part_pt, cs.part_eta, cs.part_phi, cs.part_q, part_off,
+                     dict(cs.meta, split="by sector"))
+    return out, perm.astype(np.int64), job_event
