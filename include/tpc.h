@@ -71,6 +71,7 @@ typedef struct {
   float merge_edge;                  /* distance to the sector edge of merge pieces, cm*/
   float chi2_merge;                  /* max 5-D chi2 of a merged pair                  */
   float merge_dz;                    /* max |z| gap between the pieces' ends, cm        */
+  float v_drift;                     /* drift velocity, cm/us (collision times)         */
 } tpc_params;
 
 /* Tunable launch shapes.  Results are identical for every valid setting.     */
@@ -109,6 +110,15 @@ typedef struct {
   const int32_t* job_event;     /* [n_jobs] device, or NULL */
 } tpc_jobs;
 
+/* Collision time t0 of a track (continuous read-out, section 2: the detector is read
+ * out continuously and the data come in time frames, so a track's collision time is
+ * not known in advance).  Measured z is the drift distance recomputed from the
+ * arrival time, so a collision t0 after the frame start shifts every z by v_drift*t0
+ * towards the far side of the central membrane (z - v_drift*t0 on side A,
+ * z + v_drift*t0 on side C).  A primary comes from the nominal vertex (z = 0) on the
+ * beam line, the plane x = 0 of its sector frame: the fitted state is transported
+ * along the helix (state only, FP32) from x_ref to x = 0 and t0 = -z/v_drift on side
+ * A, +z/v_drift on side C.  NaN where the fit failed or the transport fails.     */
 /* Output tracks (after tpc_fit_merge).  Capacities are [host] values; counts
  * are written on the device.  hits: CSR of cluster indices ordered along the
  * track (inner piece rows ascending, then the outer piece).  When a capacity
@@ -129,6 +139,7 @@ typedef struct {
   int32_t* sector;                /* [cap_tracks] sector of param (innermost piece)    */
   int32_t* job;                   /* [cap_tracks]                                      */
   int32_t* tracklet;              /* [cap_tracks] id of the innermost piece's tracklet */
+  float* t0;                      /* [cap_tracks] collision time, us, or NULL (below)  */
 } tpc_tracks;
 
 typedef struct tpc_ctx tpc_ctx;
@@ -143,8 +154,8 @@ int tpc_tuning_default(tpc_tuning* t);
 
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t; NULL =
  * the null stream).  Copies *p (NULL = defaults).  TPC_E_ARG if a field of *p is
- * not finite or outside its domain (sigma_y, sigma_z, nwin > 0; 0 < smax < 1;
- * min_hits >= 3; max_miss >= 1; merge_dz >= 0).                                */
+ * not finite or outside its domain (sigma_y, sigma_z, nwin, v_drift > 0;
+ * 0 < smax < 1; min_hits >= 3; max_miss >= 1; merge_dz >= 0).                   */
 int tpc_ctx_create(tpc_ctx** ctx, int device, void* hip_stream, const tpc_params* p);
 void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_set_stream(tpc_ctx* ctx, void* hip_stream);
@@ -212,7 +223,12 @@ int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int
  * whose residual code exceeds +-32767 is stored with absolute codes
  * e = rint(v / q) and the absolute bit.  Records H .. are the clusters in no
  * track, in input order, with absolute codes.  Absolute codes saturate at
- * +-32767; an invalid cluster (sector >= 36, row outside 0..151, non-finite y
+ * +-32767.  Time frames (continuous read-out, section 2) put the drift-shifted z
+ * of a 1 ms frame as far as +-2580 cm from the membrane: with ez_hi non-NULL an
+ * absolute z code has 24 bits, e = rint(z * (1/q_z)) saturated at +-(2^23 - 1),
+ * stored as its low 16 bits in ez and its signed high byte in ez_hi
+ * (e = ez_hi * 65536 + (uint16_t)ez); ez_hi is 0 for residual and invalid
+ * records, and decoding reads it the same way.  An invalid cluster (sector >= 36, row outside 0..151, non-finite y
  * or z) or a hit index outside 0..n-1 is stored as rs = 0x7FFF with zero codes.
  * Both raise TPC_E_RANGE at tpc_sync.
  * Decoding gives v = p + e*q for residual codes and v = e*q for absolute ones
@@ -225,6 +241,7 @@ typedef struct {
   uint16_t* rs;         /* [cap]                                                   */
   int16_t* ey;          /* [cap]                                                   */
   int16_t* ez;          /* [cap]                                                   */
+  int8_t* ez_hi;        /* [cap] or NULL: high byte of 24-bit absolute z codes     */
 } tpc_codes;
 
 /* Encodes the clusters `c` (device) against tracks `t` (device arrays as written

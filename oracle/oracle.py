@@ -31,7 +31,7 @@ class Params(C.Structure):
         "cy0", "cz0", "cs0", "ct0", "ck0", "cy1", "cz1", "cs1", "ct1", "ck1",
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
-        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz")]
+        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")]
 
 
 # The readings of every unstated constant (windows, cuts, priors, thresholds).
@@ -39,7 +39,7 @@ DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_con
                 link_cut=1.0, cy0=1.0, cz0=1.0, cs0=0.25, ct0=0.25, ck0=100.0,
                 cy1=1.0, cz1=1.0, cs1=1e-3, ct1=1e-3, ck1=1.0, sigma_y=0.1, sigma_z=0.1,
                 nwin=3.0, chi2_follow=15.0, max_miss=4, min_hits=10, smax=0.95, bz=0.5,
-                merge_edge=5.0, chi2_merge=50.0, merge_dz=20.0)
+                merge_edge=5.0, chi2_merge=50.0, merge_dz=20.0, v_drift=2.58)
 
 
 def params(**over) -> Params:
@@ -70,6 +70,11 @@ def lib():
         L.orc_destroy.argtypes = [P]
         L.orc_set_brute.argtypes = [P, C.c_int32]
         L.orc_status.argtypes = [P]
+        L.orc_get_track_t0.argtypes = [P, C.c_int32, P, P]
+        L.orc_collision_time_f32.argtypes = [P, C.c_float, C.c_int32, C.POINTER(Params)]
+        L.orc_collision_time_f32.restype = C.c_float
+        L.orc_collision_time_f64.argtypes = [P, C.c_double, C.c_int32, C.POINTER(Params)]
+        L.orc_collision_time_f64.restype = C.c_double
         L.orc_fp64_seconds.argtypes = [P]
         L.orc_fp64_seconds.restype = C.c_double
         L.orc_run.argtypes = [P, C.c_int32]
@@ -102,8 +107,8 @@ def lib():
         L.orc_rotate_f32.argtypes = [P, P, P, C.c_int32, C.c_int32, C.POINTER(Params)]
         L.orc_compress.restype = C.c_int32
         L.orc_compress.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, C.c_int32] + [P] * 6 + [
-            C.c_float, C.c_float, P, P, P, P]
-        L.orc_decompress.argtypes = [C.POINTER(Params), C.c_int32] + [P] * 5 + [C.c_int32, P, P, P] + [
+            C.c_float, C.c_float, P, P, P, P, P]
+        L.orc_decompress.argtypes = [C.POINTER(Params), C.c_int32] + [P] * 5 + [C.c_int32, P, P, P, P] + [
             C.c_float, C.c_float, P, P, P, P]
         L.orc_predict.restype = C.c_int32
         L.orc_rans_model.argtypes = [P, C.c_int32, P]
@@ -213,6 +218,9 @@ class Run:
         keys = ["tracklet", "job", "sector", "sector2", "off", "hits", "P", "C", "x", "chi2",
                 "ndf", "Pd", "Cd", "xd", "chi2d", "ndfd"]
         L.orc_get_tracks(self.h, int(merged), *[_p(out[k]) for k in keys])
+        out["t0"] = np.zeros(K, np.float32)
+        out["t0d"] = np.zeros(K, np.float64)
+        L.orc_get_track_t0(self.h, int(merged), _p(out["t0"]), _p(out["t0d"]))
         return out
 
     def fit_hits(self, hits, stk, fp64=True):
@@ -271,6 +279,14 @@ def update(P, Cv, my, mz, prm=None, fp64=False):
     return bool(ok), P, Cv, float(c2[0])
 
 
+def collision_time(P, x, sector, prm=None, fp64=False):
+    """T1: the collision time (us) of a track state P at plane x of `sector`."""
+    dt = np.float64 if fp64 else np.float32
+    P = np.ascontiguousarray(P, dt)
+    fn = lib().orc_collision_time_f64 if fp64 else lib().orc_collision_time_f32
+    return float(fn(_p(P), float(x), int(sector), C.byref(prm or params())))
+
+
 def asinc(u, fp64=False):
     dt = np.float64 if fp64 else np.float32
     A = np.zeros(1, dt)
@@ -311,10 +327,11 @@ def _headers(tracks):
     return K, g("off", np.int32), g("P", np.float32), g("x", np.float32), g("sector", np.int32), g("ndf", np.int32)
 
 
-def compress(sector, row, y, z, tracks, q_y, q_z, prm=None):
+def compress(sector, row, y, z, tracks, q_y, q_z, prm=None, wide_z=False):
     """C2-C4: records (rs, ey, ez) of every track hit in track order, then of the clusters in
-    no track in input order; returns dict(rs, ey, ez, n_attached, status).  `tracks` has the
-    keys of Run.tracks(): off, hits, P, x, sector, ndf."""
+    no track in input order; returns dict(rs, ey, ez, n_attached, status), plus ez_hi (C7:
+    24-bit absolute z codes) with wide_z.  `tracks` has the keys of Run.tracks(): off, hits,
+    P, x, sector, ndf."""
     prm = prm or params()
     sector = np.ascontiguousarray(sector, np.uint8)
     row = np.ascontiguousarray(row, np.int16)
@@ -327,10 +344,15 @@ def compress(sector, row, y, z, tracks, q_y, q_z, prm=None):
     rs = np.zeros(cap, np.uint16)
     ey = np.zeros(cap, np.int16)
     ez = np.zeros(cap, np.int16)
+    ezh = np.zeros(cap, np.int8) if wide_z else None
     st = np.zeros(1, np.int32)
     m = lib().orc_compress(C.byref(prm), n, _p(sector), _p(row), _p(y), _p(z), K, _p(off), _p(hits), _p(P),
-                           _p(x), _p(ts), _p(ndf), q_y, q_z, _p(rs), _p(ey), _p(ez), _p(st))
-    return dict(rs=rs[:m], ey=ey[:m], ez=ez[:m], n_attached=int(off[-1]), status=int(st[0]))
+                           _p(x), _p(ts), _p(ndf), q_y, q_z, _p(rs), _p(ey), _p(ez),
+                           None if ezh is None else _p(ezh), _p(st))
+    out = dict(rs=rs[:m], ey=ey[:m], ez=ez[:m], n_attached=int(off[-1]), status=int(st[0]))
+    if wide_z:
+        out["ez_hi"] = ezh[:m]
+    return out
 
 
 def decompress(tracks, codes, q_y, q_z, prm=None):
@@ -340,11 +362,14 @@ def decompress(tracks, codes, q_y, q_z, prm=None):
     rs = np.ascontiguousarray(codes["rs"], np.uint16)
     ey = np.ascontiguousarray(codes["ey"], np.int16)
     ez = np.ascontiguousarray(codes["ez"], np.int16)
+    ezh = codes.get("ez_hi")
+    ezh = None if ezh is None else np.ascontiguousarray(ezh, np.int8)
     m = len(rs)
     out = dict(sector=np.zeros(m, np.uint8), row=np.zeros(m, np.int16), y=np.zeros(m, np.float32),
                z=np.zeros(m, np.float32))
     lib().orc_decompress(C.byref(prm), K, _p(off), _p(P), _p(x), _p(ts), _p(ndf), m, _p(rs), _p(ey), _p(ez),
-                         q_y, q_z, *[_p(out[k]) for k in ("sector", "row", "y", "z")])
+                         None if ezh is None else _p(ezh), q_y, q_z,
+                         *[_p(out[k]) for k in ("sector", "row", "y", "z")])
     return out
 
 

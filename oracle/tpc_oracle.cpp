@@ -72,6 +72,7 @@ struct Params {
   float bz;                                                      // field, tesla
   float merge_edge, chi2_merge;                                  // O10
   float merge_dz;                                                // O10 z gate
+  float v_drift;                                                 // T1 drift velocity, cm/us
 };
 
 // Pad-row plane positions (O1, reading A2): x_r = 85 + r * 160/151 cm, rounded once.
@@ -693,6 +694,10 @@ struct Oracle {
     const int K = (int)tracks.size();
     std::vector<float> bestA(K, 0.f), bestB(K, 0.f);
     std::vector<int32_t> argA(K, -1), argB(K, -1);
+    // the tracks of each (event, sector), in ascending id: the only B a given A can pair with
+    std::unordered_map<int64_t, std::vector<int32_t>> by_sector;
+    for (int b = 0; b < K; ++b) by_sector[(int64_t)tracks[b].event * kSectors + tracks[b].sector].push_back(b);
+    const std::vector<int32_t> none;
     for (int a = 0; a < K; ++a) {
       const Track& A = tracks[a];
       if (A.ndf < 0) continue;
@@ -701,7 +706,8 @@ struct Oracle {
       if (!(edge <= p.merge_edge)) continue;
       const int dir = ta.P[0] > 0.f ? 1 : kRowsPerSide - 1;
       const int sb = (A.sector / kRowsPerSide) * kRowsPerSide + (A.sector % kRowsPerSide + dir) % kRowsPerSide;
-      for (int b = 0; b < K; ++b) {
+      const auto it = by_sector.find((int64_t)A.event * kSectors + sb);
+      for (const int b : it == by_sector.end() ? none : it->second) {
         const Track& B = tracks[b];
         if (B.ndf < 0 || B.event != A.event || B.sector != sb) continue;
         const int32_t hb = B.hits.front();
@@ -795,6 +801,12 @@ struct Oracle {
 //     in no track, in input order, with absolute codes.
 //  C5 Decoding: v = p + e*q for residual codes, v = e*q for absolute ones (FP32, each
 //     operation rounded once); the record gives sector and row.
+//  C7 Time frames: the drift-shifted z of a continuous read-out spans thousands of cm
+//     (+-2580 cm in a 1 ms frame), beyond 16-bit codes at q = 1/32 cm.  With a high-byte
+//     field, an absolute z code takes 24 bits: e = rint(z * (1/q)) saturated at
+//     +-(2^23 - 1), stored as its low 16 bits (ez) and the signed high byte (ez_hi), so
+//     that e = ez_hi * 2^16 + (ez as unsigned); residual and invalid records have
+//     ez_hi = 0.  Absolute y codes keep 16 bits (|y| <= 43.2 cm).
 // The record of a cluster: rs = row | sector << 8 | absolute << 15, plus the two codes.
 constexpr uint16_t kRecInvalid = 0x7FFF;
 constexpr int kCodeMax = 32767;
@@ -822,27 +834,44 @@ bool rotate_state(const Params& p, float* P, float& x, int from, int to) {
 }
 
 // C1, transport: the state part of O2 (propagate() above without Jacobian and covariance).
-bool transport_state(const Params& p, float* P, float x1, float x2) {
-  const float dx = x2 - x1;
-  if (dx == 0.f) return true;
-  const float curv = P[4] * curvature_factor<float>(p);
-  const float s1 = P[2];
-  const float s2 = s1 + curv * dx;
-  if (!(std::fabs(s2) < p.smax)) return false;
-  const float c1 = std::sqrt((1.f - s1) * (1.f + s1));
-  const float c2 = std::sqrt((1.f - s2) * (1.f + s2));
-  const float f = (s1 + s2) / (c1 + c2);
-  const float dy = dx * f;
-  float ch = std::sqrt(dx * dx + dy * dy);
-  if (dx < 0.f) ch = -ch;
-  const float u = curv * ch * 0.5f;
-  if (!(std::fabs(u) < 1.f)) return false;
-  float A, B;
+template <class T> bool transport_state(const Params& p, T* P, T x1, T x2) {
+  const T dx = x2 - x1;
+  if (dx == T(0)) return true;
+  const T curv = P[4] * curvature_factor<T>(p);
+  const T s1 = P[2];
+  const T s2 = s1 + curv * dx;
+  if (!(std::fabs(s2) < (T)p.smax)) return false;
+  const T c1 = std::sqrt((T(1) - s1) * (T(1) + s1));
+  const T c2 = std::sqrt((T(1) - s2) * (T(1) + s2));
+  const T f = (s1 + s2) / (c1 + c2);
+  const T dy = dx * f;
+  T ch = std::sqrt(dx * dx + dy * dy);
+  if (dx < T(0)) ch = -ch;
+  const T u = curv * ch * T(0.5);
+  if (!(std::fabs(u) < T(1))) return false;
+  T A, B;
   asinc(u, A, B);
   P[0] = P[0] + dy;
   P[1] = P[1] + P[3] * (ch * A);
   P[2] = P[2] + curv * dx;
   return true;
+}
+
+//  T1 Collision time of a track in continuous read-out.  A cluster's measured z is the
+//     drift distance recomputed from its arrival time, so a collision at time t0 after
+//     the frame start shows every cluster shifted by v_d t0 towards the central membrane's
+//     far side: z_meas = z - v_d t0 on side A, z + v_d t0 on side C.  A primary comes from
+//     the nominal vertex on the beam line (z = 0), which is the plane x = 0 of its
+//     sector frame; there the fitted helix has z_meas = -v_d t0 (A) or +v_d t0 (C).  So
+//     the fitted state is transported (O2, state alone) from its reference plane to
+//     x = 0 and t0 = -z/v_d on side A, +z/v_d on side C.  NaN when the fit failed or the
+//     transport fails (|sin phi| >= smax on the way).
+template <class T> T collision_time(const Params& p, const T* Pfit, T xref, int sector) {
+  T P[5];
+  for (int i = 0; i < 5; ++i) P[i] = Pfit[i];
+  if (!transport_state(p, P, xref, T(0))) return (T)NAN;
+  const T z0 = P[1];
+  return (sector < kRowsPerSide ? -z0 : z0) / (T)p.v_drift;
 }
 
 // C1: the predicted (y, z) of a cluster at (sec, row) of a track with fitted state Pfit.
@@ -877,6 +906,17 @@ int16_t abs_code(float v, float iq, int32_t& status) {
   if (e > (float)kCodeMax) { e = (float)kCodeMax; status |= 1; }
   if (e < -(float)kCodeMax) { e = -(float)kCodeMax; status |= 1; }
   return (int16_t)e;
+}
+
+// C7: 24-bit absolute code, split into the low 16 bits and the signed high byte.
+constexpr int32_t kWideMax = (1 << 23) - 1;
+void abs_code_wide(float v, float iq, int16_t& lo, int8_t& hi, int32_t& status) {
+  float e = std::rint(v * iq);
+  if (e > (float)kWideMax) { e = (float)kWideMax; status |= 1; }
+  if (e < -(float)kWideMax) { e = -(float)kWideMax; status |= 1; }
+  const int32_t c = (int32_t)e;
+  lo = (int16_t)(uint16_t)(c & 0xFFFF);
+  hi = (int8_t)(c >> 16);
 }
 
 struct TrackHeaders {
@@ -1083,6 +1123,26 @@ void orc_get_tracks(void* h, int32_t merged, int32_t* tracklet, int32_t* job, in
   }
 }
 
+// T1: the collision time of every output track (same order as orc_get_tracks), from the
+// FP32 fit (t0) and from the FP64 refit (t0d); NaN where the fit failed.
+void orc_get_track_t0(void* h, int32_t merged, float* t0, double* t0d) {
+  Oracle* o = (Oracle*)h;
+  int64_t m = 0;
+  for (auto& t : o->tracks) {
+    if (merged && t.merged_into >= 0) continue;
+    t0[m] = t.ndf >= 0 ? collision_time<float>(o->p, t.P, t.x, t.sector) : NAN;
+    t0d[m] = t.ndfd >= 0 ? collision_time<double>(o->p, t.Pd, t.xd, t.sector) : (double)NAN;
+    ++m;
+  }
+}
+// T1 alone (pins): the collision time of one state
+float orc_collision_time_f32(const float* P, float x, int32_t sector, const Params* p) {
+  return collision_time<float>(*p, P, x, sector);
+}
+double orc_collision_time_f64(const double* P, double x, int32_t sector, const Params* p) {
+  return collision_time<double>(*p, P, x, sector);
+}
+
 // ---- unit hooks for the pins
 // P: 10 values (hi[5], lo[5]) of the compensated state
 int32_t orc_propagate_f32(float* P, float* C, float x1, float x2, const Params* p) {
@@ -1135,23 +1195,29 @@ int32_t orc_fit_hits_f32(void* h, int32_t nh, const int32_t* hits, const float* 
 int32_t orc_compress(const Params* p, int32_t n, const uint8_t* sector, const int16_t* row,
                      const float* y, const float* z, int32_t K, const int32_t* off, const int32_t* hits,
                      const float* param, const float* x_ref, const int32_t* tsec, const int32_t* ndf,
-                     float q_y, float q_z, uint16_t* rs, int16_t* ey, int16_t* ez, int32_t* status) {
+                     float q_y, float q_z, uint16_t* rs, int16_t* ey, int16_t* ez, int8_t* ezh,
+                     int32_t* status) {
   const float iy = 1.0f / q_y, iz = 1.0f / q_z;
   int32_t st = 0;
   std::vector<uint8_t> in_track(n, 0);
   int32_t m = 0;
   auto put_abs = [&](int32_t h) {
+    if (ezh) ezh[m] = 0;
     if (!cluster_ok(sector[h], row[h], y[h], z[h])) {
       rs[m] = kRecInvalid; ey[m] = 0; ez[m] = 0; st |= 1;
       return;
     }
     rs[m] = (uint16_t)(row[h] | (sector[h] << 8) | (1 << 15));
     ey[m] = abs_code(y[h], iy, st);
-    ez[m] = abs_code(z[h], iz, st);
+    if (ezh)
+      abs_code_wide(z[h], iz, ez[m], ezh[m], st);
+    else
+      ez[m] = abs_code(z[h], iz, st);
   };
   for (int32_t i = 0; i < K; ++i) {
     for (int32_t j = off[i]; j < off[i + 1]; ++j, ++m) {
       const int32_t h = hits[j];
+      if (ezh) ezh[m] = 0;
       if (h < 0 || h >= n) { rs[m] = kRecInvalid; ey[m] = 0; ez[m] = 0; st |= 1; continue; }
       in_track[h] = 1;
       if (!cluster_ok(sector[h], row[h], y[h], z[h])) { put_abs(h); continue; }
@@ -1178,8 +1244,8 @@ int32_t orc_compress(const Params* p, int32_t n, const uint8_t* sector, const in
 // C5: decode m records; the first off[K] belong to the tracks in order.
 void orc_decompress(const Params* p, int32_t K, const int32_t* off, const float* param,
                     const float* x_ref, const int32_t* tsec, const int32_t* ndf, int32_t m,
-                    const uint16_t* rs, const int16_t* ey, const int16_t* ez, float q_y, float q_z,
-                    uint8_t* sector, int16_t* row, float* y, float* z) {
+                    const uint16_t* rs, const int16_t* ey, const int16_t* ez, const int8_t* ezh,
+                    float q_y, float q_z, uint8_t* sector, int16_t* row, float* y, float* z) {
   int32_t i = 0;
   for (int32_t j = 0; j < m; ++j) {
     while (i < K && j >= off[i + 1]) ++i;
@@ -1191,7 +1257,8 @@ void orc_decompress(const Params* p, int32_t K, const int32_t* off, const float*
     }
     sector[j] = (uint8_t)s;
     row[j] = (int16_t)r;
-    const float dy = (float)ey[j] * q_y, dz = (float)ez[j] * q_z;
+    const int32_t cz = (absolute && ezh) ? (int32_t)ezh[j] * 65536 + (int32_t)(uint16_t)ez[j] : (int32_t)ez[j];
+    const float dy = (float)ey[j] * q_y, dz = (float)cz * q_z;
     float py = 0.f, pz = 0.f;
     if (!absolute) {
       if (!(i < K && ndf[i] >= 0 && predict(*p, param + 5 * i, x_ref[i], tsec[i], s, r, py, pz))) {

@@ -1491,6 +1491,7 @@ struct OutView {
   int32_t* sector;
   int32_t* job;
   int32_t* tracklet;
+  float* t0;
 };
 
 __global__ void k_out_count(FitView F, const int32_t* keep, int32_t* outn, Bound lo_b, Bound hi_b) {
@@ -1512,7 +1513,7 @@ __global__ void k_out_count(FitView F, const int32_t* keep, int32_t* outn, Bound
 // over them (coalesced), the per-track fields written by lanes 0..23.
 __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, FitView F, OutView O,
                                                    const int32_t* keep, const int32_t* oid, const int32_t* ooff,
-                                                   Bound lo_b, Bound hi_b, int32_t* counters) {
+                                                   Bound lo_b, Bound hi_b, int32_t* counters, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
   const int lane = threadIdx.x & 63;
@@ -1557,6 +1558,10 @@ __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, F
       O.sector[o] = (sl / kRows) % kSectors;
       O.job[o] = sl / (kSectors * kRows);
       O.tracklet[o] = t;
+    } else if (lane == 24 && O.t0) {
+      const int32_t sec = (G.gh[V.start[F.sel_from[kk]]].slot / kRows) % kSectors;
+      const float* row = F.row + (int64_t)kk * kFitStride;
+      O.t0[o] = F.ndf[kk] >= 0 ? collision_time(row, row[20], sec, k) : __builtin_nanf("");
     }
   }
 }
@@ -1605,6 +1610,7 @@ struct CmpCodes {
   uint16_t* rs;
   int16_t* ey;
   int16_t* ez;
+  int8_t* ezh;  // high byte of 24-bit absolute z codes, or null (16-bit codes)
 };
 struct CmpOut {
   uint8_t* sector;
@@ -1647,9 +1653,28 @@ __global__ __launch_bounds__(256) void k_cmp_pack(CmpClusters in, int4* rec, uin
   free_mark[i] = 1;
 }
 
-// Absolute record of a packed cluster (or the invalid record).
-__device__ __forceinline__ void encode_abs(const int4& R, float iqy, float iqz, uint32_t& rs, int16_t& ey,
-                                           int16_t& ez, int32_t& st) {
+// Time frames: a 24-bit absolute z code, its low 16 bits and its signed high byte
+// (e = hi * 2^16 + lo as unsigned), saturated at +-(2^23 - 1).
+constexpr float kWideMax = 8388607.f;
+__device__ __forceinline__ void abs_code_wide(float v, float iq, int16_t& lo, int8_t& hi, int32_t& st) {
+  float e = rintf(v * iq);
+  if (e > kWideMax) {
+    e = kWideMax;
+    st |= kStatusRange;
+  }
+  if (e < -kWideMax) {
+    e = -kWideMax;
+    st |= kStatusRange;
+  }
+  const int32_t c = (int32_t)e;
+  lo = (int16_t)(uint16_t)(c & 0xFFFF);
+  hi = (int8_t)(c >> 16);
+}
+
+// Absolute record of a packed cluster (or the invalid record); ezh: the high byte of the
+// z code when wide, else untouched.
+__device__ __forceinline__ void encode_abs(const int4& R, float iqy, float iqz, bool wide, uint32_t& rs,
+                                           int16_t& ey, int16_t& ez, int8_t& ezh, int32_t& st) {
   const uint32_t w = (uint32_t)R.z;
   if (w == kRecInvalid) {
     rs = kRecInvalid;
@@ -1659,7 +1684,10 @@ __device__ __forceinline__ void encode_abs(const int4& R, float iqy, float iqz, 
   }
   rs = w | (1u << 15);
   ey = abs_code(__int_as_float(R.x), iqy, st);
-  ez = abs_code(__int_as_float(R.y), iqz, st);
+  if (wide)
+    abs_code_wide(__int_as_float(R.y), iqz, ez, ezh, st);
+  else
+    ez = abs_code(__int_as_float(R.y), iqz, st);
 }
 
 // Track hits: one wave per track (grid-stride), one lane per hit.
@@ -1702,6 +1730,7 @@ __global__ __launch_bounds__(256) void k_cmp_tracks(int32_t n, const int4* rec, 
       }
       uint32_t rs;
       int16_t ey = 0, ez = 0;
+      int8_t ezh = 0;
       const uint32_t wd = (uint32_t)R.z;
       if (!valid) {
         rs = kRecInvalid;
@@ -1721,11 +1750,12 @@ __global__ __launch_bounds__(256) void k_cmp_tracks(int32_t n, const int4* rec, 
             done = true;
           }
         }
-        if (!done) encode_abs(R, iqy, iqz, rs, ey, ez, st);
+        if (!done) encode_abs(R, iqy, iqz, O.ezh != nullptr, rs, ey, ez, ezh, st);
       }
       O.rs[j] = (uint16_t)rs;
       O.ey[j] = ey;
       O.ez[j] = ez;
+      if (O.ezh) O.ezh[j] = ezh;
     }
   }
   if (st) atomicOr(&counters[kCntStatus], st);
@@ -1776,10 +1806,12 @@ __global__ __launch_bounds__(kScanThreads) void k_cmp_free(int32_t n, const int4
       } else {
         uint32_t rs;
         int16_t ey, ez;
-        encode_abs(R, iqy, iqz, rs, ey, ez, st);
+        int8_t ezh = 0;
+        encode_abs(R, iqy, iqz, O.ezh != nullptr, rs, ey, ez, ezh, st);
         O.rs[pos] = (uint16_t)rs;
         O.ey[pos] = ey;
         O.ez[pos] = ez;
+        if (O.ezh) O.ezh[pos] = ezh;
       }
     }
     rank += tot;
@@ -1803,7 +1835,8 @@ __device__ __forceinline__ void decode_one(const CmpCodes& C, const CmpOut& D, i
   }
   D.sector[j] = (uint8_t)s;
   D.row[j] = (int16_t)r;
-  const float dy = (float)C.ey[j] * qy, dz = (float)C.ez[j] * qz;
+  const int32_t cz = (absolute && C.ezh) ? (int32_t)C.ezh[j] * 65536 + (int32_t)(uint16_t)C.ez[j] : (int32_t)C.ez[j];
+  const float dy = (float)C.ey[j] * qy, dz = (float)cz * qz;
   if (absolute) {
     D.y[j] = dy;
     D.z[j] = dz;
@@ -2673,6 +2706,7 @@ void make_consts(const tpc_params& p, Consts& k) {
   k.merge_edge = p.merge_edge;
   k.chi2_merge = p.chi2_merge;
   k.merge_dz = p.merge_dz;
+  k.v_drift = p.v_drift;
 }
 
 Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
@@ -2881,6 +2915,7 @@ int tpc_params_default(tpc_params* p) {
   p->merge_edge = 5.0f;
   p->chi2_merge = 50.0f;
   p->merge_dz = 20.0f;
+  p->v_drift = 2.58f;
   return TPC_OK;
 }
 
@@ -2899,11 +2934,11 @@ int tpc_tuning_default(tpc_tuning* t) {
 static bool params_ok(const tpc_params& p) {
   const float f[] = {p.win_dy_slope, p.win_dy_const, p.win_dz_slope, p.win_dz_const, p.link_cut, p.cy0,
                      p.cz0, p.cs0, p.ct0, p.ck0, p.cy1, p.cz1, p.cs1, p.ct1, p.ck1, p.sigma_y, p.sigma_z,
-                     p.nwin, p.chi2_follow, p.smax, p.bz, p.merge_edge, p.chi2_merge, p.merge_dz};
+                     p.nwin, p.chi2_follow, p.smax, p.bz, p.merge_edge, p.chi2_merge, p.merge_dz, p.v_drift};
   for (float v : f)
     if (!std::isfinite(v)) return false;
   return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
-         p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f;
+         p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f;
 }
 
 // the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))
@@ -3156,9 +3191,9 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   scan(c, L.keep, L.oid, klo, khi, kb, false);
   scan(c, L.outn, L.ooff, klo, khi, kb, false);
   OutView O{out->cap_tracks, out->cap_hits, out->n_tracks, out->hit_off, out->hits, out->param, out->cov,
-            out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet};
+            out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet, out->t0};
   hipLaunchKernelGGL(k_out_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
-                     make_fv(c, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters);
+                     make_fv(c, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters, c->k);
   hipLaunchKernelGGL(k_out_finish, dim3(1), dim3(1), 0, c->stream, L.oid, L.ooff, khi, L.capK, O, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
@@ -3188,7 +3223,7 @@ int tpc_run(tpc_ctx* c, const tpc_clusters* cl, const tpc_jobs* jb, tpc_tracks* 
                                 (uintptr_t)out->n_tracks, (uintptr_t)out->hit_off, (uintptr_t)out->hits,
                                 (uintptr_t)out->param, (uintptr_t)out->cov, (uintptr_t)out->x_ref,
                                 (uintptr_t)out->chi2, (uintptr_t)out->ndf, (uintptr_t)out->sector,
-                                (uintptr_t)out->job, (uintptr_t)out->tracklet};
+                                (uintptr_t)out->job, (uintptr_t)out->tracklet, (uintptr_t)out->t0};
   for (int j = 0; j <= jb->n_jobs; ++j) key.push_back((uintptr_t)(uint32_t)jb->job_off_host[j]);
   // ... and on the launch shapes
   {
@@ -3402,7 +3437,7 @@ CmpTracks tracks_view(const tpc_tracks* t) {
                    t->ndf};
 }
 CmpCodes codes_view(const tpc_codes* o) {
-  return CmpCodes{o->cap, o->n_codes, o->n_attached, o->rs, o->ey, o->ez};
+  return CmpCodes{o->cap, o->n_codes, o->n_attached, o->rs, o->ey, o->ez, o->ez_hi};
 }
 }  // namespace
 

@@ -32,6 +32,7 @@ struct Consts {
   int32_t max_miss, min_hits;
   float prior0[5], prior1[5];
   float merge_edge, chi2_merge, merge_dz;
+  float v_drift;         // cm/us
 };
 
 // lower-triangle index of a symmetric 5x5 (i >= j)
@@ -352,6 +353,18 @@ __device__ __forceinline__ bool transport_state(float* P, float x1, float x2, co
   P[1] = P[1] + P[3] * (ch * A);
   P[2] = P[2] + curv * dx;
   return true;
+}
+
+// Collision time of a track fitted to state Pf at plane xref of sector `sector`: the
+// state transported to the beam line (x = 0), where a primary's measured z is the drift
+// shift of its collision time, -v_d t0 on side A and +v_d t0 on side C.
+__device__ __forceinline__ float collision_time(const float* Pf, float xref, int sector, const Consts& k) {
+  float P[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) P[i] = Pf[i];
+  if (!transport_state(P, xref, 0.f, k)) return __builtin_nanf("");
+  const float z0 = P[1];
+  return div_rn(sector < kHalf ? -z0 : z0, k.v_drift);
 }
 
 // Predicted (y, z) at pad row `row` of sector `sec` for a track fitted to state Pf at plane

@@ -32,7 +32,7 @@ class tpc_params(C.Structure):
         "cy0", "cz0", "cs0", "ct0", "ck0", "cy1", "cz1", "cs1", "ct1", "ck1",
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
-        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz")]
+        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")]
 
 
 class tpc_tuning(C.Structure):
@@ -55,11 +55,12 @@ class tpc_jobs(C.Structure):
 class tpc_tracks(C.Structure):
     _fields_ = [("cap_tracks", C.c_int32), ("cap_hits", C.c_int32)] + [
         (n, C.c_void_p) for n in ("n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2",
-                                  "ndf", "sector", "job", "tracklet")]
+                                  "ndf", "sector", "job", "tracklet", "t0")]
 
 
 class tpc_codes(C.Structure):
-    _fields_ = [("cap", C.c_int32)] + [(n, C.c_void_p) for n in ("n_codes", "n_attached", "rs", "ey", "ez")]
+    _fields_ = [("cap", C.c_int32)] + [(n, C.c_void_p) for n in ("n_codes", "n_attached", "rs", "ey", "ez",
+                                                              "ez_hi")]
 
 
 class tpc_rans(C.Structure):
@@ -283,11 +284,12 @@ class Tracker:
                             ndf=torch.zeros(capT, dtype=i32, device=dev),
                             sector=torch.zeros(capT, dtype=i32, device=dev),
                             job=torch.zeros(capT, dtype=i32, device=dev),
-                            tracklet=torch.zeros(capT, dtype=i32, device=dev))
+                            tracklet=torch.zeros(capT, dtype=i32, device=dev),
+                            t0=torch.zeros(capT, dtype=f32, device=dev))
         o = self.out
         self._tracks = tpc_tracks(o["cap_tracks"], o["cap_hits"], *[
             _ptr(o[k]) for k in ("n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf",
-                                 "sector", "job", "tracklet")])
+                                 "sector", "job", "tracklet", "t0")])
         self._cl = tpc_clusters(ev.n, _ptr(ev.sector), _ptr(ev.row), _ptr(ev.y), _ptr(ev.z), _ptr(ev.time))
         self._jobs_host = np.ascontiguousarray(ev.job_off_host, np.int32)
         self._jb = tpc_jobs(ev.n_jobs, _ptr(ev.job_off), self._jobs_host.ctypes.data_as(C.c_void_p),
@@ -327,22 +329,25 @@ class Tracker:
         self._check(lib().tpc_counts(self.ctx, _ptr(dst)), "tpc_counts")
 
     # ---- track-model compression of the current clusters against the current tracks
-    def tpc_compress(self, q_y: float = Q_STEP, q_z: float = Q_STEP, cap: int | None = None) -> dict:
-        """Enqueues tpc_compress; returns the record buffers (device tensors, rs stored as int16)."""
+    def tpc_compress(self, q_y: float = Q_STEP, q_z: float = Q_STEP, cap: int | None = None,
+                     wide_z: bool = False) -> dict:
+        """Enqueues tpc_compress; returns the record buffers (device tensors, rs stored as int16);
+        wide_z: 24-bit absolute z codes (the high bytes in ez_hi), for time frames."""
         torch = self.torch
         dev = f"cuda:{self.device}"
         cap = max(self._keep.n, 1) if cap is None else cap
         cd = getattr(self, "codes", None)
-        if cd is None or cd["cap"] != cap:
+        if cd is None or cd["cap"] != cap or (cd["ez_hi"] is not None) != wide_z:
             i32, i16 = torch.int32, torch.int16
             cd = dict(cap=cap, n_codes=torch.zeros(1, dtype=i32, device=dev),
                       n_attached=torch.zeros(1, dtype=i32, device=dev),
                       rs=torch.zeros(max(cap, 1), dtype=i16, device=dev),
                       ey=torch.zeros(max(cap, 1), dtype=i16, device=dev),
-                      ez=torch.zeros(max(cap, 1), dtype=i16, device=dev))
+                      ez=torch.zeros(max(cap, 1), dtype=i16, device=dev),
+                      ez_hi=torch.zeros(max(cap, 1), dtype=torch.int8, device=dev) if wide_z else None)
             self.codes = cd
         cd["q"] = (q_y, q_z)
-        self._codes = tpc_codes(cap, *[_ptr(cd[k]) for k in ("n_codes", "n_attached", "rs", "ey", "ez")])
+        self._codes = tpc_codes(cap, *[_ptr(cd[k]) for k in ("n_codes", "n_attached", "rs", "ey", "ez", "ez_hi")])
         self._check(lib().tpc_compress(self.ctx, C.byref(self._cl), C.byref(self._tracks), q_y, q_z,
                                        C.byref(self._codes)), "tpc_compress")
         return cd
@@ -471,9 +476,12 @@ class Tracker:
         self.torch.cuda.synchronize(self.device)
         cd = self.codes
         m = min(int(cd["n_codes"].item()), cd["cap"])
-        return dict(n_codes=int(cd["n_codes"].item()), n_attached=int(cd["n_attached"].item()),
-                    rs=cd["rs"][:m].cpu().numpy().view(np.uint16), ey=cd["ey"][:m].cpu().numpy(),
-                    ez=cd["ez"][:m].cpu().numpy())
+        out = dict(n_codes=int(cd["n_codes"].item()), n_attached=int(cd["n_attached"].item()),
+                   rs=cd["rs"][:m].cpu().numpy().view(np.uint16), ey=cd["ey"][:m].cpu().numpy(),
+                   ez=cd["ez"][:m].cpu().numpy())
+        if cd["ez_hi"] is not None:
+            out["ez_hi"] = cd["ez_hi"][:m].cpu().numpy()
+        return out
 
     run = tpc_run
     sync = tpc_sync
@@ -509,7 +517,8 @@ class Tracker:
                     param=o["param"][:K].cpu().numpy(), cov=o["cov"][:K].cpu().numpy(),
                     x_ref=o["x_ref"][:K].cpu().numpy(), chi2=o["chi2"][:K].cpu().numpy(),
                     ndf=o["ndf"][:K].cpu().numpy(), sector=o["sector"][:K].cpu().numpy(),
-                    job=o["job"][:K].cpu().numpy(), tracklet=o["tracklet"][:K].cpu().numpy())
+                    job=o["job"][:K].cpu().numpy(), tracklet=o["tracklet"][:K].cpu().numpy(),
+                    t0=o["t0"][:K].cpu().numpy())
 
     def links_raw(self) -> dict:
         """Raw (uncleaned) links as input indices; the clean links come from tpc_find_neighbours."""

@@ -90,6 +90,9 @@ def compare_all(g, o, fp_check=True):
     assert np.array_equal(bits(gk["param"][good]), bits(ok["P"][good])), "fitted params differ from FP32 oracle"
     assert np.array_equal(bits(gk["cov"][good]), bits(ok["C"][good]))
     assert np.array_equal(bits(gk["x_ref"][good]), bits(ok["x"][good]))
+    nan = np.isnan(ok["t0"])
+    assert np.array_equal(np.isnan(gk["t0"]), nan), "collision times fail on different tracks"
+    assert np.array_equal(bits(gk["t0"][~nan]), bits(ok["t0"][~nan])), "collision times differ from FP32 oracle"
     if fp_check:
         check_fp64(gk, ok)
     return dict(n_tracks=gk["n"], n_tracklets=len(gt["start"]), merged=int((ok["sector2"] >= 0).sum()))
@@ -106,3 +109,8 @@ def check_fp64(gk, ok):
     assert np.all(np.abs(P[:, 4] - Pd[:, 4]) <= 1e-4 * np.maximum(np.abs(Pd[:, 4]), 0.1))
     assert np.all(np.abs(P[:, 0] - Pd[:, 0]) <= 1e-3)
     assert np.all(np.abs(P[:, 1] - Pd[:, 1]) <= 1e-3)
+    # collision time: the position tolerance (1e-3 cm of z) at the beam line, over v_drift
+    t0, t0d = gk["t0"][g32].astype(np.float64), ok["t0d"][g32]
+    assert np.array_equal(np.isnan(t0), np.isnan(t0d)), "collision times fail on different tracks"
+    f = ~np.isnan(t0)
+    assert np.all(np.abs(t0[f] - t0d[f]) <= 1e-3 / 2.58)

@@ -163,3 +163,58 @@ def test_failed_fits_invalid_clusters_and_saturation():
     t2["hits"][0] = cs.n + 5
     c2 = O.compress(cs.sector, cs.row, cs.y, cs.z, t2, Q, Q)
     assert c2["status"] == 1 and c2["rs"][0] == 0x7FFF
+
+
+# ------------------------------------------------------------------ C7: time frames
+def test_wide_absolute_z_codes_split_and_saturate():
+    """C7: a 24-bit absolute z code is numpy's round-half-even of z/q, split into its low 16
+    bits and signed high byte; it saturates at +-(2^23 - 1) with the range status."""
+    rng = np.random.default_rng(7)
+    n = 20000
+    z = np.concatenate([rng.uniform(-2600.0, 2600.0, n - 6),
+                        [0.0, -0.5 * Q, 1.5 * Q, 262143.9, -262143.5, 1e6]]).astype(np.float32)
+    sector = (np.arange(len(z)) % 36).astype(np.uint8)
+    row = (np.arange(len(z)) % 152).astype(np.int16)
+    y = rng.uniform(-15.0, 15.0, len(z)).astype(np.float32)
+    none = dict(off=np.zeros(1, np.int32), hits=np.zeros(0, np.int32), P=np.zeros((0, 5), np.float32),
+                x=np.zeros(0, np.float32), sector=np.zeros(0, np.int32), ndf=np.zeros(0, np.int32))
+    c = O.compress(sector, row, y, z, none, Q, Q, wide_z=True)
+    iq = np.float32(1.0) / np.float32(Q)
+    e = np.clip(np.rint(z * iq).astype(np.float64), -(2 ** 23 - 1), 2 ** 23 - 1).astype(np.int64)
+    got = c["ez_hi"].astype(np.int64) * 65536 + c["ez"].view(np.uint16).astype(np.int64)
+    assert np.array_equal(got, e)
+    assert c["status"] == 1                     # the last value saturates
+    c2 = O.compress(sector[:-1], row[:-1], y[:-1], z[:-1], none, Q, Q, wide_z=True)
+    assert c2["status"] == 0
+    # 16-bit codes: everything beyond +-1024 cm saturates
+    c16 = O.compress(sector[:-1], row[:-1], y[:-1], z[:-1], none, Q, Q)
+    assert c16["status"] == 1
+    d = O.decompress(none, c2, Q, Q)
+    assert np.abs(d["z"] - z[:-1]).max() <= Q / 2
+    assert np.array_equal(d["y"], (np.rint(y[:-1] * iq).astype(np.float32) * np.float32(Q)))
+
+
+def test_time_frame_compresses_with_wide_codes():
+    """C7 on a time frame of the workload's law spread over a whole 1 ms window (six
+    collisions 150 us apart on average, drift-shifted z beyond 1024 cm): 16-bit absolute
+    codes saturate, 24-bit ones do not; residual records carry a zero high byte; every
+    cluster decodes within half a step."""
+    pool = g.gen_collision_pool(73, 6, mult_range=(500, 1500))
+    cs = g.assemble_timeframe(74, pool, np.arange(6), 1000.0, mean_spacing_us=150.0)
+    assert np.abs(cs.z).max() > 1100.0
+    t = _tracks(cs)
+    c16 = O.compress(cs.sector, cs.row, cs.y, cs.z, t, Q, Q)
+    assert c16["status"] == 1
+    c = O.compress(cs.sector, cs.row, cs.y, cs.z, t, Q, Q, wide_z=True)
+    assert c["status"] == 0
+    H = c["n_attached"]
+    res = (c["rs"] >> 15) == 0
+    assert res[:H].mean() > 0.99 and not res[H:].any()
+    assert np.all(c["ez_hi"][res] == 0)
+    assert np.array_equal(c["ey"], c16["ey"]) and np.array_equal(c["rs"], c16["rs"])
+    assert np.array_equal(c["ez"][res], c16["ez"][res])
+    d = O.decompress(t, c, Q, Q)
+    perm = _permutation(cs.n, t)
+    assert np.array_equal(d["sector"], cs.sector[perm]) and np.array_equal(d["row"], cs.row[perm])
+    assert np.abs(d["y"] - cs.y[perm]).max() <= Q / 2 + 1e-5
+    assert np.abs(d["z"] - cs.z[perm]).max() <= Q / 2 + 2e-4

@@ -95,6 +95,42 @@ def test_codes_and_decoding_bit_exact(cfg, seed, qy, qz):
     say("records", gc["n_codes"], "track hits", H, "residual", int(((gc["rs"][:H] >> 15) == 0).sum()))
 
 
+@pytest.mark.parametrize("qy,qz", [(Q, Q), (0.25, 1.0 / 64.0)])
+def test_time_frame_wide_codes_bit_exact(qy, qz):
+    """A time frame spread over 1 ms (six collisions, drift-shifted z beyond +-1024 cm): the
+    24-bit absolute z codes, their high bytes, the tracks' collision times and the decoded
+    clusters equal the oracle's bit for bit; 16-bit codes saturate there."""
+    pool = g.gen_collision_pool(73, 6, mult_range=(500, 1500))
+    cs = g.assemble_timeframe(74, pool, np.arange(6), 1000.0, mean_spacing_us=150.0)
+    assert np.abs(cs.z).max() > 1100.0
+    tr, ev, st = _track(cs)
+    assert st == 0
+    t = tr.tracks()
+    ot = O.Run.from_set(cs).tracks(merged=True)
+    assert np.array_equal(t["hits"], ot["hits"]) and np.array_equal(t["off"], ot["off"])
+    nan = np.isnan(ot["t0"])
+    assert np.array_equal(np.isnan(t["t0"]), nan) and np.array_equal(bits(t["t0"][~nan]), bits(ot["t0"][~nan]))
+    tr.tpc_compress(qy, qz, wide_z=True)
+    assert _status(tr) == 0
+    gc = tr.codes_numpy()
+    gd, st = _decoded(tr, gc["n_codes"])
+    assert st == 0
+    oc = O.compress(cs.sector, cs.row, cs.y, cs.z, ot, qy, qz, wide_z=True)
+    od = O.decompress(ot, oc, qy, qz)
+    _compare(gc, oc, gd, od)
+    assert np.array_equal(gc["ez_hi"], oc["ez_hi"]), "high bytes differ"
+    assert np.abs(gc["ez_hi"]).max() > 0
+    rest = np.setdiff1d(np.arange(cs.n), ot["hits"])
+    perm = np.concatenate([ot["hits"], rest]).astype(np.int64)
+    assert np.abs(gd["z"] - cs.z[perm]).max() <= qz / 2 + 2e-4
+    tr.tpc_compress(qy, qz)
+    assert _status(tr) == TPC_E_RANGE_CODE
+    say("time frame", cs.n, "clusters, wide codes bit-exact; max |z|", float(np.abs(cs.z).max()))
+
+
+TPC_E_RANGE_CODE = -2
+
+
 def test_invalid_and_saturated_clusters():
     from paper_2402_01205_amd.tpc import TPC_E_RANGE
     cs = g.make_config("c1", 11)

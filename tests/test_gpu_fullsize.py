@@ -73,7 +73,10 @@ def test_batched_workload_full_size_sampled_jobs(c4):
         assert np.array_equal(got_hits, ref["hits"])
         good = ref["ndf"] >= 0
         assert np.array_equal(bits(t["param"][sel][good]), bits(ref["P"][good]))
-        check_fp64(dict(ndf=t["ndf"][sel], param=t["param"][sel]), ref)
+        nan = np.isnan(ref["t0"])
+        assert np.array_equal(np.isnan(t["t0"][sel]), nan)
+        assert np.array_equal(bits(t["t0"][sel][~nan]), bits(ref["t0"][~nan])), "collision times differ"
+        check_fp64(dict(ndf=t["ndf"][sel], param=t["param"][sel], t0=t["t0"][sel]), ref)
         say("job", j, "tracks", len(sel), "bit-exact")
 
 

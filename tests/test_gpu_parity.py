@@ -267,7 +267,7 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
         assert m["status"] == 0 and m["n_tracks"] == t["n"], ch.cid
         assert np.array_equal(m["hit_off"], t["off"]), ch.cid
         assert np.array_equal(m["hits"], t["hits"]), ch.cid
-        for k, tk in (("param", "param"), ("cov", "cov"), ("x_ref", "x_ref"), ("chi2", "chi2")):
+        for k, tk in (("param", "param"), ("cov", "cov"), ("x_ref", "x_ref"), ("chi2", "chi2"), ("t0", "t0")):
             assert np.array_equal(m[k].view(np.uint32), t[tk].view(np.uint32)), (ch.cid, k)
         for k in ("ndf", "sector"):
             assert np.array_equal(m[k], t[k]), (ch.cid, k)
@@ -308,9 +308,11 @@ def test_output_capacity_reports_required_sizes_and_truncates():
                  ndf=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
                  sector=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
                  job=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
-                 tracklet=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev))
+                 tracklet=torch.full((cap_t + guard,), -7, dtype=torch.int32, device=dev),
+                 t0=torch.full((cap_t + guard,), -7.0, device=dev))
         out = T.tpc_tracks(cap_t, cap_h, *[C.c_void_p(o[k].data_ptr()) for k in (
-            "n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet")])
+            "n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet",
+            "t0")])
         assert T.lib().tpc_fit_merge(tr.ctx, C.byref(out)) == T.TPC_OK
         assert T.lib().tpc_sync(tr.ctx) == T.TPC_E_CAPACITY
         torch.cuda.synchronize()
@@ -323,7 +325,7 @@ def test_output_capacity_reports_required_sizes_and_truncates():
         hits = o["hits"].cpu().numpy()
         nh = min(cap_h, int(full["off"][kt]))
         assert np.array_equal(hits[:nh], full["hits"][:nh])
-        for k in ("param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet"):
+        for k in ("param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet", "t0"):
             assert bool((o[k][cap_t:] == -7).all()), k
         assert bool((o["hit_off"][cap_t + 1:] == -7).all())
         assert (hits[cap_h:] == -7).all()

@@ -264,13 +264,14 @@ def gen_event(seed, n_primaries, *, sector=None, noise=0.0, ineff=0.0, smear=SIG
                        dict(kind="event", seed=seed, n_primaries=n_primaries, sector=sector))
 
 
-def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, workers=0):
+def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, workers=0,
+                       smear=SIGMA_YZ):
     """Collisions at t=0 (no noise), each reproducible from its own spawned seed."""
     ss = np.random.SeedSequence(seed)
     rng = np.random.default_rng(ss.spawn(1)[0])
     mult = rng.integers(mult_range[0], mult_range[1] + 1, n_collisions)
     kids = ss.spawn(n_collisions + 1)[1:]
-    args = [(kids[i], int(mult[i]), ineff) for i in range(n_collisions)]
+    args = [(kids[i], int(mult[i]), ineff, smear) for i in range(n_collisions)]
     if workers and workers > 1 and n_collisions > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(min(workers, n_collisions)) as p:
@@ -279,10 +280,11 @@ def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, wo
 
 
 def _pool_collision(args):
-    kid, mult, ineff = args
+    kid, mult, ineff, smear = args
     r = np.random.default_rng(kid)
     parts, (ti, sec, row, y, z) = _signal_clusters(r, mult, eta_range=(-0.9, 0.9),
-                                                   phi_range=(0, 2 * math.pi), ineff=ineff)
+                                                   phi_range=(0, 2 * math.pi), ineff=ineff,
+                                                   smear=smear)
     return dict(parts=parts, ti=ti, sec=sec.astype(np.uint8), row=row.astype(np.int16),
                 y=y, z=z)
 
@@ -316,9 +318,11 @@ def assemble_timeframe(seed, pool, coll_ids, window_us, noise=0.05, mean_spacing
     n_noise = int(round(noise * len(sig[0])))
     nz = _noise_clusters(rng, n_noise, window_us=window_us)
     parts = tuple(np.concatenate(a) for a in (pts, etas, phis, qs))
+    coll_part_off = np.concatenate([[0], np.cumsum([len(p) for p in pts])]).astype(np.int64)
     return _finish_job(rng, sig, nz, parts, shuffle,
                        dict(kind="timeframe", seed=seed, n_collisions=len(coll_ids),
-                            window_us=window_us, t_collisions=tk.tolist()))
+                            window_us=window_us, t_collisions=tk.tolist(),
+                            coll_part_off=coll_part_off.tolist()))
 
 
 # --------------------------------------------------------------------------------------
