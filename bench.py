@@ -447,6 +447,19 @@ def kernel_json(kern):
             for k, v in kern.items()}
 
 
+def by_decile(pj, sizes):
+    """Efficiency and fake rate over the jobs sorted by size (clusters), in ten groups."""
+    order = np.argsort(sizes, kind="stable")
+    out = []
+    for grp in np.array_split(order, 10):
+        f, fd = int(pj["findable"][grp].sum()), int(pj["found"][grp].sum())
+        t, fk = int(pj["tracks"][grp].sum()), int(pj["fakes"][grp].sum())
+        out.append({"jobs": len(grp), "clusters_per_job": [int(sizes[grp].min()), int(sizes[grp].max())],
+                    "clusters": int(sizes[grp].sum()), "efficiency": fd / f if f else None,
+                    "fake_rate": fk / t if t else None})
+    return out
+
+
 def same_tracks(a, b, perm=None):
     """Two track outputs hold the same tracks (as sets of hit lists); perm maps b's cluster
     indices to a's."""
@@ -626,7 +639,10 @@ def main():
 
     probe = copy_probe(tr, torch, 1024, 5)
     log(f"copy probe: {probe:.0f} GB/s")
-    q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off, cs.part_pt)
+    q = quality(cs.label, cs.job_off, cs.sector, tracks["off"], tracks["hits"], cs.part_off, cs.part_pt,
+                by_job=cs.n_jobs > 1)
+    if "per_job" in q:
+        q["by_job_size_decile"] = by_decile(q.pop("per_job"), np.diff(cs.job_off))
     log("quality: " + json.dumps(q))
     also = {}
     def time_run(tracker, dev_set, steps):

@@ -147,7 +147,10 @@ typedef struct tpc_ctx tpc_ctx;
 /* Launch modes: how the stage entry points launch their kernels.             */
 #define TPC_MODE_PLAIN 0      /* one launch sequence per job (per sector-job)           */
 #define TPC_MODE_BATCHED 1    /* one launch per kernel over all jobs                    */
-#define TPC_MODE_PERSISTENT 2 /* batched, tracklet/fit stages as persistent work-queue  */
+#define TPC_MODE_PERSISTENT 2 /* batched, the tracklet stage as resident waves taking   */
+                              /* work from a device queue; the other stages stay one   */
+                              /* launch over all jobs, whose items (clusters, tracks)  */
+                              /* outnumber the resident waves many times over          */
 
 int tpc_params_default(tpc_params* p);
 int tpc_tuning_default(tpc_tuning* t);

@@ -17,7 +17,9 @@ PURITY = 0.9
 PT_BINS = (0.1, 0.2, 0.5, 1.0, 10.0001)
 
 
-def quality(label, job_off, sector, trk_off, trk_hits, part_off=None, part_pt=None):
+def quality(label, job_off, sector, trk_off, trk_hits, part_off=None, part_pt=None, by_job=False):
+    """Efficiency, fake and clone rates (and efficiency per pT bin); with by_job, the counts
+    behind them per job as well (findable particles, found ones, tracks, fakes)."""
     label = np.asarray(label)
     job_off = np.asarray(job_off, np.int64)
     n_jobs = len(job_off) - 1
@@ -64,6 +66,14 @@ def quality(label, job_off, sector, trk_off, trk_hits, part_off=None, part_pt=No
     clones = int(np.maximum(found - 1, 0).sum())
     out = dict(n_tracks=K, n_findable=nf, efficiency=eff, fake_rate=(K - n_good) / K,
                clone_rate=clones / K, hits_in_tracks=int(trk_off[-1]))
+    if by_job:
+        part_job = np.searchsorted(part_off, np.arange(n_part), side="right") - 1
+        trk_job = job_of[np.asarray(trk_hits)[trk_off[:-1]]]
+        out["per_job"] = dict(findable=np.bincount(part_job[findable], minlength=n_jobs),
+                              found=np.bincount(part_job[findable & (found > 0)], minlength=n_jobs),
+                              tracks=np.bincount(trk_job, minlength=n_jobs),
+                              fakes=np.bincount(trk_job, minlength=n_jobs)
+                              - np.bincount(trk_job[best_t[good]], minlength=n_jobs))
     if part_pt is not None:
         pt = np.asarray(part_pt)
         eff_pt = {}
