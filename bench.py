@@ -697,6 +697,20 @@ def main():
             also[name]["collision_times"] = {"tracks": int(ot["n"]), "without_t0": int(nt)}
             log(f"{name} compression (24-bit z codes): {cms:.3f} ms")
         del otr, oev
+        if name == "c3":
+            # the synchronous phase's cut set on the same time frame
+            from paper_2402_01205_amd.tpc import preset_params
+            sev = DeviceClusters.from_set(ocs, dev)
+            str_ = Tracker(0, params=preset_params("sync"), mode=args.mode, tuning=tuning)
+            sms = time_run(str_, sev, args.steps)
+            st = str_.tracks()
+            sq = quality(ocs.label, ocs.job_off, ocs.sector, st["off"], st["hits"], ocs.part_off, ocs.part_pt)
+            also[name]["sync_preset"] = {"ms_per_step": sms, "clusters_per_s": ocs.n / (sms / 1e3),
+                                         "tracks": int(st["n"]), "quality": sq,
+                                         "attached_clusters": int(st["off"][-1]) / ocs.n,
+                                         "async_attached_clusters": int(ot["off"][-1]) / ocs.n}
+            log(f"{name} sync preset: {sms:.3f} ms/step, quality {sq}")
+            del str_, sev
         if name == "c3" and args.plain_steps > 0:
             # the per-sector form: every sector its own job, launched one after the other
             split, perm, jev = g.split_by_sector(ocs)

@@ -68,7 +68,8 @@ typedef struct {
   int32_t min_hits;                  /* hits of a valid tracklet / accepted track      */
   float smax;                        /* limit of |sin(phi)|                            */
   float bz;                          /* solenoid field along +z, tesla                 */
-  float merge_edge;                  /* distance to the sector edge of merge pieces, cm*/
+  float merge_edge;                  /* distance to the sector edge of merge pieces, cm;*/
+                                     /* negative: no merge across sectors              */
   float chi2_merge;                  /* max 5-D chi2 of a merged pair                  */
   float merge_dz;                    /* max |z| gap between the pieces' ends, cm        */
   float v_drift;                     /* drift velocity, cm/us (collision times)         */
@@ -153,6 +154,15 @@ typedef struct tpc_ctx tpc_ctx;
                               /* outnumber the resident waves many times over          */
 
 int tpc_params_default(tpc_params* p);
+/* Cut sets of the two processing phases (section 2: the synchronous phase uses
+ * different cuts to speed up the processing).  TPC_PRESET_ASYNC is the default
+ * reading.  TPC_PRESET_SYNC serves the synchronous phase, whose tracks feed the
+ * track-model compression: that attaches a cluster to any piece of its track,
+ * so the pieces are not merged across sector edges (merge_edge < 0 disables the
+ * merge); every other field is the default.  TPC_E_ARG for another preset.    */
+#define TPC_PRESET_ASYNC 0
+#define TPC_PRESET_SYNC 1
+int tpc_params_preset(tpc_params* p, int preset);
 int tpc_tuning_default(tpc_tuning* t);
 
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t; NULL =

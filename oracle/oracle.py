@@ -42,6 +42,11 @@ DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_con
                 merge_edge=5.0, chi2_merge=50.0, merge_dz=20.0, v_drift=2.58)
 
 
+# The synchronous phase's cut set (its tracks feed the compression, which attaches clusters to
+# track pieces alike): no merge across sector edges; everything else as DEFAULTS.
+SYNC = dict(DEFAULTS, merge_edge=-1.0)
+
+
 def params(**over) -> Params:
     d = dict(DEFAULTS)
     d.update(over)

@@ -2919,6 +2919,13 @@ int tpc_params_default(tpc_params* p) {
   return TPC_OK;
 }
 
+int tpc_params_preset(tpc_params* p, int preset) {
+  if (!p || (preset != TPC_PRESET_ASYNC && preset != TPC_PRESET_SYNC)) return TPC_E_ARG;
+  tpc_params_default(p);
+  if (preset == TPC_PRESET_SYNC) p->merge_edge = -1.0f;
+  return TPC_OK;
+}
+
 int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_E_ARG;
   t->cells_per_cluster = 2.0f;

@@ -106,6 +106,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         V, P, I = C.c_void_p, C.POINTER, C.c_int
         L.tpc_params_default.argtypes = [P(tpc_params)]
+        L.tpc_params_preset.argtypes = [P(tpc_params), I]
         L.tpc_tuning_default.argtypes = [P(tpc_tuning)]
         L.tpc_ctx_create.argtypes = [P(V), I, V, P(tpc_params)]
         L.tpc_ctx_destroy.argtypes = [V]
@@ -152,7 +153,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["tpc_params_default", "tpc_tuning_default", "tpc_ctx_create", "tpc_ctx_destroy",
+EXPORTED = ["tpc_params_default", "tpc_params_preset", "tpc_tuning_default", "tpc_ctx_create", "tpc_ctx_destroy",
             "tpc_set_stream", "tpc_set_mode", "tpc_set_tuning", "tpc_last_error",
             "tpc_workspace_size", "tpc_bind_workspace", "tpc_grid_build", "tpc_find_neighbours", "tpc_counts",
             "tpc_construct_tracklets", "tpc_select_tracks", "tpc_fit_merge", "tpc_run", "tpc_sync",
@@ -169,6 +170,19 @@ PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "co
 def default_params(**over) -> tpc_params:
     p = tpc_params()
     lib().tpc_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+PRESETS = {"async": 0, "sync": 1}
+
+
+def preset_params(name: str, **over) -> tpc_params:
+    """The cut set of a processing phase ("async" = the defaults, "sync"), then overrides."""
+    p = tpc_params()
+    if lib().tpc_params_preset(C.byref(p), PRESETS[name]) != TPC_OK:
+        raise TpcError(TPC_E_ARG, f"unknown preset {name!r}")
     for k, v in over.items():
         setattr(p, k, v)
     return p

@@ -32,6 +32,19 @@ def test_default_params_equal_the_oracle_reading():
         assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
 
 
+def test_sync_preset_equals_the_oracle_reading():
+    from paper_2402_01205_amd import tpc
+    p = tpc.preset_params("sync")
+    for name, v in O.SYNC.items():
+        got = getattr(p, name)
+        assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
+    a = tpc.preset_params("async")
+    for name, v in O.DEFAULTS.items():
+        got = getattr(a, name)
+        assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
+    assert tpc.lib().tpc_params_preset(ctypes.byref(tpc.tpc_params()), 7) == tpc.TPC_E_ARG
+
+
 def test_product_path_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_2402_01205_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -8,6 +8,7 @@ q/pT (floor 0.1 GeV^-1) and 1e-3 cm on y, z.
 import numpy as np
 import pytest
 
+import oracle.oracle as O
 import tpcsynth as g
 from tests.gpu_helpers import bits, compare_all, gpu_run, oracle_run, say
 
@@ -107,6 +108,18 @@ def test_sector_jobs_of_one_event_merge_across_jobs():
     ev = np.zeros(36, np.int32)
     s = compare_all(gpu_run(split, job_event=ev), oracle_run(split, job_event=ev))
     assert s["merged"] > 50
+
+
+@pytest.mark.parametrize("cfg,seed,scale", [("c2", 21, 0.5), ("c3", 31, 0.1)])
+def test_sync_preset_bit_exact(cfg, seed, scale):
+    """The synchronous phase's cut set (no merge across sector edges): every stage equals the
+    oracle's with the same reading, and no track is merged."""
+    from paper_2402_01205_amd.tpc import preset_params
+    cs = g.make_config(cfg, seed, scale=scale)
+    o = oracle_run(cs, O.params(**O.SYNC))
+    s = compare_all(gpu_run(cs, params=preset_params("sync")), o)
+    assert s["merged"] == 0 and s["n_tracks"] > 500
+    say(cfg, "sync preset: tracks", s["n_tracks"])
 
 
 @pytest.mark.parametrize("mode,tune", [
