@@ -608,21 +608,19 @@ __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, flo
 #pragma unroll
                 for (int j = 0; j < kLinkBatch; ++j) {
                   const int32_t dd = db0 + j;
-                  if (dd >= B1[e]) break;
                   const float ry = (yu + D[j].x) - y2;
                   const float rz = (zu + D[j].y) - z2;
                   const float sc = ry * ry + rz * rz;
-                  if (!(sc <= k.cut2)) continue;
-                  bool win = bu < 0 || sc < best;
-                  if (!win && sc == best) {
+                  // the best pair is kept with selects; only an exact tie takes a branch
+                  const bool ok = dd < B1[e] && sc <= k.cut2;
+                  bool win = ok && (bu < 0 || sc < best);
+                  if (ok && bu >= 0 && sc == best) {
                     const int32_t uo = G.gh[u].idx, bo = G.gh[bu].idx;
                     win = uo < bo || (uo == bo && G.gh[dd].idx < G.gh[bd].idx);
                   }
-                  if (win) {
-                    best = sc;
-                    bu = u;
-                    bd = dd;
-                  }
+                  best = win ? sc : best;
+                  bu = win ? u : bu;
+                  bd = win ? dd : bd;
                 }
               }
             }
