@@ -12,7 +12,7 @@
 // that reading (O1 frame/track model, O2 helix propagation, O3 grid (not
 // needed here: rows are searched in full or by binary search in z), O4
 // neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
-// O9 selection and fit, O10 merge), C1-C5 for the track-model compression that
+// O9 selection and fit, A13 downward extension, O10 merge), C1-C5 for the track-model compression that
 // consumes the tracks, E1-E5 for the rANS entropy coder after it, and F1-F6 for the
 // cluster finding before the tracking (section 5).
 //
@@ -32,9 +32,11 @@
 // finite differences; the Kalman update against the information-form identity;
 // the FP32 asin(u)/u series against libm; neighbour links against a
 // brute-force triple search; chain/ownership invariants; zero-smear fits
-// recovering the truth.  The hit-picking heuristic of the tracklet following
-// (O7 window search) and the merge pairing (O10) are pinned only by invariants
-// and special cases: parity unpinned beyond those.  Compression: the prediction
+// recovering the truth; the downward extension (A13) recovering every lower cluster of
+// tracks whose chains cannot start below a row, its miss limit, and the rule for
+// clusters found by two tracks.  The hit-picking heuristic of the tracklet following
+// (O7 window search), of the extension's window search (A13) and the merge pairing
+// (O10) are pinned only by invariants and special cases: parity unpinned beyond those.  Compression: the prediction
 // against an FP64 closed-form circle in the rotated frame, zero residual codes for
 // clusters placed exactly on the fitted helix, absolute codes against numpy's rint,
 // and the round trip within half a quantisation step.  Cluster finding: exact centroids
@@ -73,6 +75,7 @@ struct Params {
   float merge_edge, chi2_merge;                                  // O10
   float merge_dz;                                                // O10 z gate
   float v_drift;                                                 // T1 drift velocity, cm/us
+  int32_t ext_down;                                              // A13 downward extension (0: off)
 };
 
 // Pad-row plane positions (O1, reading A2): x_r = 85 + r * 160/151 cm, rounded once.
@@ -326,6 +329,8 @@ struct Track {
   int32_t job, sector, event;
   std::vector<int32_t> hits;  // original indices, inner -> outer
   float P[5], C[15], x, chi2; int32_t ndf;   // FP32 fit at the innermost hit
+  float L[5];                 // its compensation terms (the low parts of P)
+  int32_t n_ext = 0;          // hits gained by the downward extension (A13)
   double Pd[5], Cd[15], xd, chi2d; int32_t ndfd;   // FP64 refit
   // merge bookkeeping: a merged track keeps the inner piece's id; the outer piece is absorbed
   int32_t merged_into = -1;
@@ -617,7 +622,8 @@ struct Oracle {
   // -------- O9: Kalman refit from the outermost to the innermost hit
   template <class T>
   bool fit(const std::vector<int32_t>& hits, const float* sinit, int sec_outer,
-           const std::vector<int>& hit_sector, T* P, T* C, T& xout, T& chi2, int32_t& ndf) {
+           const std::vector<int>& hit_sector, T* P, T* C, T& xout, T& chi2, int32_t& ndf,
+           T* Lout = nullptr) {
     const T cb = curvature_factor<T>(p);
     const T vy = (T)p.sigma_y * (T)p.sigma_y, vz = (T)p.sigma_z * (T)p.sigma_z;
     const T smax = (T)p.smax;
@@ -651,6 +657,8 @@ struct Oracle {
     }
     xout = x;
     ndf = 2 * nh - 5;
+    if (Lout)
+      for (int i = 0; i < 5; ++i) Lout[i] = L[i];
     return true;
   }
 
@@ -660,6 +668,89 @@ struct Oracle {
 
   void fit_all() {
     for (Track& tr : tracks) fit_track(tr);
+    if (p.ext_down) extend_down();
+  }
+
+  // -------- A13: downward extension of the selected tracks.  The chain of a track need not
+  // start at the track's first row (a cluster lost to inefficiency or a link lost to a
+  // denser neighbourhood breaks it), and the following only visits the rows above the chain.
+  // So every track whose fit succeeded continues below its innermost hit: from the FP32
+  // fitted state there (compensation terms included) the rows under it are visited one by
+  // one, inwards, in the track's sector, the way the following visits the rows above a
+  // chain (O7: transport, 3-sigma window, minimum chi2 with ties to the smaller index, the
+  // chi2 cut, at most max_miss consecutive misses), except that only clusters owned by no
+  // selected track may be taken.  Two tracks may take the same cluster: it goes to the track
+  // with more owned hits, then to the smaller track id, and a track keeps its extension hits
+  // up to the first one it lost.  The kept hits are put in front of the track's hits (rows
+  // ascending) and the track is fitted again over the whole list.
+  void extend_down() {
+    const float cb = curvature_factor<float>(p);
+    const float vy = p.sigma_y * p.sigma_y, vz = p.sigma_z * p.sigma_z;
+    const int K = (int)tracks.size();
+    std::vector<uint8_t> owned(n, 0);
+    for (const Track& tr : tracks)
+      for (int32_t h : tr.hits) owned[h] = 1;
+    std::vector<std::vector<int32_t>> found(K);
+    for (int k = 0; k < K; ++k) {
+      const Track& tr = tracks[k];
+      if (tr.ndf < 0) continue;
+      float P[5], L[5], C[15];
+      std::memcpy(P, tr.P, sizeof(P));
+      std::memcpy(L, tr.L, sizeof(L));
+      std::memcpy(C, tr.C, sizeof(C));
+      float x = tr.x;
+      int misses = 0;
+      for (int r = row[tr.hits.front()] - 1; r >= 0; --r) {
+        const float xr = kGeo.x[r];
+        if (!propagate(P, L, C, x, xr, cb, p.smax)) break;
+        x = xr;
+        const SInv<float> si = s_inverse(C, vy, vz);
+        if (!si.ok) break;
+        const float wy = p.nwin * std::sqrt(C[tri(0, 0)] + vy);
+        const float wz = p.nwin * std::sqrt(C[tri(1, 1)] + vz);
+        int64_t lo, hi;
+        z_range(slot(tr.job, tr.sector, r), P[1] - wz - 0.01f, P[1] + wz + 0.01f, lo, hi);
+        int32_t best = -1;
+        float bchi = 0.f;
+        for (int64_t a = lo; a < hi; ++a) {
+          const int32_t c = slot_idx[a];
+          if (owned[c]) continue;
+          const float r0 = (y[c] - P[0]) - L[0];
+          const float r1 = (z[c] - P[1]) - L[1];
+          if (!(std::fabs(r0) <= wy) || !(std::fabs(r1) <= wz)) continue;
+          const float chi2 = chi2_of(si, r0, r1);
+          if (best < 0 || chi2 < bchi || (chi2 == bchi && c < best)) {
+            best = c;
+            bchi = chi2;
+          }
+        }
+        if (best >= 0 && bchi <= p.chi2_follow) {
+          if (!kf_update(P, L, C, y[best], z[best], vy, vz, p.smax, (float*)nullptr)) break;
+          found[k].push_back(best);
+          misses = 0;
+        } else if (++misses >= p.max_miss) {
+          break;
+        }
+      }
+    }
+    // contested clusters: more owned hits first, then the smaller track id
+    std::vector<uint64_t> key(K);
+    for (int k = 0; k < K; ++k)
+      key[k] = ((uint64_t)tracks[k].hits.size() << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+    std::vector<uint64_t> claim(n, 0);
+    for (int k = 0; k < K; ++k)
+      for (int32_t c : found[k]) claim[c] = std::max(claim[c], key[k]);
+    for (int k = 0; k < K; ++k) {
+      size_t m = 0;
+      while (m < found[k].size() && claim[found[k][m]] == key[k]) ++m;
+      if (m == 0) continue;
+      Track& tr = tracks[k];
+      std::vector<int32_t> h(found[k].rend() - (std::ptrdiff_t)m, found[k].rend());  // rows ascending
+      h.insert(h.end(), tr.hits.begin(), tr.hits.end());
+      tr.hits.swap(h);
+      tr.n_ext = (int32_t)m;
+      fit_track(tr);
+    }
   }
 
   void fit_track(Track& tr) {
@@ -669,7 +760,7 @@ struct Oracle {
     const Tracklet& st = tracklets[tracks[last].tracklet];
     const float sinit[3] = {st.P[2], st.P[3], st.P[4]};
     const int so = hs.back();
-    if (!fit<float>(tr.hits, sinit, so, hs, tr.P, tr.C, tr.x, tr.chi2, tr.ndf)) {
+    if (!fit<float>(tr.hits, sinit, so, hs, tr.P, tr.C, tr.x, tr.chi2, tr.ndf, tr.L)) {
       tr.ndf = -1;
       for (float& v : tr.P) v = NAN;
     }
@@ -1120,6 +1211,17 @@ void orc_get_tracks(void* h, int32_t merged, int32_t* tracklet, int32_t* job, in
     std::memcpy(Cd + 15 * m, t.Cd, sizeof(t.Cd));
     xd[m] = t.xd; chi2d[m] = t.chi2d; ndfd[m] = t.ndfd;
     ++m;
+  }
+}
+
+// A13: hits each output track gained by the downward extension (same order as orc_get_tracks;
+// a merged track reports its inner piece's)
+void orc_get_track_ext(void* h, int32_t merged, int32_t* n_ext) {
+  Oracle* o = (Oracle*)h;
+  int64_t m = 0;
+  for (auto& t : o->tracks) {
+    if (merged && t.merged_into >= 0) continue;
+    n_ext[m++] = t.n_ext;
   }
 }
 
