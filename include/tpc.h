@@ -73,6 +73,8 @@ typedef struct {
   float chi2_merge;                  /* max 5-D chi2 of a merged pair                  */
   float merge_dz;                    /* max |z| gap between the pieces' ends, cm        */
   float v_drift;                     /* drift velocity, cm/us (collision times)         */
+  int32_t ext_down;                  /* 1: extend the tracks below their innermost hit, */
+                                     /* 0 (default): no extension (see tpc_fit_merge)   */
 } tpc_params;
 
 /* Tunable launch shapes.  Results are identical for every valid setting.     */
@@ -157,9 +159,11 @@ int tpc_params_default(tpc_params* p);
 /* Cut sets of the two processing phases (section 2: the synchronous phase uses
  * different cuts to speed up the processing).  TPC_PRESET_ASYNC is the default
  * reading.  TPC_PRESET_SYNC serves the synchronous phase, whose tracks feed the
- * track-model compression: that attaches a cluster to any piece of its track,
- * so the pieces are not merged across sector edges (merge_edge < 0 disables the
- * merge); every other field is the default.  TPC_E_ARG for another preset.    */
+ * track-model compression (section 5): that attaches a cluster to any piece of
+ * its track, so the pieces are not merged across sector edges (merge_edge < 0
+ * disables the merge), and it codes the clusters on tracks as small residuals,
+ * so the tracks are extended below their innermost hits (ext_down = 1); every
+ * other field is the default.  TPC_E_ARG for another preset.                  */
 #define TPC_PRESET_ASYNC 0
 #define TPC_PRESET_SYNC 1
 int tpc_params_preset(tpc_params* p, int preset);
@@ -168,7 +172,7 @@ int tpc_tuning_default(tpc_tuning* t);
 /* Create a context on `device`, enqueueing on `hip_stream` (a hipStream_t; NULL =
  * the null stream).  Copies *p (NULL = defaults).  TPC_E_ARG if a field of *p is
  * not finite or outside its domain (sigma_y, sigma_z, nwin, v_drift > 0;
- * 0 < smax < 1; min_hits >= 3; max_miss >= 1; merge_dz >= 0).                   */
+ * 0 < smax < 1; min_hits >= 3; max_miss >= 1; merge_dz >= 0; ext_down 0 or 1). */
 int tpc_ctx_create(tpc_ctx** ctx, int device, void* hip_stream, const tpc_params* p);
 void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_set_stream(tpc_ctx* ctx, void* hip_stream);
@@ -194,7 +198,16 @@ int tpc_find_neighbours(tpc_ctx* ctx, int32_t* up, int32_t* down);
 int tpc_construct_tracklets(tpc_ctx* ctx, int32_t* n_tracklets);
 /* a5: selection.  n_selected ([1] device or NULL) receives K.                */
 int tpc_select_tracks(tpc_ctx* ctx, int32_t* n_selected);
-/* a6: refit, sector merge and merged refit; writes *out.                    */
+/* a6: refit, downward extension, sector merge and merged refit; writes *out.
+ * Downward extension (ext_down = 1): a track's chain need not start at the
+ * track's first row, and the following (section 6's tracking on the GPU) only
+ * visits the rows above the chain, so every track whose fit succeeded continues
+ * below its innermost hit, row by row inwards in its sector, with the following's
+ * window, chi2 cut and miss limit, taking only clusters that no selected track
+ * owns; a cluster found by several tracks goes to the one with more hits (then
+ * the smaller track id), a track keeps its found clusters up to the first one it
+ * lost, and its fit continues over them.  More clusters end up on tracks, which
+ * the track-model compression (section 5) codes as small residuals.           */
 int tpc_fit_merge(tpc_ctx* ctx, tpc_tracks* out);
 /* Run a1..a6 in order (graph-captured in TPC_MODE_BATCHED/PERSISTENT when the
  * tuning asks for it).                                                        */

@@ -44,8 +44,10 @@ DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_con
 
 
 # The synchronous phase's cut set (its tracks feed the compression, which attaches clusters to
-# track pieces alike): no merge across sector edges; everything else as DEFAULTS.
-SYNC = dict(DEFAULTS, merge_edge=-1.0)
+# track pieces alike and codes the clusters on tracks as small residuals): no merge across
+# sector edges, and the tracks extended below their innermost hits (A13); everything else as
+# DEFAULTS.
+SYNC = dict(DEFAULTS, merge_edge=-1.0, ext_down=1)
 
 
 def params(**over) -> Params:

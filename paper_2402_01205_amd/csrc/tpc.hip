@@ -1197,11 +1197,51 @@ struct FitView {
   const int32_t* sel_hits;
   const int32_t* chain_next;  // merged outer piece of a track, -1 if none (NULL: no merge)
   const int32_t* chain_prev;  // merged inner piece, -1 if none; chains are walked from heads only
-  float* row;                 // [capK][kFitStride]: P[5], C[15], x (one record per track)
+  float* row;                 // [capK][kFitStride]: P[5], C[15], x, L[5] (one record per track)
   float* chi2;
   int32_t* ndf;
   int32_t capK;
 };
+
+// The fit record of track kk: the state at the innermost hit (with its compensation terms,
+// which the downward extension continues from), chi2 and ndf; NaN parameters, zero
+// covariance and ndf = -1 when the fit failed.
+__device__ __forceinline__ void store_fit(const FitView& F, int32_t kk, const State& S, float x, float chi2,
+                                          int nh, bool ok) {
+  float v[kFitStride];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = ok ? S.P[i] : __builtin_nanf("");
+#pragma unroll
+  for (int i = 0; i < 15; ++i) v[5 + i] = ok ? S.C[i] : 0.f;
+  v[20] = ok ? x : 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[21 + i] = ok ? S.L[i] : 0.f;
+#pragma unroll
+  for (int i = 26; i < kFitStride; ++i) v[i] = 0.f;
+  float* dst = F.row + (int64_t)kk * kFitStride;
+#pragma unroll
+  for (int i = 0; i < kFitStride; i += 4)
+    *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+  F.chi2[kk] = ok ? chi2 : 0.f;
+  F.ndf[kk] = ok ? 2 * nh - 5 : -1;
+}
+
+__device__ __forceinline__ void load_fit(const FitView& F, int32_t kk, State& S, float& x) {
+  const float* src = F.row + (int64_t)kk * kFitStride;
+  float v[28];
+#pragma unroll
+  for (int i = 0; i < 28; i += 4) {
+    const float4 q = *reinterpret_cast<const float4*>(src + i);
+    v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S.P[i] = v[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) S.C[i] = v[5 + i];
+  x = v[20];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S.L[i] = v[21 + i];
+}
 
 // Fit of a hit list given as up to 18 consecutive pieces (inner -> outer); crossing a
 // piece boundary rotates the state into the inner piece's sector frame.
@@ -1250,19 +1290,7 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
       ++nh;
     }
   }
-  float v[kFitStride];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) v[i] = ok ? S.P[i] : __builtin_nanf("");
-#pragma unroll
-  for (int i = 0; i < 15; ++i) v[5 + i] = ok ? S.C[i] : 0.f;
-  v[20] = ok ? x : 0.f;
-  v[21] = v[22] = v[23] = 0.f;
-  float* dst = F.row + (int64_t)kk * kFitStride;
-#pragma unroll
-  for (int i = 0; i < kFitStride; i += 4)
-    *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
-  F.chi2[kk] = ok ? chi2 : 0.f;
-  F.ndf[kk] = ok ? 2 * nh - 5 : -1;
+  store_fit(F, kk, S, x, chi2, nh, ok);
 }
 
 __global__ __launch_bounds__(256) void k_fit(GridView G, TrackletView V, FitView F, Bound lo_b,
@@ -1281,6 +1309,181 @@ __global__ __launch_bounds__(256) void k_fit_heads(GridView G, TrackletView V, F
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *n_heads) return;
   fit_track(G, V, F, head_list[i], k);
+}
+
+// ------------------------------------------------------------------ downward extension
+// A track's chain need not start at its first row (a cluster lost to inefficiency or a
+// link lost in a dense neighbourhood breaks it), and the following visits only the rows
+// above the chain (reading A13).  Every track whose fit succeeded therefore continues
+// below its innermost hit: from the fitted state there, row by row inwards in its sector,
+// with the following's window, minimum chi2 (ties: smaller input index), chi2 cut and
+// miss limit, taking only clusters that no selected track owns.  A cluster found by
+// several tracks goes to the one with more owned hits, then the smaller track id (a
+// 32-bit max key, as for the tracklets: (owned hits << 24) | (2^24-1 - job-local track
+// id)); a track keeps its found hits up to the first one it lost.  The kept hits go in
+// front of the track's hits and its fit continues over them from the stored state, which
+// equals a refit of the whole list (the fit runs outer -> inner, hit to hit).
+struct ExtView {
+  const int32_t* K_off;    // [J+1] first track of each job
+  const int32_t* accf;     // [capT] 1 if the tracklet became a track
+  const int32_t* ext_off;  // [capK+1] first slot of each track in ext_hits (scan of its rows below)
+  int32_t* ext_hits;       // found clusters (grid order), rows descending, per track
+  int32_t* ext_n;          // [capK] found, then kept
+  uint32_t* claim;         // [N] grid order: max key of the tracks that found the cluster
+  int32_t* xn;             // [capK+1] hits of the extended track
+  int32_t capX;            // slots of ext_hits
+};
+
+// Rows below the innermost hit of every track whose fit succeeded: its slots in ext_hits.
+__global__ void k_ext_rows(GridView G, FitView F, ExtView E, int32_t* rows, Bound lo_b, Bound hi_b) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  rows[kk] = F.ndf[kk] >= 0 ? G.gh[F.sel_hits[F.sel_off[kk]]].slot % kRows : 0;
+}
+
+__device__ __forceinline__ uint32_t ext_key(const FitView& F, const ExtView& E, int32_t kk, int32_t slot) {
+  const int32_t local = kk - E.K_off[slot / kSlotsPerJob];
+  const int32_t n = F.sel_off[kk + 1] - F.sel_off[kk];
+  return ((uint32_t)n << 24) | (uint32_t)(kLocalIdMax - local);
+}
+
+// One lane per track: the search below the innermost hit; every found cluster is claimed.
+__global__ __launch_bounds__(128) void k_ext_search(GridView G, TrackletView V, FitView F, ExtView E,
+                                                    Bound lo_b, Bound hi_b, int32_t* counters, Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  int m = 0;
+  if (F.ndf[kk] >= 0) {
+    const int32_t hs = G.gh[F.sel_hits[F.sel_off[kk]]].slot;
+    const int r_in = hs % kRows;
+    const int32_t slot_base = hs - r_in;
+    const int32_t base = E.ext_off[kk];
+    if (base + r_in > E.capX) {
+      atomicOr(&counters[kCntStatus], kStatusCapacity);
+      E.ext_n[kk] = 0;
+      return;
+    }
+    const uint32_t key = ext_key(F, E, kk, hs);
+    State S;
+    float x;
+    load_fit(F, kk, S, x);
+    int misses = 0;
+    for (int r = r_in - 1; r >= 0; --r) {
+      const float xr = k.x[r];
+      if (!propagate(S, x, xr, k)) break;
+      x = xr;
+      const SInv si = s_inverse(S.C, k.vy, k.vz);
+      if (!si.ok) break;
+      const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
+      const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
+      const SlotGrid g = G.sg[slot_base + r];
+      int32_t cand = -1;
+      float bchi = 0.f, cy = 0.f, cz = 0.f;
+      if (g.ncell > 0) {
+        const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+        const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+        const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+        const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+        for (int zc = z0c; zc <= z1c; ++zc) {
+          const int32_t e0 = g.cbase + zc * g.ny;
+          const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
+          for (int32_t c = a0; c < a1; ++c) {
+            const float2 Cc = G.yz[c];
+            const float rr0 = (Cc.x - S.P[0]) - S.L[0];
+            const float rr1 = (Cc.y - S.P[1]) - S.L[1];
+            if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+            const float chi2 = chi2_of(si, rr0, rr1);
+            if (!(cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx))) continue;
+            // owned by a selected track: not a candidate (looked up only for a would-be winner)
+            const uint32_t w = V.hitw[c];
+            if (w != 0u) {
+              const int32_t t = key_tracklet(w, V.T_off, slot_base);
+              if ((uint32_t)t < (uint32_t)V.capT && E.accf[t]) continue;
+            }
+            cand = c;
+            bchi = chi2;
+            cy = Cc.x;
+            cz = Cc.y;
+          }
+        }
+      }
+      if (cand >= 0 && bchi <= k.chi2_follow) {
+        if (!kf_update(S, cy, cz, k, nullptr)) break;
+        E.ext_hits[base + m] = cand;
+        ++m;
+        atomicMax(&E.claim[cand], key);
+        misses = 0;
+      } else if (++misses >= k.max_miss) {
+        break;
+      }
+    }
+  }
+  E.ext_n[kk] = m;
+}
+
+// One lane per track: the kept prefix of the found hits, the fit continued over them, and
+// the length of the extended hit list.
+__global__ __launch_bounds__(128) void k_ext_keep(GridView G, FitView F, ExtView E, Bound lo_b, Bound hi_b,
+                                                  Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= hi) return;
+  const int32_t n0 = F.sel_off[kk + 1] - F.sel_off[kk];
+  const int m = E.ext_n[kk];
+  int kept = 0;
+  if (m > 0) {
+    const int32_t base = E.ext_off[kk];
+    const int32_t hs = G.gh[F.sel_hits[F.sel_off[kk]]].slot;
+    const uint32_t key = ext_key(F, E, kk, hs);
+    while (kept < m && E.claim[E.ext_hits[base + kept]] == key) ++kept;
+    if (kept > 0) {
+      State S;
+      float x;
+      load_fit(F, kk, S, x);
+      float chi2 = F.chi2[kk];
+      bool ok = true;
+      for (int q = 0; q < kept && ok; ++q) {
+        const GHit Hq = ldh(G.gh + E.ext_hits[base + q]);
+        const float xh = k.x[Hq.slot % kRows];
+        if (!propagate(S, x, xh, k)) { ok = false; break; }
+        x = xh;
+        float c2;
+        if (!kf_update(S, Hq.y, Hq.z, k, &c2)) { ok = false; break; }
+        chi2 = chi2 + c2;
+      }
+      store_fit(F, kk, S, x, chi2, n0 + kept, ok);
+    }
+  }
+  E.ext_n[kk] = kept;
+  E.xn[kk] = n0 + kept;
+}
+
+// One wave per track: the extended hit list (kept hits in ascending rows, then the owned
+// hits) written at its offset in the new list.
+__global__ __launch_bounds__(256) void k_ext_write(FitView F, ExtView E, const int32_t* xoff, int32_t* xhits,
+                                                   Bound lo_b, Bound hi_b, int32_t capH, int32_t* counters) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w0 = lo + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); w0 < hi; w0 += nw) {
+    const int32_t kk = (int32_t)w0;
+    const int32_t o = xoff[kk];
+    const int kept = E.ext_n[kk];
+    const int32_t base = E.ext_off[kk];
+    const int32_t q0 = F.sel_off[kk], q1 = F.sel_off[kk + 1];
+    const int32_t n = kept + (q1 - q0);
+    for (int32_t i = lane; i < n; i += 64) {
+      const int32_t c = i < kept ? E.ext_hits[base + kept - 1 - i] : F.sel_hits[q0 + i - kept];
+      if (o + i < capH) xhits[o + i] = c;
+    }
+    if (lane == 0 && o + n > capH) atomicOr(&counters[kCntStatus], kStatusCapacity);
+  }
 }
 
 // --- merge: candidate search.  Tracks are bucketed by (event, sector).
@@ -2483,6 +2686,11 @@ struct Layout {
   float* trk_state;
   uint32_t* hitw;
   int32_t *own, *accf, *kid, *hoff, *sel_off, *sel_hits, *sel_from;
+  // downward extension: slots of the found hits, the hits, their counts, the claims, and the
+  // extended hit lists (the tracks' lists from then on)
+  int32_t capX = 0;
+  int32_t *ext_off, *ext_hits, *ext_n, *xn, *xsel_off, *xsel_hits;
+  uint32_t* claim;
   float *fitrow, *fitchi2;
   int32_t* fitndf;
   int32_t *T_off, *K_off, *counters, *bsum;
@@ -2559,6 +2767,14 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.sel_off, L.capK + 1, t, set);
   carve(p, L.sel_hits, L.capH, t, set);
   carve(p, L.sel_from, L.capK, t, set);
+  L.capX = (int32_t)(N + 1);
+  carve(p, L.ext_off, L.capK + 1, t, set);
+  carve(p, L.ext_n, L.capK + 1, t, set);
+  carve(p, L.ext_hits, L.capX, t, set);
+  carve(p, L.claim, N, t, set);
+  carve(p, L.xn, L.capK + 1, t, set);
+  carve(p, L.xsel_off, L.capK + 1, t, set);
+  carve(p, L.xsel_hits, L.capH, t, set);
   carve(p, L.fitrow, (int64_t)kFitStride * L.capK, t, set);
   carve(p, L.fitchi2, L.capK, t, set);
   carve(p, L.fitndf, L.capK, t, set);
@@ -2757,9 +2973,18 @@ TrackletView make_tv(tpc_ctx* c) {
   return TrackletView{L.start, L.up_raw, L.dn_raw, L.up, L.trk_hits, L.trk_n, L.trk_state, L.hitw, L.T_off,
                       L.capT};
 }
-FitView make_fv(tpc_ctx* c, bool with_chain) {
+// The tracks' hit lists: the selection's, or after the downward extension (when enabled)
+// the extended ones.
+const int32_t* trk_off(tpc_ctx* c, bool extended) {
+  return extended && c->p.ext_down ? c->L.xsel_off : c->L.sel_off;
+}
+const int32_t* trk_hits(tpc_ctx* c, bool extended) {
+  return extended && c->p.ext_down ? c->L.xsel_hits : c->L.sel_hits;
+}
+
+FitView make_fv(tpc_ctx* c, bool with_chain, bool extended) {
   Layout& L = c->L;
-  return FitView{L.sel_from, L.sel_off, L.sel_hits, with_chain ? L.chain_next : nullptr,
+  return FitView{L.sel_from, trk_off(c, extended), trk_hits(c, extended), with_chain ? L.chain_next : nullptr,
                  with_chain ? L.chain_prev : nullptr, L.fitrow, L.fitchi2, L.fitndf, L.capK};
 }
 
@@ -2914,13 +3139,17 @@ int tpc_params_default(tpc_params* p) {
   p->chi2_merge = 50.0f;
   p->merge_dz = 20.0f;
   p->v_drift = 2.58f;
+  p->ext_down = 0;
   return TPC_OK;
 }
 
 int tpc_params_preset(tpc_params* p, int preset) {
   if (!p || (preset != TPC_PRESET_ASYNC && preset != TPC_PRESET_SYNC)) return TPC_E_ARG;
   tpc_params_default(p);
-  if (preset == TPC_PRESET_SYNC) p->merge_edge = -1.0f;
+  if (preset == TPC_PRESET_SYNC) {
+    p->merge_edge = -1.0f;
+    p->ext_down = 1;
+  }
   return TPC_OK;
 }
 
@@ -2943,7 +3172,8 @@ static bool params_ok(const tpc_params& p) {
   for (float v : f)
     if (!std::isfinite(v)) return false;
   return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
-         p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f;
+         p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f &&
+         (p.ext_down == 0 || p.ext_down == 1);
 }
 
 // the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))
@@ -3156,15 +3386,31 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   // per-track fit (no merge yet): the track range is [K_off[j0], K_off[j1])
   auto fit_range = [&](int j0, int j1, int64_t bound) {
     hipLaunchKernelGGL(k_fit, dim3(blocks_for(bound, 128)), dim3(128), 0, c->stream, make_grid(c), make_tv(c),
-                       make_fv(c, false), dbc(L.K_off + j0, L.capK), dbc(L.K_off + j1, L.capK), c->k);
+                       make_fv(c, false, false), dbc(L.K_off + j0, L.capK), dbc(L.K_off + j1, L.capK), c->k);
   };
   if (c->mode == TPC_MODE_PLAIN) {
     for (int j = 0; j < J; ++j) fit_range(j, j + 1, std::min<int64_t>((c->job_off_h[j + 1] - c->job_off_h[j]) / 3 + 1, L.capK));
   } else {
     fit_range(0, J, kb);
   }
-  // ---- merge across adjacent sectors of one event
   const Bound klo = hb(0), khi = dbc(L.counters + kCntSelected, L.capK);
+  // ---- downward extension below the innermost hits (all selected tracks at once)
+  if (c->p.ext_down) {
+    const ExtView E{L.K_off, L.accf, L.ext_off, L.ext_hits, L.ext_n, L.claim, L.xn, L.capX};
+    const FitView F = make_fv(c, false, false);
+    hipLaunchKernelGGL(k_ext_rows, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_grid(c), F, E,
+                       L.ext_n, klo, khi);
+    scan(c, L.ext_n, L.ext_off, klo, khi, kb, false);
+    fill_i32(c, (int32_t*)L.claim, L.N, 0);
+    hipLaunchKernelGGL(k_ext_search, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
+                       make_tv(c), F, E, klo, khi, L.counters, c->k);
+    hipLaunchKernelGGL(k_ext_keep, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c), F, E, klo,
+                       khi, c->k);
+    scan(c, L.xn, L.xsel_off, klo, khi, kb, false);
+    hipLaunchKernelGGL(k_ext_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, F, E, L.xsel_off,
+                       L.xsel_hits, klo, khi, L.capH, L.counters);
+  }
+  // ---- merge across adjacent sectors of one event
   const int nev = J;
   const int64_t nbk = (int64_t)nev * kSectors * 2 * L.nzb;
   fill_i32(c, L.bucket_cnt, nbk + 1, 0);
@@ -3175,30 +3421,30 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
   fill_i32(c, L.counters + kCntMergeCand, 1, 0);
   hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.sel_off, L.sel_hits, L.gh, c->jobs.job_event, L.fitndf, L.trk_event, L.bucket_cnt, klo,
+                     trk_off(c, true), trk_hits(c, true), L.gh, c->jobs.job_event, L.fitndf, L.trk_event, L.bucket_cnt, klo,
                      khi, L.capK, nev, L.nzb, c->k, L.counters);
   scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb((int32_t)nbk), nbk, false);
   MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bucket_z, L.bestA,
               L.bestB, L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev, L.nzb,
               c->p.merge_dz};
   hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     L.sel_off, L.sel_hits, L.gh, L.fitndf, M, klo, khi, L.capK, c->k);
+                     trk_off(c, true), trk_hits(c, true), L.gh, L.fitndf, M, klo, khi, L.capK, c->k);
   hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
-                     make_tv(c), make_fv(c, false), M, klo, khi, c->k);
+                     make_tv(c), make_fv(c, false, true), M, klo, khi, c->k);
   hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);
   hipLaunchKernelGGL(k_merge_heads, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK,
                      L.keep);
   hipLaunchKernelGGL(k_fit_heads, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
-                     make_tv(c), make_fv(c, true), L.head_list, L.counters + kCntMergeCand, c->k);
+                     make_tv(c), make_fv(c, true, true), L.head_list, L.counters + kCntMergeCand, c->k);
   // ---- output compaction in track-id order
-  hipLaunchKernelGGL(k_out_count, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_fv(c, true),
+  hipLaunchKernelGGL(k_out_count, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_fv(c, true, true),
                      L.keep, L.outn, klo, khi);
   scan(c, L.keep, L.oid, klo, khi, kb, false);
   scan(c, L.outn, L.ooff, klo, khi, kb, false);
   OutView O{out->cap_tracks, out->cap_hits, out->n_tracks, out->hit_off, out->hits, out->param, out->cov,
             out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet, out->t0};
   hipLaunchKernelGGL(k_out_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
-                     make_fv(c, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters, c->k);
+                     make_fv(c, true, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters, c->k);
   hipLaunchKernelGGL(k_out_finish, dim3(1), dim3(1), 0, c->stream, L.oid, L.ooff, khi, L.capK, O, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());

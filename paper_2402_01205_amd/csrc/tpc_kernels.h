@@ -55,8 +55,9 @@ constexpr int kHitStride = 160;
 // Largest job-local tracklet id that the 32-bit hit-weight key can hold.
 constexpr int32_t kLocalIdMax = (1 << 24) - 1;
 constexpr int kStateStride = 24;
-// Fitted track records: P[5], C[15], x, padding (kFitStride floats, 32-byte aligned).
-constexpr int kFitStride = 24;
+// Fitted track records: P[5], C[15], x, the compensation terms L[5], padding (kFitStride
+// floats, one 128-byte line).
+constexpr int kFitStride = 32;
 
 struct SlotGrid {
   float ylo, zlo, inv_by, inv_bz;

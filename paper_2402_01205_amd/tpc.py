@@ -32,7 +32,8 @@ class tpc_params(C.Structure):
         "cy0", "cz0", "cs0", "ct0", "ck0", "cy1", "cz1", "cs1", "ct1", "ck1",
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
-        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")]
+        (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")] + [
+        ("ext_down", C.c_int32)]
 
 
 class tpc_tuning(C.Structure):
