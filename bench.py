@@ -331,6 +331,52 @@ def compression_run(tr, cs, tracks, steps, log):
     return out
 
 
+def sync_preset_run(ev, cs, tracks, tuning, args, timed, log, torch):
+    """The synchronous phase's cut set on the same workload (no merge across sector edges,
+    tracks extended below their innermost hits): step time, per-stage times, tracking quality,
+    the share of clusters on tracks and what that does to the compression."""
+    from paper_2402_01205_amd.evaluate import quality
+    from paper_2402_01205_amd.tpc import Tracker, preset_params
+    ts = Tracker(0, params=preset_params("sync"), mode=args.mode, tuning=tuning)
+    ts.run(ev)
+    ts.sync()
+    sms = timed(ts, args.steps)
+    ts.sync()
+    st = ts.tracks()
+    ts.profile(True)
+    ts.profile_read(reset=True)
+    for _ in range(args.steps):
+        ts.run(ev)
+    sprof = ts.profile_read(reset=True)
+    ts.profile(False)
+    sq = quality(cs.label, cs.job_off, cs.sector, st["off"], st["hits"], cs.part_off, cs.part_pt,
+                 by_job=cs.n_jobs > 1)
+    if "per_job" in sq:
+        sq["by_job_size_decile"] = by_decile(sq.pop("per_job"), np.diff(cs.job_off))
+    sc = compression_run(ts, cs, st, args.steps, lambda m: None)
+    sig = cs.label >= 0
+
+    def attached_signal(t):
+        a = np.zeros(cs.n, bool)
+        a[t["hits"]] = True
+        return float(a[sig].mean())
+
+    row = {"params": "TPC_PRESET_SYNC (merge_edge < 0, ext_down = 1)", "ms_per_step": sms,
+           "clusters_per_s": cs.n / (sms / 1e3), "tracks": int(st["n"]),
+           "stages_ms": {k: v[0] / max(1, v[1]) for k, v in sprof.items() if v[1]},
+           "attached_clusters": int(st["off"][-1]) / cs.n,
+           "async_attached_clusters": int(tracks["off"][-1]) / cs.n,
+           "attached_signal_clusters": attached_signal(st),
+           "async_attached_signal_clusters": attached_signal(tracks),
+           "quality": sq,
+           "compression": {k: sc[k] for k in ("ms", "track_hit_records", "residual_records",
+                                             "entropy_bits_per_cluster")},
+           "rans_coded_bits_per_cluster": sc["rans"]["coded_bits_per_cluster"]}
+    log("sync preset: " + json.dumps({k: v for k, v in row.items() if k != "quality"}))
+    del ts
+    return row
+
+
 def cf_cpu_baseline(dg):
     """The oracle's cluster finder on the digits of sectors 0-3 of the digit workload."""
     import oracle.oracle as O
@@ -620,6 +666,7 @@ def main():
     log("stage ms/step: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f}" for k, v in prof.items() if v[1]))
     log("kernels: " + json.dumps(kern))
     compression = compression_run(tr, cs, tracks, args.steps, log)
+    sync_row = sync_preset_run(ev, cs, tracks, tuning, args, timed, log, torch)
     clusters_row = cf_run(tr, dg, args.steps, torch) if dg is not None else None
     if clusters_row is not None:
         clusters_row["cpu_baseline"] = cf_cpu
@@ -766,6 +813,7 @@ def main():
         "tuning": tune_report["best"] if tune_report else None,
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items() if v[1]},
         "compression": compression,
+        "sync_preset": sync_row,
         "cluster_finding": clusters_row,
         "tracks": int(tracks["n"]),
         "tracklets": int(T),

@@ -1349,80 +1349,103 @@ __device__ __forceinline__ uint32_t ext_key(const FitView& F, const ExtView& E, 
   return ((uint32_t)n << 24) | (uint32_t)(kLocalIdMax - local);
 }
 
-// One lane per track: the search below the innermost hit; every found cluster is claimed.
+// The search of one track as a step machine: ext_begin sets it up (false when there is
+// nothing to search: a failed fit, the innermost hit on row 0, or no room in ext_hits),
+// ext_step searches one row (true when the search has ended) and claims what it finds.
+struct ExtLane {
+  State S;
+  float x;
+  int32_t kk, base, slot_base;
+  uint32_t key;
+  int r, misses, m;
+};
+
+__device__ __forceinline__ bool ext_begin(const GridView& G, const FitView& F, const ExtView& E, ExtLane& T,
+                                          int32_t kk, int32_t* counters) {
+  T.kk = kk;
+  T.m = 0;
+  if (F.ndf[kk] < 0) return false;
+  const int32_t hs = G.gh[F.sel_hits[F.sel_off[kk]]].slot;
+  const int r_in = hs % kRows;
+  if (r_in == 0) return false;
+  T.slot_base = hs - r_in;
+  T.base = E.ext_off[kk];
+  if (T.base + r_in > E.capX) {
+    atomicOr(&counters[kCntStatus], kStatusCapacity);
+    return false;
+  }
+  T.key = ext_key(F, E, kk, hs);
+  load_fit(F, kk, T.S, T.x);
+  T.r = r_in - 1;
+  T.misses = 0;
+  return true;
+}
+
+__device__ __forceinline__ bool ext_step(const GridView& G, const TrackletView& V, const ExtView& E, ExtLane& T,
+                                         const Consts& k) {
+  const float xr = k.x[T.r];
+  if (!propagate(T.S, T.x, xr, k)) return true;
+  T.x = xr;
+  const SInv si = s_inverse(T.S.C, k.vy, k.vz);
+  if (!si.ok) return true;
+  const float wy = k.nwin * sqrt_rn(T.S.C[0] + k.vy);
+  const float wz = k.nwin * sqrt_rn(T.S.C[2] + k.vz);
+  const SlotGrid g = G.sg[T.slot_base + T.r];
+  int32_t cand = -1;
+  float bchi = 0.f, cy = 0.f, cz = 0.f;
+  if (g.ncell > 0) {
+    const int y0c = cell_of(T.S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+    const int y1c = cell_of(T.S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+    const int z0c = cell_of(T.S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+    const int z1c = cell_of(T.S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+    for (int zc = z0c; zc <= z1c; ++zc) {
+      const int32_t e0 = g.cbase + zc * g.ny;
+      const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
+      for (int32_t c = a0; c < a1; ++c) {
+        const float2 Cc = G.yz[c];
+        const float rr0 = (Cc.x - T.S.P[0]) - T.S.L[0];
+        const float rr1 = (Cc.y - T.S.P[1]) - T.S.L[1];
+        if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+        const float chi2 = chi2_of(si, rr0, rr1);
+        if (!(cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx))) continue;
+        // owned by a selected track: not a candidate (looked up only for a would-be winner)
+        const uint32_t w = V.hitw[c];
+        if (w != 0u) {
+          const int32_t t = key_tracklet(w, V.T_off, T.slot_base);
+          if ((uint32_t)t < (uint32_t)V.capT && E.accf[t]) continue;
+        }
+        cand = c;
+        bchi = chi2;
+        cy = Cc.x;
+        cz = Cc.y;
+      }
+    }
+  }
+  if (cand >= 0 && bchi <= k.chi2_follow) {
+    if (!kf_update(T.S, cy, cz, k, nullptr)) return true;
+    E.ext_hits[T.base + T.m] = cand;
+    ++T.m;
+    atomicMax(&E.claim[cand], T.key);
+    T.misses = 0;
+  } else if (++T.misses >= k.max_miss) {
+    return true;
+  }
+  return --T.r < 0;
+}
+
+// One lane per track.
 __global__ __launch_bounds__(128) void k_ext_search(GridView G, TrackletView V, FitView F, ExtView E,
                                                     Bound lo_b, Bound hi_b, int32_t* counters, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
-  int m = 0;
-  if (F.ndf[kk] >= 0) {
-    const int32_t hs = G.gh[F.sel_hits[F.sel_off[kk]]].slot;
-    const int r_in = hs % kRows;
-    const int32_t slot_base = hs - r_in;
-    const int32_t base = E.ext_off[kk];
-    if (base + r_in > E.capX) {
-      atomicOr(&counters[kCntStatus], kStatusCapacity);
-      E.ext_n[kk] = 0;
-      return;
-    }
-    const uint32_t key = ext_key(F, E, kk, hs);
-    State S;
-    float x;
-    load_fit(F, kk, S, x);
-    int misses = 0;
-    for (int r = r_in - 1; r >= 0; --r) {
-      const float xr = k.x[r];
-      if (!propagate(S, x, xr, k)) break;
-      x = xr;
-      const SInv si = s_inverse(S.C, k.vy, k.vz);
-      if (!si.ok) break;
-      const float wy = k.nwin * sqrt_rn(S.C[0] + k.vy);
-      const float wz = k.nwin * sqrt_rn(S.C[2] + k.vz);
-      const SlotGrid g = G.sg[slot_base + r];
-      int32_t cand = -1;
-      float bchi = 0.f, cy = 0.f, cz = 0.f;
-      if (g.ncell > 0) {
-        const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
-        const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
-        const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
-        const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
-        for (int zc = z0c; zc <= z1c; ++zc) {
-          const int32_t e0 = g.cbase + zc * g.ny;
-          const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
-          for (int32_t c = a0; c < a1; ++c) {
-            const float2 Cc = G.yz[c];
-            const float rr0 = (Cc.x - S.P[0]) - S.L[0];
-            const float rr1 = (Cc.y - S.P[1]) - S.L[1];
-            if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
-            const float chi2 = chi2_of(si, rr0, rr1);
-            if (!(cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx))) continue;
-            // owned by a selected track: not a candidate (looked up only for a would-be winner)
-            const uint32_t w = V.hitw[c];
-            if (w != 0u) {
-              const int32_t t = key_tracklet(w, V.T_off, slot_base);
-              if ((uint32_t)t < (uint32_t)V.capT && E.accf[t]) continue;
-            }
-            cand = c;
-            bchi = chi2;
-            cy = Cc.x;
-            cz = Cc.y;
-          }
-        }
-      }
-      if (cand >= 0 && bchi <= k.chi2_follow) {
-        if (!kf_update(S, cy, cz, k, nullptr)) break;
-        E.ext_hits[base + m] = cand;
-        ++m;
-        atomicMax(&E.claim[cand], key);
-        misses = 0;
-      } else if (++misses >= k.max_miss) {
-        break;
-      }
+  ExtLane T;
+  if (ext_begin(G, F, E, T, kk, counters)) {
+    while (!ext_step(G, V, E, T, k)) {
     }
   }
-  E.ext_n[kk] = m;
+  E.ext_n[kk] = T.m;
 }
 
 // One lane per track: the kept prefix of the found hits, the fit continued over them, and
