@@ -75,6 +75,8 @@ typedef struct {
   float v_drift;                     /* drift velocity, cm/us (collision times)         */
   int32_t ext_down;                  /* 1: extend the tracks below their innermost hit, */
                                      /* 0 (default): no extension (see tpc_fit_merge)   */
+  int32_t merge_membrane;            /* 1: merge pieces across the central membrane,   */
+                                     /* 0 (default): no such merge (see tpc_fit_merge)  */
 } tpc_params;
 
 /* Tunable launch shapes.  Results are identical for every valid setting.     */

@@ -32,7 +32,7 @@ class Params(C.Structure):
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
         (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")] + [
-        ("ext_down", C.c_int32)]
+        ("ext_down", C.c_int32), ("merge_membrane", C.c_int32)]
 
 
 # The readings of every unstated constant (windows, cuts, priors, thresholds).
@@ -40,7 +40,7 @@ DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_con
                 link_cut=1.0, cy0=1.0, cz0=1.0, cs0=0.25, ct0=0.25, ck0=100.0,
                 cy1=1.0, cz1=1.0, cs1=1e-3, ct1=1e-3, ck1=1.0, sigma_y=0.1, sigma_z=0.1,
                 nwin=3.0, chi2_follow=15.0, max_miss=4, min_hits=10, smax=0.95, bz=0.5,
-                merge_edge=5.0, chi2_merge=50.0, merge_dz=20.0, v_drift=2.58, ext_down=0)
+                merge_edge=5.0, chi2_merge=50.0, merge_dz=20.0, v_drift=2.58, ext_down=0, merge_membrane=0)
 
 
 # The synchronous phase's cut set (its tracks feed the compression, which attaches clusters to

@@ -76,6 +76,7 @@ struct Params {
   float merge_dz;                                                // O10 z gate
   float v_drift;                                                 // T1 drift velocity, cm/us
   int32_t ext_down;                                              // A13 downward extension (0: off)
+  int32_t merge_membrane;                                        // A21 central-membrane merge (0: off)
 };
 
 // Pad-row plane positions (O1, reading A2): x_r = 85 + r * 160/151 cm, rounded once.
@@ -331,6 +332,8 @@ struct Track {
   float P[5], C[15], x, chi2; int32_t ndf;   // FP32 fit at the innermost hit
   float L[5];                 // its compensation terms (the low parts of P)
   int32_t n_ext = 0;          // hits gained by the downward extension (A13)
+  float link_t0 = NAN;        // A21: collision time of the membrane link to the outer partner
+  float t0m = NAN;            // A21: a chain head's collision time from its membrane link
   double Pd[5], Cd[15], xd, chi2d; int32_t ndfd;   // FP64 refit
   // merge bookkeeping: a merged track keeps the inner piece's id; the outer piece is absorbed
   int32_t merged_into = -1;
@@ -623,7 +626,7 @@ struct Oracle {
   template <class T>
   bool fit(const std::vector<int32_t>& hits, const float* sinit, int sec_outer,
            const std::vector<int>& hit_sector, T* P, T* C, T& xout, T& chi2, int32_t& ndf,
-           T* Lout = nullptr) {
+           T* Lout = nullptr, const std::vector<float>* zshift = nullptr) {
     const T cb = curvature_factor<T>(p);
     const T vy = (T)p.sigma_y * (T)p.sigma_y, vz = (T)p.sigma_z * (T)p.sigma_z;
     const T smax = (T)p.smax;
@@ -644,8 +647,14 @@ struct Oracle {
     for (int i = nh - 1; i >= 0; --i) {
       const int32_t h = hits[i];
       if (hit_sector[i] != cur_sec) {
-        // crossing into the neighbouring sector of the inner piece (O10)
-        if (!rotate(P, L, C, x, cur_sec, hit_sector[i])) return false;
+        if ((hit_sector[i] < kRowsPerSide) != (cur_sec < kRowsPerSide)) {
+          // crossing the central membrane into the inner piece's side (A21): the same
+          // sector frame, z moved by the drift of the link's collision time
+          acc(P[1], L[1], zshift ? (T)(*zshift)[i] : T(0));
+        } else {
+          // crossing into the neighbouring sector of the inner piece (O10)
+          if (!rotate(P, L, C, x, cur_sec, hit_sector[i])) return false;
+        }
         cur_sec = hit_sector[i];
       }
       const T xh = (T)kGeo.x[row[h]];
@@ -756,16 +765,37 @@ struct Oracle {
   void fit_track(Track& tr) {
     std::vector<int> hs(tr.hits.size());
     for (size_t i = 0; i < tr.hits.size(); ++i) hs[i] = sector[tr.hits[i]];
-    const int last = tr.pieces.empty() ? (int)(&tr - tracks.data()) : tr.pieces.back();
+    const int self = (int)(&tr - tracks.data());
+    const int last = tr.pieces.empty() ? self : tr.pieces.back();
     const Tracklet& st = tracklets[tracks[last].tracklet];
     const float sinit[3] = {st.P[2], st.P[3], st.P[4]};
     const int so = hs.back();
-    if (!fit<float>(tr.hits, sinit, so, hs, tr.P, tr.C, tr.x, tr.chi2, tr.ndf, tr.L)) {
+    // A21: the z shift at each membrane crossing of a chain, entered on the inner piece's
+    // outermost hit: the drift of the link's collision time, twice (one side's z is short
+    // of the true z by v t0, the other's long by as much)
+    std::vector<float> zs(tr.hits.size(), 0.f);
+    if (!tr.pieces.empty()) {
+      std::vector<int> chain = {self};
+      chain.insert(chain.end(), tr.pieces.begin(), tr.pieces.end());
+      size_t absorbed = 0;
+      for (size_t c = 1; c < chain.size(); ++c) absorbed += tracks[chain[c]].hits.size();
+      size_t pos = tr.hits.size() - absorbed;  // one past the head's own hits
+      for (size_t c = 0; c + 1 < chain.size(); ++c) {
+        const int inner = chain[c];
+        const bool a_side = tracks[inner].sector < kRowsPerSide;
+        if (a_side != (tracks[chain[c + 1]].sector < kRowsPerSide)) {
+          const float d = (2.0f * p.v_drift) * tracks[inner].link_t0;
+          zs[pos - 1] = a_side ? -d : d;
+        }
+        pos += tracks[chain[c + 1]].hits.size();
+      }
+    }
+    if (!fit<float>(tr.hits, sinit, so, hs, tr.P, tr.C, tr.x, tr.chi2, tr.ndf, tr.L, &zs)) {
       tr.ndf = -1;
       for (float& v : tr.P) v = NAN;
     }
     const auto t0 = std::chrono::steady_clock::now();
-    if (!fit<double>(tr.hits, sinit, so, hs, tr.Pd, tr.Cd, tr.xd, tr.chi2d, tr.ndfd)) {
+    if (!fit<double>(tr.hits, sinit, so, hs, tr.Pd, tr.Cd, tr.xd, tr.chi2d, tr.ndfd, nullptr, &zs)) {
       tr.ndfd = -1;
       for (double& v : tr.Pd) v = NAN;
     }
@@ -789,10 +819,15 @@ struct Oracle {
     std::unordered_map<int64_t, std::vector<int32_t>> by_sector;
     for (int b = 0; b < K; ++b) by_sector[(int64_t)tracks[b].event * kSectors + tracks[b].sector].push_back(b);
     const std::vector<int32_t> none;
+    auto consider = [&](int a, int b, float c) {
+      if (argA[a] < 0 || c < bestA[a] || (c == bestA[a] && b < argA[a])) { bestA[a] = c; argA[a] = b; }
+      if (argB[b] < 0 || c < bestB[b] || (c == bestB[b] && a < argB[b])) { bestB[b] = c; argB[b] = a; }
+    };
     for (int a = 0; a < K; ++a) {
       const Track& A = tracks[a];
       if (A.ndf < 0) continue;
       const Tracklet& ta = tracklets[A.tracklet];
+      if (p.merge_membrane) membrane_candidates(a, by_sector, consider);
       const float edge = ta.x * kGeo.tan10 - std::fabs(ta.P[0]);
       if (!(edge <= p.merge_edge)) continue;
       const int dir = ta.P[0] > 0.f ? 1 : kRowsPerSide - 1;
@@ -816,8 +851,7 @@ struct Oracle {
         if (!propagate(P, L, C, x, B.x, cb, p.smax)) continue;
         const float c = merge_chi2(P, C, B.P, B.C);
         if (!(c <= p.chi2_merge)) continue;
-        if (argA[a] < 0 || c < bestA[a] || (c == bestA[a] && b < argA[a])) { bestA[a] = c; argA[a] = b; }
-        if (argB[b] < 0 || c < bestB[b] || (c == bestB[b] && a < argB[b])) { bestB[b] = c; argB[b] = a; }
+        consider(a, b, c);
       }
     }
     std::vector<int32_t> prev(K, -1);
@@ -826,20 +860,111 @@ struct Oracle {
       if (b >= 0 && argB[b] == a) {
         tracks[a].partner = b;
         prev[b] = a;
+        if ((tracks[a].sector < kRowsPerSide) != (tracks[b].sector < kRowsPerSide)) {
+          float P[5], C[15];
+          membrane_transport(tracklets[tracks[a].tracklet], tracks[b], P, C);
+          tracks[a].link_t0 = membrane_t0(tracks[a].sector < kRowsPerSide, P[1], tracks[b].P[1]);
+        }
       }
     }
     for (int a = 0; a < K; ++a) {
       if (prev[a] >= 0 || tracks[a].partner < 0) continue;   // chain heads only
       Track& A = tracks[a];
       // a chain walked from its head is a simple path (every piece has one inner partner)
+      int inner = a;
       for (int b = A.partner; b >= 0 && (int)A.pieces.size() < kRowsPerSide; b = tracks[b].partner) {
         tracks[b].merged_into = a;
         A.pieces.push_back(b);
         A.hits.insert(A.hits.end(), tracks[b].hits.begin(), tracks[b].hits.end());
         A.sector2 = tracks[b].sector;
+        // the chain's collision time: its innermost membrane link's (A21)
+        if (std::isnan(A.t0m) && (tracks[inner].sector < kRowsPerSide) != (tracks[b].sector < kRowsPerSide))
+          A.t0m = tracks[inner].link_t0;
+        inner = b;
       }
       fit_track(A);
     }
+  }
+
+  // -------- A21: merge across the central membrane.  A track from a vertex off z = 0 whose
+  // z changes sign inside the chamber leaves a piece on each side, in the same sector frame.
+  // In a time frame the two sides' measured z are off by v t0 in opposite directions (side
+  // A: z - v t0, side C: z + v t0), so z cannot be compared; the other four parameters can.
+  // A (inner piece) heads for the membrane: tan lambda < 0 on side A, > 0 on side C.  B
+  // lies in the same sector on the other side of the same event, starts beyond A's end
+  // (B.x > A's end x), has the same sign of tan lambda, and its innermost measured z
+  // mirrors A's end: |z_A + z_B| <= merge_dz (both ends at the membrane, so the true z of
+  // both are near 0 and the offsets cancel in the sum).  A's tracklet end state is carried
+  // to B's innermost plane; the true z there, the mean of the two measured z, must be
+  // within merge_edge of the membrane, and chi2 = d^T (C_A + C_B)^-1 d over (y, sin phi,
+  // tan lambda, q/pT) <= chi2_merge.  These candidates join the sector candidates in the
+  // mutual-best pairing.  The link's collision time is (z_B - z_A) / (2 v) with A on side A
+  // (the other way round on side C).
+  bool membrane_transport(const Tracklet& ta, const Track& B, float* P, float* C) const {
+    float L[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    std::memcpy(P, ta.P, sizeof(float) * 5);
+    std::memcpy(C, ta.C, sizeof(float) * 15);
+    float x = ta.x;
+    return propagate(P, L, C, x, B.x, curvature_factor<float>(p), p.smax);
+  }
+  float membrane_t0(bool a_side, float za, float zb) const {
+    return a_side ? (zb - za) / (2.0f * p.v_drift) : (za - zb) / (2.0f * p.v_drift);
+  }
+  template <class F>
+  void membrane_candidates(int a, const std::unordered_map<int64_t, std::vector<int32_t>>& by_sector,
+                           F&& consider) {
+    const Track& A = tracks[a];
+    const Tracklet& ta = tracklets[A.tracklet];
+    const bool a_side = A.sector < kRowsPerSide;
+    if (!(a_side ? ta.P[3] < 0.f : ta.P[3] > 0.f)) return;
+    const int sb = (A.sector + kRowsPerSide) % kSectors;
+    const auto it = by_sector.find((int64_t)A.event * kSectors + sb);
+    if (it == by_sector.end()) return;
+    for (const int b : it->second) {
+      const Track& B = tracks[b];
+      if (B.ndf < 0 || B.event != A.event || B.sector != sb) continue;
+      if (!(a_side ? B.P[3] < 0.f : B.P[3] > 0.f)) continue;
+      if (!(B.x > ta.x)) continue;
+      if (!(std::fabs(ta.P[1] + z[B.hits.front()]) <= p.merge_dz)) continue;
+      float P[5], C[15];
+      if (!membrane_transport(ta, B, P, C)) continue;
+      if (!(std::fabs((P[1] + B.P[1]) * 0.5f) <= p.merge_edge)) continue;
+      const float c = membrane_chi2(P, C, B.P, B.C);
+      if (!(c <= p.chi2_merge)) continue;
+      consider(a, b, c);
+    }
+  }
+
+  // chi2 = d^T (CA + CB)^-1 d over y, sin phi, tan lambda and q/pT (indices 0, 2, 3, 4), by
+  // Cholesky in fixed order
+  static float membrane_chi2(const float* PA, const float* CA, const float* PB, const float* CB) {
+    const int ix[4] = {0, 2, 3, 4};
+    float S[10], d[4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j <= i; ++j) S[tri(i, j)] = CA[tri(ix[i], ix[j])] + CB[tri(ix[i], ix[j])];
+    for (int i = 0; i < 4; ++i) d[i] = PA[ix[i]] - PB[ix[i]];
+    float L[10];
+    for (int i = 0; i < 4; ++i) {
+      for (int j = 0; j <= i; ++j) {
+        float acc_ = S[tri(i, j)];
+        for (int k = 0; k < j; ++k) acc_ = acc_ - L[tri(i, k)] * L[tri(j, k)];
+        if (i == j) {
+          if (!(acc_ > 0.f)) return INFINITY;
+          L[tri(i, i)] = std::sqrt(acc_);
+        } else {
+          L[tri(i, j)] = acc_ / L[tri(j, j)];
+        }
+      }
+    }
+    float w[4];
+    float c = 0.f;
+    for (int i = 0; i < 4; ++i) {
+      float acc_ = d[i];
+      for (int k = 0; k < i; ++k) acc_ = acc_ - L[tri(i, k)] * w[k];
+      w[i] = acc_ / L[tri(i, i)];
+      c = c + w[i] * w[i];
+    }
+    return c;
   }
 
   // chi2 = d^T (CA + CB)^-1 d over the 5 parameters, by Cholesky in fixed order
@@ -1232,8 +1357,13 @@ void orc_get_track_t0(void* h, int32_t merged, float* t0, double* t0d) {
   int64_t m = 0;
   for (auto& t : o->tracks) {
     if (merged && t.merged_into >= 0) continue;
-    t0[m] = t.ndf >= 0 ? collision_time<float>(o->p, t.P, t.x, t.sector) : NAN;
-    t0d[m] = t.ndfd >= 0 ? collision_time<double>(o->p, t.Pd, t.xd, t.sector) : (double)NAN;
+    if (!std::isnan(t.t0m)) {  // a chain across the membrane: its link's time (A21)
+      t0[m] = t.ndf >= 0 ? t.t0m : NAN;
+      t0d[m] = t.ndfd >= 0 ? (double)t.t0m : (double)NAN;
+    } else {
+      t0[m] = t.ndf >= 0 ? collision_time<float>(o->p, t.P, t.x, t.sector) : NAN;
+      t0d[m] = t.ndfd >= 0 ? collision_time<double>(o->p, t.Pd, t.xd, t.sector) : (double)NAN;
+    }
     ++m;
   }
 }

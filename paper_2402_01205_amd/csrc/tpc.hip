@@ -3163,6 +3163,7 @@ int tpc_params_default(tpc_params* p) {
   p->merge_dz = 20.0f;
   p->v_drift = 2.58f;
   p->ext_down = 0;
+  p->merge_membrane = 0;
   return TPC_OK;
 }
 
@@ -3196,7 +3197,7 @@ static bool params_ok(const tpc_params& p) {
     if (!std::isfinite(v)) return false;
   return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
          p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f &&
-         (p.ext_down == 0 || p.ext_down == 1);
+         (p.ext_down == 0 || p.ext_down == 1) && p.merge_membrane == 0;
 }
 
 // the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))

@@ -33,7 +33,7 @@ class tpc_params(C.Structure):
         "sigma_y", "sigma_z", "nwin", "chi2_follow")] + [
         ("max_miss", C.c_int32), ("min_hits", C.c_int32)] + [
         (n, C.c_float) for n in ("smax", "bz", "merge_edge", "chi2_merge", "merge_dz", "v_drift")] + [
-        ("ext_down", C.c_int32)]
+        ("ext_down", C.c_int32), ("merge_membrane", C.c_int32)]
 
 
 class tpc_tuning(C.Structure):

@@ -12,8 +12,9 @@ import numpy as np
 import tpcsynth as g
 
 
-def true_state(pt, eta, phi, q, sector, x):
-    """(ok, y, z, s, t, k) at local plane x of `sector` on the first outgoing half turn."""
+def true_state(pt, eta, phi, q, sector, x, z0=0.0):
+    """(ok, y, z, s, t, k) at local plane x of `sector` on the first outgoing half turn of a
+    primary from (0, 0, z0)."""
     pt, eta, phi, q, x = (np.asarray(v, np.float64) for v in (pt, eta, phi, q, x))
     R, h, xc, yc = g.helix_geometry(pt, phi, q)
     a = g.sector_alpha(sector)
@@ -29,7 +30,7 @@ def true_state(pt, eta, phi, q, sector, x):
     ok &= (dphi > 0) & (dphi <= math.pi)
     arc = R * dphi
     t = np.sinh(eta)
-    z = t * arc
+    z = z0 + t * arc
     s = h * (x - xcl) / R
     k = q / pt
     return ok, y, z, s, t, k

@@ -133,12 +133,16 @@ def helix_geometry(pt, phi, q):
     return R, h, xc, yc
 
 
-def crossings(pt, eta, phi, q, only_sector=None):
+def crossings(pt, eta, phi, q, only_sector=None, z0=None):
     """Exact crossings of each primary with every pad-row plane on its outgoing half turn.
 
     Returns (track_index, sector, row, y_local, z, arc) for crossings inside the sector
-    acceptance |y| <= x tan10 and |z| <= drift length; the z side follows the sign of eta.
-    ``only_sector`` restricts to one sector (single-sector workloads).
+    acceptance |y| <= x tan10 and |z| <= drift length.  Without ``z0`` every primary starts
+    at the origin and its z side follows the sign of eta; with ``z0`` (vertex z per primary)
+    z = z0 + tan(lambda) * arc and each crossing's side follows the sign of its own z, so a
+    primary whose z changes sign inside the chamber crosses the central membrane and leaves
+    clusters on both sides.  ``only_sector`` restricts to one sector (single-sector
+    workloads).
     """
     n = pt.shape[0]
     R, h, xc, yc = helix_geometry(pt, phi, q)
@@ -154,8 +158,11 @@ def crossings(pt, eta, phi, q, only_sector=None):
     for k in range(0, 7):
         m = reach & (lo + k <= hi)
         if only_sector is not None:
-            sec_k = np.mod(lo + k, 18) + np.where(side_c, 18, 0)
-            m &= sec_k == only_sector
+            if z0 is None:
+                sec_k = np.mod(lo + k, 18) + np.where(side_c, 18, 0)
+                m &= sec_k == only_sector
+            else:
+                m &= np.mod(lo + k, 18) == only_sector % 18
         idx = np.nonzero(m)[0]
         if idx.size == 0:
             continue
@@ -177,10 +184,18 @@ def crossings(pt, eta, phi, q, only_sector=None):
         ok &= (dphi > 0) & (dphi <= math.pi)
         arc = Ri * dphi
         zz = tanl[idx][:, None] * arc
+        if z0 is not None:
+            zz = zz + np.asarray(z0, np.float64)[idx][:, None]
         ok &= np.abs(yy) <= ROW_X[None, :] * TAN_HALF
         ok &= np.abs(zz) <= DRIFT_LENGTH
         ti, ri = np.nonzero(ok)
-        out.append((idx[ti], sec[ti], ri, yy[ti, ri], zz[ti, ri], arc[ti, ri]))
+        sec_c = sec[ti]
+        if z0 is not None:  # the side of each crossing from the sign of its z
+            sec_c = np.mod(sec_c, 18) + np.where(zz[ti, ri] < 0, 18, 0)
+            if only_sector is not None:
+                keep = sec_c == only_sector
+                ti, ri, sec_c = ti[keep], ri[keep], sec_c[keep]
+        out.append((idx[ti], sec_c, ri, yy[ti, ri], zz[ti, ri], arc[ti, ri]))
     if not out:
         e = np.zeros(0)
         return (e.astype(np.int64), e.astype(np.int64), e.astype(np.int64), e, e, e)
@@ -192,12 +207,13 @@ def crossings(pt, eta, phi, q, only_sector=None):
 # --------------------------------------------------------------------------------------
 
 def _signal_clusters(rng, n, *, eta_range, phi_range, only_sector=None, smear=SIGMA_YZ,
-                     ineff=0.0, block=20000):
+                     ineff=0.0, block=20000, vertex_z=None):
     pt, eta, phi, q = draw_primaries(rng, n, eta_range, phi_range)
     parts = []
     for b0 in range(0, n, block):
         sl = slice(b0, min(n, b0 + block))
-        ti, sec, row, y, z, _ = crossings(pt[sl], eta[sl], phi[sl], q[sl], only_sector)
+        z0 = None if vertex_z is None else np.full(sl.stop - sl.start, float(vertex_z))
+        ti, sec, row, y, z, _ = crossings(pt[sl], eta[sl], phi[sl], q[sl], only_sector, z0)
         parts.append((ti + b0, sec, row, y, z))
     ti, sec, row, y, z = (np.concatenate([p[i] for p in parts]) for i in range(5))
     m = len(ti)
@@ -244,9 +260,11 @@ def _finish_job(rng, sig, noise, parts, shuffle=True, meta=None):
 
 
 def gen_event(seed, n_primaries, *, sector=None, noise=0.0, ineff=0.0, smear=SIGMA_YZ,
-              shuffle=True):
-    """One collision at t=0 from the origin.  ``sector`` given: a single-sector event with
-    phi inside that sector and eta on its side (clusters elsewhere dropped)."""
+              shuffle=True, vertex_z=None):
+    """One collision at t=0 from the origin, or from (0, 0, vertex_z) when given (then the
+    clusters' sides follow their own z: primaries near eta 0 cross the central membrane).
+    ``sector`` given: a single-sector event with phi inside that sector and eta on its side
+    (clusters elsewhere dropped)."""
     rng = np.random.default_rng(seed)
     if sector is None:
         eta_r, phi_r = (-0.9, 0.9), (0.0, 2 * math.pi)
@@ -256,22 +274,24 @@ def gen_event(seed, n_primaries, *, sector=None, noise=0.0, ineff=0.0, smear=SIG
         phi_r = (a - math.radians(10.0), a + math.radians(10.0))
     parts, (ti, sec, row, y, z) = _signal_clusters(rng, n_primaries, eta_range=eta_r,
                                                    phi_range=phi_r, only_sector=sector,
-                                                   smear=smear, ineff=ineff)
+                                                   smear=smear, ineff=ineff, vertex_z=vertex_z)
     t = (DRIFT_LENGTH - np.abs(z)) / V_DRIFT
     n_noise = int(round(noise * len(ti)))
     nz = _noise_clusters(rng, n_noise)
     return _finish_job(rng, (ti, sec, row, y, z, t), nz, parts, shuffle,
-                       dict(kind="event", seed=seed, n_primaries=n_primaries, sector=sector))
+                       dict(kind="event", seed=seed, n_primaries=n_primaries, sector=sector,
+                            vertex_z=vertex_z))
 
 
 def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, workers=0,
-                       smear=SIGMA_YZ):
-    """Collisions at t=0 (no noise), each reproducible from its own spawned seed."""
+                       smear=SIGMA_YZ, vz_sigma=0.0):
+    """Collisions at t=0 (no noise), each reproducible from its own spawned seed.  With
+    ``vz_sigma`` > 0 each collision's vertex z is drawn from N(0, vz_sigma) (cm)."""
     ss = np.random.SeedSequence(seed)
     rng = np.random.default_rng(ss.spawn(1)[0])
     mult = rng.integers(mult_range[0], mult_range[1] + 1, n_collisions)
     kids = ss.spawn(n_collisions + 1)[1:]
-    args = [(kids[i], int(mult[i]), ineff, smear) for i in range(n_collisions)]
+    args = [(kids[i], int(mult[i]), ineff, smear, vz_sigma) for i in range(n_collisions)]
     if workers and workers > 1 and n_collisions > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(min(workers, n_collisions)) as p:
@@ -280,13 +300,14 @@ def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, wo
 
 
 def _pool_collision(args):
-    kid, mult, ineff, smear = args
+    kid, mult, ineff, smear, vz_sigma = args
     r = np.random.default_rng(kid)
+    vz = float(r.normal(0.0, vz_sigma)) if vz_sigma > 0 else None
     parts, (ti, sec, row, y, z) = _signal_clusters(r, mult, eta_range=(-0.9, 0.9),
                                                    phi_range=(0, 2 * math.pi), ineff=ineff,
-                                                   smear=smear)
+                                                   smear=smear, vertex_z=vz)
     return dict(parts=parts, ti=ti, sec=sec.astype(np.uint8), row=row.astype(np.int16),
-                y=y, z=z)
+                y=y, z=z, vz=vz or 0.0)
 
 
 def assemble_timeframe(seed, pool, coll_ids, window_us, noise=0.05, mean_spacing_us=20.0,
@@ -322,7 +343,8 @@ def assemble_timeframe(seed, pool, coll_ids, window_us, noise=0.05, mean_spacing
     return _finish_job(rng, sig, nz, parts, shuffle,
                        dict(kind="timeframe", seed=seed, n_collisions=len(coll_ids),
                             window_us=window_us, t_collisions=tk.tolist(),
-                            coll_part_off=coll_part_off.tolist()))
+                            coll_part_off=coll_part_off.tolist(),
+                            vertex_z=[float(pool[int(c)].get("vz", 0.0)) for c in coll_ids]))
 
 
 # --------------------------------------------------------------------------------------
@@ -341,17 +363,21 @@ def _c4_job(args):
 
 
 def make_config(cfg: str, seed: int, *, workers: int = 0, n_jobs: int = 512,
-                jobs=None, scale: float = 1.0) -> ClusterSet:
+                jobs=None, scale: float = 1.0, vz_sigma: float = 0.0) -> ClusterSet:
     """Build one of the workloads.  ``scale`` shrinks multiplicities (tests only);
-    ``jobs`` selects a subset of the c4 job list; ``workers`` > 1 uses a process pool."""
+    ``jobs`` selects a subset of the c4 job list; ``workers`` > 1 uses a process pool.
+    ``vz_sigma`` > 0 (c2, c3): collision vertices at z ~ N(0, vz_sigma) cm instead of z = 0,
+    so that primaries near eta 0 cross the central membrane."""
     if cfg == "c1":
         cs = gen_event(seed, max(1, int(round(200 * scale))), sector=0)
     elif cfg == "c2":
-        cs = gen_event(seed, max(1, int(round(8000 * scale))), noise=0.05, ineff=0.1)
+        vz = float(np.random.default_rng([seed, 7]).normal(0.0, vz_sigma)) if vz_sigma > 0 else None
+        cs = gen_event(seed, max(1, int(round(8000 * scale))), noise=0.05, ineff=0.1, vertex_z=vz)
     elif cfg == "c3":
         rng = np.random.default_rng(seed)
         n_coll = 50 if scale >= 1 else max(1, int(round(50 * scale)))
-        pool = gen_collision_pool(int(rng.integers(1 << 31)), n_coll, workers=workers)
+        pool = gen_collision_pool(int(rng.integers(1 << 31)), n_coll, workers=workers,
+                                  vz_sigma=vz_sigma)
         window = 1000.0 * n_coll / 50.0
         cs = assemble_timeframe(int(rng.integers(1 << 31)), pool, np.arange(n_coll), window)
     elif cfg == "c4":
@@ -369,7 +395,7 @@ def make_config(cfg: str, seed: int, *, workers: int = 0, n_jobs: int = 512,
     else:
         raise ValueError(f"unknown workload {cfg!r}")
     cs.meta.update(dict(workload=cfg, seed=seed, generator_version=GENERATOR_VERSION,
-                        scale=scale))
+                        scale=scale, vz_sigma=vz_sigma))
     return cs
 
 
