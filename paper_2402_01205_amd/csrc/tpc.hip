@@ -1197,6 +1197,7 @@ struct FitView {
   const int32_t* sel_hits;
   const int32_t* chain_next;  // merged outer piece of a track, -1 if none (NULL: no merge)
   const int32_t* chain_prev;  // merged inner piece, -1 if none; chains are walked from heads only
+  const float* link_t0;       // collision time of a membrane link to the outer piece
   float* row;                 // [capK][kFitStride]: P[5], C[15], x, L[5] (one record per track)
   float* chi2;
   int32_t* ndf;
@@ -1278,7 +1279,15 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
       const int32_t sl = Hq.slot;
       const int sec = (sl / kRows) % kSectors;
       if (sec != cur_sec) {
-        if (!rotate(S, x, cur_sec, sec, k)) { ok = false; break; }
+        if ((sec < kHalf) != (cur_sec < kHalf)) {
+          // across the central membrane into the inner piece's side: z moves by twice the
+          // drift of the link's collision time
+          const float d = (2.0f * k.v_drift) * F.link_t0[p];
+          acc(S.P[1], S.L[1], sec < kHalf ? -d : d);
+        } else if (!rotate(S, x, cur_sec, sec, k)) {
+          ok = false;
+          break;
+        }
         cur_sec = sec;
       }
       const float xh = k.x[sl % kRows];
@@ -1526,6 +1535,7 @@ struct MergeView {
   int32_t* chain_prev;        // [capK]
   int32_t* head_list;         // [capK]
   int32_t* n_heads;           // [1]
+  float* link_t0;             // [capK] collision time of a membrane link a -> chain_next[a]
   int32_t n_events;
   int32_t nz;                 // z bins per (event, sector)
   float dz;
@@ -1537,20 +1547,29 @@ __device__ __forceinline__ int merge_zbin(float z, float dz, int nz) {
   return (int)b;
 }
 
-// Event of every selected track; tracks that can be an outer piece (fitted, innermost
-// cluster within merge_edge of a sector edge) are counted into the bucket of their
-// (event, sector, edge side, z bin).  Side 0: the -y edge (y < 0), side 1: the +y edge.
+// Event of every selected track; tracks that can be an outer piece are counted into the
+// bucket of their (event, sector, side, z bin of the innermost cluster).  Side 0: across
+// the -y sector edge (fitted, innermost cluster within merge_edge of the edge, y < 0), side
+// 1: the +y edge; side 2: across the central membrane (fitted, tan lambda pointing away from
+// it: > 0 on side A, < 0 on side C), when that merge is on.
 __device__ __forceinline__ int merge_bkey(int ev, int sec, int side, float z, float dz, int nz) {
-  return ((ev * kSectors + sec) * 2 + side) * nz + merge_zbin(z, dz, nz);
+  return ((ev * kSectors + sec) * 3 + side) * nz + merge_zbin(z, dz, nz);
 }
 __device__ __forceinline__ bool outer_piece(const GHit& Hb, const int32_t* ndf, int32_t kk, const Consts& k) {
   const float eb = k.x[Hb.slot % kRows] * k.tan10 - fabsf(Hb.y);
   return ndf[kk] >= 0 && eb <= k.merge_edge;
 }
+__device__ __forceinline__ bool membrane_outer_piece(const int32_t* ndf, const float* fitrow, int32_t kk,
+                                                     int sec, const Consts& k) {
+  if (!k.membrane || ndf[kk] < 0) return false;
+  const float t = fitrow[(int64_t)kk * kFitStride + 3];
+  return sec < kHalf ? t > 0.f : t < 0.f;
+}
 
 __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
                               const int32_t* sel_hits, const GHit* gh, const int32_t* job_event,
-                              const int32_t* ndf, int32_t* trk_event, int32_t* bucket_cnt, Bound lo_b,
+                              const int32_t* ndf, const float* fitrow, int32_t* trk_event,
+                              int32_t* bucket_cnt, Bound lo_b,
                               Bound hi_b, int32_t capK, int32_t n_events, int32_t nz, Consts k,
                               int32_t* counters) {
   const int32_t lo = lo_b.get();
@@ -1570,11 +1589,13 @@ __global__ void k_track_event(const int32_t* sel_from, const int32_t* start, con
   const GHit Hb = ldh(gh + sel_hits[sel_off[kk]]);
   if (outer_piece(Hb, ndf, kk, k))
     atomicAdd(&bucket_cnt[merge_bkey(ev, sec, Hb.y < 0.f ? 0 : 1, Hb.z, k.merge_dz, nz)], 1);
+  if (membrane_outer_piece(ndf, fitrow, kk, sec, k))
+    atomicAdd(&bucket_cnt[merge_bkey(ev, sec, 2, Hb.z, k.merge_dz, nz)], 1);
 }
 
 __global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, const int32_t* sel_off,
-                               const int32_t* sel_hits, const GHit* gh, const int32_t* ndf, MergeView M,
-                               Bound lo_b, Bound hi_b, int32_t capK, Consts k) {
+                               const int32_t* sel_hits, const GHit* gh, const int32_t* ndf, const float* fitrow,
+                               MergeView M, Bound lo_b, Bound hi_b, int32_t capK, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1582,16 +1603,86 @@ __global__ void k_track_bucket(const int32_t* sel_from, const int32_t* start, co
   const int32_t sl = gh[start[sel_from[kk]]].slot;
   const int sec = (sl / kRows) % kSectors;
   const GHit Hb = ldh(gh + sel_hits[sel_off[kk]]);
-  if (!outer_piece(Hb, ndf, kk, k)) return;
-  const int b = merge_bkey(M.trk_event[kk], sec, Hb.y < 0.f ? 0 : 1, Hb.z, k.merge_dz, M.nz);
-  const int32_t q = M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1);
-  M.bucket_trk[q] = kk;
-  M.bucket_z[q] = Hb.z;
+  if (outer_piece(Hb, ndf, kk, k)) {
+    const int b = merge_bkey(M.trk_event[kk], sec, Hb.y < 0.f ? 0 : 1, Hb.z, k.merge_dz, M.nz);
+    const int32_t q = M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1);
+    M.bucket_trk[q] = kk;
+    M.bucket_z[q] = Hb.z;
+  }
+  if (membrane_outer_piece(ndf, fitrow, kk, sec, k)) {
+    const int b = merge_bkey(M.trk_event[kk], sec, 2, Hb.z, k.merge_dz, M.nz);
+    const int32_t q = M.bucket_off[b] + atomicAdd(&M.bucket_fill[b], 1);
+    M.bucket_trk[q] = kk;
+    M.bucket_z[q] = Hb.z;
+  }
 }
 
 // packed (chi2, id): chi2 >= 0 so its bits order like the value; smaller wins.
 __device__ __forceinline__ uint64_t pack_best(float c, int32_t id) {
   return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)id;
+}
+
+// A's tracklet end state carried to plane x (same sector frame: the other side of the
+// membrane); false when the transport fails.
+__device__ __forceinline__ bool membrane_transport(const TrackletView& V, int32_t ta, float x_to, State& S,
+                                                   const Consts& k) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    S.P[i] = V.state[(int64_t)ta * kStateStride + i];
+    S.L[i] = 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < 15; ++i) S.C[i] = V.state[(int64_t)ta * kStateStride + 5 + i];
+  float x = V.state[(int64_t)ta * kStateStride + 20];
+  return propagate(S, x, x_to, k);
+}
+
+__device__ __forceinline__ void load_fit_pc(const FitView& F, int32_t b, float* P, float* C, float& x) {
+  float rb[kFitStride];
+  const float* src = F.row + (int64_t)b * kFitStride;
+#pragma unroll
+  for (int i = 0; i < 24; i += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src + i);
+    rb[i] = v.x;
+    rb[i + 1] = v.y;
+    rb[i + 2] = v.z;
+    rb[i + 3] = v.w;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) P[i] = rb[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) C[i] = rb[5 + i];
+  x = rb[20];
+}
+
+// Candidates across the central membrane: A's end heads for it (tan lambda < 0 on side A,
+// > 0 on side C); B (bucket side 2 of the same sector on the other side) starts beyond A's
+// end, its innermost measured z mirrors A's end (|z_A + z_B| <= merge_dz), the true z at B's
+// plane (the mean of the two measured z) lies within merge_edge of the membrane, and the
+// chi2 over y, sin phi, tan lambda and q/pT is at most chi2_merge.
+__device__ void membrane_candidates(const TrackletView& V, const FitView& F, const MergeView& M, int32_t a,
+                                    int32_t ta, int seca, float za, float xa, const Consts& k) {
+  const bool a_side = seca < kHalf;
+  const float tA = V.state[(int64_t)ta * kStateStride + 3];
+  if (!(a_side ? tA < 0.f : tA > 0.f)) return;
+  const int sb = (seca + kHalf) % kSectors;
+  const float zlo = -za - k.merge_dz - 1.f, zhi = -za + k.merge_dz + 1.f;
+  const int32_t b0 = M.bucket_off[merge_bkey(M.trk_event[a], sb, 2, zlo, k.merge_dz, M.nz)];
+  const int32_t b1 = M.bucket_off[merge_bkey(M.trk_event[a], sb, 2, zhi, k.merge_dz, M.nz) + 1];
+  for (int32_t q = b0; q < b1; ++q) {
+    if (!(fabsf(za + M.bucket_z[q]) <= k.merge_dz)) continue;
+    const int32_t b = M.bucket_trk[q];
+    float PB[5], CB[15], xb;
+    load_fit_pc(F, b, PB, CB, xb);
+    if (!(xb > xa)) continue;
+    State S;
+    if (!membrane_transport(V, ta, xb, S, k)) continue;
+    if (!(fabsf((S.P[1] + PB[1]) * 0.5f) <= k.merge_edge)) continue;
+    const float c = membrane_chi2(S.P, S.C, PB, CB);
+    if (!(c <= k.chi2_merge)) continue;
+    atomicMin((unsigned long long*)&M.bestA[a], (unsigned long long)pack_best(c, b));
+    atomicMin((unsigned long long*)&M.bestB[b], (unsigned long long)pack_best(c, a));
+  }
 }
 
 __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletView V, FitView F,
@@ -1606,10 +1697,11 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   const float ya = V.state[(int64_t)ta * kStateStride + 0];
   const float za = V.state[(int64_t)ta * kStateStride + 1];
   const float xa = V.state[(int64_t)ta * kStateStride + 20];
-  const float edge = xa * k.tan10 - fabsf(ya);
-  if (!(edge <= k.merge_edge)) return;
   const int32_t sla = G.gh[V.start[ta]].slot;
   const int seca = (sla / kRows) % kSectors;
+  if (k.membrane) membrane_candidates(V, F, M, a, ta, seca, za, xa, k);
+  const float edge = xa * k.tan10 - fabsf(ya);
+  if (!(edge <= k.merge_edge)) return;
   const int dir = ya > 0.f ? 1 : kHalf - 1;
   const int sb = (seca / kHalf) * kHalf + (seca % kHalf + dir) % kHalf;
   // outer pieces start at the edge shared with A's sector: their -y edge if A leaves
@@ -1661,8 +1753,9 @@ __global__ __launch_bounds__(256) void k_merge_candidates(GridView G, TrackletVi
   }
 }
 
-// Mutual best pairs -> chain links.
-__global__ void k_merge_links(MergeView M, Bound lo_b, Bound hi_b, int32_t capK) {
+// Mutual best pairs -> chain links; a link across the membrane gets its collision time.
+__global__ void k_merge_links(GridView G, TrackletView V, FitView F, MergeView M, Bound lo_b, Bound hi_b,
+                              int32_t capK, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), capK);
   const int32_t a = lo + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1674,6 +1767,16 @@ __global__ void k_merge_links(MergeView M, Bound lo_b, Bound hi_b, int32_t capK)
   if ((int32_t)(uint32_t)bb != a) return;
   M.chain_next[a] = b;
   M.chain_prev[b] = a;
+  const int32_t ta = F.sel_from[a];
+  const int seca = (G.gh[V.start[ta]].slot / kRows) % kSectors;
+  const int secb = (G.gh[V.start[F.sel_from[b]]].slot / kRows) % kSectors;
+  if ((seca < kHalf) != (secb < kHalf)) {
+    float PB[5], CB[15], xb;
+    load_fit_pc(F, b, PB, CB, xb);
+    State S;
+    membrane_transport(V, ta, xb, S, k);
+    M.link_t0[a] = membrane_t0(seca < kHalf, S.P[1], PB[1], k);
+  }
 }
 
 // Chain heads (no inner partner, an outer partner) are listed for the refit; every
@@ -1785,7 +1888,25 @@ __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, F
     } else if (lane == 24 && O.t0) {
       const int32_t sec = (G.gh[V.start[F.sel_from[kk]]].slot / kRows) % kSectors;
       const float* row = F.row + (int64_t)kk * kFitStride;
-      O.t0[o] = F.ndf[kk] >= 0 ? collision_time(row, row[20], sec, k) : __builtin_nanf("");
+      // a chain across the central membrane: its innermost membrane link's time
+      bool memb = false;
+      float tm = 0.f;
+      if (walk) {
+        int32_t p = kk;
+        int ps = sec;
+        for (int n = 0; n < kHalf && F.chain_next[p] >= 0; ++n) {
+          const int32_t q = F.chain_next[p];
+          const int qs = (G.gh[V.start[F.sel_from[q]]].slot / kRows) % kSectors;
+          if ((ps < kHalf) != (qs < kHalf)) {
+            memb = true;
+            tm = F.link_t0[p];
+            break;
+          }
+          p = q;
+          ps = qs;
+        }
+      }
+      O.t0[o] = F.ndf[kk] < 0 ? __builtin_nanf("") : memb ? tm : collision_time(row, row[20], sec, k);
     }
   }
 }
@@ -2727,7 +2848,7 @@ struct Layout {
   uint16_t* rans_buf;
   int64_t rans_lanesN = 0;
   // merge
-  float* bucket_z;
+  float *bucket_z, *link_t0;
   int32_t *trk_event, *bucket_cnt, *bucket_off, *bucket_fill, *bucket_trk, *chain_next, *chain_prev,
       *head_list, *keep, *outn, *oid, *ooff;
   uint64_t *bestA, *bestB;
@@ -2749,7 +2870,7 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   L.capK = L.capT;
   L.capH = (int32_t)(N + 1);
   L.nzb = std::max(1, std::min(2048, 4194304 / std::max(1, J * kSectors)));
-  L.capE = J * kSectors * 2 * L.nzb;
+  L.capE = J * kSectors * 3 * L.nzb;
   const int64_t big = std::max<int64_t>(
       {N + 1, L.capCells + 1, (int64_t)L.S + 1, (int64_t)L.capT + 1, (int64_t)L.capE + 1});
   L.bsumN = big / kScanTile + 4;
@@ -2809,8 +2930,9 @@ void layout(Layout& L, int64_t N, int32_t J, float cpc, char* base, bool set) {
   carve(p, L.bucket_cnt, L.capE + 1, t, set);
   carve(p, L.bucket_off, L.capE + 1, t, set);
   carve(p, L.bucket_fill, L.capE + 1, t, set);
-  carve(p, L.bucket_trk, L.capK, t, set);
-  carve(p, L.bucket_z, L.capK, t, set);
+  carve(p, L.bucket_trk, 2 * (int64_t)L.capK, t, set);  // a track may be in a sector and a membrane bucket
+  carve(p, L.bucket_z, 2 * (int64_t)L.capK, t, set);
+  carve(p, L.link_t0, L.capK, t, set);
   carve(p, L.chain_next, L.capK, t, set);
   carve(p, L.chain_prev, L.capK, t, set);
   carve(p, L.head_list, L.capK, t, set);
@@ -2944,6 +3066,7 @@ void make_consts(const tpc_params& p, Consts& k) {
   k.chi2_merge = p.chi2_merge;
   k.merge_dz = p.merge_dz;
   k.v_drift = p.v_drift;
+  k.membrane = p.merge_membrane;
 }
 
 Bound hb(int32_t v) { return Bound{nullptr, v, INT32_MAX}; }
@@ -3008,7 +3131,7 @@ const int32_t* trk_hits(tpc_ctx* c, bool extended) {
 FitView make_fv(tpc_ctx* c, bool with_chain, bool extended) {
   Layout& L = c->L;
   return FitView{L.sel_from, trk_off(c, extended), trk_hits(c, extended), with_chain ? L.chain_next : nullptr,
-                 with_chain ? L.chain_prev : nullptr, L.fitrow, L.fitchi2, L.fitndf, L.capK};
+                 with_chain ? L.chain_prev : nullptr, L.link_t0, L.fitrow, L.fitchi2, L.fitndf, L.capK};
 }
 
 // ---- stage launch sequences over the job range [j0, j1)
@@ -3197,7 +3320,7 @@ static bool params_ok(const tpc_params& p) {
     if (!std::isfinite(v)) return false;
   return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
          p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f &&
-         (p.ext_down == 0 || p.ext_down == 1) && p.merge_membrane == 0;
+         (p.ext_down == 0 || p.ext_down == 1) && (p.merge_membrane == 0 || p.merge_membrane == 1);
 }
 
 // the reason of the last failed tpc_ctx_create (read through tpc_last_error(NULL))
@@ -3436,7 +3559,7 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   }
   // ---- merge across adjacent sectors of one event
   const int nev = J;
-  const int64_t nbk = (int64_t)nev * kSectors * 2 * L.nzb;
+  const int64_t nbk = (int64_t)nev * kSectors * 3 * L.nzb;
   fill_i32(c, L.bucket_cnt, nbk + 1, 0);
   fill_i32(c, L.bucket_fill, nbk + 1, 0);
   fill_i32(c, L.chain_next, L.capK, -1);
@@ -3445,17 +3568,19 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
   fill_i32(c, (int32_t*)L.bestB, 2 * (int64_t)L.capK, -1);
   fill_i32(c, L.counters + kCntMergeCand, 1, 0);
   hipLaunchKernelGGL(k_track_event, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     trk_off(c, true), trk_hits(c, true), L.gh, c->jobs.job_event, L.fitndf, L.trk_event, L.bucket_cnt, klo,
+                     trk_off(c, true), trk_hits(c, true), L.gh, c->jobs.job_event, L.fitndf, L.fitrow, L.trk_event,
+                     L.bucket_cnt, klo,
                      khi, L.capK, nev, L.nzb, c->k, L.counters);
   scan(c, L.bucket_cnt, L.bucket_off, hb(0), hb((int32_t)nbk), nbk, false);
   MergeView M{L.trk_event, L.bucket_cnt, L.bucket_off, L.bucket_fill, L.bucket_trk, L.bucket_z, L.bestA,
-              L.bestB, L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, nev, L.nzb,
-              c->p.merge_dz};
+              L.bestB, L.chain_next, L.chain_prev, L.head_list, L.counters + kCntMergeCand, L.link_t0, nev,
+              L.nzb, c->p.merge_dz};
   hipLaunchKernelGGL(k_track_bucket, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, L.sel_from, L.start,
-                     trk_off(c, true), trk_hits(c, true), L.gh, L.fitndf, M, klo, khi, L.capK, c->k);
+                     trk_off(c, true), trk_hits(c, true), L.gh, L.fitndf, L.fitrow, M, klo, khi, L.capK, c->k);
   hipLaunchKernelGGL(k_merge_candidates, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
                      make_tv(c), make_fv(c, false, true), M, klo, khi, c->k);
-  hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK);
+  hipLaunchKernelGGL(k_merge_links, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
+                     make_fv(c, false, true), M, klo, khi, L.capK, c->k);
   hipLaunchKernelGGL(k_merge_heads, dim3(blocks_for(kb, 256)), dim3(256), 0, c->stream, M, klo, khi, L.capK,
                      L.keep);
   hipLaunchKernelGGL(k_fit_heads, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),

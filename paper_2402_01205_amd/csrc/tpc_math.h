@@ -33,6 +33,7 @@ struct Consts {
   float prior0[5], prior1[5];
   float merge_edge, chi2_merge, merge_dz;
   float v_drift;         // cm/us
+  int membrane;          // 1: merge across the central membrane
 };
 
 // lower-triangle index of a symmetric 5x5 (i >= j)
@@ -393,6 +394,52 @@ __device__ __forceinline__ bool predict_yz(const float* Pf, float xref, int sref
 }
 
 // chi2 = d^T (CA + CB)^-1 d by a 5x5 Cholesky factorisation in fixed order.
+// The same over y, sin phi, tan lambda and q/pT (indices 0, 2, 3, 4): the comparison across
+// the central membrane, where z is off by the drift of the collision time.
+__device__ __forceinline__ float membrane_chi2(const float* PA, const float* CA, const float* PB,
+                                               const float* CB) {
+  constexpr int ix[4] = {0, 2, 3, 4};
+  float S[10], d[4], L[10];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) S[tri(i, j)] = CA[tri(ix[i], ix[j])] + CB[tri(ix[i], ix[j])];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d[i] = PA[ix[i]] - PB[ix[i]];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      float a = S[tri(i, j)];
+#pragma unroll
+      for (int q = 0; q < j; ++q) a = a - L[tri(i, q)] * L[tri(j, q)];
+      if (i == j) {
+        if (!(a > 0.f)) return __builtin_inff();
+        L[tri(i, i)] = sqrt_rn(a);
+      } else {
+        L[tri(i, j)] = div_rn(a, L[tri(j, j)]);
+      }
+    }
+  }
+  float w[4];
+  float c = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float a = d[i];
+#pragma unroll
+    for (int q = 0; q < i; ++q) a = a - L[tri(i, q)] * w[q];
+    w[i] = div_rn(a, L[tri(i, i)]);
+    c = c + w[i] * w[i];
+  }
+  return c;
+}
+
+// Collision time of a membrane link from the two pieces' z at the same plane: side A
+// measures z - v t0, side C z + v t0.
+__device__ __forceinline__ float membrane_t0(bool a_side, float za, float zb, const Consts& k) {
+  return a_side ? div_rn(zb - za, 2.0f * k.v_drift) : div_rn(za - zb, 2.0f * k.v_drift);
+}
+
 __device__ __forceinline__ float merge_chi2(const float* PA, const float* CA, const float* PB,
                                             const float* CB) {
   float S[15], d[5], L[15];
