@@ -377,6 +377,61 @@ def sync_preset_run(ev, cs, tracks, tuning, args, timed, log, torch):
     return row
 
 
+def _majority(cs, t):
+    """Majority particle, its share and the hit count of every output track."""
+    off, hits = t["off"], t["hits"]
+    nh = np.diff(off)
+    tid = np.repeat(np.arange(len(nh)), nh)
+    lab = cs.label[hits].astype(np.int64)
+    ok = lab >= 0
+    big = int(lab.max()) + 1 if lab.size else 1
+    u, c = np.unique(tid[ok] * big + lab[ok], return_counts=True)
+    trk, part = u // big, u % big
+    order = np.lexsort((-c, trk))
+    first = np.concatenate([[True], trk[order][1:] != trk[order][:-1]]) if len(order) else np.zeros(0, bool)
+    maj = np.full(len(nh), -1, np.int64)
+    cnt = np.zeros(len(nh), np.int64)
+    maj[trk[order][first]] = part[order][first]
+    cnt[trk[order][first]] = c[order][first]
+    return maj, cnt, nh
+
+
+def membrane_run(cs, args, tuning, time_run, log, dev):
+    """The time-frame slice with its collision vertices spread in z: the default reading
+    against the asynchronous cut set, which merges pieces across the central membrane; the
+    collision times of the tracks joined across it against the generator's, beside the
+    vertex-based times of the other good tracks (off by the vertex z over v_drift)."""
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker, preset_params
+    ev = DeviceClusters.from_set(cs, dev)
+    off_c = np.asarray(cs.meta["coll_part_off"], np.int64)
+    coll = np.repeat(np.arange(len(off_c) - 1), np.diff(off_c))
+    t_true = np.asarray(cs.meta["t_collisions"])[coll]
+    out = {"workload": f"c3: {WORKLOADS['c3']}, vertices at z ~ N(0, {args.vz_sigma} cm)",
+           "n_clusters": cs.n}
+    for name, prm in (("default", None), ("async_preset", preset_params("async"))):
+        tr = Tracker(0, params=prm, mode=args.mode, tuning=tuning)
+        ms = time_run(tr, ev, args.steps)
+        t = tr.tracks()
+        maj, cnt, nh = _majority(cs, t)
+        good = (maj >= 0) & (cnt >= 0.9 * nh) & (nh >= 30) & ~np.isnan(t["t0"])
+        tid = np.repeat(np.arange(len(nh)), nh)
+        side = (cs.sector[t["hits"]] < 18).astype(np.int64)
+        both = np.zeros(len(nh), np.int64)
+        np.bitwise_or.at(both, tid, 1 << side)
+        across = both == 3
+        row = {"ms_per_step": ms, "clusters_per_s": cs.n / (ms / 1e3), "tracks": int(t["n"]),
+               "tracks_across_membrane": int(across.sum())}
+        for key, m in (("across_membrane", good & across), ("vertex_based", good & ~across)):
+            if m.any():
+                d = np.abs(t["t0"][m] - t_true[maj[m]])
+                row[f"t0_abs_err_us_{key}"] = {"tracks": int(m.sum()), "median": float(np.median(d)),
+                                               "p95": float(np.percentile(d, 95))}
+        out[name] = row
+        del tr
+    log("membrane merge: " + json.dumps(out))
+    return out
+
+
 def cf_cpu_baseline(dg):
     """The oracle's cluster finder on the digits of sectors 0-3 of the digit workload."""
     import oracle.oracle as O
@@ -540,6 +595,8 @@ def main():
                     help="chunks of the run at 0.8x the measured capacity when the stated rate saturates")
     ap.add_argument("--cf-config", default="d3", choices=["d1", "d2", "d3", ""],
                     help="digit workload of the cluster-finding row ('' = skip)")
+    ap.add_argument("--vz-sigma", type=float, default=5.0,
+                    help="vertex z spread (cm) of the extra time frame for the membrane merge (0: skip)")
     ap.add_argument("--also", default="c2,c3",
                     help="other workloads timed in the same launch configuration (comma list, '' = none)")
     args = ap.parse_args()
@@ -561,10 +618,14 @@ def main():
     log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
         f"in {time.perf_counter() - t0:.1f}s")
     others = {}
+    vz_set = None
     if not args.profile_only:
         for name in [x for x in args.also.split(",") if x and x != args.config]:
             others[name] = g.make_config(name, SEEDS[name], workers=args.workers)
             log(f"generated {name}: {others[name].n} clusters")
+        if args.vz_sigma > 0:
+            vz_set = g.make_config("c3", SEEDS["c3"], workers=args.workers, vz_sigma=args.vz_sigma)
+            log(f"generated c3 with vertices spread in z ({args.vz_sigma} cm): {vz_set.n} clusters")
     # the oracle baselines first, before any GPU use
     cpu = cpu_par = cpu_chain = None
     if not args.no_cpu and not args.profile_only:
@@ -771,6 +832,7 @@ def main():
                                "plain_identical_tracks": same})
             log(f"{name} plain per sector ({split.n_jobs} jobs): {pms:.3f} ms/step; identical tracks: {same}")
             del ptr, sev
+    membrane = membrane_run(vz_set, args, tuning, time_run, log, dev) if vz_set is not None else None
     serving = None
     if args.serve_chunks > 0:
         del tr, ev                 # the serving run sizes its admission by free HBM
@@ -814,6 +876,7 @@ def main():
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items() if v[1]},
         "compression": compression,
         "sync_preset": sync_row,
+        "membrane_merge": membrane,
         "cluster_finding": clusters_row,
         "tracks": int(tracks["n"]),
         "tracklets": int(T),

@@ -123,7 +123,10 @@ typedef struct {
  * z + v_drift*t0 on side C).  A primary comes from the nominal vertex (z = 0) on the
  * beam line, the plane x = 0 of its sector frame: the fitted state is transported
  * along the helix (state only, FP32) from x_ref to x = 0 and t0 = -z/v_drift on side
- * A, +z/v_drift on side C.  NaN where the fit failed or the transport fails.     */
+ * A, +z/v_drift on side C.  A track merged across the central membrane
+ * (merge_membrane = 1) reports instead the time its two sides' z offset gives,
+ * which does not assume the vertex at z = 0.  NaN where the fit failed or the
+ * transport fails.                                                              */
 /* Output tracks (after tpc_fit_merge).  Capacities are [host] values; counts
  * are written on the device.  hits: CSR of cluster indices ordered along the
  * track (inner piece rows ascending, then the outer piece).  When a capacity
@@ -160,7 +163,10 @@ typedef struct tpc_ctx tpc_ctx;
 int tpc_params_default(tpc_params* p);
 /* Cut sets of the two processing phases (section 2: the synchronous phase uses
  * different cuts to speed up the processing).  TPC_PRESET_ASYNC is the default
- * reading.  TPC_PRESET_SYNC serves the synchronous phase, whose tracks feed the
+ * reading plus the merge across the central membrane (merge_membrane = 1), which
+ * joins the two sides of a track from a vertex off z = 0 and measures its
+ * collision time from their z offset.  TPC_PRESET_SYNC serves the synchronous
+ * phase, whose tracks feed the
  * track-model compression (section 5): that attaches a cluster to any piece of
  * its track, so the pieces are not merged across sector edges (merge_edge < 0
  * disables the merge), and it codes the clusters on tracks as small residuals,
@@ -200,7 +206,18 @@ int tpc_find_neighbours(tpc_ctx* ctx, int32_t* up, int32_t* down);
 int tpc_construct_tracklets(tpc_ctx* ctx, int32_t* n_tracklets);
 /* a5: selection.  n_selected ([1] device or NULL) receives K.                */
 int tpc_select_tracks(tpc_ctx* ctx, int32_t* n_selected);
-/* a6: refit, downward extension, sector merge and merged refit; writes *out.
+/* a6: refit, downward extension, merges across sector edges and the central
+ * membrane, merged refit; writes *out.
+ * Membrane merge (merge_membrane = 1): a track from a vertex off z = 0 whose z
+ * changes sign inside the chamber leaves one piece on each side, in the same
+ * sector frame, whose measured z differ by twice the drift of the collision time
+ * in a time frame.  An inner piece heading for the membrane is compared with the
+ * pieces of the same sector on the other side that start beyond its end and whose
+ * innermost z mirrors its end z (|z_A + z_B| <= merge_dz): after transport, the
+ * mean of the two z (the true z there) must lie within merge_edge of the
+ * membrane and the chi2 over y, sin(phi), tan(lambda), q/pT within chi2_merge;
+ * such pairs compete with the sector pairs for the mutual best.  The merged refit
+ * moves z across the membrane by twice the drift of the link's time.             
  * Downward extension (ext_down = 1): a track's chain need not start at the
  * track's first row, and the following (section 6's tracking on the GPU) only
  * visits the rows above the chain, so every track whose fit succeeded continues

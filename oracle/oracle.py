@@ -49,6 +49,10 @@ DEFAULTS = dict(win_dy_slope=1.0, win_dy_const=0.5, win_dz_slope=2.0, win_dz_con
 # DEFAULTS.
 SYNC = dict(DEFAULTS, merge_edge=-1.0, ext_down=1)
 
+# The asynchronous phase's cut set: the default reading plus the merge across the central
+# membrane (A21).
+ASYNC = dict(DEFAULTS, merge_membrane=1)
+
 
 def params(**over) -> Params:
     d = dict(DEFAULTS)

@@ -3296,6 +3296,8 @@ int tpc_params_preset(tpc_params* p, int preset) {
   if (preset == TPC_PRESET_SYNC) {
     p->merge_edge = -1.0f;
     p->ext_down = 1;
+  } else {
+    p->merge_membrane = 1;
   }
   return TPC_OK;
 }

@@ -180,7 +180,8 @@ PRESETS = {"async": 0, "sync": 1}
 
 
 def preset_params(name: str, **over) -> tpc_params:
-    """The cut set of a processing phase ("async" = the defaults, "sync"), then overrides."""
+    """The cut set of a processing phase ("async": the defaults plus the membrane merge,
+    "sync"), then overrides."""
     p = tpc_params()
     if lib().tpc_params_preset(C.byref(p), PRESETS[name]) != TPC_OK:
         raise TpcError(TPC_E_ARG, f"unknown preset {name!r}")

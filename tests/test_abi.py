@@ -39,7 +39,7 @@ def test_sync_preset_equals_the_oracle_reading():
         got = getattr(p, name)
         assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
     a = tpc.preset_params("async")
-    for name, v in O.DEFAULTS.items():
+    for name, v in O.ASYNC.items():
         got = getattr(a, name)
         assert got == (int(v) if isinstance(got, int) else float(ctypes.c_float(v).value)), name
     assert tpc.lib().tpc_params_preset(ctypes.byref(tpc.tpc_params()), 7) == tpc.TPC_E_ARG
