@@ -36,6 +36,29 @@ def true_state(pt, eta, phi, q, sector, x, z0=0.0):
     return ok, y, z, s, t, k
 
 
+def true_state_return(pt, eta, phi, q, sector, x, z0=0.0):
+    """(ok, y, z, s, t, k) at local plane x of `sector` on the return leg of a looper (the
+    second half turn), as the tracker parametrises it: along increasing x, which is against
+    the momentum there, so sin(phi), tan(lambda) and q/pT change sign."""
+    pt, eta, phi, q, x = (np.asarray(v, np.float64) for v in (pt, eta, phi, q, x))
+    R, h, xc, yc = g.helix_geometry(pt, phi, q)
+    a = g.sector_alpha(sector)
+    ca, sa = np.cos(a), np.sin(a)
+    xcl = xc * ca + yc * sa
+    ycl = -xc * sa + yc * ca
+    D = R * R - (x - xcl) ** 2
+    ok = D >= 0
+    y = ycl + h * np.sqrt(np.where(ok, D, 0.0))
+    ox, oy = -xcl, -ycl
+    px, py = x - xcl, y - ycl
+    dphi = np.mod(h * np.arctan2(ox * py - oy * px, ox * px + oy * py), 2 * math.pi)
+    ok &= (dphi > math.pi) & (dphi < 2 * math.pi)
+    t = np.sinh(eta)
+    z = z0 + t * R * dphi
+    s = -h * (x - xcl) / R
+    return ok, y, z, s, -t, -q / pt
+
+
 def rk4_crossing(pt, eta, phi, q, sector, x_target, step=0.02):
     """Integrate dr/dl = p/|p|, dp/dl = kappa q (p/|p| x B) from the origin (RK4) until
     the local x of `sector` reaches x_target; returns local (y, z)."""

@@ -133,7 +133,7 @@ def helix_geometry(pt, phi, q):
     return R, h, xc, yc
 
 
-def crossings(pt, eta, phi, q, only_sector=None, z0=None):
+def crossings(pt, eta, phi, q, only_sector=None, z0=None, leg=0):
     """Exact crossings of each primary with every pad-row plane on its outgoing half turn.
 
     Returns (track_index, sector, row, y_local, z, arc) for crossings inside the sector
@@ -143,17 +143,28 @@ def crossings(pt, eta, phi, q, only_sector=None, z0=None):
     primary whose z changes sign inside the chamber crosses the central membrane and leaves
     clusters on both sides.  ``only_sector`` restricts to one sector (single-sector
     workloads).
+
+    ``leg`` = 1 gives instead the crossings of the return leg of a looper: a primary whose
+    circle turns back inside the chamber (2R < R_MAX) crosses the rows again on the second
+    half turn (turned angle in (pi, 2 pi)), moving inwards, while z keeps growing with the
+    arc; primaries that leave the chamber first have no return leg.
     """
     n = pt.shape[0]
     R, h, xc, yc = helix_geometry(pt, phi, q)
     tanl = np.sinh(eta)
     side_c = eta < 0
-    # polar angle of the position at radius rho on the first half turn: phi + h asin(rho / 2R)
-    th_a = phi + h * np.arcsin(np.minimum(1.0, X_FIRST / (2 * R)))
-    th_b = phi + h * np.arcsin(np.minimum(1.0, R_MAX / (2 * R)))
+    if leg == 0:
+        # polar angle of the position at radius rho on the first half turn: phi + h asin(rho / 2R)
+        th_a = phi + h * np.arcsin(np.minimum(1.0, X_FIRST / (2 * R)))
+        th_b = phi + h * np.arcsin(np.minimum(1.0, R_MAX / (2 * R)))
+        reach = 2 * R >= X_FIRST
+    else:
+        # on the second half turn: phi + h (pi - asin(rho / 2R)), from the turn (rho = 2R) inwards
+        th_a = phi + h * (math.pi / 2)
+        th_b = phi + h * (math.pi - np.arcsin(np.minimum(1.0, X_FIRST / (2 * R))))
+        reach = (2 * R >= X_FIRST) & (2 * R < R_MAX)
     lo = np.floor(np.minimum(th_a, th_b) / math.radians(20.0)).astype(np.int64)
     hi = np.floor(np.maximum(th_a, th_b) / math.radians(20.0)).astype(np.int64)
-    reach = 2 * R >= X_FIRST
     out = []
     for k in range(0, 7):
         m = reach & (lo + k <= hi)
@@ -176,12 +187,16 @@ def crossings(pt, eta, phi, q, only_sector=None, z0=None):
         dxr = ROW_X[None, :] - xcl[:, None]
         D = Ri * Ri - dxr * dxr
         ok = D >= 0
-        yy = ycl[:, None] - hi_ * np.sqrt(np.where(ok, D, 0.0))
+        root = -hi_ if leg == 0 else hi_
+        yy = ycl[:, None] + root * np.sqrt(np.where(ok, D, 0.0))
         # turned angle from the origin's phase (-xcl, -ycl) to the crossing's phase
         py = yy - ycl[:, None]
         ox, oy = -xcl[:, None], -ycl[:, None]
         dphi = np.mod(hi_ * np.arctan2(ox * py - oy * dxr, ox * dxr + oy * py), 2 * math.pi)
-        ok &= (dphi > 0) & (dphi <= math.pi)
+        if leg == 0:
+            ok &= (dphi > 0) & (dphi <= math.pi)
+        else:
+            ok &= (dphi > math.pi) & (dphi < 2 * math.pi)
         arc = Ri * dphi
         zz = tanl[idx][:, None] * arc
         if z0 is not None:
@@ -207,22 +222,25 @@ def crossings(pt, eta, phi, q, only_sector=None, z0=None):
 # --------------------------------------------------------------------------------------
 
 def _signal_clusters(rng, n, *, eta_range, phi_range, only_sector=None, smear=SIGMA_YZ,
-                     ineff=0.0, block=20000, vertex_z=None):
+                     ineff=0.0, block=20000, vertex_z=None, loopers=False, legs_out=None):
     pt, eta, phi, q = draw_primaries(rng, n, eta_range, phi_range)
     parts = []
     for b0 in range(0, n, block):
         sl = slice(b0, min(n, b0 + block))
         z0 = None if vertex_z is None else np.full(sl.stop - sl.start, float(vertex_z))
-        ti, sec, row, y, z, _ = crossings(pt[sl], eta[sl], phi[sl], q[sl], only_sector, z0)
-        parts.append((ti + b0, sec, row, y, z))
-    ti, sec, row, y, z = (np.concatenate([p[i] for p in parts]) for i in range(5))
+        for leg in ((0, 1) if loopers else (0,)):
+            ti, sec, row, y, z, _ = crossings(pt[sl], eta[sl], phi[sl], q[sl], only_sector, z0, leg)
+            parts.append((ti + b0, sec, row, y, z, np.full(len(ti), leg, np.int8)))
+    ti, sec, row, y, z, lg = (np.concatenate([p[i] for p in parts]) for i in range(6))
     m = len(ti)
     if smear > 0:
         y = y + rng.normal(0.0, smear, m)
         z = z + rng.normal(0.0, smear, m)
     if ineff > 0:
         keep = rng.random(m) >= ineff
-        ti, sec, row, y, z = ti[keep], sec[keep], row[keep], y[keep], z[keep]
+        ti, sec, row, y, z, lg = ti[keep], sec[keep], row[keep], y[keep], z[keep], lg[keep]
+    if legs_out is not None:
+        legs_out.append(lg)
     return (pt, eta, phi, q), (ti, sec, row, y, z)
 
 
@@ -253,6 +271,8 @@ def _finish_job(rng, sig, noise, parts, shuffle=True, meta=None):
     if shuffle:
         p = rng.permutation(len(ya))
         sector, rowa, ya, za, ta, lab = sector[p], rowa[p], ya[p], za[p], ta[p], lab[p]
+        if meta and "leg" in meta:
+            meta["leg"] = meta["leg"][p]
     pt, eta, phi, q = parts
     return ClusterSet(sector, rowa, ya, za, ta, lab, np.array([0, len(ya)], np.int32),
                       pt, eta, phi, q.astype(np.int8), np.array([0, len(pt)], np.int64),
@@ -260,11 +280,13 @@ def _finish_job(rng, sig, noise, parts, shuffle=True, meta=None):
 
 
 def gen_event(seed, n_primaries, *, sector=None, noise=0.0, ineff=0.0, smear=SIGMA_YZ,
-              shuffle=True, vertex_z=None):
+              shuffle=True, vertex_z=None, loopers=False):
     """One collision at t=0 from the origin, or from (0, 0, vertex_z) when given (then the
     clusters' sides follow their own z: primaries near eta 0 cross the central membrane).
     ``sector`` given: a single-sector event with phi inside that sector and eta on its side
-    (clusters elsewhere dropped)."""
+    (clusters elsewhere dropped).  ``loopers``: the return legs of primaries that turn back
+    inside the chamber are generated too; ``meta["leg"]`` then gives each cluster's leg (0
+    outgoing, 1 return, -1 noise)."""
     rng = np.random.default_rng(seed)
     if sector is None:
         eta_r, phi_r = (-0.9, 0.9), (0.0, 2 * math.pi)
@@ -272,26 +294,30 @@ def gen_event(seed, n_primaries, *, sector=None, noise=0.0, ineff=0.0, smear=SIG
         a = float(sector_alpha(sector))
         eta_r = (0.0, 0.9) if sector < 18 else (-0.9, 0.0)
         phi_r = (a - math.radians(10.0), a + math.radians(10.0))
+    legs = [] if loopers else None
     parts, (ti, sec, row, y, z) = _signal_clusters(rng, n_primaries, eta_range=eta_r,
                                                    phi_range=phi_r, only_sector=sector,
-                                                   smear=smear, ineff=ineff, vertex_z=vertex_z)
+                                                   smear=smear, ineff=ineff, vertex_z=vertex_z,
+                                                   loopers=loopers, legs_out=legs)
     t = (DRIFT_LENGTH - np.abs(z)) / V_DRIFT
     n_noise = int(round(noise * len(ti)))
     nz = _noise_clusters(rng, n_noise)
-    return _finish_job(rng, (ti, sec, row, y, z, t), nz, parts, shuffle,
-                       dict(kind="event", seed=seed, n_primaries=n_primaries, sector=sector,
-                            vertex_z=vertex_z))
+    meta = dict(kind="event", seed=seed, n_primaries=n_primaries, sector=sector, vertex_z=vertex_z)
+    if loopers:
+        meta["leg"] = np.concatenate([legs[0], np.full(n_noise, -1, np.int8)])
+    return _finish_job(rng, (ti, sec, row, y, z, t), nz, parts, shuffle, meta)
 
 
 def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, workers=0,
-                       smear=SIGMA_YZ, vz_sigma=0.0):
+                       smear=SIGMA_YZ, vz_sigma=0.0, loopers=False):
     """Collisions at t=0 (no noise), each reproducible from its own spawned seed.  With
-    ``vz_sigma`` > 0 each collision's vertex z is drawn from N(0, vz_sigma) (cm)."""
+    ``vz_sigma`` > 0 each collision's vertex z is drawn from N(0, vz_sigma) (cm); with
+    ``loopers`` the return legs of primaries that turn back inside the chamber are kept."""
     ss = np.random.SeedSequence(seed)
     rng = np.random.default_rng(ss.spawn(1)[0])
     mult = rng.integers(mult_range[0], mult_range[1] + 1, n_collisions)
     kids = ss.spawn(n_collisions + 1)[1:]
-    args = [(kids[i], int(mult[i]), ineff, smear, vz_sigma) for i in range(n_collisions)]
+    args = [(kids[i], int(mult[i]), ineff, smear, vz_sigma, loopers) for i in range(n_collisions)]
     if workers and workers > 1 and n_collisions > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(min(workers, n_collisions)) as p:
@@ -300,12 +326,12 @@ def gen_collision_pool(seed, n_collisions, mult_range=(500, 8000), ineff=0.1, wo
 
 
 def _pool_collision(args):
-    kid, mult, ineff, smear, vz_sigma = args
+    kid, mult, ineff, smear, vz_sigma, loopers = args
     r = np.random.default_rng(kid)
     vz = float(r.normal(0.0, vz_sigma)) if vz_sigma > 0 else None
     parts, (ti, sec, row, y, z) = _signal_clusters(r, mult, eta_range=(-0.9, 0.9),
                                                    phi_range=(0, 2 * math.pi), ineff=ineff,
-                                                   smear=smear, vertex_z=vz)
+                                                   smear=smear, vertex_z=vz, loopers=loopers)
     return dict(parts=parts, ti=ti, sec=sec.astype(np.uint8), row=row.astype(np.int16),
                 y=y, z=z, vz=vz or 0.0)
 
@@ -363,21 +389,24 @@ def _c4_job(args):
 
 
 def make_config(cfg: str, seed: int, *, workers: int = 0, n_jobs: int = 512,
-                jobs=None, scale: float = 1.0, vz_sigma: float = 0.0) -> ClusterSet:
+                jobs=None, scale: float = 1.0, vz_sigma: float = 0.0,
+                loopers: bool = False) -> ClusterSet:
     """Build one of the workloads.  ``scale`` shrinks multiplicities (tests only);
     ``jobs`` selects a subset of the c4 job list; ``workers`` > 1 uses a process pool.
     ``vz_sigma`` > 0 (c2, c3): collision vertices at z ~ N(0, vz_sigma) cm instead of z = 0,
-    so that primaries near eta 0 cross the central membrane."""
+    so that primaries near eta 0 cross the central membrane.  ``loopers`` (c2, c3): the return
+    legs of primaries that turn back inside the chamber are generated too."""
     if cfg == "c1":
         cs = gen_event(seed, max(1, int(round(200 * scale))), sector=0)
     elif cfg == "c2":
         vz = float(np.random.default_rng([seed, 7]).normal(0.0, vz_sigma)) if vz_sigma > 0 else None
-        cs = gen_event(seed, max(1, int(round(8000 * scale))), noise=0.05, ineff=0.1, vertex_z=vz)
+        cs = gen_event(seed, max(1, int(round(8000 * scale))), noise=0.05, ineff=0.1, vertex_z=vz,
+                       loopers=loopers)
     elif cfg == "c3":
         rng = np.random.default_rng(seed)
         n_coll = 50 if scale >= 1 else max(1, int(round(50 * scale)))
         pool = gen_collision_pool(int(rng.integers(1 << 31)), n_coll, workers=workers,
-                                  vz_sigma=vz_sigma)
+                                  vz_sigma=vz_sigma, loopers=loopers)
         window = 1000.0 * n_coll / 50.0
         cs = assemble_timeframe(int(rng.integers(1 << 31)), pool, np.arange(n_coll), window)
     elif cfg == "c4":
@@ -395,7 +424,7 @@ def make_config(cfg: str, seed: int, *, workers: int = 0, n_jobs: int = 512,
     else:
         raise ValueError(f"unknown workload {cfg!r}")
     cs.meta.update(dict(workload=cfg, seed=seed, generator_version=GENERATOR_VERSION,
-                        scale=scale, vz_sigma=vz_sigma))
+                        scale=scale, vz_sigma=vz_sigma, loopers=loopers))
     return cs
 
 
