@@ -432,6 +432,35 @@ def membrane_run(cs, args, tuning, time_run, log, dev):
     return out
 
 
+def looper_run(cs, args, tuning, time_run, log, dev):
+    """The full TPC event with the return legs of its loopers: step time, and how many of the
+    return-leg clusters end on tracks (each return leg is tracked on its own, described
+    against its momentum)."""
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker
+    ev = DeviceClusters.from_set(cs, dev)
+    tr = Tracker(0, mode=args.mode, tuning=tuning)
+    ms = time_run(tr, ev, args.steps)
+    t = tr.tracks()
+    leg = cs.meta["leg"]
+    att = np.zeros(cs.n, bool)
+    att[t["hits"]] = True
+    nh = np.diff(t["off"])
+    tid = np.repeat(np.arange(len(nh)), nh)
+    lg = leg[t["hits"]].astype(np.int64)
+    n1 = np.bincount(tid, weights=(lg == 1), minlength=len(nh))
+    n0 = np.bincount(tid, weights=(lg == 0), minlength=len(nh))
+    out = {"workload": f"c2: {WORKLOADS['c2']}, with the return legs of its loopers",
+           "n_clusters": cs.n, "return_leg_clusters": int((leg == 1).sum()),
+           "ms_per_step": ms, "clusters_per_s": cs.n / (ms / 1e3), "tracks": int(t["n"]),
+           "return_leg_tracks": int(((n1 > 0) & (n0 == 0)).sum()),
+           "tracks_mixing_legs": int(((n1 > 0) & (n0 > 0)).sum()),
+           "attached_outgoing_leg_clusters": float(att[leg == 0].mean()),
+           "attached_return_leg_clusters": float(att[leg == 1].mean())}
+    log("return legs: " + json.dumps(out))
+    del tr
+    return out
+
+
 def cf_cpu_baseline(dg):
     """The oracle's cluster finder on the digits of sectors 0-3 of the digit workload."""
     import oracle.oracle as O
@@ -595,6 +624,8 @@ def main():
                     help="chunks of the run at 0.8x the measured capacity when the stated rate saturates")
     ap.add_argument("--cf-config", default="d3", choices=["d1", "d2", "d3", ""],
                     help="digit workload of the cluster-finding row ('' = skip)")
+    ap.add_argument("--no-loopers", dest="loopers", action="store_false",
+                    help="skip the full event with its loopers' return legs")
     ap.add_argument("--vz-sigma", type=float, default=5.0,
                     help="vertex z spread (cm) of the extra time frame for the membrane merge (0: skip)")
     ap.add_argument("--also", default="c2,c3",
@@ -618,7 +649,7 @@ def main():
     log(f"generated {args.config} seed {seed}: {cs.n} clusters, {cs.n_jobs} jobs "
         f"in {time.perf_counter() - t0:.1f}s")
     others = {}
-    vz_set = None
+    vz_set = loop_set = None
     if not args.profile_only:
         for name in [x for x in args.also.split(",") if x and x != args.config]:
             others[name] = g.make_config(name, SEEDS[name], workers=args.workers)
@@ -626,6 +657,7 @@ def main():
         if args.vz_sigma > 0:
             vz_set = g.make_config("c3", SEEDS["c3"], workers=args.workers, vz_sigma=args.vz_sigma)
             log(f"generated c3 with vertices spread in z ({args.vz_sigma} cm): {vz_set.n} clusters")
+        loop_set = g.make_config("c2", SEEDS["c2"], loopers=True) if args.loopers else None
     # the oracle baselines first, before any GPU use
     cpu = cpu_par = cpu_chain = None
     if not args.no_cpu and not args.profile_only:
@@ -833,6 +865,7 @@ def main():
             log(f"{name} plain per sector ({split.n_jobs} jobs): {pms:.3f} ms/step; identical tracks: {same}")
             del ptr, sev
     membrane = membrane_run(vz_set, args, tuning, time_run, log, dev) if vz_set is not None else None
+    loopers = looper_run(loop_set, args, tuning, time_run, log, dev) if loop_set is not None else None
     serving = None
     if args.serve_chunks > 0:
         del tr, ev                 # the serving run sizes its admission by free HBM
@@ -877,6 +910,7 @@ def main():
         "compression": compression,
         "sync_preset": sync_row,
         "membrane_merge": membrane,
+        "return_legs": loopers,
         "cluster_finding": clusters_row,
         "tracks": int(tracks["n"]),
         "tracklets": int(T),
