@@ -200,10 +200,11 @@ class Server:
     slot's pinned buffers, valid during the call only.  A batch whose run reported a
     range or capacity condition (tpc_counts status bits) raises ServingError with its
     chunk ids unless ``strict`` is False, in which case its chunks are reported with
-    ``result["status"]`` set."""
+    ``result["status"]`` set.  ``params`` (a tpc_params, e.g. ``preset_params("sync")``)
+    chooses the cut set; the default reading otherwise."""
 
     def __init__(self, pool: Pool, device=0, n_slots=2, hbm_budget=None, tuning=None, max_batch=64,
-                 max_batch_clusters=100_000_000, strict=True):
+                 max_batch_clusters=100_000_000, strict=True, params=None):
         import torch
         self.torch = torch
         self.pool = pool
@@ -219,7 +220,8 @@ class Server:
         self.slots = []
         for _ in range(n_slots):
             s = torch.cuda.Stream(device)
-            self.slots.append(Slot(s, Tracker(device, mode="persistent" if tuning.persistent_waves else "batched",
+            self.slots.append(Slot(s, Tracker(device, params=params,
+                                              mode="persistent" if tuning.persistent_waves else "batched",
                                               tuning=tuning, stream=s),
                                    counts=torch.zeros(6, dtype=torch.int32, pin_memory=True)))
         self.max_batch = max_batch

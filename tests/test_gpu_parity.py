@@ -246,15 +246,18 @@ def test_autotune_candidates_are_bit_identical():
     assert rep["verified"] and len(rep["trials"]) >= 8
 
 
-def test_serving_chunk_alone_equals_chunk_in_mix():
+@pytest.mark.parametrize("preset", [None, "sync"])
+def test_serving_chunk_alone_equals_chunk_in_mix(preset):
     """Each chunk's full result from the concurrent Server (three slots busy at once,
     batches of up to two chunks, results copied back from overlapping streams) equals
     the same chunk tracked alone, bit for bit: hit lists, parameters, covariance,
-    x_ref, chi2, ndf and sector."""
+    x_ref, chi2, ndf and sector; with the default reading and with the synchronous cut
+    set (whose downward extension claims clusters within each chunk's job only)."""
     import torch
 
     from paper_2402_01205_amd.serve import Pool, Server, assemble, make_stream
-    from paper_2402_01205_amd.tpc import Tracker
+    from paper_2402_01205_amd.tpc import Tracker, preset_params
+    prm = preset_params(preset) if preset else None
     cols = g.gen_collision_pool(61, 8, mult_range=(100, 400))
     pool = Pool.from_collisions(cols)
     got = {}
@@ -262,7 +265,7 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
     def keep(cid, res):
         got[cid] = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in res.items()}
 
-    srv = Server(pool, 0, n_slots=3, max_batch=2)
+    srv = Server(pool, 0, n_slots=3, max_batch=2, params=prm)
     chunks = make_stream(8, 14, rate_hz=1e5, coll_range=(2, 6), seed=63)
     res = srv.run(chunks, realtime=True, on_result=keep)
     say("server", {k: v for k, v in res.items() if k not in ("tracks", "latencies")})
@@ -270,7 +273,7 @@ def test_serving_chunk_alone_equals_chunk_in_mix():
     assert res["max_concurrent"] == 3 and res["batches"] < 14      # overlap and shared batches
     assert sorted(got) == list(range(14))
     s = torch.cuda.current_stream()
-    tr = Tracker(0, mode="batched")
+    tr = Tracker(0, params=prm, mode="batched")
     n_cmp = 0
     for ch in chunks:
         ev = assemble(pool, [ch], s)
