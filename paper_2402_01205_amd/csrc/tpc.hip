@@ -833,6 +833,62 @@ __device__ __forceinline__ void trk_begin(const GridView& G, const TrackletView&
   T.misses = 0;
 }
 
+// The following's window search: the cluster of minimum chi2 inside the window
+// |y - y_pred| <= wy, |z - z_pred| <= wz (ties: the smaller input index) among those
+// `eligible` accepts, which is asked only about a candidate that would win.  The candidate
+// ranges of two cell rows are read at a time, then their positions four at a time, so one
+// memory wait serves several of them (rows of 1-4 and batches of 2-8 were measured: 2 and 4
+// gave the shortest tracklet stage); the scan order, rows then cells, is unchanged.
+constexpr int kFollowRows = 2;
+constexpr int kFollowBatch = 4;
+template <class Eligible>
+__device__ __forceinline__ void window_best(const GridView& G, const SlotGrid& g, const State& S, const SInv& si,
+                                            float wy, float wz, Eligible eligible, int32_t& cand, float& bchi,
+                                            float& cy, float& cz) {
+  if (g.ncell <= 0) return;
+  const int32_t cb0 = g.cbase;
+  const int y0c = cell_of(S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
+  const int y1c = cell_of(S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
+  const int z0c = cell_of(S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
+  const int z1c = cell_of(S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
+  for (int zc = z0c; zc <= z1c; zc += kFollowRows) {
+    int32_t A0[kFollowRows], A1[kFollowRows];
+#pragma unroll
+    for (int e = 0; e < kFollowRows; ++e) {
+      A0[e] = A1[e] = 0;
+      if (zc + e <= z1c) {
+        const int32_t e0 = cb0 + (zc + e) * g.ny;
+        A0[e] = G.cell_off[e0 + y0c];
+        A1[e] = G.cell_off[e0 + y1c + 1];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kFollowRows; ++e) {
+      for (int32_t c0 = A0[e]; c0 < A1[e]; c0 += kFollowBatch) {
+        float2 Cb[kFollowBatch];
+#pragma unroll
+        for (int i = 0; i < kFollowBatch; ++i) Cb[i] = c0 + i < A1[e] ? G.yz[c0 + i] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kFollowBatch; ++i) {
+          const int32_t c = c0 + i;
+          if (c >= A1[e]) break;
+          const float rr0 = (Cb[i].x - S.P[0]) - S.L[0];
+          const float rr1 = (Cb[i].y - S.P[1]) - S.L[1];
+          if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
+          const float chi2 = chi2_of(si, rr0, rr1);
+          // equal chi2: the smaller input index wins (read only for such ties)
+          if (!(cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx))) continue;
+          if (!eligible(c)) continue;
+          cand = c;
+          bchi = chi2;
+          cy = Cb[i].x;
+          cz = Cb[i].y;
+        }
+      }
+    }
+  }
+}
+
 // One step; returns true when the tracklet has ended.
 __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& V, TrkLane& T,
                                          const Consts& k) {
@@ -849,6 +905,9 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
   } else {
     row = T.r;
   }
+  // the row's grid geometry is loaded before the transport, which hides its latency
+  SlotGrid g{};
+  if (!chain) g = G.sg[T.slot_base + row];
   const float xt = k.x[row];
   if (!propagate(T.S, T.x, xt, k)) return true;
   T.x = xt;
@@ -858,34 +917,8 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
     if (!si.ok) return true;
     const float wy = k.nwin * sqrt_rn(T.S.C[0] + k.vy);
     const float wz = k.nwin * sqrt_rn(T.S.C[2] + k.vz);
-    const int32_t slot = T.slot_base + row;
-    const SlotGrid g = G.sg[slot];
     float bchi = 0.f;
-    if (g.ncell > 0) {
-      const int32_t cb0 = g.cbase;
-      const int y0c = cell_of(T.S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
-      const int y1c = cell_of(T.S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
-      const int z0c = cell_of(T.S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
-      const int z1c = cell_of(T.S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
-      for (int zc = z0c; zc <= z1c; ++zc) {
-        const int32_t e0 = cb0 + zc * g.ny;
-        const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
-        for (int32_t c = a0; c < a1; ++c) {
-          const float2 Cc = G.yz[c];
-          const float rr0 = (Cc.x - T.S.P[0]) - T.S.L[0];
-          const float rr1 = (Cc.y - T.S.P[1]) - T.S.L[1];
-          if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
-          const float chi2 = chi2_of(si, rr0, rr1);
-          // equal chi2: the smaller input index wins (read only for such ties)
-          if (cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx)) {
-            cand = c;
-            bchi = chi2;
-            cy = Cc.x;
-            cz = Cc.y;
-          }
-        }
-      }
-    }
+    window_best(G, g, T.S, si, wy, wz, [](int32_t) { return true; }, cand, bchi, cy, cz);
     take = cand >= 0 && bchi <= k.chi2_follow;
   }
   if (take) {
@@ -1361,16 +1394,25 @@ __device__ __forceinline__ uint32_t ext_key(const FitView& F, const ExtView& E, 
 // The search of one track as a step machine: ext_begin sets it up (false when there is
 // nothing to search: a failed fit, the innermost hit on row 0, or no room in ext_hits),
 // ext_step searches one row (true when the search has ended) and claims what it finds.
+// The search of one track as a step machine: ext_begin sets it up (false when there is
+// nothing to search: a failed fit, or the innermost hit on row 0), ext_step searches one
+// row (true when the search has ended).  A track's found clusters go to its slots in
+// ext_hits, one per row below its innermost hit, allocated in track order; a track whose
+// slots would pass the end of ext_hits (its rows below outnumber the clusters, which only
+// inputs cut short of their inner rows reach) keeps no list: the later kernels replay its
+// search, which takes the same steps (it reads only the grid, the ownership and its own
+// state), instead of reading the list.
 struct ExtLane {
   State S;
   float x;
-  int32_t kk, base, slot_base;
+  int32_t kk, base, slot_base, last;
   uint32_t key;
   int r, misses, m;
+  bool store, claim;
 };
 
 __device__ __forceinline__ bool ext_begin(const GridView& G, const FitView& F, const ExtView& E, ExtLane& T,
-                                          int32_t kk, int32_t* counters) {
+                                          int32_t kk, bool replay) {
   T.kk = kk;
   T.m = 0;
   if (F.ndf[kk] < 0) return false;
@@ -1379,10 +1421,8 @@ __device__ __forceinline__ bool ext_begin(const GridView& G, const FitView& F, c
   if (r_in == 0) return false;
   T.slot_base = hs - r_in;
   T.base = E.ext_off[kk];
-  if (T.base + r_in > E.capX) {
-    atomicOr(&counters[kCntStatus], kStatusCapacity);
-    return false;
-  }
+  T.store = !replay && (int64_t)T.base + r_in <= (int64_t)E.capX;
+  T.claim = !replay;
   T.key = ext_key(F, E, kk, hs);
   load_fit(F, kk, T.S, T.x);
   T.r = r_in - 1;
@@ -1392,6 +1432,7 @@ __device__ __forceinline__ bool ext_begin(const GridView& G, const FitView& F, c
 
 __device__ __forceinline__ bool ext_step(const GridView& G, const TrackletView& V, const ExtView& E, ExtLane& T,
                                          const Consts& k) {
+  const SlotGrid g = G.sg[T.slot_base + T.r];  // loaded before the transport (latency)
   const float xr = k.x[T.r];
   if (!propagate(T.S, T.x, xr, k)) return true;
   T.x = xr;
@@ -1399,42 +1440,23 @@ __device__ __forceinline__ bool ext_step(const GridView& G, const TrackletView& 
   if (!si.ok) return true;
   const float wy = k.nwin * sqrt_rn(T.S.C[0] + k.vy);
   const float wz = k.nwin * sqrt_rn(T.S.C[2] + k.vz);
-  const SlotGrid g = G.sg[T.slot_base + T.r];
   int32_t cand = -1;
   float bchi = 0.f, cy = 0.f, cz = 0.f;
-  if (g.ncell > 0) {
-    const int y0c = cell_of(T.S.P[0] - wy - 0.01f, g.ylo, g.inv_by, g.ny);
-    const int y1c = cell_of(T.S.P[0] + wy + 0.01f, g.ylo, g.inv_by, g.ny);
-    const int z0c = cell_of(T.S.P[1] - wz - 0.01f, g.zlo, g.inv_bz, g.nz);
-    const int z1c = cell_of(T.S.P[1] + wz + 0.01f, g.zlo, g.inv_bz, g.nz);
-    for (int zc = z0c; zc <= z1c; ++zc) {
-      const int32_t e0 = g.cbase + zc * g.ny;
-      const int32_t a0 = G.cell_off[e0 + y0c], a1 = G.cell_off[e0 + y1c + 1];
-      for (int32_t c = a0; c < a1; ++c) {
-        const float2 Cc = G.yz[c];
-        const float rr0 = (Cc.x - T.S.P[0]) - T.S.L[0];
-        const float rr1 = (Cc.y - T.S.P[1]) - T.S.L[1];
-        if (!(fabsf(rr0) <= wy) || !(fabsf(rr1) <= wz)) continue;
-        const float chi2 = chi2_of(si, rr0, rr1);
-        if (!(cand < 0 || chi2 < bchi || (chi2 == bchi && G.gh[c].idx < G.gh[cand].idx))) continue;
-        // owned by a selected track: not a candidate (looked up only for a would-be winner)
-        const uint32_t w = V.hitw[c];
-        if (w != 0u) {
-          const int32_t t = key_tracklet(w, V.T_off, T.slot_base);
-          if ((uint32_t)t < (uint32_t)V.capT && E.accf[t]) continue;
-        }
-        cand = c;
-        bchi = chi2;
-        cy = Cc.x;
-        cz = Cc.y;
-      }
-    }
-  }
+  // clusters owned by a selected track are not candidates
+  window_best(G, g, T.S, si, wy, wz,
+              [&](int32_t c) {
+                const uint32_t w = V.hitw[c];
+                if (w == 0u) return true;
+                const int32_t t = key_tracklet(w, V.T_off, T.slot_base);
+                return !((uint32_t)t < (uint32_t)V.capT && E.accf[t]);
+              },
+              cand, bchi, cy, cz);
   if (cand >= 0 && bchi <= k.chi2_follow) {
     if (!kf_update(T.S, cy, cz, k, nullptr)) return true;
-    E.ext_hits[T.base + T.m] = cand;
+    if (T.store) E.ext_hits[T.base + T.m] = cand;
+    if (T.claim) atomicMax(&E.claim[cand], T.key);
+    T.last = cand;
     ++T.m;
-    atomicMax(&E.claim[cand], T.key);
     T.misses = 0;
   } else if (++T.misses >= k.max_miss) {
     return true;
@@ -1442,63 +1464,100 @@ __device__ __forceinline__ bool ext_step(const GridView& G, const TrackletView& 
   return --T.r < 0;
 }
 
-// One lane per track.
+// The next found cluster of a replayed search (-1 when the search ends first).
+__device__ __forceinline__ int32_t ext_next(const GridView& G, const TrackletView& V, const ExtView& E,
+                                            ExtLane& T, bool& ended, const Consts& k) {
+  while (!ended) {
+    const int m0 = T.m;
+    ended = ext_step(G, V, E, T, k);
+    if (T.m > m0) return T.last;
+  }
+  return -1;
+}
+
+// One lane per track: the search, claiming every cluster it finds.  ext_n: the number found,
+// or -1 - that number for a track that kept no list.
 __global__ __launch_bounds__(128) void k_ext_search(GridView G, TrackletView V, FitView F, ExtView E,
-                                                    Bound lo_b, Bound hi_b, int32_t* counters, Consts k) {
+                                                    Bound lo_b, Bound hi_b, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
   ExtLane T;
-  if (ext_begin(G, F, E, T, kk, counters)) {
+  bool listed = true;
+  if (ext_begin(G, F, E, T, kk, false)) {
+    listed = T.store;
     while (!ext_step(G, V, E, T, k)) {
     }
   }
-  E.ext_n[kk] = T.m;
+  E.ext_n[kk] = listed ? T.m : -1 - T.m;
 }
 
-// One lane per track: the kept prefix of the found hits, the fit continued over them, and
-// the length of the extended hit list.
-__global__ __launch_bounds__(128) void k_ext_keep(GridView G, FitView F, ExtView E, Bound lo_b, Bound hi_b,
-                                                  Consts k) {
+// The fit of track kk continued over its kept clusters from the stored state (hit to hit,
+// as the fit runs), stored in its record.
+template <class Next>
+__device__ __forceinline__ void ext_continue(const GridView& G, const FitView& F, int32_t kk, int n0, int kept,
+                                             Next next, const Consts& k) {
+  State S;
+  float x;
+  load_fit(F, kk, S, x);
+  float chi2 = F.chi2[kk];
+  bool ok = true;
+  for (int q = 0; q < kept && ok; ++q) {
+    const GHit Hq = ldh(G.gh + next(q));
+    const float xh = k.x[Hq.slot % kRows];
+    if (!propagate(S, x, xh, k)) { ok = false; break; }
+    x = xh;
+    float c2;
+    if (!kf_update(S, Hq.y, Hq.z, k, &c2)) { ok = false; break; }
+    chi2 = chi2 + c2;
+  }
+  store_fit(F, kk, S, x, chi2, n0 + kept, ok);
+}
+
+// One lane per track: the kept prefix of the found clusters (up to the first one another
+// track won), the fit continued over them from the stored state, and the length of the
+// extended hit list.  ext_n becomes the kept number (-1 - it without a list: such a track's
+// fit is continued by k_ext_write, which replays its search from the stored state).
+__global__ __launch_bounds__(128) void k_ext_keep(GridView G, TrackletView V, FitView F, ExtView E,
+                                                  Bound lo_b, Bound hi_b, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
   const int32_t kk = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (kk >= hi) return;
   const int32_t n0 = F.sel_off[kk + 1] - F.sel_off[kk];
-  const int m = E.ext_n[kk];
+  const int32_t v = E.ext_n[kk];
+  const bool listed = v >= 0;
+  const int m = listed ? v : -1 - v;
   int kept = 0;
   if (m > 0) {
     const int32_t base = E.ext_off[kk];
     const int32_t hs = G.gh[F.sel_hits[F.sel_off[kk]]].slot;
     const uint32_t key = ext_key(F, E, kk, hs);
-    while (kept < m && E.claim[E.ext_hits[base + kept]] == key) ++kept;
-    if (kept > 0) {
-      State S;
-      float x;
-      load_fit(F, kk, S, x);
-      float chi2 = F.chi2[kk];
-      bool ok = true;
-      for (int q = 0; q < kept && ok; ++q) {
-        const GHit Hq = ldh(G.gh + E.ext_hits[base + q]);
-        const float xh = k.x[Hq.slot % kRows];
-        if (!propagate(S, x, xh, k)) { ok = false; break; }
-        x = xh;
-        float c2;
-        if (!kf_update(S, Hq.y, Hq.z, k, &c2)) { ok = false; break; }
-        chi2 = chi2 + c2;
+    if (listed) {
+      while (kept < m && E.claim[E.ext_hits[base + kept]] == key) ++kept;
+      if (kept > 0) ext_continue(G, F, kk, n0, kept, [&](int q) { return E.ext_hits[base + q]; }, k);
+    } else {
+      ExtLane R;
+      bool ended = false;
+      ext_begin(G, F, E, R, kk, true);
+      for (int q = 0; q < m; ++q) {
+        const int32_t c = ext_next(G, V, E, R, ended, k);
+        if (c < 0 || E.claim[c] != key) break;
+        ++kept;
       }
-      store_fit(F, kk, S, x, chi2, n0 + kept, ok);
     }
   }
-  E.ext_n[kk] = kept;
+  E.ext_n[kk] = listed ? kept : -1 - kept;
   E.xn[kk] = n0 + kept;
 }
 
-// One wave per track: the extended hit list (kept hits in ascending rows, then the owned
-// hits) written at its offset in the new list.
-__global__ __launch_bounds__(256) void k_ext_write(FitView F, ExtView E, const int32_t* xoff, int32_t* xhits,
-                                                   Bound lo_b, Bound hi_b, int32_t capH, int32_t* counters) {
+// One wave per track: the extended hit list (kept clusters in ascending rows, then the
+// owned hits) written at its offset in the new list; a track without a list replays its
+// search on lane 0.
+__global__ __launch_bounds__(256) void k_ext_write(GridView G, TrackletView V, FitView F, ExtView E,
+                                                   const int32_t* xoff, int32_t* xhits, Bound lo_b, Bound hi_b,
+                                                   int32_t capH, int32_t* counters, Consts k) {
   const int32_t lo = lo_b.get();
   const int32_t hi = min(hi_b.get(), F.capK);
   const int lane = threadIdx.x & 63;
@@ -1506,17 +1565,34 @@ __global__ __launch_bounds__(256) void k_ext_write(FitView F, ExtView E, const i
   for (int64_t w0 = lo + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); w0 < hi; w0 += nw) {
     const int32_t kk = (int32_t)w0;
     const int32_t o = xoff[kk];
-    const int kept = E.ext_n[kk];
+    const int32_t v = E.ext_n[kk];
+    const bool listed = v >= 0;
+    const int kept = listed ? v : -1 - v;
     const int32_t base = E.ext_off[kk];
     const int32_t q0 = F.sel_off[kk], q1 = F.sel_off[kk + 1];
     const int32_t n = kept + (q1 - q0);
     for (int32_t i = lane; i < n; i += 64) {
+      if (i < kept && !listed) continue;
       const int32_t c = i < kept ? E.ext_hits[base + kept - 1 - i] : F.sel_hits[q0 + i - kept];
       if (o + i < capH) xhits[o + i] = c;
+    }
+    if (!listed && kept > 0 && lane == 0) {
+      // the search replayed from the stored state, which k_ext_keep left unchanged; its kept
+      // clusters written in ascending rows, then the fit continued over them
+      ExtLane R;
+      bool ended = false;
+      ext_begin(G, F, E, R, kk, true);
+      for (int j = 0; j < kept; ++j) {
+        const int32_t c = ext_next(G, V, E, R, ended, k);
+        if (o + kept - 1 - j < capH) xhits[o + kept - 1 - j] = c;
+      }
+      if (o + n <= capH)  // (past the capacity the run reports it and the lists are cut)
+        ext_continue(G, F, kk, q1 - q0, kept, [&](int q) { return xhits[o + kept - 1 - q]; }, k);
     }
     if (lane == 0 && o + n > capH) atomicOr(&counters[kCntStatus], kStatusCapacity);
   }
 }
+
 
 // --- merge: candidate search.  Tracks are bucketed by (event, sector).
 // Merge buckets: (event, sector, z bin of the track's innermost cluster); bins are
@@ -3552,12 +3628,12 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
     scan(c, L.ext_n, L.ext_off, klo, khi, kb, false);
     fill_i32(c, (int32_t*)L.claim, L.N, 0);
     hipLaunchKernelGGL(k_ext_search, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c),
-                       make_tv(c), F, E, klo, khi, L.counters, c->k);
-    hipLaunchKernelGGL(k_ext_keep, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c), F, E, klo,
-                       khi, c->k);
+                       make_tv(c), F, E, klo, khi, c->k);
+    hipLaunchKernelGGL(k_ext_keep, dim3(blocks_for(kb, 128)), dim3(128), 0, c->stream, make_grid(c), make_tv(c),
+                       F, E, klo, khi, c->k);
     scan(c, L.xn, L.xsel_off, klo, khi, kb, false);
-    hipLaunchKernelGGL(k_ext_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, F, E, L.xsel_off,
-                       L.xsel_hits, klo, khi, L.capH, L.counters);
+    hipLaunchKernelGGL(k_ext_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, make_grid(c), make_tv(c), F,
+                       E, L.xsel_off, L.xsel_hits, klo, khi, L.capH, L.counters, c->k);
   }
   // ---- merge across adjacent sectors of one event
   const int nev = J;

@@ -48,19 +48,19 @@ def _cluster_set(parts):
                 job_off=np.array([0, n], np.int32), label=np.array(lab, np.int32))
 
 
-def _thinned_event(seed, n, step):
-    """n primaries in sector 0 (pT 0.5-5 GeV), all rows from R_CUT up, below it every
-    `step`-th row counted down from R_CUT."""
+def _thinned_event(seed, n, step, r_cut=R_CUT):
+    """n primaries in sector 0 (pT 0.5-5 GeV), all rows from r_cut up, below it every
+    `step`-th row counted down from r_cut."""
     rng = np.random.default_rng(seed)
     a = float(g.sector_alpha(0))
-    lower = [r for r in range(R_CUT - step, -1, -step)]
+    lower = [r for r in range(r_cut - step, -1, -step)]
     parts, truth = [], []
     for p in range(n):
         pt = float(np.exp(rng.uniform(np.log(0.5), np.log(5.0))))
         eta = float(rng.uniform(0.05, 0.85))
         phi = float(a + rng.uniform(-0.12, 0.12))
         q = float(rng.choice([-1.0, 1.0]))
-        parts.append((p, _particle_clusters(pt, eta, phi, q, list(range(R_CUT, 152)) + lower)))
+        parts.append((p, _particle_clusters(pt, eta, phi, q, list(range(r_cut, 152)) + lower)))
         truth.append((pt, eta, phi, q))
     return _cluster_set(parts), truth
 

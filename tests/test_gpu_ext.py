@@ -53,6 +53,20 @@ def test_extension_pin_geometry_bit_exact(step):
     assert (o["tracks"]["n_ext"].sum() > 0) == (step == 3)
 
 
+def test_extension_of_tracks_beyond_the_list_room_bit_exact():
+    """Tracks that start at row 130 with their lower clusters every third row: the rows
+    below the tracks outnumber the clusters, so the later tracks keep no list of found
+    clusters and their searches are replayed; every stage still equals the oracle."""
+    ev, _ = _thinned_event(5, 30, 3, r_cut=130)
+    cs = _Set(ev)
+    o = oracle_run(cs, O.params(ext_down=1))
+    sel = o["sel"]
+    rows_below = sum(int(cs.row[sel["hits"][sel["off"][i]]]) for i in range(len(sel["tracklet"])))
+    assert rows_below > cs.n + 1, (rows_below, cs.n)
+    compare_all(gpu_run(cs, params=_ext_params()), o)
+    assert o["tracks"]["n_ext"].sum() > 300
+
+
 @pytest.mark.parametrize("longer", ["A", "B"])
 def test_contested_pair_bit_exact(longer):
     a = float(g.sector_alpha(0))
