@@ -5,9 +5,11 @@ The scheduler admits every arrived chunk it can, as slots and device memory
 free up: all admitted waiting chunks are packed as independent jobs (one job
 and event per chunk) into one batched library launch on a free slot; slots are
 separate HIP streams, so a batch that arrives while others are on the GPU
-overlaps with them.  Admission is sized by free HBM: a batch is launched only if
-its workspace (tpc_workspace_size), its cluster buffers and its outputs fit in
-the budget left by the batches in flight.  Cluster and track state stay on the
+overlaps with them.  Each slot allocates its workspace and outputs for a full batch
+when the server starts, so nothing is allocated while chunks wait.  Admission is
+sized by the HBM left after that: a batch is launched only if its workspace
+(tpc_workspace_size), its cluster buffers and its outputs fit in the budget left by
+the batches in flight.  Cluster and track state stay on the
 device; each chunk's results are copied to pinned host memory when its batch
 completes: the library's counters (tpc_counts) first, then exactly the tracks and hits
 found, all copied to pinned host memory; the end of those copies ends the chunk's
@@ -204,26 +206,26 @@ class Server:
     chooses the cut set; the default reading otherwise."""
 
     def __init__(self, pool: Pool, device=0, n_slots=2, hbm_budget=None, tuning=None, max_batch=64,
-                 max_batch_clusters=100_000_000, strict=True, params=None):
+                 max_batch_clusters=100_000_000, strict=True, params=None, reserve=True):
         import torch
         self.torch = torch
         self.pool = pool
         self.device = device
         self.strict = strict
-        torch.cuda.synchronize(device)
-        torch.cuda.empty_cache()
-        free, total = torch.cuda.mem_get_info(device)
-        self.budget = int(hbm_budget if hbm_budget is not None else 0.7 * free)
         self.max_batch_clusters = max_batch_clusters
         tuning = tuning or default_tuning(use_graph=0)
         tuning.use_graph = 0
         self.slots = []
         for _ in range(n_slots):
             s = torch.cuda.Stream(device)
-            self.slots.append(Slot(s, Tracker(device, params=params,
-                                              mode="persistent" if tuning.persistent_waves else "batched",
-                                              tuning=tuning, stream=s),
-                                   counts=torch.zeros(6, dtype=torch.int32, pin_memory=True)))
+            tr = Tracker(device, params=params, mode="persistent" if tuning.persistent_waves else "batched",
+                         tuning=tuning, stream=s)
+            if reserve:  # every slot's buffers for a full batch up front, not while chunks wait
+                tr.reserve(max_batch_clusters, max_batch)
+            self.slots.append(Slot(s, tr, counts=torch.zeros(6, dtype=torch.int32, pin_memory=True)))
+        torch.cuda.synchronize(device)
+        free, total = torch.cuda.mem_get_info(device)
+        self.budget = int(hbm_budget if hbm_budget is not None else 0.7 * free)
         self.max_batch = max_batch
         self.in_flight_bytes = 0
 

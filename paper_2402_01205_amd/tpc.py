@@ -278,14 +278,20 @@ class Tracker:
     def workspace_size(self, n: int, n_jobs: int) -> int:
         return int(lib().tpc_workspace_size(self.ctx, n, n_jobs))
 
-    def _prepare(self, ev: DeviceClusters):
+    def reserve(self, n: int, n_jobs: int):
+        """Allocates the workspace and the output buffers for inputs of up to n clusters in
+        n_jobs jobs now, so that later runs of that size allocate nothing."""
+        self._ensure(n, n_jobs)
+
+    def _ensure(self, n: int, n_jobs: int):
         torch = self.torch
-        need = self.workspace_size(ev.n, ev.n_jobs)
+        need = self.workspace_size(n, n_jobs)
         if self.ws is None or self.ws.numel() < need:
+            self.ws = None
             self.ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
             self._check(lib().tpc_bind_workspace(self.ctx, _ptr(self.ws), need), "tpc_bind_workspace")
-        capT = min(ev.n // 8 + 1024, ev.n + 1024)
-        capH = ev.n + 1
+        capT = min(n // 8 + 1024, n + 1024)
+        capH = n + 1
         if self.out is None or self.out["cap_tracks"] < capT or self.out["cap_hits"] < capH:
             dev = f"cuda:{self.device}"
             i32, f32 = torch.int32, torch.float32
@@ -302,6 +308,9 @@ class Tracker:
                             job=torch.zeros(capT, dtype=i32, device=dev),
                             tracklet=torch.zeros(capT, dtype=i32, device=dev),
                             t0=torch.zeros(capT, dtype=f32, device=dev))
+
+    def _prepare(self, ev: DeviceClusters):
+        self._ensure(ev.n, ev.n_jobs)
         o = self.out
         self._tracks = tpc_tracks(o["cap_tracks"], o["cap_hits"], *[
             _ptr(o[k]) for k in ("n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf",
