@@ -1287,24 +1287,39 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
   const bool walk = F.chain_next && F.chain_prev[kk] < 0;
   for (int32_t p = kk; p >= 0 && np <= kHalf; p = walk ? F.chain_next[p] : -1) pieces[np++] = p;
   const int32_t last_piece = pieces[np - 1];
-  const int32_t tl = F.sel_from[last_piece];
   State S;
-  const int32_t ho = F.sel_hits[F.sel_off[last_piece + 1] - 1];
-  const GHit Ho = ldh(G.gh + ho);
-  S.P[0] = Ho.y;
-  S.P[1] = Ho.z;
-  S.P[2] = V.state[(int64_t)tl * kStateStride + 2];
-  S.P[3] = V.state[(int64_t)tl * kStateStride + 3];
-  S.P[4] = V.state[(int64_t)tl * kStateStride + 4];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
-  init_cov(S, k.prior1);
-  float x = k.x[Ho.slot % kRows];
-  float chi2 = 0.f;
-  int nh = 0;
+  float x, chi2;
+  int nh, cur_sec, pstart;
   bool ok = true;
-  int cur_sec = (Ho.slot / kRows) % kSectors;
-  for (int pi = np - 1; pi >= 0 && ok; --pi) {
+  if (np >= 2 && F.ndf[last_piece] >= 0) {
+    // A chain's fit starts on its outermost piece exactly as that piece's own fit did (its
+    // outermost hit, its tracklet's direction and curvature, the same priors) and runs over
+    // the same hits first, so it continues from that piece's stored record (state with its
+    // compensation terms, chi2, hit count) instead of refitting them.
+    load_fit(F, last_piece, S, x);
+    chi2 = F.chi2[last_piece];
+    nh = (F.ndf[last_piece] + 5) / 2;
+    cur_sec = (G.gh[F.sel_hits[F.sel_off[last_piece]]].slot / kRows) % kSectors;
+    pstart = np - 2;
+  } else {
+    const int32_t tl = F.sel_from[last_piece];
+    const int32_t ho = F.sel_hits[F.sel_off[last_piece + 1] - 1];
+    const GHit Ho = ldh(G.gh + ho);
+    S.P[0] = Ho.y;
+    S.P[1] = Ho.z;
+    S.P[2] = V.state[(int64_t)tl * kStateStride + 2];
+    S.P[3] = V.state[(int64_t)tl * kStateStride + 3];
+    S.P[4] = V.state[(int64_t)tl * kStateStride + 4];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S.L[i] = 0.f;
+    init_cov(S, k.prior1);
+    x = k.x[Ho.slot % kRows];
+    chi2 = 0.f;
+    nh = 0;
+    cur_sec = (Ho.slot / kRows) % kSectors;
+    pstart = np - 1;
+  }
+  for (int pi = pstart; pi >= 0 && ok; --pi) {
     const int32_t p = pieces[pi];
     const int32_t a = F.sel_off[p], b = F.sel_off[p + 1];
     for (int32_t q = b - 1; q >= a; --q) {
