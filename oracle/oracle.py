@@ -84,6 +84,8 @@ def lib():
         L.orc_status.argtypes = [P]
         L.orc_get_track_t0.argtypes = [P, C.c_int32, P, P]
         L.orc_get_track_ext.argtypes = [P, C.c_int32, P]
+        L.orc_pair_legs.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, P, P]
+        L.orc_pair_legs.restype = None
         L.orc_collision_time_f32.argtypes = [P, C.c_float, C.c_int32, C.POINTER(Params)]
         L.orc_collision_time_f32.restype = C.c_float
         L.orc_collision_time_f64.argtypes = [P, C.c_double, C.c_int32, C.POINTER(Params)]
@@ -250,6 +252,21 @@ class Run:
         fn = L.orc_fit_hits_f64 if fp64 else L.orc_fit_hits_f32
         ok = fn(self.h, len(hits), _p(hits), _p(stk), _p(P), _p(Cv), _p(x), _p(c2))
         return bool(ok), P, Cv, float(x[0]), float(c2[0])
+
+
+def pair_legs(tracks, event, prm=None):
+    """A25: the output index of each track's other looper leg, or -1 (tracks as returned by
+    Run.tracks(); event: the event id of each track)."""
+    K = len(tracks["ndf"])
+    leg = np.full(K, -1, np.int32)
+    if K:
+        P = np.ascontiguousarray(tracks["P"], np.float32)
+        x = np.ascontiguousarray(tracks["x"], np.float32)
+        sec = np.ascontiguousarray(tracks["sector"], np.int32)
+        ev = np.ascontiguousarray(event, np.int32)
+        ndf = np.ascontiguousarray(tracks["ndf"], np.int32)
+        lib().orc_pair_legs(C.byref(prm or params()), K, _p(P), _p(x), _p(sec), _p(ev), _p(ndf), _p(leg))
+    return leg
 
 
 # ----------------------------------------------------------------- unit hooks (pins)

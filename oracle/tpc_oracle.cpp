@@ -12,7 +12,8 @@
 // that reading (O1 frame/track model, O2 helix propagation, O3 grid (not
 // needed here: rows are searched in full or by binary search in z), O4
 // neighbours, O5 cleaning, O6 starts, O7 tracklets, O8 Kalman update,
-// O9 selection and fit, A13 downward extension, O10 merge), C1-C5 for the track-model compression that
+// O9 selection and fit, A13 downward extension, O10 merge, A21 central-membrane merge,
+// A25 pairing of a looper's two legs), C1-C5 for the track-model compression that
 // consumes the tracks, E1-E5 for the rANS entropy coder after it, and F1-F6 for the
 // cluster finding before the tracking (section 5).
 //
@@ -34,7 +35,9 @@
 // brute-force triple search; chain/ownership invariants; zero-smear fits
 // recovering the truth; the downward extension (A13) recovering every lower cluster of
 // tracks whose chains cannot start below a row, its miss limit, and the rule for
-// clusters found by two tracks.  The hit-picking heuristic of the tracklet following
+// clusters found by two tracks; the two legs of exact loopers paired with each other and with
+// nothing across events or with one curvature flipped, and on a full event every pair joining
+// both legs of one particle.  The hit-picking heuristic of the tracklet following
 // (O7 window search), of the extension's window search (A13) and the merge pairing
 // (O10) are pinned only by invariants and special cases: parity unpinned beyond those.  Compression: the prediction
 // against an FP64 closed-form circle in the rotated frame, zero residual codes for
@@ -1420,6 +1423,90 @@ int32_t orc_fit_hits_f32(void* h, int32_t nh, const int32_t* hits, const float* 
   for (int i = 0; i < nh; ++i) hs[i] = o->sector[hits[i]];
   int32_t ndf;
   return o->fit<float>(v, stk, hs.back(), hs, P, C, *x, *chi2, ndf);
+}
+
+// ---------------------------------------------------------------- A25: looper leg pairs
+// A looper's two legs are tracked separately, each along increasing x (the return leg against
+// its momentum), so they describe the same circle with opposite signed curvature and opposite
+// tan(lambda), and both run towards the circle's point farthest from the beam line, where the
+// looper turned.  Reading: among fitted output tracks of one event and one z side whose
+// circles turn inside the chamber (2R < 245 cm / cos 10 deg), A and B pair when their
+// curvatures and tan(lambda) have opposite signs, their circle centres (global x, y) agree
+// within LEG_GATE in each coordinate, and so do their z extrapolated along the helix to that
+// turning point; the score is the sum of the three squared differences, pairs are mutual
+// best ones (ties: smaller output index).  Which leg left the vertex is not decided.
+// Geometry in FP32, in this order: C = cb k; c = sqrt((1 - s)(1 + s)); local centre
+// (x - s/C, y + c/C); global by the sector angle (x ca - y sa, x sa + y ca); R = 1/|C|; the
+// turning point centre + R centre/|centre|; the chord from the track's point to it; the arc
+// chord A(u), u = min(1, chord |C| / 2) with the FP32 asin(u)/u of R5; z + t arc.
+constexpr float kLegGate = 3.0f;
+struct LegGeo {
+  bool looper;
+  float cx, cy, zt, C, t;
+};
+LegGeo leg_geometry(const Params& p, const float* P, float x, int sector) {
+  LegGeo L{};
+  const float C = curvature_factor<float>(p) * P[4];
+  const float cmin = (float)(2.0 / (245.0 / std::cos(10.0 * 3.14159265358979323846 / 180.0)));
+  L.looper = std::fabs(C) > cmin;
+  if (!L.looper) return L;
+  const double al = (10.0 + 20.0 * (double)(sector % kRowsPerSide)) * 3.14159265358979323846 / 180.0;
+  const float ca = (float)std::cos(al), sa = (float)std::sin(al);
+  const float s = P[2];
+  const float c = std::sqrt((1.0f - s) * (1.0f + s));
+  const float lx = x - s / C, ly = P[0] + c / C;
+  L.cx = lx * ca - ly * sa;
+  L.cy = lx * sa + ly * ca;
+  const float R = 1.0f / std::fabs(C);
+  const float cn = std::sqrt(L.cx * L.cx + L.cy * L.cy);
+  const float tx = L.cx + R * (L.cx / cn), ty = L.cy + R * (L.cy / cn);
+  const float px = x * ca - P[0] * sa, py = x * sa + P[0] * ca;
+  const float dx = tx - px, dy = ty - py;
+  const float chord = std::sqrt(dx * dx + dy * dy);
+  const float u = std::fmin(1.0f, chord * std::fabs(C) * 0.5f);
+  float A, B;
+  asinc(u, A, B);
+  L.zt = P[1] + P[3] * (chord * A);
+  L.C = C;
+  L.t = P[3];
+  return L;
+}
+
+// leg[i] = the output index of track i's other leg, or -1.
+void orc_pair_legs(const Params* p, int32_t K, const float* param, const float* x_ref, const int32_t* sector,
+                   const int32_t* event, const int32_t* ndf, int32_t* leg) {
+  std::vector<LegGeo> G(K);
+  for (int i = 0; i < K; ++i) {
+    G[i] = LegGeo{};
+    if (ndf[i] >= 0) G[i] = leg_geometry(*p, param + 5 * i, x_ref[i], sector[i]);
+  }
+  // candidates by (event, side, 4-cm cell of the centre)
+  std::unordered_map<int64_t, std::vector<int32_t>> cells;
+  auto key = [&](int i, int dx, int dy) {
+    const int64_t ix = (int64_t)std::floor(G[i].cx / 4.0f) + dx, iy = (int64_t)std::floor(G[i].cy / 4.0f) + dy;
+    return (((int64_t)event[i] * 2 + (sector[i] >= kRowsPerSide)) * 4096 + (ix & 4095)) * 4096 + (iy & 4095);
+  };
+  for (int i = 0; i < K; ++i)
+    if (G[i].looper) cells[key(i, 0, 0)].push_back(i);
+  std::vector<float> best(K, 0.f);
+  std::vector<int32_t> arg(K, -1);
+  for (int a = 0; a < K; ++a) {
+    if (!G[a].looper) continue;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        const auto it = cells.find(key(a, dx, dy));
+        if (it == cells.end()) continue;
+        for (const int b : it->second) {
+          if (b == a || event[b] != event[a] || (sector[b] >= kRowsPerSide) != (sector[a] >= kRowsPerSide)) continue;
+          if (!(G[a].C * G[b].C < 0.f) || !(G[a].t * G[b].t <= 0.f)) continue;
+          const float ex = G[a].cx - G[b].cx, ey = G[a].cy - G[b].cy, ez = G[a].zt - G[b].zt;
+          if (!(std::fabs(ex) <= kLegGate) || !(std::fabs(ey) <= kLegGate) || !(std::fabs(ez) <= kLegGate)) continue;
+          const float sc = (ex * ex + ey * ey) + ez * ez;
+          if (arg[a] < 0 || sc < best[a] || (sc == best[a] && b < arg[a])) { best[a] = sc; arg[a] = b; }
+        }
+      }
+  }
+  for (int i = 0; i < K; ++i) leg[i] = (arg[i] >= 0 && arg[arg[i]] == i) ? arg[i] : -1;
 }
 
 // C2-C4: encode n clusters against K tracks.  Writes H + U records (H = off[K] track

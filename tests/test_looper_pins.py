@@ -8,7 +8,10 @@ leg's clusters there form one track of their own (separate from the outgoing leg
 FP64 fit is the reversed exact state at the innermost hit (the generator's closed form on
 the second half turn).  On a full event with return legs: both legs of most loopers are
 found, every pure return-leg track of 20 hits or more has a q/pT of the opposite sign of its
-particle's charge, and few tracks mix the legs (near the turning point).
+particle's charge, and few tracks mix the legs (near the turning point).  The pairing of the
+two legs (same circle centre, opposite curvature and tan(lambda), the same z at the turning
+point): the legs of exact loopers pair with each other and with nothing across events or
+with a flipped curvature; on a full event every pair joins the two legs of one particle.
 """
 import math
 
@@ -95,3 +98,48 @@ def test_full_event_with_return_legs():
     assert len(found_ret) >= 0.75 * len(has_ret)
     assert n_ret > 300 and sign_ok == n_ret
     assert mixed <= 0.03 * len(t["ndf"])
+
+
+@pytest.mark.parametrize("pt,eta,phi,q", LOOPERS)
+def test_the_two_legs_of_an_exact_looper_pair(pt, eta, phi, q):
+    """Exact looper, sector merge on: one track per leg, and the pairing joins them."""
+    ev = _looper(pt, eta, phi, q)
+    t = O.Run(ev["sector"], ev["row"], ev["y"], ev["z"], ev["job_off"], O.params()).tracks()
+    kinds = [int(ev["leg"][t["hits"][t["off"][i]]]) for i in range(len(t["ndf"]))]
+    assert sorted(kinds) == [0, 1]
+    leg = O.pair_legs(t, np.zeros(len(kinds), np.int32))
+    assert leg.tolist() == [1, 0]
+    # no pair across events, nor with the curvature of one leg flipped
+    assert O.pair_legs(t, np.array([0, 1], np.int32)).tolist() == [-1, -1]
+    t2 = dict(t)
+    t2["P"] = t["P"].copy()
+    t2["P"][1, 4] = -t2["P"][1, 4]
+    assert O.pair_legs(t2, np.zeros(2, np.int32)).tolist() == [-1, -1]
+
+
+def test_legs_pair_within_their_particle_on_a_full_event():
+    """Full event with return legs: nearly every return-leg track is paired, every pair joins
+    the two legs of one particle, and only looper curvatures pair."""
+    cs = g.gen_event(21, 3000, loopers=True)
+    leg = cs.meta["leg"]
+    t = O.Run.from_set(cs).tracks()
+    pairs = O.pair_legs(t, np.zeros(len(t["ndf"]), np.int32))
+    assert np.all(pairs[pairs[pairs >= 0]] == np.flatnonzero(pairs >= 0))   # mutual
+    n_ret, good, n_pairs = 0, 0, 0
+    cmin = 2.0 / (245.0 / math.cos(math.radians(10.0)))
+    for i in range(len(t["ndf"])):
+        h = t["hits"][t["off"][i]:t["off"][i + 1]]
+        lab = cs.label[h]
+        maj = np.bincount(lab[lab >= 0]).argmax()
+        lg = np.bincount(leg[h][leg[h] >= 0]).argmax()
+        n_ret += int(lg == 1 and (lab == maj).mean() >= 0.9)
+        j = pairs[i]
+        if j < 0 or j < i:
+            continue
+        n_pairs += 1
+        assert abs(0.299792458e-2 * 0.5 * t["P"][i][4]) > cmin
+        hj = t["hits"][t["off"][j]:t["off"][j + 1]]
+        mj = np.bincount(cs.label[hj][cs.label[hj] >= 0]).argmax()
+        lj = np.bincount(leg[hj][leg[hj] >= 0]).argmax()
+        good += int(maj == mj and lg != lj)
+    assert n_pairs >= 0.9 * n_ret and good == n_pairs, (n_pairs, n_ret, good)
