@@ -449,13 +449,30 @@ def looper_run(cs, args, tuning, time_run, log, dev):
     lg = leg[t["hits"]].astype(np.int64)
     n1 = np.bincount(tid, weights=(lg == 1), minlength=len(nh))
     n0 = np.bincount(tid, weights=(lg == 0), minlength=len(nh))
+    # the pairing of the two legs: time per call (HIP events on the library's stream) and how
+    # many pairs join both legs of one particle
+    tr.profile(True)
+    tr.profile_read(reset=True)
+    for _ in range(max(args.steps, 1)):
+        legs = tr.tpc_pair_legs()
+    prof = tr.profile_read(reset=True)
+    tr.profile(False)
+    legs = legs[:t["n"]].cpu().numpy()
+    maj = _majority(cs, t)[0]
+    kind = np.where(n1 > n0, 1, 0)
+    i = np.flatnonzero(legs > np.arange(len(legs)))
+    j = legs[i]
+    pairs = len(i)
+    right = int(((maj[i] == maj[j]) & (maj[i] >= 0) & (kind[i] != kind[j])).sum())
     out = {"workload": f"c2: {WORKLOADS['c2']}, with the return legs of its loopers",
            "n_clusters": cs.n, "return_leg_clusters": int((leg == 1).sum()),
            "ms_per_step": ms, "clusters_per_s": cs.n / (ms / 1e3), "tracks": int(t["n"]),
            "return_leg_tracks": int(((n1 > 0) & (n0 == 0)).sum()),
            "tracks_mixing_legs": int(((n1 > 0) & (n0 > 0)).sum()),
            "attached_outgoing_leg_clusters": float(att[leg == 0].mean()),
-           "attached_return_leg_clusters": float(att[leg == 1].mean())}
+           "attached_return_leg_clusters": float(att[leg == 1].mean()),
+           "leg_pairs": pairs, "leg_pairs_of_one_particle": right,
+           "pair_legs_ms": prof["pair_legs"][0] / max(prof["pair_legs"][1], 1)}
     log("return legs: " + json.dumps(out))
     del tr
     return out

@@ -235,8 +235,8 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 /* Per-kernel timing with HIP events recorded on the context's stream around the
  * launches of: the neighbour kernel (index 0), the tracklet kernel (1), the grid
  * build (2), the selection (3), fit + merge (4), tpc_compress (5),
- * tpc_decompress (6), tpc_rans_encode (7), tpc_rans_decode (8) and
- * tpc_find_clusters (9).  While
+ * tpc_decompress (6), tpc_rans_encode (7), tpc_rans_decode (8),
+ * tpc_find_clusters (9) and tpc_pair_legs (10).  While
  * enabled, tpc_run does
  * not use a graph.  tpc_profile_read waits for the stream and returns the summed
  * milliseconds and the number of timed launches per index since the last reset. */
@@ -250,7 +250,8 @@ int tpc_run(tpc_ctx* ctx, const tpc_clusters* c, const tpc_jobs* j, tpc_tracks* 
 #define TPC_PROF_RANS_ENCODE 7
 #define TPC_PROF_RANS_DECODE 8
 #define TPC_PROF_CLUSTERS 9   /* tpc_find_clusters (all its kernels) */
-#define TPC_PROF_KERNELS 10
+#define TPC_PROF_LEGS 10      /* tpc_pair_legs (all its kernels)     */
+#define TPC_PROF_KERNELS 11
 int tpc_profile(tpc_ctx* ctx, int enable);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
 
@@ -306,6 +307,31 @@ int tpc_compress(tpc_ctx* ctx, const tpc_clusters* c, const tpc_tracks* t, float
  * belong to these tracks) to NaN coordinates and TPC_E_RANGE at tpc_sync.    */
 int tpc_decompress(tpc_ctx* ctx, const tpc_tracks* t, const tpc_codes* in, float q_y, float q_z,
                    uint8_t* sector, int16_t* row, float* y, float* z);
+
+/* Looper legs (section 5: every collision is reconstructed in full).  A particle
+ * whose circle turns back inside the chamber (2R < 245 cm / cos 10 deg, pT below
+ * about 0.19 GeV at 0.5 T) crosses the pad rows twice and leaves two tracks, the
+ * return leg followed against the particle's momentum: the same circle with the
+ * signs of sin(phi), tan(lambda) and q/pT flipped.  leg[i] ([t->cap_tracks],
+ * device) receives the output index of track i's other leg, or -1; entries from
+ * min(*n_tracks, cap_tracks) on are -1.  Two fitted tracks (ndf >= 0) of one
+ * event (job_event[job], or the job when job_event is NULL) and one z side pair
+ * when their circles turn inside the chamber, their signed curvatures and
+ * tan(lambda) have opposite signs, and their circle centres (global x, y) and z
+ * carried along the helix to the circle's point farthest from the beam line
+ * agree within 3 cm each; the score is the sum of the three squared differences
+ * and pairs are mutual best ones (ties: the smaller index).  Which leg left the
+ * vertex is not decided.  Reads n_tracks, param, x_ref, sector, ndf and job of
+ * `t` (as written by tpc_fit_merge; no tracking run is needed on this context,
+ * whose field sets the curvature).  ws: device memory of at least
+ * tpc_pair_legs_workspace_size(t->cap_tracks) bytes, 256-byte aligned, owned by
+ * the caller and free again when the stream has passed the call.  TPC_E_ARG for
+ * a null or negative argument, a missing, small or unaligned workspace, or more
+ * than 2^28 track slots (the size function returns 0 then).  Runs on the
+ * context's stream.                                                            */
+size_t tpc_pair_legs_workspace_size(int32_t cap_tracks);
+int tpc_pair_legs(tpc_ctx* ctx, const tpc_tracks* t, const int32_t* job_event, void* ws, size_t ws_bytes,
+                  int32_t* leg);
 
 /* rANS entropy coding (section 5: every detector's data, the TPC's after the
  * track-model compression, goes through a common rANS coder; Tables 1 and 2

@@ -1457,6 +1457,10 @@ LegGeo leg_geometry(const Params& p, const float* P, float x, int sector) {
   const float lx = x - s / C, ly = P[0] + c / C;
   L.cx = lx * ca - ly * sa;
   L.cy = lx * sa + ly * ca;
+  if (!std::isfinite(L.cx) || !std::isfinite(L.cy)) {  // no circle: not a looper
+    L.looper = false;
+    return L;
+  }
   const float R = 1.0f / std::fabs(C);
   const float cn = std::sqrt(L.cx * L.cx + L.cy * L.cy);
   const float tx = L.cx + R * (L.cx / cn), ty = L.cy + R * (L.cy / cn);

@@ -3913,6 +3913,146 @@ int tpc_get_selected(tpc_ctx* c, int32_t* tr, int32_t* off, int32_t* hits) {
 }
 
 namespace {
+// ---------------------------------------------------------------- looper leg pairs
+// A particle whose circle turns back inside the chamber leaves two tracks: the outgoing
+// leg and the return leg, which the tracking follows along increasing x like every track,
+// i.e. against the particle's momentum.  Both describe one circle, with opposite signed
+// curvature and opposite tan(lambda), and both end at the circle's point farthest from the
+// beam line, where the particle turned.  Two fitted tracks of one event and one z side whose
+// circles turn inside the chamber (2R < 245 cm / cos 10 deg) pair when those signs are
+// opposite and their circle centres (global x, y) and their z carried along the helix to
+// the turning point agree within kLegGate each; the score is the sum of the three squared
+// differences and pairs are mutual best ones (ties: the smaller output index).
+//
+// One thread per track.  Loopers go into a hash table of 4-cm cells of the circle centre
+// keyed by (event, side, cell), each cell holding a list of its tracks; each looper scans
+// the 3 x 3 cells around its own centre.  The order in which the lists were built does not
+// matter: the best partner is the smallest (score, index).
+constexpr float kLegGate = 3.0f;
+constexpr float kLegCell = 4.0f;   // > kLegGate: the 3 x 3 cells hold every candidate
+constexpr int kLegSectorsPerSide = 18;
+constexpr unsigned long long kLegEmpty = ~0ull;
+
+struct LegConsts {
+  float ca[kLegSectorsPerSide], sa[kLegSectorsPerSide];  // sector angle 10 + 20 s degrees
+  float cmin;                                            // |C| of a circle with 2R = 245 / cos 10
+  float cb;                                              // curvature per unit q/pT
+};
+struct LegWork {
+  float4* geo;              // [cap] circle centre x, y, z at the turning point, signed curvature
+  float* tl;                // [cap] tan(lambda)
+  unsigned long long* grp;  // [cap] (event, side) of a looper, kLegEmpty otherwise
+  int32_t* next;            // [cap] next track of the same cell
+  int32_t* arg;             // [cap] best partner or -1
+  unsigned long long* key;  // [hmask + 1] cell keys, kLegEmpty when free
+  int32_t* head;            // [hmask + 1] first track of the cell
+  uint32_t hmask;
+};
+
+__device__ __forceinline__ uint32_t leg_hash(unsigned long long k) {
+  // the 64-bit finaliser of MurmurHash3
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+__device__ __forceinline__ unsigned long long leg_cell(unsigned long long grp, int ix, int iy) {
+  return (grp * 4096ull + (unsigned long long)(ix & 4095)) * 4096ull + (unsigned long long)(iy & 4095);
+}
+
+__global__ void k_leg_geometry(CmpTracks T, const int32_t* job, const int32_t* job_event, LegWork W, LegConsts LC) {
+  const int n = min(*T.n_tracks, T.cap_tracks);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < T.cap_tracks; i += gridDim.x * blockDim.x) {
+    W.grp[i] = kLegEmpty;
+    W.arg[i] = -1;
+    if (i >= n || T.ndf[i] < 0) continue;
+    const float* P = T.param + 5 * (int64_t)i;
+    const float C = P[4] * LC.cb;
+    if (!(fabsf(C) > LC.cmin)) continue;
+    const int sec = T.sector[i];
+    const float ca = LC.ca[sec % kLegSectorsPerSide], sa = LC.sa[sec % kLegSectorsPerSide];
+    const float x = T.x_ref[i], s = P[2];
+    const float c = sqrt_rn((1.0f - s) * (1.0f + s));
+    const float lx = x - div_rn(s, C), ly = P[0] + div_rn(c, C);
+    const float cx = lx * ca - ly * sa, cy = lx * sa + ly * ca;
+    if (!isfinite(cx) || !isfinite(cy)) continue;
+    // the turning point: the centre moved by R away from the beam line
+    const float R = div_rn(1.0f, fabsf(C));
+    const float cn = sqrt_rn(cx * cx + cy * cy);
+    const float tx = cx + R * div_rn(cx, cn), ty = cy + R * div_rn(cy, cn);
+    const float px = x * ca - P[0] * sa, py = x * sa + P[0] * ca;
+    const float dx = tx - px, dy = ty - py;
+    const float chord = sqrt_rn(dx * dx + dy * dy);
+    const float u = fminf(1.0f, chord * fabsf(C) * 0.5f);
+    float A, B;
+    asinc(u, A, B);
+    W.geo[i] = make_float4(cx, cy, P[1] + P[3] * (chord * A), C);
+    W.tl[i] = P[3];
+    const int ev = job_event ? job_event[job[i]] : job[i];
+    const unsigned long long g = (unsigned long long)(uint32_t)ev * 2ull + (sec >= kLegSectorsPerSide ? 1ull : 0ull);
+    W.grp[i] = g;
+    const unsigned long long k = leg_cell(g, (int)floorf(cx / kLegCell), (int)floorf(cy / kLegCell));
+    // at most cap distinct keys in a table of >= 2 cap slots: a free or equal slot exists
+    uint32_t h = leg_hash(k) & W.hmask;
+    for (;;) {
+      const unsigned long long prev = atomicCAS(&W.key[h], kLegEmpty, k);
+      if (prev == kLegEmpty || prev == k) break;
+      h = (h + 1) & W.hmask;
+    }
+    W.next[i] = atomicExch(&W.head[h], i);
+  }
+}
+
+__global__ void k_leg_best(CmpTracks T, LegWork W) {
+  const int n = min(*T.n_tracks, T.cap_tracks);
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+    const unsigned long long g = W.grp[a];
+    if (g == kLegEmpty) continue;
+    const float4 ga = W.geo[a];
+    const float ta = W.tl[a];
+    const int ix = (int)floorf(ga.x / kLegCell), iy = (int)floorf(ga.y / kLegCell);
+    float best = 0.f;
+    int arg = -1;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        const unsigned long long k = leg_cell(g, ix + dx, iy + dy);
+        uint32_t h = leg_hash(k) & W.hmask;
+        unsigned long long kh;
+        while ((kh = W.key[h]) != kLegEmpty && kh != k) h = (h + 1) & W.hmask;
+        if (kh == kLegEmpty) continue;
+        for (int b = W.head[h]; b >= 0; b = W.next[b]) {
+          if (b == a || W.grp[b] != g) continue;
+          const float4 gb = W.geo[b];
+          if (!(ga.w * gb.w < 0.f) || !(ta * W.tl[b] <= 0.f)) continue;
+          const float ex = ga.x - gb.x, ey = ga.y - gb.y, ez = ga.z - gb.z;
+          if (!(fabsf(ex) <= kLegGate) || !(fabsf(ey) <= kLegGate) || !(fabsf(ez) <= kLegGate)) continue;
+          const float sc = (ex * ex + ey * ey) + ez * ez;
+          if (arg < 0 || sc < best || (sc == best && b < arg)) {
+            best = sc;
+            arg = b;
+          }
+        }
+      }
+    W.arg[a] = arg;
+  }
+}
+
+__global__ void k_leg_mutual(CmpTracks T, LegWork W, int32_t* leg) {
+  const int n = min(*T.n_tracks, T.cap_tracks);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < T.cap_tracks; i += gridDim.x * blockDim.x) {
+    const int b = i < n ? W.arg[i] : -1;
+    leg[i] = (b >= 0 && W.arg[b] == i) ? b : -1;
+  }
+}
+
+size_t leg_align(size_t b) { return (b + 255) & ~(size_t)255; }
+uint32_t leg_slots(int32_t cap) {
+  uint32_t h = 256;
+  while (h < 2u * (uint32_t)cap) h <<= 1;
+  return h;
+}
 bool cmp_tracks_ok(const tpc_tracks* t) {
   return t && t->cap_tracks >= 0 && t->cap_hits >= 0 && t->n_tracks && t->hit_off &&
          (t->cap_hits == 0 || t->hits) &&
@@ -3984,6 +4124,60 @@ int tpc_decompress(tpc_ctx* c, const tpc_tracks* t, const tpc_codes* in, float q
   if (in->cap > 0)
     hipLaunchKernelGGL(k_dcmp_free, dim3(blocks_for(in->cap, 256)), dim3(256), 0, c->stream, C, D, c->k, q_y, q_z,
                        c->L.counters);
+  prof_end(c, pm);
+  HIPCHK(c, hipGetLastError());
+  return TPC_OK;
+}
+
+size_t tpc_pair_legs_workspace_size(int32_t cap_tracks) {
+  if (cap_tracks < 0 || cap_tracks > (1 << 28)) return 0;
+  const size_t k = (size_t)std::max(cap_tracks, 1), h = leg_slots(cap_tracks);
+  return leg_align(k * sizeof(float4)) + leg_align(k * sizeof(float)) + leg_align(k * sizeof(unsigned long long)) +
+         2 * leg_align(k * sizeof(int32_t)) + leg_align(h * sizeof(unsigned long long)) + leg_align(h * sizeof(int32_t));
+}
+
+int tpc_pair_legs(tpc_ctx* c, const tpc_tracks* t, const int32_t* job_event, void* ws, size_t ws_bytes, int32_t* leg) {
+  if (!c) return TPC_E_ARG;
+  if (!cmp_tracks_ok(t) || (t->cap_tracks > 0 && (!t->job || !leg)))
+    return fail(c, TPC_E_ARG, "tpc_pair_legs: null or negative argument");
+  const size_t need = tpc_pair_legs_workspace_size(t->cap_tracks);
+  if (need == 0) return fail(c, TPC_E_ARG, "tpc_pair_legs: more than 2^28 tracks");
+  if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(c, TPC_E_ARG, "tpc_pair_legs: workspace missing, unaligned or smaller than tpc_pair_legs_workspace_size");
+  if (t->cap_tracks == 0) return TPC_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t k = (size_t)t->cap_tracks, h = leg_slots(t->cap_tracks);
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += leg_align(bytes);
+    return q;
+  };
+  LegWork W;
+  W.geo = reinterpret_cast<float4*>(take(k * sizeof(float4)));
+  W.tl = reinterpret_cast<float*>(take(k * sizeof(float)));
+  W.grp = reinterpret_cast<unsigned long long*>(take(k * sizeof(unsigned long long)));
+  W.next = reinterpret_cast<int32_t*>(take(k * sizeof(int32_t)));
+  W.arg = reinterpret_cast<int32_t*>(take(k * sizeof(int32_t)));
+  W.key = reinterpret_cast<unsigned long long*>(take(h * sizeof(unsigned long long)));
+  W.head = reinterpret_cast<int32_t*>(take(h * sizeof(int32_t)));
+  W.hmask = (uint32_t)h - 1;
+  LegConsts LC;
+  for (int s = 0; s < kLegSectorsPerSide; ++s) {
+    const double al = (10.0 + 20.0 * s) * 3.14159265358979323846 / 180.0;
+    LC.ca[s] = (float)std::cos(al);
+    LC.sa[s] = (float)std::sin(al);
+  }
+  LC.cmin = (float)(2.0 / (245.0 / std::cos(10.0 * 3.14159265358979323846 / 180.0)));
+  LC.cb = c->k.cb;
+  const CmpTracks T = tracks_view(t);
+  const int pm = prof_begin(c, TPC_PROF_LEGS);
+  fill_i32(c, reinterpret_cast<int32_t*>(W.key), 2 * (int64_t)h, -1);
+  fill_i32(c, W.head, (int64_t)h, -1);
+  const int nb = std::min(blocks_for(t->cap_tracks, 256), 65536);
+  hipLaunchKernelGGL(k_leg_geometry, dim3(nb), dim3(256), 0, c->stream, T, t->job, job_event, W, LC);
+  hipLaunchKernelGGL(k_leg_best, dim3(nb), dim3(256), 0, c->stream, T, W);
+  hipLaunchKernelGGL(k_leg_mutual, dim3(nb), dim3(256), 0, c->stream, T, W, leg);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
   return TPC_OK;

@@ -145,6 +145,9 @@ def lib():
         L.tpc_cf_workspace_size.argtypes = [P(tpc_cf_params), C.c_int32]
         L.tpc_cf_workspace_size.restype = C.c_size_t
         L.tpc_find_clusters.argtypes = [V, P(tpc_cf_params), P(tpc_digits), V, C.c_size_t, P(tpc_cf_clusters)]
+        L.tpc_pair_legs_workspace_size.argtypes = [C.c_int32]
+        L.tpc_pair_legs_workspace_size.restype = C.c_size_t
+        L.tpc_pair_legs.argtypes = [V, P(tpc_tracks), V, V, C.c_size_t, V]
         L.tpc_rans_lanes.argtypes = [C.c_int64]
         L.tpc_rans_lanes.restype = C.c_int64
         L.tpc_rans_encode.argtypes = [V, V, C.c_int32, P(tpc_rans)]
@@ -163,9 +166,9 @@ EXPORTED = ["tpc_params_default", "tpc_params_preset", "tpc_tuning_default", "tp
             "tpc_profile", "tpc_profile_read", "tpc_copy_probe", "tpc_compress", "tpc_decompress",
             "tpc_rans_lanes", "tpc_rans_encode", "tpc_rans_decode", "tpc_rans_encode_static",
             "tpc_cf_params_default",
-            "tpc_cf_workspace_size", "tpc_find_clusters"]
+            "tpc_cf_workspace_size", "tpc_find_clusters", "tpc_pair_legs_workspace_size", "tpc_pair_legs"]
 PROF_NAMES = ["k_links", "k_tracklets", "grid_build", "select", "fit_merge", "compress", "decompress",
-              "rans_encode", "rans_decode", "find_clusters"]
+              "rans_encode", "rans_decode", "find_clusters", "pair_legs"]
 
 
 def default_params(**over) -> tpc_params:
@@ -394,6 +397,26 @@ class Tracker:
                                          *[_ptr(out[k]) for k in ("sector", "row", "y", "z")]),
                     "tpc_decompress")
         return out
+
+    # ---- the two legs of loopers among the current tracks
+    def tpc_pair_legs(self, job_event=None):
+        """Enqueues tpc_pair_legs on the current tracks (job_event: device int32 [n_jobs] or
+        None); returns the device int32 tensor leg [cap_tracks], kept until the next call:
+        the index of each track's other leg, or -1."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        cap = self.out["cap_tracks"]
+        need = int(lib().tpc_pair_legs_workspace_size(cap))
+        if need == 0:
+            raise TpcError(TPC_E_ARG, "tpc_pair_legs_workspace_size: too many track slots")
+        if getattr(self, "leg_ws", None) is None or self.leg_ws.numel() < need:
+            self.leg_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        if getattr(self, "legs", None) is None or self.legs.numel() != max(cap, 1):
+            self.legs = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        ev = None if job_event is None else _ptr(job_event)
+        self._check(lib().tpc_pair_legs(self.ctx, C.byref(self._tracks), ev, _ptr(self.leg_ws), need,
+                                        _ptr(self.legs)), "tpc_pair_legs")
+        return self.legs
 
     # ---- rANS entropy coding of a device stream of 16-bit symbols
     def tpc_rans_encode(self, sym, cap_words: int | None = None) -> dict:

@@ -12,7 +12,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_run(cs, mode="batched", tuning=None, params=None, job_event=None, stages=True):
+def gpu_run(cs, mode="batched", tuning=None, params=None, job_event=None, stages=True, legs=False):
     import torch
 
     from paper_2402_01205_amd.tpc import DeviceClusters, Tracker
@@ -26,12 +26,16 @@ def gpu_run(cs, mode="batched", tuning=None, params=None, job_event=None, stages
     tr.tpc_construct_tracklets()
     tr.tpc_select_tracks()
     tr.tpc_fit_merge()
+    if legs:
+        tr.tpc_pair_legs(ev.job_event)
     status = None
     try:
         tr.sync()
     except Exception as e:  # range errors are reported at sync; outputs stay valid
         status = getattr(e, "code", None)
     res = dict(status=status, tracks=tr.tracks_nosync() if status else tr.tracks())
+    if legs:
+        res["legs"] = tr.legs[:tr.out["cap_tracks"]].cpu().numpy()
     if stages:
         res.update(up=up.cpu().numpy()[:cs.n], down=dn.cpu().numpy()[:cs.n], raw=tr.links_raw(),
                    rows=tr.rows(), trk=tr.tracklets(), sel=tr.selected())

@@ -1,7 +1,8 @@
 """Loopers' return legs on the GPU (needs a gfx950 GPU): events and time frames whose
 primaries that turn back inside the chamber also leave their return legs, tracked bit for bit
 with the oracle through the C ABI (the default reading, the asynchronous and synchronous cut
-sets), and the exact loopers of the pins."""
+sets), and the exact loopers of the pins.  The pairing of the two legs (tpc_pair_legs) equals
+the oracle's on the oracle's tracks, which the GPU's equal bit for bit."""
 import numpy as np
 import pytest
 
@@ -37,3 +38,70 @@ def test_return_legs_bit_exact(cfg, preset):
     o = oracle_run(cs, O.params(**prm))
     s = compare_all(gpu_run(cs, params=preset_params(preset) if preset else None), o)
     say(cfg, preset, "tracks", s["n_tracks"], "merged", s["merged"])
+
+
+def _oracle_legs(o, job_event=None):
+    t = o["tracks"]
+    ev = t["job"] if job_event is None else np.asarray(job_event)[t["job"]]
+    return O.pair_legs(t, ev)
+
+
+def _compare_legs(gr, o, job_event=None):
+    K = len(o["tracks"]["ndf"])
+    want = _oracle_legs(o, job_event)
+    got = gr["legs"]
+    assert np.array_equal(got[:K], want), int((got[:K] != want).sum())
+    assert np.all(got[K:] == -1)
+    return int((want >= 0).sum()) // 2
+
+
+@pytest.mark.parametrize("pt,eta,phi,q", LOOPERS)
+def test_exact_looper_legs_pair(pt, eta, phi, q):
+    cs = _Set(_looper(pt, eta, phi, q))
+    gr = gpu_run(cs, stages=False, legs=True)
+    assert _compare_legs(gr, dict(tracks=O.Run.from_set(cs).tracks())) == 1
+
+
+@pytest.mark.parametrize("cfg,scale,preset", [("c2", 1.0, None), ("c3", 0.1, "sync"), ("c3", 0.1, "async")])
+def test_leg_pairs_equal_the_oracle(cfg, scale, preset):
+    """The full c2 event with return legs (1.08M clusters, the size the benchmark pairs) and a
+    collision pool with a 5-cm vertex spread (one job per collision)."""
+    from paper_2402_01205_amd.tpc import preset_params
+    cs = (g.make_config("c2", 21, scale=scale, loopers=True) if cfg == "c2" else
+          g.make_config("c3", 31, scale=scale, loopers=True, vz_sigma=5.0))
+    prm = {None: O.DEFAULTS, "async": O.ASYNC, "sync": O.SYNC}[preset]
+    o = dict(tracks=O.Run.from_set(cs, O.params(**prm)).tracks())
+    gr = gpu_run(cs, params=preset_params(preset) if preset else None, stages=False, legs=True)
+    for k in ("off", "hits", "ndf", "job", "sector"):
+        assert np.array_equal(gr["tracks"][k], o["tracks"][k]), k
+    n = _compare_legs(gr, o)
+    say(cfg, preset, "tracks", gr["tracks"]["n"], "leg pairs", n)
+    assert n > (300 if cfg == "c2" else 20)
+
+
+def test_leg_pairs_by_event_id_and_on_no_tracks():
+    """One event with return legs in two jobs: as separate events both copies pair their legs;
+    as one event (job_event) every leg of the second copy ties with its own partner and the
+    first copy's, the smaller index wins, so only the first copy keeps its pairs, as in the
+    oracle.  A run with no tracks leaves every slot at -1."""
+    import torch
+
+    from paper_2402_01205_amd.tpc import DeviceClusters, Tracker
+    ev = g.gen_event(5, 600, loopers=True)
+    cs = g.concat([ev, ev], {})
+    tr = Tracker(0)
+    tr.tpc_run(DeviceClusters.from_set(cs, "cuda:0"))
+    o = dict(tracks=O.Run.from_set(cs).tracks())
+    K = len(o["tracks"]["ndf"])
+    sep = tr.tpc_pair_legs().cpu().numpy()
+    assert np.array_equal(sep[:K], _oracle_legs(o)) and np.all(sep[K:] == -1)
+    je = np.zeros(2, np.int32)
+    one = tr.tpc_pair_legs(torch.from_numpy(je).to("cuda:0")).cpu().numpy()
+    assert np.array_equal(one[:K], _oracle_legs(o, je)) and np.all(one[K:] == -1)
+    n_sep, n_one = int((sep >= 0).sum()) // 2, int((one >= 0).sum()) // 2
+    say("leg pairs as two events", n_sep, "as one", n_one)
+    assert n_sep == 2 * n_one > 100
+    e = _Set(dict(sector=np.zeros(0, np.uint8), row=np.zeros(0, np.int16), y=np.zeros(0, np.float32),
+                  z=np.zeros(0, np.float32), job_off=np.array([0, 0], np.int32)))
+    gr = gpu_run(e, stages=False, legs=True)
+    assert gr["tracks"]["n"] == 0 and np.all(gr["legs"] == -1)
