@@ -105,3 +105,43 @@ def test_leg_pairs_by_event_id_and_on_no_tracks():
                   z=np.zeros(0, np.float32), job_off=np.array([0, 0], np.int32)))
     gr = gpu_run(e, stages=False, legs=True)
     assert gr["tracks"]["n"] == 0 and np.all(gr["legs"] == -1)
+
+
+def test_leg_pairs_within_the_track_capacity_and_argument_errors():
+    """Tracks past cap_tracks are not read (the pairs are those of the first cap_tracks tracks
+    alone, as the oracle finds them on those tracks); a missing, small or unaligned workspace
+    and a null output are argument errors that enqueue nothing."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2402_01205_amd.tpc import (TPC_E_ARG, DeviceClusters, Tracker, _ptr, lib,
+                                          tpc_tracks)
+    cs = g.make_config("c2", 21, scale=0.4, loopers=True)
+    tr = Tracker(0)
+    tr.tpc_run(DeviceClusters.from_set(cs, "cuda:0"))
+    full = tr.tracks()
+    K = full["n"]
+    o = tr.out
+    cap = K // 2
+    t = tpc_tracks(cap, o["cap_hits"], *[_ptr(o[k]) for k in (
+        "n_tracks", "hit_off", "hits", "param", "cov", "x_ref", "chi2", "ndf", "sector", "job", "tracklet", "t0")])
+    need = int(lib().tpc_pair_legs_workspace_size(cap))
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda:0")
+    leg = torch.full((cap + 8,), 7, dtype=torch.int32, device="cuda:0")
+    assert lib().tpc_pair_legs(tr.ctx, C.byref(t), None, _ptr(ws), need, _ptr(leg)) == 0
+    tr.sync()
+    got = leg.cpu().numpy()
+    ref = O.Run.from_set(cs).tracks()
+    assert len(ref["ndf"]) == K
+    part = {k: (v[:cap] if k in ("P", "x", "sector", "ndf", "job") else v) for k, v in ref.items()}
+    want = O.pair_legs(part, part["job"])
+    assert np.array_equal(got[:cap], want) and np.all(got[cap:] == 7)
+    assert (want >= 0).sum() > 20
+    base = ws.data_ptr()
+    for wptr, wbytes, out in ((None, need, leg), (base, need - 1, leg), (base + 4, need, leg), (base, need, None)):
+        rc = lib().tpc_pair_legs(tr.ctx, C.byref(t), None, None if wptr is None else C.c_void_p(wptr), wbytes,
+                                 None if out is None else _ptr(out))
+        assert rc == TPC_E_ARG
+    assert int(lib().tpc_pair_legs_workspace_size(-1)) == 0
+    assert np.array_equal(leg.cpu().numpy(), got)
