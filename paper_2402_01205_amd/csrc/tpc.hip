@@ -1928,7 +1928,8 @@ __global__ void k_out_count(FitView F, const int32_t* keep, int32_t* outn, Bound
 }
 
 // One wave per output track: the hit lists of its pieces copied with the lanes striding
-// over them (coalesced), the per-track fields written by lanes 0..23.
+// over them (coalesced), the per-track fields written by lanes 0..23 (the collision time by
+// k_out_t0).
 __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, FitView F, OutView O,
                                                    const int32_t* keep, const int32_t* oid, const int32_t* ooff,
                                                    Bound lo_b, Bound hi_b, int32_t* counters, Consts k) {
@@ -1976,29 +1977,45 @@ __global__ __launch_bounds__(256) void k_out_write(GridView G, TrackletView V, F
       O.sector[o] = (sl / kRows) % kSectors;
       O.job[o] = sl / (kSectors * kRows);
       O.tracklet[o] = t;
-    } else if (lane == 24 && O.t0) {
-      const int32_t sec = (G.gh[V.start[F.sel_from[kk]]].slot / kRows) % kSectors;
-      const float* row = F.row + (int64_t)kk * kFitStride;
-      // a chain across the central membrane: its innermost membrane link's time
-      bool memb = false;
-      float tm = 0.f;
-      if (walk) {
-        int32_t p = kk;
-        int ps = sec;
-        for (int n = 0; n < kHalf && F.chain_next[p] >= 0; ++n) {
-          const int32_t q = F.chain_next[p];
-          const int qs = (G.gh[V.start[F.sel_from[q]]].slot / kRows) % kSectors;
-          if ((ps < kHalf) != (qs < kHalf)) {
-            memb = true;
-            tm = F.link_t0[p];
-            break;
-          }
-          p = q;
-          ps = qs;
-        }
-      }
-      O.t0[o] = F.ndf[kk] < 0 ? __builtin_nanf("") : memb ? tm : collision_time(row, row[20], sec, k);
     }
+  }
+}
+
+// The collision time of each output track, one lane per track: the transport of the fitted
+// state to the beam line is the longest per-track computation of the output, and a wave per
+// track would run it on one lane.
+__global__ __launch_bounds__(256) void k_out_t0(GridView G, TrackletView V, FitView F, OutView O,
+                                                const int32_t* keep, const int32_t* oid, Bound lo_b, Bound hi_b,
+                                                Consts k) {
+  const int32_t lo = lo_b.get();
+  const int32_t hi = min(hi_b.get(), F.capK);
+  for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t kk = (int32_t)i;
+    if (!keep[kk]) continue;
+    const int32_t o = oid[kk];
+    if (o >= O.cap_tracks) continue;
+    const bool walk = F.chain_next && F.chain_prev[kk] < 0;
+    const int32_t sec = (G.gh[V.start[F.sel_from[kk]]].slot / kRows) % kSectors;
+    const float* row = F.row + (int64_t)kk * kFitStride;
+    // a chain across the central membrane: its innermost membrane link's time
+    bool memb = false;
+    float tm = 0.f;
+    if (walk) {
+      int32_t p = kk;
+      int ps = sec;
+      for (int n = 0; n < kHalf && F.chain_next[p] >= 0; ++n) {
+        const int32_t q = F.chain_next[p];
+        const int qs = (G.gh[V.start[F.sel_from[q]]].slot / kRows) % kSectors;
+        if ((ps < kHalf) != (qs < kHalf)) {
+          memb = true;
+          tm = F.link_t0[p];
+          break;
+        }
+        p = q;
+        ps = qs;
+      }
+    }
+    O.t0[o] = F.ndf[kk] < 0 ? __builtin_nanf("") : memb ? tm : collision_time(row, row[20], sec, k);
   }
 }
 
@@ -3687,6 +3704,9 @@ int tpc_fit_merge(tpc_ctx* c, tpc_tracks* out) {
             out->x_ref, out->chi2, out->ndf, out->sector, out->job, out->tracklet, out->t0};
   hipLaunchKernelGGL(k_out_write, dim3(wave_grid(c, kb)), dim3(256), 0, c->stream, make_grid(c), make_tv(c),
                      make_fv(c, true, true), O, L.keep, L.oid, L.ooff, klo, khi, L.counters, c->k);
+  if (O.t0)
+    hipLaunchKernelGGL(k_out_t0, dim3(std::min(blocks_for(kb, 256), 65536)), dim3(256), 0, c->stream, make_grid(c),
+                       make_tv(c), make_fv(c, true, true), O, L.keep, L.oid, klo, khi, c->k);
   hipLaunchKernelGGL(k_out_finish, dim3(1), dim3(1), 0, c->stream, L.oid, L.ooff, khi, L.capK, O, L.counters);
   prof_end(c, pm);
   HIPCHK(c, hipGetLastError());
