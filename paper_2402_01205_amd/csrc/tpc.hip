@@ -1322,8 +1322,15 @@ __device__ void fit_track(const GridView& G, const TrackletView& V, const FitVie
   for (int pi = pstart; pi >= 0 && ok; --pi) {
     const int32_t p = pieces[pi];
     const int32_t a = F.sel_off[p], b = F.sel_off[p + 1];
+    // the next hit's record is loaded while the current one is fitted, the index after it one
+    // step earlier still
+    int32_t hn = b - 2 >= a ? F.sel_hits[b - 2] : 0;
+    GHit Hn;
+    if (b - 1 >= a) Hn = ldh(G.gh + F.sel_hits[b - 1]);
     for (int32_t q = b - 1; q >= a; --q) {
-      const GHit Hq = ldh(G.gh + F.sel_hits[q]);
+      const GHit Hq = Hn;
+      if (q - 1 >= a) Hn = ldh(G.gh + hn);
+      if (q - 2 >= a) hn = F.sel_hits[q - 2];
       const int32_t sl = Hq.slot;
       const int sec = (sl / kRows) % kSectors;
       if (sec != cur_sec) {
