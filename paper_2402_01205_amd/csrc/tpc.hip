@@ -896,7 +896,10 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
   int row;
   float cy = 0.f, cz = 0.f;
   int32_t cand = -1;
+  int32_t up_next = -1;
   if (chain) {
+    // the chain's next link is read with the cluster, not after the update
+    up_next = V.up[T.cur];
     const GHit Hc = ldh(G.gh + T.cur);
     row = Hc.slot % kRows;
     cy = Hc.y;
@@ -929,7 +932,7 @@ __device__ __forceinline__ bool trk_step(const GridView& G, const TrackletView& 
     keep_state(T);
     if (chain) {
       T.last_row = row;
-      T.cur = (T.cur == T.first && T.first != T.h) ? T.h : V.up[T.cur];
+      T.cur = (T.cur == T.first && T.first != T.h) ? T.h : up_next;
       if (T.cur < 0) {
         T.phase = 2;
         T.r = T.last_row + 1;
