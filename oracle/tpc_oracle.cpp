@@ -37,7 +37,8 @@
 // tracks whose chains cannot start below a row, its miss limit, and the rule for
 // clusters found by two tracks; the two legs of exact loopers paired with each other and with
 // nothing across events or with one curvature flipped, and on a full event every pair joining
-// both legs of one particle.  The hit-picking heuristic of the tracklet following
+// both legs of one particle; the window searches over the z range of a row against scans of
+// the whole row.  The hit-picking heuristic of the tracklet following
 // (O7 window search), of the extension's window search (A13) and the merge pairing
 // (O10) are pinned only by invariants and special cases: parity unpinned beyond those.  Compression: the prediction
 // against an FP64 closed-form circle in the rotated frame, zero residual codes for

@@ -2,8 +2,9 @@
 
 Each test checks the oracle against something other than itself: the helix
 closed form, finite differences, the information-form Kalman identity, libm's
-asin, a brute-force neighbour search, invariants of the cellular automaton and
-of the ownership arbitration, and zero-smear special cases.
+asin, a brute-force neighbour search, whole-row scans in place of the window searches'
+z ranges, invariants of the cellular automaton and of the ownership arbitration, and
+zero-smear special cases.
 """
 import math
 
@@ -323,6 +324,34 @@ def test_neighbours_equal_brute_force(case):
         assert np.array_equal(L["up_raw"], ref_up)
         assert np.array_equal(L["down_raw"], ref_dn)
     assert (ref_up >= 0).mean() > 0.5
+
+
+@pytest.mark.parametrize("case,preset", [("c1", "default"), ("c2loopers", "default"), ("c2loopers", "sync"),
+                                         ("c2loopers", "async"), ("c4medium", "sync")])
+def test_window_searches_equal_whole_row_scans(case, preset):
+    """The following's and the extension's window searches visit only the clusters of the row
+    whose z lies in the window (a binary search in the z-sorted row); scanning every cluster
+    of the row instead (the plain definition: the minimum chi2 inside the window) gives the
+    same links, tracklets and tracks, merged and extended, bit for bit."""
+    if case == "c1":
+        cs = g.make_config("c1", 21)
+    elif case == "c2loopers":
+        cs = g.make_config("c2", 21, scale=0.05, loopers=True)
+    else:
+        sizes = g.c4_job_sizes(41)
+        cs = g.make_config("c4", 41, jobs=[int(np.argsort(sizes)[len(sizes) // 2])])
+    prm = O.params(**{"default": O.DEFAULTS, "sync": O.SYNC, "async": O.ASYNC}[preset])
+    a = O.Run.from_set(cs, prm)
+    b = O.Run.from_set(cs, prm, brute=True)
+    ta, tb = a.tracklets(), b.tracklets()
+    for k in ("start", "off", "hits", "hitw"):
+        assert np.array_equal(ta[k], tb[k]), k
+    ka, kb = a.tracks(), b.tracks()
+    for k in ("off", "hits", "tracklet", "P", "C", "x", "ndf", "n_ext", "t0"):
+        assert np.array_equal(ka[k], kb[k], equal_nan=True), k
+    assert len(ka["ndf"]) > 50
+    if preset == "sync":
+        assert int(ka["n_ext"].sum()) > 0
 
 
 # ------------------------------------------------------------------ CA invariants
