@@ -84,7 +84,7 @@ def lib():
         L.orc_status.argtypes = [P]
         L.orc_get_track_t0.argtypes = [P, C.c_int32, P, P]
         L.orc_get_track_ext.argtypes = [P, C.c_int32, P]
-        L.orc_pair_legs.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, P, P]
+        L.orc_pair_legs.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, P, P, P, C.c_int32]
         L.orc_pair_legs.restype = None
         L.orc_collision_time_f32.argtypes = [P, C.c_float, C.c_int32, C.POINTER(Params)]
         L.orc_collision_time_f32.restype = C.c_float
@@ -254,9 +254,10 @@ class Run:
         return bool(ok), P, Cv, float(x[0]), float(c2[0])
 
 
-def pair_legs(tracks, event, prm=None):
+def pair_legs(tracks, event, prm=None, brute=False):
     """A25: the output index of each track's other looper leg, or -1 (tracks as returned by
-    Run.tracks(); event: the event id of each track)."""
+    Run.tracks(); event: the event id of each track; brute: compare every pair of tracks
+    instead of the neighbouring centre cells)."""
     K = len(tracks["ndf"])
     leg = np.full(K, -1, np.int32)
     if K:
@@ -265,7 +266,8 @@ def pair_legs(tracks, event, prm=None):
         sec = np.ascontiguousarray(tracks["sector"], np.int32)
         ev = np.ascontiguousarray(event, np.int32)
         ndf = np.ascontiguousarray(tracks["ndf"], np.int32)
-        lib().orc_pair_legs(C.byref(prm or params()), K, _p(P), _p(x), _p(sec), _p(ev), _p(ndf), _p(leg))
+        lib().orc_pair_legs(C.byref(prm or params()), K, _p(P), _p(x), _p(sec), _p(ev), _p(ndf), _p(leg),
+                            int(brute))
     return leg
 
 

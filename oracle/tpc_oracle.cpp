@@ -1477,9 +1477,10 @@ LegGeo leg_geometry(const Params& p, const float* P, float x, int sector) {
   return L;
 }
 
-// leg[i] = the output index of track i's other leg, or -1.
+// leg[i] = the output index of track i's other leg, or -1.  brute: every pair of tracks is
+// compared instead of the tracks of the 3 x 3 centre cells (the same pairs result).
 void orc_pair_legs(const Params* p, int32_t K, const float* param, const float* x_ref, const int32_t* sector,
-                   const int32_t* event, const int32_t* ndf, int32_t* leg) {
+                   const int32_t* event, const int32_t* ndf, int32_t* leg, int32_t brute) {
   std::vector<LegGeo> G(K);
   for (int i = 0; i < K; ++i) {
     G[i] = LegGeo{};
@@ -1495,13 +1496,23 @@ void orc_pair_legs(const Params* p, int32_t K, const float* param, const float* 
     if (G[i].looper) cells[key(i, 0, 0)].push_back(i);
   std::vector<float> best(K, 0.f);
   std::vector<int32_t> arg(K, -1);
+  std::vector<int32_t> all;
+  if (brute)
+    for (int i = 0; i < K; ++i)
+      if (G[i].looper) all.push_back(i);
   for (int a = 0; a < K; ++a) {
     if (!G[a].looper) continue;
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy) {
-        const auto it = cells.find(key(a, dx, dy));
-        if (it == cells.end()) continue;
-        for (const int b : it->second) {
+        const std::vector<int32_t>* list = &all;
+        if (!brute) {
+          const auto it = cells.find(key(a, dx, dy));
+          if (it == cells.end()) continue;
+          list = &it->second;
+        } else if (dx != 0 || dy != 0) {
+          continue;
+        }
+        for (const int b : *list) {
           if (b == a || event[b] != event[a] || (sector[b] >= kRowsPerSide) != (sector[a] >= kRowsPerSide)) continue;
           if (!(G[a].C * G[b].C < 0.f) || !(G[a].t * G[b].t <= 0.f)) continue;
           const float ex = G[a].cx - G[b].cx, ey = G[a].cy - G[b].cy, ez = G[a].zt - G[b].zt;

@@ -125,6 +125,8 @@ def test_legs_pair_within_their_particle_on_a_full_event():
     t = O.Run.from_set(cs).tracks()
     pairs = O.pair_legs(t, np.zeros(len(t["ndf"]), np.int32))
     assert np.all(pairs[pairs[pairs >= 0]] == np.flatnonzero(pairs >= 0))   # mutual
+    # the centre cells only prune: every pair of tracks compared gives the same pairs
+    assert np.array_equal(pairs, O.pair_legs(t, np.zeros(len(t["ndf"]), np.int32), brute=True))
     n_ret, good, n_pairs = 0, 0, 0
     cmin = 2.0 / (245.0 / math.cos(math.radians(10.0)))
     for i in range(len(t["ndf"])):
