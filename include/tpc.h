@@ -58,7 +58,8 @@ extern "C" {
 typedef struct {
   float win_dy_slope, win_dy_const;  /* up-neighbour window in y: slope*dx + const, cm */
   float win_dz_slope, win_dz_const;  /* up-neighbour window in z, cm                   */
-  float link_cut;                    /* max second difference of a link triplet, cm    */
+  float link_cut;                    /* max second difference of a link triplet, cm;  */
+                                     /* > 0 with link_cut^2 a normal float             */
   float cy0, cz0, cs0, ct0, ck0;     /* tracklet Kalman priors (diagonal)              */
   float cy1, cz1, cs1, ct1, ck1;     /* refit Kalman priors (diagonal)                 */
   float sigma_y, sigma_z;            /* cluster errors, cm                             */

@@ -538,7 +538,9 @@ __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, flo
   const float y2 = yh + yh, z2 = zh + zh;
   const float m = 0.01f;
   int32_t bu = -1, bd = -1;
-  float best = 0.f;
+  // until a pair is found, best is the float just above the cut, so that "sc < best" alone
+  // admits exactly the pairs within the cut (sc <= cut2; cut2 is a normal float)
+  float best = k.cut2_above;
   for (int d = 1; d <= 2; ++d) {
     if (r - d < 0 || r + d >= kRows) break;
     const float dxu = k.x[r + d] - k.x[r];
@@ -612,9 +614,9 @@ __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, flo
                   const float rz = (zu + D[j].y) - z2;
                   const float sc = ry * ry + rz * rz;
                   // the best pair is kept with selects; only an exact tie takes a branch
-                  const bool ok = dd < B1[e] && sc <= k.cut2;
-                  bool win = ok && (bu < 0 || sc < best);
-                  if (ok && bu >= 0 && sc == best) {
+                  const bool in = dd < B1[e];
+                  bool win = in && sc < best;
+                  if (in && sc == best && bu >= 0) {
                     const int32_t uo = G.gh[u].idx, bo = G.gh[bu].idx;
                     win = uo < bo || (uo == bo && G.gh[dd].idx < G.gh[bd].idx);
                   }
@@ -3168,6 +3170,7 @@ void make_consts(const tpc_params& p, Consts& k) {
   k.vy = p.sigma_y * p.sigma_y;
   k.vz = p.sigma_z * p.sigma_z;
   k.cut2 = p.link_cut * p.link_cut;
+  k.cut2_above = std::nextafter(k.cut2, INFINITY);
   k.smax = p.smax;
   k.win_dy_slope = p.win_dy_slope;
   k.win_dy_const = p.win_dy_const;
@@ -3438,7 +3441,8 @@ static bool params_ok(const tpc_params& p) {
                      p.nwin, p.chi2_follow, p.smax, p.bz, p.merge_edge, p.chi2_merge, p.merge_dz, p.v_drift};
   for (float v : f)
     if (!std::isfinite(v)) return false;
-  return p.sigma_y > 0.f && p.sigma_z > 0.f && p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
+  return p.link_cut > 0.f && std::isnormal(p.link_cut * p.link_cut) && p.sigma_y > 0.f && p.sigma_z > 0.f &&
+         p.nwin > 0.f && p.smax > 0.f && p.smax < 1.f &&
          p.min_hits >= 3 && p.max_miss >= 1 && p.merge_dz >= 0.f && p.v_drift > 0.f &&
          (p.ext_down == 0 || p.ext_down == 1) && (p.merge_membrane == 0 || p.merge_membrane == 1);
 }

@@ -26,6 +26,7 @@ struct Consts {
   float cos20, sin20, tan10;
   float vy, vz;          // sigma^2
   float cut2;            // link_cut^2
+  float cut2_above;      // the float just above cut2 (cut2 is a normal float)
   float smax;
   float win_dy_slope, win_dy_const, win_dz_slope, win_dz_const, link_cut;
   float nwin, chi2_follow;

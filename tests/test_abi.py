@@ -60,6 +60,7 @@ def test_context_rejects_parameters_outside_their_domain():
     lib = tpc.lib()
     bad = [("sigma_y", 0.0), ("sigma_z", -1.0), ("nwin", 0.0), ("smax", 1.0), ("smax", 0.0),
            ("min_hits", 2), ("max_miss", 0), ("merge_dz", -0.5), ("link_cut", float("nan")),
+           ("link_cut", 0.0), ("link_cut", -1.0), ("link_cut", 1e-30), ("link_cut", 1e20),
            ("bz", float("inf")), ("chi2_merge", float("-inf"))]
     for name, v in bad:
         p = tpc.default_params()
