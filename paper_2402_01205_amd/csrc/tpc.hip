@@ -605,20 +605,22 @@ __device__ __forceinline__ void link_search(const GridView& G, int32_t slot, flo
               for (int32_t db0 = B0[e]; db0 < B1[e]; db0 += kLinkBatch) {
                 float2 D[kLinkBatch];
 #pragma unroll
-                for (int j = 0; j < kLinkBatch; ++j)
-                  D[j] = db0 + j < B1[e] ? G.yz[db0 + j] : make_float2(0.f, 0.f);
+                for (int j = 0; j < kLinkBatch; ++j)  // past the range: a position whose score is inf
+                  D[j] = db0 + j < B1[e] ? G.yz[db0 + j] : make_float2(__builtin_inff(), __builtin_inff());
 #pragma unroll
                 for (int j = 0; j < kLinkBatch; ++j) {
                   const int32_t dd = db0 + j;
                   const float ry = (yu + D[j].x) - y2;
                   const float rz = (zu + D[j].y) - z2;
                   const float sc = ry * ry + rz * rz;
-                  // the best pair is kept with selects; only an exact tie takes a branch
-                  const bool in = dd < B1[e];
-                  bool win = in && sc < best;
-                  if (in && sc == best && bu >= 0) {
-                    const int32_t uo = G.gh[u].idx, bo = G.gh[bu].idx;
-                    win = uo < bo || (uo == bo && G.gh[dd].idx < G.gh[bd].idx);
+                  // the best pair is kept with selects; only an equal score takes a branch (an
+                  // exact tie, or before any pair a score just above the cut)
+                  bool win = sc < best;
+                  if (sc == best) {
+                    if (bu >= 0) {
+                      const int32_t uo = G.gh[u].idx, bo = G.gh[bu].idx;
+                      win = uo < bo || (uo == bo && G.gh[dd].idx < G.gh[bd].idx);
+                    }
                   }
                   best = win ? sc : best;
                   bu = win ? u : bu;
